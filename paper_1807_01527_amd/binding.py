@@ -1,0 +1,229 @@
+"""ctypes binding of libatpool.so (the C ABI in include/at.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device arrays are torch tensors (PyTorch provides device memory and
+the stream); host arrays are numpy.  The library must be built for gfx950 --
+there is no fallback: a missing library raises at first use.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libatpool.so")
+
+AT_OK, AT_E_INVAL, AT_E_STATE, AT_E_NOMEM, AT_E_OVERFLOW, AT_E_DEVICE, AT_E_BUDGET = 0, -1, -2, -3, -4, -5, -6
+AT_F_SAT, AT_F_NEG, AT_F_FALLBACK, AT_F_SUPER = 1, 2, 4, 8
+
+
+class AtError(RuntimeError):
+    def __init__(self, rc: int, where: str):
+        super().__init__(f"{where}: {strerror(rc)} (rc={rc})")
+        self.rc = rc
+
+
+class Params(C.Structure):
+    _fields_ = [("k", C.c_uint32), ("r", C.c_uint32), ("c", C.c_uint32), ("s", C.c_uint32),
+                ("u", C.c_uint32), ("log2g", C.c_uint32), ("theta", C.c_double),
+                ("seed", C.c_uint64), ("tuple_budget", C.c_uint64)]
+
+
+# name -> (restype, argtypes); every symbol include/at.h declares
+_vp = C.c_void_p
+_u8p, _u32p, _u64p, _f64p, _f32p = (C.POINTER(C.c_uint8), C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_float))
+SIGNATURES = {
+    "at_create": (C.c_int, [C.POINTER(Params), _vp, C.POINTER(_vp)]),
+    "at_ingest_slice": (C.c_int, [_vp, _vp, _vp, C.c_uint64]),
+    "at_close_slice": (C.c_int, [_vp, C.c_uint32]),
+    "at_estimate": (C.c_int, [_vp, _u32p, C.c_uint64, _f64p, _u8p]),
+    "at_restore": (C.c_int, [_vp, _u32p, _f64p, _u8p, C.c_uint64, _u64p]),
+    "at_destroy": (C.c_int, [_vp]),
+    "at_strerror": (C.c_char_p, [C.c_int]),
+    "at_pool_info": (C.c_int, [_vp, _u64p, _u64p]),
+    "at_read_pool": (C.c_int, [_vp, _u8p]),
+    "at_read_summary": (C.c_int, [_vp, _u32p, _u64p]),
+    "at_clock": (C.c_int, [_vp, _u64p]),
+    "at_constants": (C.c_int, [_vp, _u64p]),
+    "at_estimate_detail": (C.c_int, [_vp, _u32p, C.c_uint64, _f64p, _u8p, _u32p]),
+    "at_estimate_dev": (C.c_int, [_vp, _vp, C.c_uint64, _vp, _vp, _vp]),
+    "at_tuple_count": (C.c_int, [_vp, _u64p]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with paper_1807_01527_amd/build.py "
+                              "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+        lib = C.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def strerror(rc: int) -> str:
+    try:
+        return load().at_strerror(rc).decode()
+    except ImportError:
+        return str(rc)
+
+
+def _p(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _dev_ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device (cuda) tensor")
+    if not t.is_contiguous():
+        raise ValueError("device tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _check(rc: int, where: str):
+    if rc != AT_OK:
+        raise AtError(rc, where)
+
+
+class AtPool:
+    """One link: an ATVC pool in device memory, driven on a HIP stream."""
+
+    def __init__(self, k: int, r: int, c: int, s: int, u: int, log2g: int, theta: float = 1024.0,
+                 seed: int = 0, tuple_budget: int = 0, stream=None):
+        import torch
+        self.lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        p = Params(k, r, c, s, u, log2g, theta, seed, tuple_budget)
+        h = C.c_void_p()
+        _check(self.lib.at_create(C.byref(p), C.c_void_p(stream.cuda_stream), C.byref(h)), "at_create")
+        self.h = h
+        self.k, self.r, self.c, self.s, self.u, self.log2g = k, r, c, s, u, log2g
+        self.g = 1 << log2g
+        self.theta = theta
+        pb, na = C.c_uint64(), C.c_uint64()
+        _check(self.lib.at_pool_info(self.h, C.byref(pb), C.byref(na)), "at_pool_info")
+        self.pool_bytes, self.n_atv = int(pb.value), int(na.value)
+
+    @staticmethod
+    def try_create(**kw) -> int:
+        import torch
+        lib = load()
+        p = Params(kw["k"], kw["r"], kw["c"], kw["s"], kw["u"], kw["log2g"], kw.get("theta", 1024.0),
+                   kw.get("seed", 0), kw.get("tuple_budget", 0))
+        h = C.c_void_p()
+        rc = lib.at_create(C.byref(p), C.c_void_p(torch.cuda.current_stream().cuda_stream), C.byref(h))
+        if rc == AT_OK:
+            lib.at_destroy(h)
+        return rc
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            self.lib.at_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def _handle(self):
+        if not self.h:
+            raise AtError(AT_E_STATE, "handle destroyed")
+        return self.h
+
+    # ---- the six calls --------------------------------------------------
+    def ingest(self, aip_dev, bip_dev, n: Optional[int] = None):
+        if n is None:
+            n = aip_dev.numel()
+        if aip_dev.numel() < n or bip_dev.numel() < n:
+            raise ValueError("n exceeds the device arrays")
+        _check(self.lib.at_ingest_slice(self._handle(), C.c_void_p(_dev_ptr(aip_dev)),
+                                        C.c_void_p(_dev_ptr(bip_dev)), n), "at_ingest_slice")
+
+    def ingest_raw(self, aip_ptr: int, bip_ptr: int, n: int) -> int:
+        return self.lib.at_ingest_slice(self._handle(), C.c_void_p(aip_ptr), C.c_void_p(bip_ptr), n)
+
+    def close(self, kprime: Optional[int] = None):
+        _check(self.lib.at_close_slice(self._handle(), self.k if kprime is None else kprime), "at_close_slice")
+
+    def estimate(self, aip_host: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        aip = np.ascontiguousarray(aip_host, np.uint32)
+        est = np.zeros(aip.size, np.float64)
+        fl = np.zeros(aip.size, np.uint8)
+        nat = np.zeros(aip.size, np.uint32)
+        _check(self.lib.at_estimate_detail(self._handle(), _p(aip, C.c_uint32), aip.size, _p(est, C.c_double),
+                                           _p(fl, C.c_uint8), _p(nat, C.c_uint32)), "at_estimate")
+        return est, fl, nat
+
+    def estimate_plain(self, aip_host: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+        aip = np.ascontiguousarray(aip_host, np.uint32)
+        est = np.zeros(aip.size, np.float64)
+        fl = np.zeros(aip.size, np.uint8)
+        _check(self.lib.at_estimate(self._handle(), _p(aip, C.c_uint32), aip.size, _p(est, C.c_double),
+                                    _p(fl, C.c_uint8)), "at_estimate")
+        return est, fl
+
+    def estimate_dev(self, aip_dev, est_dev=None, flags_dev=None, nat_dev=None):
+        n = aip_dev.numel()
+        ptr = lambda t: C.c_void_p(_dev_ptr(t)) if t is not None else C.c_void_p(0)  # noqa: E731
+        _check(self.lib.at_estimate_dev(self._handle(), ptr(aip_dev), n, ptr(est_dev), ptr(flags_dev),
+                                        ptr(nat_dev)), "at_estimate_dev")
+
+    def restore(self, cap: int = 1 << 22):
+        """Returns (rc, sips, est, flags, n_out); arrays are None unless rc == AT_OK."""
+        sip = np.zeros(max(cap, 1), np.uint32)
+        est = np.zeros(max(cap, 1), np.float64)
+        fl = np.zeros(max(cap, 1), np.uint8)
+        n = C.c_uint64()
+        rc = self.lib.at_restore(self._handle(), _p(sip, C.c_uint32), _p(est, C.c_double), _p(fl, C.c_uint8),
+                                 cap, C.byref(n))
+        m = int(n.value)
+        if rc == AT_OK:
+            return rc, sip[:m].copy(), est[:m].copy(), fl[:m].copy(), m
+        if rc in (AT_E_OVERFLOW, AT_E_BUDGET):
+            return rc, None, None, None, m
+        raise AtError(rc, "at_restore")
+
+    # ---- introspection --------------------------------------------------
+    def read_pool(self) -> np.ndarray:
+        out = np.zeros(self.pool_bytes, np.uint8)
+        _check(self.lib.at_read_pool(self._handle(), _p(out, C.c_uint8)), "at_read_pool")
+        return out
+
+    def read_summary(self) -> Tuple[np.ndarray, np.ndarray]:
+        w = np.zeros(self.n_atv, np.uint32)
+        aat = np.zeros((1 << self.u) * self.r, np.uint64)
+        _check(self.lib.at_read_summary(self._handle(), _p(w, C.c_uint32), _p(aat, C.c_uint64)),
+               "at_read_summary")
+        return w, aat
+
+    def clock(self) -> dict:
+        out = np.zeros(5, np.uint64)
+        _check(self.lib.at_clock(self._handle(), _p(out, C.c_uint64)), "at_clock")
+        return dict(zip(["t", "open", "queryable", "c0_query", "kq"], map(int, out)))
+
+    def constants(self) -> dict:
+        out = np.zeros(8, np.uint64)
+        _check(self.lib.at_constants(self._handle(), _p(out, C.c_uint64)), "at_constants")
+        return dict(zip(["p", "A", "Ainv", "alpha", "beta", "T", "W", "blk_a"], map(int, out)))
+
+    def tuple_count(self) -> int:
+        U = C.c_uint64()
+        _check(self.lib.at_tuple_count(self._handle(), C.byref(U)), "at_tuple_count")
+        return int(U.value)

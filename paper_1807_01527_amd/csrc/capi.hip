@@ -1,0 +1,459 @@
+// C ABI of the ATVC library: parameter validation, derived constants, the
+// slice clock, device buffers and the sequencing of the kernels in
+// kernels.hip.  All device work of a handle is ordered on its stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "at.h"
+#include "atpool.hpp"
+
+using atp::Geometry;
+
+struct at_ctx {
+    at_params p{};
+    Geometry G{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    uint64_t n_atv = 0, pool_bytes = 0;
+    uint32_t nframe = 0, ngroups = 0;  // frames and (frame,row) groups
+    // device state
+    uint8_t* pool = nullptr;
+    uint32_t* w = nullptr;        // per ATV weight of the last close
+    uint64_t* aat = nullptr;      // per (frame,row)
+    uint32_t* sa = nullptr;       // per (frame,row): ascending super columns
+    uint32_t* sa_cnt = nullptr;   // per (frame,row)
+    unsigned long long* counter = nullptr;
+    uint64_t* prefix = nullptr;   // nframe+1 restore item offsets
+    // grow-on-demand device scratch
+    uint32_t* cand = nullptr;
+    uint64_t cand_cap = 0;
+    uint32_t* q_aip = nullptr;
+    double* q_est = nullptr;
+    uint8_t* q_flags = nullptr;
+    uint32_t* q_nat = nullptr;
+    uint64_t q_cap = 0;
+    // slice clock
+    uint64_t t = 0;
+    bool open = false;
+    bool queryable = false;
+    uint32_t c0 = 0, c0_query = 0, kq = 0;
+};
+
+namespace {
+
+uint64_t splitmix_next(uint64_t& s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t pow_mod_p(uint64_t b, uint64_t e) {
+    const uint64_t p = atp::kPrime;
+    uint64_t r = 1;
+    b %= p;
+    while (e) {
+        if (e & 1) r = (r * b) % p;  // operands < 2^32: products fit in 64 bits
+        b = (b * b) % p;
+        e >>= 1;
+    }
+    return r;
+}
+
+int validate(const at_params& p) {
+    if (p.u > 16 || p.k < 1 || p.k > 127 || p.r < 1 || p.r > (uint32_t)atp::kMaxRows) return AT_E_INVAL;
+    const uint32_t W = 32 - p.u;
+    if (p.c < 1 || p.c > 20 || p.s < 1 || p.s > p.c || p.c > W) return AT_E_INVAL;
+    if (p.c + p.s * (p.r - 1) < W) return AT_E_INVAL;  // completeness
+    if (p.c * p.r <= W) return AT_E_INVAL;             // redundancy
+    if (p.s * (p.r - 1) >= W) return AT_E_INVAL;
+    if (p.log2g < 4 || p.log2g > 16) return AT_E_INVAL;
+    if (!(p.theta > 0) || !std::isfinite(p.theta)) return AT_E_INVAL;
+    if ((uint64_t)p.c + p.u + p.log2g > 36) return AT_E_INVAL;  // pool <= r * 64 GiB
+    return AT_OK;
+}
+
+Geometry derive(const at_params& p) {
+    Geometry G{};
+    G.k = p.k;
+    G.twok = 2 * p.k;
+    G.r = p.r;
+    G.c = p.c;
+    G.s = p.s;
+    G.u = p.u;
+    G.W = 32 - p.u;
+    G.log2g = p.log2g;
+    G.g = 1u << p.log2g;
+    G.ncol_mask = (1u << p.c) - 1u;
+    G.umask = (1u << p.u) - 1u;
+    uint64_t st = p.seed;
+    const uint64_t x0 = splitmix_next(st), x1 = splitmix_next(st), x2 = splitmix_next(st);
+    const uint64_t A = (1ull << 31) + x0 % (atp::kPrime - (1ull << 31));
+    G.A = (uint32_t)A;
+    G.Ainv = (uint32_t)pow_mod_p(A, atp::kPrime - 2);
+    G.alpha = x1 | 1ull;
+    G.beta = x2;
+    G.blk_a = G.g / G.twok;
+    G.last_blk = G.twok - 1;
+    G.blk_magic = G.blk_a ? (((1ull << 32) + G.blk_a - 1) / G.blk_a) : 0;
+    G.maskW = G.W == 32 ? 0xFFFFFFFFull : ((1ull << G.W) - 1);
+    for (uint32_t j = 0; j < (uint32_t)atp::kMaxRows; j++) {
+        G.sh[j] = j < p.r ? (p.s * j) % G.W : 0;
+        if (j < p.r) {
+            uint64_t t = (uint64_t)G.ncol_mask << G.sh[j];
+            G.win[j] = (uint32_t)((t | (t >> G.W)) & G.maskW);
+        }
+    }
+    // Section 4.2: super ATVs hold at least g - g*exp(-theta/g) active ATs
+    const double thr = (double)G.g - (double)G.g * std::exp(-p.theta / (double)G.g);
+    double Tc = std::ceil(thr);
+    if (Tc < 0) Tc = 0;
+    G.T = (uint32_t)Tc;
+    G.theta = p.theta;
+    return G;
+}
+
+int dev_err(hipError_t e) { return e == hipSuccess ? AT_OK : (e == hipErrorOutOfMemory ? AT_E_NOMEM : AT_E_DEVICE); }
+
+template <typename T>
+int dev_alloc(T** p, uint64_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? AT_E_NOMEM : AT_E_DEVICE;
+    }
+    return AT_OK;
+}
+
+void free_all(at_ctx* h) {
+    void* bufs[] = {h->pool, h->w, h->aat, h->sa, h->sa_cnt, h->counter, h->prefix, h->cand,
+                    h->q_aip, h->q_est, h->q_flags, h->q_nat};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+}
+
+bool device_accessible(const void* ptr) {
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged ||
+           attr.type == hipMemoryTypeUnified || (attr.type == hipMemoryTypeHost && attr.devicePointer != nullptr);
+}
+
+int open_slice(at_ctx* h) {
+    if (h->open) return AT_OK;
+    h->c0 = (uint32_t)(h->t % h->G.twok);
+    hipError_t e = atp::launch_preserve(h->pool, h->n_atv, h->G, h->c0, h->stream);
+    if (e != hipSuccess) return AT_E_DEVICE;
+    h->open = true;
+    h->queryable = false;
+    return AT_OK;
+}
+
+int ensure_query(at_ctx* h, uint64_t n) {
+    if (n <= h->q_cap) return AT_OK;
+    uint64_t cap = std::max<uint64_t>(n, 1024);
+    if (h->q_aip) (void)hipFree(h->q_aip);
+    if (h->q_est) (void)hipFree(h->q_est);
+    if (h->q_flags) (void)hipFree(h->q_flags);
+    if (h->q_nat) (void)hipFree(h->q_nat);
+    h->q_aip = nullptr;
+    h->q_est = nullptr;
+    h->q_flags = nullptr;
+    h->q_nat = nullptr;
+    h->q_cap = 0;
+    int rc;
+    if ((rc = dev_alloc(&h->q_aip, cap)) || (rc = dev_alloc(&h->q_est, cap)) || (rc = dev_alloc(&h->q_flags, cap)) ||
+        (rc = dev_alloc(&h->q_nat, cap)))
+        return rc;
+    h->q_cap = cap;
+    return AT_OK;
+}
+
+uint64_t sat_mul(uint64_t a, uint64_t b) {
+    if (a == 0 || b == 0) return 0;
+    if (a > UINT64_MAX / b) return UINT64_MAX;
+    return a * b;
+}
+
+int read_counts(at_ctx* h, std::vector<uint32_t>& cnt) {
+    cnt.assign(h->ngroups, 0);
+    hipError_t e = hipMemcpyAsync(cnt.data(), h->sa_cnt, h->ngroups * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                  h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return dev_err(e);
+}
+
+uint64_t tuple_count(const at_ctx* h, const std::vector<uint32_t>& cnt) {
+    uint64_t total = 0;
+    for (uint32_t z = 0; z < h->nframe; z++) {
+        uint64_t prod = 1;
+        for (uint32_t j = 0; j < h->p.r; j++) prod = sat_mul(prod, cnt[(uint64_t)z * h->p.r + j]);
+        total = (UINT64_MAX - total < prod) ? UINT64_MAX : total + prod;
+    }
+    return total;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* at_strerror(int rc) {
+    switch (rc) {
+        case AT_OK: return "ok";
+        case AT_E_INVAL: return "invalid argument";
+        case AT_E_STATE: return "call not valid in the current state";
+        case AT_E_NOMEM: return "out of memory";
+        case AT_E_OVERFLOW: return "result exceeds capacity";
+        case AT_E_DEVICE: return "HIP device error";
+        case AT_E_BUDGET: return "restore tuple budget exceeded";
+        default: return "unknown error";
+    }
+}
+
+int at_create(const at_params* p, void* hip_stream, at_ctx** out) {
+    if (!out) return AT_E_INVAL;
+    *out = nullptr;
+    if (!p) return AT_E_INVAL;
+    int rc = validate(*p);
+    if (rc) return rc;
+    at_ctx* h = new (std::nothrow) at_ctx();
+    if (!h) return AT_E_NOMEM;
+    h->p = *p;
+    if (h->p.tuple_budget == 0) h->p.tuple_budget = 1ull << 32;
+    h->G = derive(h->p);
+    h->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return AT_E_DEVICE;
+    }
+    h->nframe = 1u << p->u;
+    h->ngroups = h->nframe * p->r;
+    h->n_atv = (uint64_t)h->ngroups << p->c;
+    h->pool_bytes = h->n_atv << p->log2g;
+    if ((rc = dev_alloc(&h->pool, h->pool_bytes)) || (rc = dev_alloc(&h->w, h->n_atv)) ||
+        (rc = dev_alloc(&h->aat, h->ngroups)) || (rc = dev_alloc(&h->sa, h->n_atv)) ||
+        (rc = dev_alloc(&h->sa_cnt, h->ngroups)) || (rc = dev_alloc(&h->counter, 1)) ||
+        (rc = dev_alloc(&h->prefix, h->nframe + 1))) {
+        free_all(h);
+        delete h;
+        return rc;
+    }
+    // InitAT (Section 3): every AT starts inactive
+    hipError_t e = atp::launch_fill_u8(h->pool, h->pool_bytes, (uint8_t)h->G.twok, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        free_all(h);
+        delete h;
+        return AT_E_DEVICE;
+    }
+    *out = h;
+    return AT_OK;
+}
+
+int at_destroy(at_ctx* h) {
+    if (!h) return AT_OK;
+    (void)hipStreamSynchronize(h->stream);
+    free_all(h);
+    delete h;
+    return AT_OK;
+}
+
+int at_ingest_slice(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, uint64_t n) {
+    if (!h) return AT_E_INVAL;
+    if (n > 0) {
+        if (!aip_dev || !bip_dev) return AT_E_INVAL;
+        if (!device_accessible(aip_dev) || !device_accessible(bip_dev)) return AT_E_INVAL;
+    }
+    int rc = open_slice(h);
+    if (rc) return rc;
+    return atp::launch_ingest(h->pool, aip_dev, bip_dev, n, h->G, h->c0, h->stream) == hipSuccess ? AT_OK
+                                                                                                 : AT_E_DEVICE;
+}
+
+int at_close_slice(at_ctx* h, uint32_t kprime) {
+    if (!h) return AT_E_INVAL;
+    if (kprime < 1 || kprime > h->p.k) return AT_E_INVAL;
+    int rc = open_slice(h);
+    if (rc) return rc;
+    hipError_t e = atp::launch_close(h->pool, h->w, h->n_atv, h->G, h->c0, kprime, h->stream);
+    if (e == hipSuccess) e = atp::launch_summarize(h->w, h->aat, h->sa, h->sa_cnt, h->G, h->stream);
+    if (e != hipSuccess) return AT_E_DEVICE;
+    h->c0_query = h->c0;
+    h->kq = kprime;
+    h->t += 1;
+    h->open = false;
+    h->queryable = true;
+    return AT_OK;
+}
+
+int at_estimate_dev(at_ctx* h, const uint32_t* aip_dev, uint64_t n, double* est_dev, uint8_t* flags_dev,
+                    uint32_t* nat_dev) {
+    if (!h) return AT_E_INVAL;
+    if (!h->queryable) return AT_E_STATE;
+    if (n == 0) return AT_OK;
+    if (!aip_dev) return AT_E_INVAL;
+    hipError_t e = atp::launch_estimate(h->pool, h->aat, aip_dev, n, h->G, h->c0_query, h->kq, est_dev, flags_dev,
+                                        nat_dev, h->stream);
+    return e == hipSuccess ? AT_OK : AT_E_DEVICE;
+}
+
+int at_estimate_detail(at_ctx* h, const uint32_t* aip_host, uint64_t n, double* est_out, uint8_t* flags_out,
+                       uint32_t* nat_out) {
+    if (!h) return AT_E_INVAL;
+    if (!h->queryable) return AT_E_STATE;
+    if (n == 0) return AT_OK;
+    if (!aip_host) return AT_E_INVAL;
+    int rc = ensure_query(h, n);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(h->q_aip, aip_host, n * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = atp::launch_estimate(h->pool, h->aat, h->q_aip, n, h->G, h->c0_query, h->kq, h->q_est, h->q_flags,
+                                 h->q_nat, h->stream);
+    if (e == hipSuccess && est_out)
+        e = hipMemcpyAsync(est_out, h->q_est, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && flags_out)
+        e = hipMemcpyAsync(flags_out, h->q_flags, n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && nat_out)
+        e = hipMemcpyAsync(nat_out, h->q_nat, n * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return dev_err(e);
+}
+
+int at_estimate(at_ctx* h, const uint32_t* aip_host, uint64_t n, double* est_out, uint8_t* flags_out) {
+    return at_estimate_detail(h, aip_host, n, est_out, flags_out, nullptr);
+}
+
+int at_tuple_count(at_ctx* h, uint64_t* U) {
+    if (!h || !U) return AT_E_INVAL;
+    if (!h->queryable) return AT_E_STATE;
+    std::vector<uint32_t> cnt;
+    int rc = read_counts(h, cnt);
+    if (rc) return rc;
+    *U = tuple_count(h, cnt);
+    return AT_OK;
+}
+
+int at_restore(at_ctx* h, uint32_t* sip_out, double* est_out, uint8_t* flags_out, uint64_t cap, uint64_t* n_out) {
+    if (!h || !n_out) return AT_E_INVAL;
+    if (!h->queryable) return AT_E_STATE;
+    std::vector<uint32_t> cnt;
+    int rc = read_counts(h, cnt);
+    if (rc) return rc;
+    const uint64_t U = tuple_count(h, cnt);
+    if (U > h->p.tuple_budget) {
+        *n_out = U;
+        return AT_E_BUDGET;
+    }
+    // work items: (x0, x1) pairs per frame (single columns when r == 1)
+    std::vector<uint64_t> prefix(h->nframe + 1, 0);
+    for (uint32_t z = 0; z < h->nframe; z++) {
+        uint64_t items = cnt[(uint64_t)z * h->p.r];
+        if (h->p.r >= 2) items *= cnt[(uint64_t)z * h->p.r + 1];
+        bool empty = false;
+        for (uint32_t j = 0; j < h->p.r; j++) empty |= cnt[(uint64_t)z * h->p.r + j] == 0;
+        prefix[z + 1] = prefix[z] + (empty ? 0 : items);
+    }
+    const uint64_t n_items = prefix[h->nframe];
+    // candidates are at most U (distinct tuples give distinct addresses)
+    uint64_t need = std::min<uint64_t>(U, cap);
+    uint64_t pow2 = 1;
+    while (pow2 < need) pow2 <<= 1;
+    if (pow2 > h->cand_cap) {
+        if (h->cand) (void)hipFree(h->cand);
+        h->cand = nullptr;
+        h->cand_cap = 0;
+        if ((rc = dev_alloc(&h->cand, pow2))) return rc;
+        h->cand_cap = pow2;
+    }
+    hipError_t e = hipMemcpyAsync(h->prefix, prefix.data(), prefix.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
+                                  h->stream);
+    if (e == hipSuccess) e = atp::launch_zero_u64(h->counter, 1, h->stream);
+    if (e == hipSuccess)
+        e = atp::launch_restore_join(h->sa, h->sa_cnt, h->prefix, n_items, h->G, h->cand, need, h->counter,
+                                     h->stream);
+    unsigned long long m = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&m, h->counter, sizeof(m), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return dev_err(e);
+    *n_out = m;
+    if (m > cap) return AT_E_OVERFLOW;
+    if (m == 0) return AT_OK;
+    uint64_t mp2 = 1;
+    while (mp2 < m) mp2 <<= 1;
+    if ((rc = ensure_query(h, m))) return rc;
+    e = atp::launch_sort_u32(h->cand, m, mp2, h->stream);
+    if (e == hipSuccess && (est_out || flags_out))
+        e = atp::launch_estimate(h->pool, h->aat, h->cand, m, h->G, h->c0_query, h->kq, h->q_est, h->q_flags,
+                                 nullptr, h->stream);
+    if (e == hipSuccess && sip_out)
+        e = hipMemcpyAsync(sip_out, h->cand, m * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && est_out)
+        e = hipMemcpyAsync(est_out, h->q_est, m * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && flags_out) e = hipMemcpyAsync(flags_out, h->q_flags, m, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return dev_err(e);
+}
+
+int at_pool_info(const at_ctx* h, uint64_t* pool_bytes, uint64_t* n_atv) {
+    if (!h) return AT_E_INVAL;
+    if (pool_bytes) *pool_bytes = h->pool_bytes;
+    if (n_atv) *n_atv = h->n_atv;
+    return AT_OK;
+}
+
+int at_read_pool(at_ctx* h, uint8_t* host_out) {
+    if (!h || !host_out) return AT_E_INVAL;
+    hipError_t e = hipMemcpyAsync(host_out, h->pool, h->pool_bytes, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return dev_err(e);
+}
+
+int at_read_summary(at_ctx* h, uint32_t* w_host, uint64_t* aat_host) {
+    if (!h) return AT_E_INVAL;
+    if (h->t == 0) return AT_E_STATE;
+    hipError_t e = hipSuccess;
+    if (w_host) e = hipMemcpyAsync(w_host, h->w, h->n_atv * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && aat_host)
+        e = hipMemcpyAsync(aat_host, h->aat, h->ngroups * sizeof(uint64_t), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return dev_err(e);
+}
+
+int at_clock(const at_ctx* h, uint64_t* out5) {
+    if (!h || !out5) return AT_E_INVAL;
+    out5[0] = h->t;
+    out5[1] = h->open;
+    out5[2] = h->queryable;
+    out5[3] = h->c0_query;
+    out5[4] = h->kq;
+    return AT_OK;
+}
+
+int at_constants(const at_ctx* h, uint64_t* out8) {
+    if (!h || !out8) return AT_E_INVAL;
+    out8[0] = atp::kPrime;
+    out8[1] = h->G.A;
+    out8[2] = h->G.Ainv;
+    out8[3] = h->G.alpha;
+    out8[4] = h->G.beta;
+    out8[5] = h->G.T;
+    out8[6] = h->G.W;
+    out8[7] = h->G.blk_a;
+    return AT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,651 @@
+// gfx950 kernels of the ATVC hot path: slice open (lazy preserve), pair scan,
+// slice close (window weights, AAT, super lists), restore join, sort, and
+// the per-host estimate.  Wave64 throughout; one byte per AT.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "atpool.hpp"
+
+namespace atp {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ uint32_t mod_mul_p(uint32_t a, uint32_t m) {
+    // a*m mod (2^32 - 5): fold the high word twice (2^32 = 5 mod p), then one
+    // conditional subtract (after two folds the value is below 2^32 + 25 < 2p).
+    uint64_t x = (uint64_t)a * m;
+    uint64_t y = (x >> 32) * 5ull + (x & 0xFFFFFFFFull);
+    uint64_t y2 = (y >> 32) * 5ull + (y & 0xFFFFFFFFull);
+    return (uint32_t)(y2 >= kPrime ? y2 - kPrime : y2);
+}
+
+// Section 4.1 IP mangling: bijection of 32-bit words, identity on [p, 2^32).
+__device__ __forceinline__ uint32_t mangle(uint32_t a, uint32_t A) {
+    return (uint64_t)a >= kPrime ? a : mod_mul_p(a, A);
+}
+
+__device__ __forceinline__ uint32_t block_of(uint32_t i, const Geometry& G) {
+    if (G.blk_a == 0) return G.last_blk;
+    uint32_t b = (uint32_t)(((uint64_t)i * G.blk_magic) >> 32);
+    return b < G.last_blk ? b : G.last_blk;
+}
+
+__device__ __forceinline__ uint32_t act_of(uint32_t i, uint32_t c0, const Geometry& G) {
+    uint32_t v = c0 + block_of(i, G);
+    return v >= G.twok ? v - G.twok : v;
+}
+
+// Column x_j of LBS: c bits starting at bit sh[j], cyclic modulo W.  LL holds
+// L twice (L | L << W) so one 64-bit shift reads across the wrap.
+__device__ __forceinline__ uint32_t column(uint64_t LL, uint32_t sh, uint32_t mask) {
+    return (uint32_t)(LL >> sh) & mask;
+}
+
+// Alg 1 on one byte: inactive value 2k, otherwise active when the distance
+// from the block's timestamp is below k'.
+__device__ __forceinline__ uint32_t is_active(uint32_t at, uint32_t act, uint32_t twok, uint32_t kq) {
+    uint32_t d = act >= at ? act - at : act + twok - at;
+    return (at != twok) & (d < kq);
+}
+
+__device__ __forceinline__ uint32_t active_mask4(uint32_t atw, uint32_t actw, uint32_t twok, uint32_t kq) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int b = 0; b < 4; b++)
+        m |= is_active((atw >> (8 * b)) & 0xFFu, (actw >> (8 * b)) & 0xFFu, twok, kq) << b;
+    return m;
+}
+
+__device__ __forceinline__ uint32_t active_mask16(uint4 at, uint4 act, uint32_t twok, uint32_t kq) {
+    return active_mask4(at.x, act.x, twok, kq) | (active_mask4(at.y, act.y, twok, kq) << 4) |
+           (active_mask4(at.z, act.z, twok, kq) << 8) | (active_mask4(at.w, act.w, twok, kq) << 12);
+}
+
+// per-position block timestamp table for the slice whose first block has C0
+__device__ void fill_act_lut(uint8_t* lut, uint32_t c0, const Geometry& G) {
+    for (uint32_t i = threadIdx.x; i < G.g; i += blockDim.x) lut[i] = (uint8_t)act_of(i, c0, G);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- utilities
+
+__global__ void k_fill_u8(uint8_t* __restrict__ p, uint64_t n, uint8_t v) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 16;
+    uint32_t v4 = v * 0x01010101u;
+    uint4 vv = make_uint4(v4, v4, v4, v4);
+    for (uint64_t o = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16; o < n; o += stride) {
+        if (o + 16 <= n) *(uint4*)(p + o) = vv;
+        else
+            for (uint64_t q = o; q < n; q++) p[q] = v;
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, uint32_t n) {
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// ---------------------------------------------------------------- a1: open
+// Alg 2 applied lazily: of the 2k blocks of every ATV only the two whose
+// timestamp becomes 0 or k can change (Section 3); every other AT is left
+// alone, which is exactly what Alg 2 does to it.  Work items are 4-byte words
+// of one or two disjoint word spans per ATV; bytes outside the due blocks are
+// written back unchanged.
+struct PreserveSpans {
+    uint32_t r0lo, r0hi;  // byte range of the block with timestamp 0
+    uint32_t r1lo, r1hi;  // byte range of the block with timestamp k
+    uint32_t w0lo, nw0;   // word span 0
+    uint32_t w1lo, nw1;   // word span 1 (may be empty)
+};
+
+__global__ __launch_bounds__(kBlock) void k_preserve(uint8_t* __restrict__ pool, uint64_t n_atv,
+                                                     uint32_t log2g, uint32_t k, PreserveSpans S) {
+    const uint32_t per_atv = S.nw0 + S.nw1;
+    const uint64_t total = n_atv * per_atv;
+    const uint32_t twok = 2 * k;
+    for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+         it += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t atv = it / per_atv;
+        uint32_t wi = (uint32_t)(it - atv * per_atv);
+        uint32_t word = wi < S.nw0 ? S.w0lo + wi : S.w1lo + (wi - S.nw0);
+        uint32_t* p = (uint32_t*)(pool + (atv << log2g)) + word;
+        uint32_t v = *p, nv = v;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            uint32_t pos = word * 4 + b;
+            uint32_t at = (v >> (8 * b)) & 0xFFu;
+            uint32_t out = at;
+            if (pos >= S.r0lo && pos < S.r0hi && at <= k) out = twok;
+            if (pos >= S.r1lo && pos < S.r1hi && ((at >= k && at < twok) || at == 0)) out = twok;
+            nv = (nv & ~(0xFFu << (8 * b))) | (out << (8 * b));
+        }
+        if (nv != v) *p = nv;
+    }
+}
+
+// ---------------------------------------------------------------- a2+a3: scan
+// Alg 3 fused with the hashing of Section 4.1: f = A*aip mod p, frame = low u
+// bits, columns from LBS, AT index BH(bip), value = that AT's block timestamp.
+// The r byte stores need no atomics: every writer of an AT in a slice stores
+// the same value.
+template <int R>
+__device__ __forceinline__ void scan_pair(uint8_t* __restrict__ pool, uint32_t a, uint32_t b,
+                                          const Geometry& G, uint32_t c0) {
+    uint32_t f = mangle(a, G.A);
+    uint32_t z = f & G.umask;
+    uint64_t L = (uint64_t)(f >> G.u);
+    uint64_t LL = L | (L << G.W);
+    uint32_t i = (uint32_t)((G.alpha * (uint64_t)b + G.beta) >> (64 - G.log2g));
+    uint8_t v = (uint8_t)act_of(i, c0, G);
+    uint64_t zr = (uint64_t)z * R;
+#pragma unroll
+    for (int j = 0; j < R; j++) {
+        uint32_t x = column(LL, G.sh[j], G.ncol_mask);
+        uint64_t idx = ((((zr + j) << G.c) + x) << G.log2g) | i;
+        pool[idx] = v;
+    }
+}
+
+template <int R, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_ingest(uint8_t* __restrict__ pool, const uint32_t* __restrict__ aip,
+                                                   const uint32_t* __restrict__ bip, uint64_t n, Geometry G,
+                                                   uint32_t c0) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t done = 0;
+    if (VEC) {
+        const uint64_t n4 = n / 4;
+        const uint4* a4 = reinterpret_cast<const uint4*>(aip);
+        const uint4* b4 = reinterpret_cast<const uint4*>(bip);
+        for (uint64_t q = tid; q < n4; q += stride) {
+            uint4 a = a4[q];
+            uint4 b = b4[q];
+            scan_pair<R>(pool, a.x, b.x, G, c0);
+            scan_pair<R>(pool, a.y, b.y, G, c0);
+            scan_pair<R>(pool, a.z, b.z, G, c0);
+            scan_pair<R>(pool, a.w, b.w, G, c0);
+        }
+        done = n4 * 4;
+    }
+    for (uint64_t q = done + tid; q < n; q += stride) scan_pair<R>(pool, aip[q], bip[q], G, c0);
+}
+
+// ---------------------------------------------------------------- a4: close
+// One read of the pool: k'-weight of every ATV (Alg 1 per AT).  A group of
+// lpa = min(64, g/16) lanes covers one ATV with 16-byte loads; a wave covers
+// 64/lpa ATVs per step.  Block timestamps come from an LDS table of g bytes.
+__global__ __launch_bounds__(kBlock) void k_close(const uint8_t* __restrict__ pool, uint32_t* __restrict__ w,
+                                                  uint64_t n_atv, Geometry G, uint32_t c0, uint32_t kq) {
+    extern __shared__ __align__(16) uint8_t act_lut[];
+    fill_act_lut(act_lut, c0, G);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t lpa = G.g / 16 < 64 ? G.g / 16 : 64;
+    const uint32_t apw = 64 / lpa;
+    const uint32_t sub = lane / lpa, sl = lane % lpa;
+    const uint32_t steps = G.g / (16 * lpa);
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
+    for (uint64_t base = wave * apw; base < n_atv; base += nwaves * apw) {
+        uint64_t atv = base + sub;
+        uint32_t cnt = 0;
+        if (atv < n_atv) {
+            const uint8_t* p = pool + (atv << G.log2g);
+            for (uint32_t st = 0; st < steps; st++) {
+                uint32_t off = (st * lpa + sl) * 16;
+                uint4 d = *reinterpret_cast<const uint4*>(p + off);
+                uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
+                cnt += __popc(active_mask16(d, ac, G.twok, kq));
+            }
+        }
+        for (uint32_t o = lpa / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if (sl == 0 && atv < n_atv) w[atv] = cnt;
+    }
+}
+
+// One workgroup per (frame, row): AAT = sum of the row's weights, and the
+// ascending list of super columns (weight >= T) with its length.
+__global__ __launch_bounds__(kBlock) void k_summarize(const uint32_t* __restrict__ w, uint64_t* __restrict__ aat,
+                                                      uint32_t* __restrict__ sa, uint32_t* __restrict__ sa_cnt,
+                                                      Geometry G) {
+    __shared__ uint32_t wave_cnt[kBlock / 64];
+    __shared__ unsigned long long wave_sum[kBlock / 64];
+    const uint32_t grp = blockIdx.x;
+    const uint64_t base = (uint64_t)grp << G.c;
+    const uint32_t ncol = G.ncol_mask + 1;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    uint64_t sum = 0;
+    uint32_t written = 0;
+    for (uint32_t x0 = 0; x0 < ncol; x0 += kBlock) {
+        uint32_t x = x0 + threadIdx.x;
+        uint32_t wx = x < ncol ? w[base + x] : 0u;
+        bool sup = x < ncol && wx >= G.T;
+        sum += wx;
+        uint64_t ball = __ballot(sup);
+        uint32_t before = __popcll(ball & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_cnt[wv] = __popcll(ball);
+        __syncthreads();
+        uint32_t off = written;
+        for (uint32_t q = 0; q < wv; q++) off += wave_cnt[q];
+        uint32_t tot = 0;
+        for (uint32_t q = 0; q < kBlock / 64; q++) tot += wave_cnt[q];
+        if (sup) sa[base + off + before] = x;
+        written += tot;
+        __syncthreads();
+    }
+    for (uint32_t o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if (lane == 0) wave_sum[wv] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (uint32_t q = 0; q < kBlock / 64; q++) t += wave_sum[q];
+        aat[grp] = t;
+        sa_cnt[grp] = written;
+    }
+}
+
+// ---------------------------------------------------------------- a5: restore
+// Alg 4 as a pruned join.  One work item per (x_0, x_1) pair of a frame; rows
+// 2..r-1 are added depth first, and a column is kept only if its bits agree
+// with the LBS bits fixed so far -- so a tuple survives exactly when all its
+// duplicate positions agree.  The survivor's LBS with the frame index gives f,
+// unmangled into the address.
+__device__ __forceinline__ uint32_t place(uint32_t x, uint32_t sh, const Geometry& G) {
+    uint64_t t = (uint64_t)x << sh;
+    return (uint32_t)((t | (t >> G.W)) & G.maskW);
+}
+
+__device__ __forceinline__ void emit(uint32_t L, uint32_t z, const Geometry& G, uint32_t* cand, uint64_t cap,
+                                     unsigned long long* counter) {
+    uint32_t F = G.u ? ((L << G.u) | z) : L;
+    uint32_t a = mangle(F, G.Ainv);
+    unsigned long long pos = atomicAdd(counter, 1ull);
+    if (pos < cap) cand[pos] = a;
+}
+
+__global__ __launch_bounds__(kBlock) void k_restore_join(const uint32_t* __restrict__ sa,
+                                                         const uint32_t* __restrict__ sa_cnt,
+                                                         const uint64_t* __restrict__ prefix, uint64_t n_items,
+                                                         Geometry G, uint32_t* __restrict__ cand, uint64_t cap,
+                                                         unsigned long long* counter) {
+    const uint32_t nframe = G.umask + 1, R = G.r;
+    for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < n_items;
+         it += (uint64_t)gridDim.x * blockDim.x) {
+        // frame of this item: last z with prefix[z] <= it
+        uint32_t lo = 0, hi = nframe;
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (prefix[mid] <= it) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t z = lo;
+        const uint64_t rem = it - prefix[z];
+        const uint32_t* cnt = sa_cnt + (uint64_t)z * R;
+        const uint64_t rowbase = (uint64_t)z * R << G.c;
+        if (R == 1) {
+            emit(place(sa[rowbase + rem], G.sh[0], G), z, G, cand, cap, counter);
+            continue;
+        }
+        const uint32_t c1 = cnt[1];
+        const uint32_t i0 = (uint32_t)(rem / c1), i1 = (uint32_t)(rem - (uint64_t)i0 * c1);
+        uint32_t L = place(sa[rowbase + i0], G.sh[0], G);
+        uint32_t M = G.win[0];
+        uint32_t P = place(sa[rowbase + (1ull << G.c) + i1], G.sh[1], G);
+        if ((P ^ L) & M & G.win[1]) continue;
+        L |= P;
+        M |= G.win[1];
+        if (R == 2) {
+            emit(L, z, G, cand, cap, counter);
+            continue;
+        }
+        uint32_t Ls[kMaxRows], Ms[kMaxRows], idx[kMaxRows];
+        uint32_t lvl = 2;
+        Ls[2] = L;
+        Ms[2] = M;
+        idx[2] = 0;
+        for (;;) {
+            if (idx[lvl] >= cnt[lvl]) {
+                if (lvl == 2) break;
+                lvl--;
+                idx[lvl]++;
+                continue;
+            }
+            uint32_t Pq = place(sa[rowbase + ((uint64_t)lvl << G.c) + idx[lvl]], G.sh[lvl], G);
+            if ((Pq ^ Ls[lvl]) & Ms[lvl] & G.win[lvl]) {
+                idx[lvl]++;
+                continue;
+            }
+            if (lvl == R - 1) {
+                emit(Ls[lvl] | Pq, z, G, cand, cap, counter);
+                idx[lvl]++;
+            } else {
+                Ls[lvl + 1] = Ls[lvl] | Pq;
+                Ms[lvl + 1] = Ms[lvl] | G.win[lvl];
+                lvl++;
+                idx[lvl] = 0;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- sort
+// Bitonic sort of a power-of-two array: 2048-key tiles in LDS, global steps
+// for strides of a tile or more.
+constexpr uint32_t kTile = 2048;
+
+__device__ __forceinline__ void cmp_swap_lds(uint32_t* s, uint32_t li, uint32_t lj, bool up) {
+    uint32_t a = s[li], b = s[lj];
+    if ((a > b) == up) {
+        s[li] = b;
+        s[lj] = a;
+    }
+}
+
+// kfrom..kto: sizes of bitonic sequences merged inside the tile; if merge_only,
+// only the j < kTile steps of size k = kfrom are run.
+__global__ __launch_bounds__(kBlock) void k_bitonic_tile(uint32_t* __restrict__ keys, uint32_t kfrom,
+                                                         uint32_t kto) {
+    __shared__ uint32_t s[kTile];
+    const uint64_t base = (uint64_t)blockIdx.x * kTile;
+    for (uint32_t q = threadIdx.x; q < kTile; q += kBlock) s[q] = keys[base + q];
+    __syncthreads();
+    for (uint32_t k = kfrom; k <= kto; k <<= 1) {
+        for (uint32_t j = (k >> 1) < (kTile >> 1) ? (k >> 1) : (kTile >> 1); j > 0; j >>= 1) {
+            for (uint32_t p = threadIdx.x; p < kTile / 2; p += kBlock) {
+                uint32_t li = 2 * p - (p & (j - 1));
+                uint32_t lj = li + j;
+                bool up = ((base + li) & k) == 0;
+                cmp_swap_lds(s, li, lj, up);
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t q = threadIdx.x; q < kTile; q += kBlock) keys[base + q] = s[q];
+}
+
+__global__ __launch_bounds__(kBlock) void k_bitonic_global(uint32_t* __restrict__ keys, uint64_t n, uint64_t k,
+                                                           uint64_t j) {
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n / 2;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t i = 2 * p - (p & (j - 1));
+        uint64_t l = i + j;
+        bool up = (i & k) == 0;
+        uint32_t a = keys[i], b = keys[l];
+        if ((a > b) == up) {
+            keys[i] = b;
+            keys[l] = a;
+        }
+    }
+}
+
+__global__ void k_small_sort(uint32_t* keys, uint32_t n) {
+    // n <= kTile, power of two, single workgroup
+    __shared__ uint32_t s[kTile];
+    for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) s[q] = keys[q];
+    __syncthreads();
+    for (uint32_t k = 2; k <= n; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t p = threadIdx.x; p < n / 2; p += blockDim.x) {
+                uint32_t li = 2 * p - (p & (j - 1));
+                cmp_swap_lds(s, li, li + j, (li & k) == 0);
+            }
+            __syncthreads();
+        }
+    for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) keys[q] = s[q];
+}
+
+__global__ void k_pad_u32(uint32_t* keys, uint64_t from, uint64_t to) {
+    for (uint64_t q = from + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < to;
+         q += (uint64_t)gridDim.x * blockDim.x)
+        keys[q] = 0xFFFFFFFFu;
+}
+
+// ---------------------------------------------------------------- a6: estimate
+// Alg 5 + Eq 4.  One wave per host: lanes read 16-byte chunks of the host's r
+// ATVs, AND the per-row active masks (Alg 1), count, reduce; lane 0 applies
+// Eq 4 in FP64 with the same operation order as a plain evaluation (P_j
+// exact, UP multiplied left to right, no contraction).
+__device__ double eq4(uint32_t nat, uint32_t z, const uint64_t* __restrict__ aat, const Geometry& G,
+                      uint8_t* flags_out) {
+    uint8_t fl = 0;
+    const double gd = (double)G.g;
+    const double cells = (double)((uint64_t)G.g << G.c);
+    double UP = 1.0;
+    for (uint32_t j = 0; j < G.r; j++) {
+        double Pj = (double)aat[(uint64_t)z * G.r + j] / cells;
+        UP = (j == 0) ? Pj : UP * Pj;
+    }
+    const double one_minus = 1.0 - UP;
+    double est;
+    if (one_minus == 0.0) {
+        est = __builtin_inf();
+        fl |= AT_F_SAT;
+    } else {
+        uint32_t natc = nat;
+        if (nat >= G.g) {
+            natc = G.g - 1;
+            fl |= AT_F_SAT;
+        }
+        const double q = (double)(G.g - natc) / (gd * one_minus);
+        est = -gd * log(q);
+        if (est < 0) fl |= AT_F_NEG;
+    }
+    if (est >= G.theta) fl |= AT_F_SUPER;
+    *flags_out = fl;
+    return est;
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_estimate(const uint8_t* __restrict__ pool, const uint64_t* __restrict__ aat,
+                                                     const uint32_t* __restrict__ aips, uint64_t n, Geometry G,
+                                                     uint32_t c0q, uint32_t kq, double* __restrict__ est,
+                                                     uint8_t* __restrict__ flags, uint32_t* __restrict__ nat_out) {
+    extern __shared__ __align__(16) uint8_t act_lut[];
+    fill_act_lut(act_lut, c0q, G);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
+    for (uint64_t h = wave; h < n; h += nwaves) {
+        const uint32_t a = aips[h];
+        const uint32_t f = mangle(a, G.A);
+        const uint32_t z = f & G.umask;
+        const uint64_t L = (uint64_t)(f >> G.u);
+        const uint64_t LL = L | (L << G.W);
+        const uint8_t* rows[R];
+#pragma unroll
+        for (int j = 0; j < R; j++) {
+            uint32_t x = column(LL, G.sh[j], G.ncol_mask);
+            rows[j] = pool + (((((uint64_t)z * R + j) << G.c) + x) << G.log2g);
+        }
+        uint32_t cnt = 0;
+        for (uint32_t off = lane * 16; off < G.g; off += 64 * 16) {
+            const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
+            uint32_t m = 0xFFFFu;
+#pragma unroll
+            for (int j = 0; j < R; j++) {
+                uint4 d = *reinterpret_cast<const uint4*>(rows[j] + off);
+                m &= active_mask16(d, ac, G.twok, kq);
+            }
+            cnt += __popc(m);
+        }
+        for (uint32_t o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if (lane == 0) {
+            uint8_t fl;
+            double e = eq4(cnt, z, aat, G, &fl);
+            if (est) est[h] = e;
+            if (flags) flags[h] = fl;
+            if (nat_out) nat_out[h] = cnt;
+        }
+    }
+}
+
+uint32_t grid_for(uint64_t items, uint32_t cap) {
+    uint64_t b = (items + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    return (uint32_t)(b < cap ? b : cap);
+}
+
+}  // namespace
+
+// ============================================================== launchers
+
+hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for((n + 15) / 16, 1u << 16)), dim3(kBlock), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, uint32_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u64, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_preserve(uint8_t* pool, uint64_t n_atv, const Geometry& G, uint32_t c0, hipStream_t st) {
+    // blocks whose timestamp (c0 + b) mod 2k becomes 0 and k
+    const uint32_t twok = G.twok, k = G.k;
+    const uint32_t b0 = (twok - c0) % twok, b1 = (3 * k - c0) % twok;
+    auto range = [&](uint32_t b, uint32_t& lo, uint32_t& hi) {
+        if (G.blk_a == 0) {  // all ATs sit in the last block
+            lo = 0;
+            hi = (b == G.last_blk) ? G.g : 0;
+        } else {
+            lo = b * G.blk_a;
+            hi = (b == G.last_blk) ? G.g : lo + G.blk_a;
+        }
+        if (hi <= lo) lo = hi = 0;
+    };
+    PreserveSpans S{};
+    range(b0, S.r0lo, S.r0hi);
+    range(b1, S.r1lo, S.r1hi);
+    // word spans of the two byte ranges, merged when they touch a common word
+    uint32_t sp[2][2];
+    int ns = 0;
+    if (S.r0hi > S.r0lo) { sp[ns][0] = S.r0lo / 4; sp[ns][1] = (S.r0hi + 3) / 4; ns++; }
+    if (S.r1hi > S.r1lo) { sp[ns][0] = S.r1lo / 4; sp[ns][1] = (S.r1hi + 3) / 4; ns++; }
+    if (ns == 2) {
+        if (sp[0][0] > sp[1][0]) {
+            uint32_t t0 = sp[0][0], t1 = sp[0][1];
+            sp[0][0] = sp[1][0]; sp[0][1] = sp[1][1];
+            sp[1][0] = t0; sp[1][1] = t1;
+        }
+        if (sp[1][0] <= sp[0][1]) {  // overlapping or adjacent word spans
+            sp[0][1] = sp[1][1] > sp[0][1] ? sp[1][1] : sp[0][1];
+            ns = 1;
+        }
+    }
+    if (ns == 0) return hipSuccess;
+    S.w0lo = sp[0][0];
+    S.nw0 = sp[0][1] - sp[0][0];
+    S.w1lo = ns == 2 ? sp[1][0] : 0;
+    S.nw1 = ns == 2 ? sp[1][1] - sp[1][0] : 0;
+    const uint64_t items = n_atv * (S.nw0 + S.nw1);
+    hipLaunchKernelGGL(k_preserve, dim3(grid_for(items, 1u << 16)), dim3(kBlock), 0, st, pool, n_atv, G.log2g,
+                       G.k, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_ingest(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n, const Geometry& G,
+                         uint32_t c0, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const bool vec = ((reinterpret_cast<uintptr_t>(aip) | reinterpret_cast<uintptr_t>(bip)) & 15u) == 0;
+    const uint32_t grid = grid_for(vec ? (n + 3) / 4 : n, 1u << 20);
+#define AT_INGEST_CASE(RR)                                                                              \
+    case RR:                                                                                            \
+        if (vec)                                                                                        \
+            hipLaunchKernelGGL((k_ingest<RR, true>), dim3(grid), dim3(kBlock), 0, st, pool, aip, bip, n, G, c0); \
+        else                                                                                            \
+            hipLaunchKernelGGL((k_ingest<RR, false>), dim3(grid), dim3(kBlock), 0, st, pool, aip, bip, n, G, c0); \
+        break;
+    switch (G.r) {
+        AT_INGEST_CASE(1)
+        AT_INGEST_CASE(2)
+        AT_INGEST_CASE(3)
+        AT_INGEST_CASE(4)
+        AT_INGEST_CASE(5)
+        AT_INGEST_CASE(6)
+        AT_INGEST_CASE(7)
+        AT_INGEST_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef AT_INGEST_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_close(const uint8_t* pool, uint32_t* w, uint64_t n_atv, const Geometry& G, uint32_t c0,
+                        uint32_t kq, hipStream_t st) {
+    const uint32_t lpa = G.g / 16 < 64 ? G.g / 16 : 64;
+    const uint64_t atv_per_block = (kBlock / 64) * (64 / lpa);
+    uint64_t blocks = (n_atv + atv_per_block - 1) / atv_per_block;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_close, dim3((uint32_t)blocks), dim3(kBlock), G.g, st, pool, w, n_atv, G, c0, kq);
+    return hipGetLastError();
+}
+
+hipError_t launch_summarize(const uint32_t* w, uint64_t* aat, uint32_t* sa, uint32_t* sa_cnt, const Geometry& G,
+                            hipStream_t st) {
+    const uint32_t groups = (G.umask + 1) * G.r;
+    hipLaunchKernelGGL(k_summarize, dim3(groups), dim3(kBlock), 0, st, w, aat, sa, sa_cnt, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_restore_join(const uint32_t* sa, const uint32_t* sa_cnt, const uint64_t* pair_prefix,
+                               uint64_t n_items, const Geometry& G, uint32_t* cand, uint64_t cap,
+                               unsigned long long* counter, hipStream_t st) {
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restore_join, dim3(grid_for(n_items, 1u << 16)), dim3(kBlock), 0, st, sa, sa_cnt,
+                       pair_prefix, n_items, G, cand, cap, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_u32(uint32_t* keys, uint64_t m, uint64_t n_pow2, hipStream_t st) {
+    if (m <= 1) return hipSuccess;
+    if (n_pow2 > m)
+        hipLaunchKernelGGL(k_pad_u32, dim3(grid_for(n_pow2 - m, 4096)), dim3(kBlock), 0, st, keys, m, n_pow2);
+    if (n_pow2 <= kTile) {
+        hipLaunchKernelGGL(k_small_sort, dim3(1), dim3(kBlock), 0, st, keys, (uint32_t)n_pow2);
+        return hipGetLastError();
+    }
+    const uint32_t tiles = (uint32_t)(n_pow2 / kTile);
+    hipLaunchKernelGGL(k_bitonic_tile, dim3(tiles), dim3(kBlock), 0, st, keys, 2u, kTile);
+    for (uint64_t k = 2 * (uint64_t)kTile; k <= n_pow2; k <<= 1) {
+        for (uint64_t j = k >> 1; j >= kTile; j >>= 1)
+            hipLaunchKernelGGL(k_bitonic_global, dim3(grid_for(n_pow2 / 2, 1u << 16)), dim3(kBlock), 0, st, keys,
+                               n_pow2, k, j);
+        // remaining strides j < kTile of this k inside each tile
+        hipLaunchKernelGGL(k_bitonic_tile, dim3(tiles), dim3(kBlock), 0, st, keys, (uint32_t)k, (uint32_t)k);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_estimate(const uint8_t* pool, const uint64_t* aat, const uint32_t* aip, uint64_t n,
+                           const Geometry& G, uint32_t c0q, uint32_t kq, double* est, uint8_t* flags, uint32_t* nat,
+                           hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + 3) / 4;
+    if (blocks > 16384) blocks = 16384;
+#define AT_EST_CASE(RR)                                                                                  \
+    case RR:                                                                                             \
+        hipLaunchKernelGGL((k_estimate<RR>), dim3((uint32_t)blocks), dim3(kBlock), G.g, st, pool, aat, aip, n, G, \
+                           c0q, kq, est, flags, nat);                                                    \
+        break;
+    switch (G.r) {
+        AT_EST_CASE(1)
+        AT_EST_CASE(2)
+        AT_EST_CASE(3)
+        AT_EST_CASE(4)
+        AT_EST_CASE(5)
+        AT_EST_CASE(6)
+        AT_EST_CASE(7)
+        AT_EST_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef AT_EST_CASE
+    return hipGetLastError();
+}
+
+}  // namespace atp

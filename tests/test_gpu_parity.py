@@ -1,0 +1,152 @@
+"""HIP path vs CPU oracle, element by element, through the C ABI.
+
+AT pool bytes, clock, per-ATV weights, AAT, NAT, flags and restore lists must
+be identical; FP64 estimates agree to 1e-12 relative.  Sizes span several
+tiles/workgroups with ragged tails; the literal-size workloads are covered in
+test_gpu_fullsize.py.
+"""
+import numpy as np
+import pytest
+
+from paper_1807_01527_amd import traffic
+
+from ._parity import compare_estimates, compare_restore, compare_state, compare_summary, make_pair, run_trace, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_01527_amd import binding
+    binding.load()
+    return torch
+
+
+def _tiny(seed=0, **kw):
+    return traffic.generate(traffic.config_tiny(seed=seed, **kw))
+
+
+def test_constants_match(cuda, oracle_lib):
+    for seed in (0, 1, 99, 2**64 - 1):
+        params = dict(k=4, r=4, c=9, s=8, u=0, log2g=9, seed=seed)
+        g, o = make_pair(params, oracle_lib)
+        assert g.constants() == o.constants()
+
+
+@pytest.mark.parametrize("geom", [
+    dict(k=3, r=4, c=8, s=8, u=1, log2g=6),        # several blocks per ATV
+    dict(k=13, r=4, c=8, s=8, u=1, log2g=4),       # g < 2k: every AT in the last block
+    dict(k=1, r=4, c=8, s=8, u=1, log2g=5),        # discrete window
+    dict(k=5, r=3, c=11, s=10, u=3, log2g=7),      # r = 3, 8 frames
+    dict(k=7, r=5, c=8, s=6, u=2, log2g=8),        # r = 5
+    dict(k=4, r=2, c=16, s=16, u=2, log2g=4),      # r = 2
+])
+def test_small_geometries(cuda, oracle_lib, geom):
+    tr = _tiny(seed=geom["k"], n_slices=2 * geom["k"] + 5, pairs_per_slice=3001, hosts=1 << 9, planted=3,
+               lo=100, hi=700)
+    aip = list(tr.aip)
+    bip = list(tr.bip)
+    aip[3] = aip[3][:0]  # an empty slice
+    bip[3] = bip[3][:0]
+    g, o = make_pair(dict(**geom, theta=64.0, seed=5), oracle_lib)
+    kps = list(range(1, geom["k"] + 1))
+    run_trace(g, o, aip, bip, kprimes=kps, batches=4, seed=1, query_hosts=tr.planted_hosts)
+
+
+def test_unaligned_and_tiny_batches(cuda, oracle_lib):
+    tr = _tiny(seed=3, n_slices=5, pairs_per_slice=4099)
+    g, o = make_pair(dict(k=2, r=4, c=8, s=8, u=1, log2g=6, theta=100.0, seed=2), oracle_lib)
+    run_trace(g, o, tr.aip, tr.bip, batches=7, seed=3, query_hosts=tr.planted_hosts, unaligned=True)
+
+
+def test_small_config_literal(cuda, oracle_lib):
+    """1M pairs in 4 slices of 250k into the 2^20-AT literal pool: pool bytes
+    after every slice; restore exceeds the tuple budget on both sides."""
+    tr = traffic.generate(traffic.config_small(seed=0))
+    g, o = make_pair(dict(k=4, r=4, c=9, s=8, u=0, log2g=9, theta=1024.0, seed=0, tuple_budget=10**7), oracle_lib)
+    h, cnt = traffic.window_counts(tr.aip, tr.bip, min_count=800)
+    run_trace(g, o, tr.aip, tr.bip, batches=3, seed=4, query_hosts=h, cap=1 << 16)
+
+
+def test_small_config_companion(cuda, oracle_lib):
+    """Same traffic at paper-like load (2^26 ATs): the restored list equals the
+    oracle's and contains the true super points."""
+    tr = traffic.generate(traffic.config_small(seed=1))
+    g, o = make_pair(dict(k=4, r=4, c=9, s=7, u=3, log2g=12, theta=1024.0, seed=1), oracle_lib)
+    h, cnt = traffic.window_counts(tr.aip, tr.bip, min_count=1024)
+    run_trace(g, o, tr.aip, tr.bip, batches=2, seed=5, query_hosts=h, check_pool_every=False)
+    compare_state(g, o, "final")
+    rc, cs, m = compare_restore(g, o)
+    assert rc == 0 and m > 0
+    assert np.isin(h[cnt >= 2048], cs).all()
+
+
+def test_order_split_and_repeats_invariant(cuda, oracle_lib):
+    """Shuffled order, other batch splits and repeated pairs give the same pool."""
+    tr = _tiny(seed=9, n_slices=4, pairs_per_slice=20000)
+    params = dict(k=3, r=4, c=8, s=8, u=1, log2g=6, seed=7)
+    from paper_1807_01527_amd.binding import AtPool
+    pools = []
+    rng = np.random.default_rng(0)
+    for variant in range(3):
+        g = AtPool(**params)
+        for a, b in zip(tr.aip, tr.bip):
+            if variant == 1:
+                p = rng.permutation(a.size)
+                a, b = a[p], b[p]
+            if variant == 2:
+                a = np.concatenate([a, a[::3]])
+                b = np.concatenate([b, b[::3]])
+            da, db = to_dev(a), to_dev(b)
+            step = [a.size, 777, 5000][variant]
+            for lo in range(0, a.size, step):
+                g.ingest(da[lo:lo + step], db[lo:lo + step])
+            g.close(3)
+        pools.append(g.read_pool())
+    assert np.array_equal(pools[0], pools[1]) and np.array_equal(pools[0], pools[2])
+
+
+def test_error_paths(cuda, oracle_lib):
+    from paper_1807_01527_amd import binding
+    from paper_1807_01527_amd.binding import AtError, AtPool
+    bad = [dict(k=4, r=4, c=9, s=7, u=0, log2g=9), dict(k=0, r=4, c=9, s=8, u=0, log2g=9),
+           dict(k=128, r=4, c=9, s=8, u=0, log2g=9), dict(k=4, r=4, c=7, s=7, u=4, log2g=9),
+           dict(k=4, r=4, c=9, s=8, u=0, log2g=9, theta=0.0)]
+    for p in bad:
+        assert AtPool.try_create(**p) == binding.AT_E_INVAL
+        assert oracle_lib.Oracle.try_create(**p) == oracle_lib.E_INVAL
+    g = AtPool(k=3, r=4, c=8, s=8, u=1, log2g=6)
+    with pytest.raises(AtError) as e:
+        g.estimate(np.array([1], np.uint32))
+    assert e.value.rc == binding.AT_E_STATE
+    with pytest.raises(AtError) as e:
+        g.close(4)
+    assert e.value.rc == binding.AT_E_INVAL
+    host = np.zeros(16, np.uint32)
+    rc = g.ingest_raw(host.ctypes.data, host.ctypes.data, 16)
+    assert rc == binding.AT_E_INVAL
+    g.close(3)
+    e_, f_, n_ = g.estimate(np.array([1, 2, 3], np.uint32))
+    assert (n_ == 0).all()
+    g.ingest(to_dev(np.array([1], np.uint32)), to_dev(np.array([2], np.uint32)))
+    with pytest.raises(AtError) as e:
+        g.estimate(np.array([1], np.uint32))
+    assert e.value.rc == binding.AT_E_STATE
+    g.destroy()
+
+
+def test_restore_cap_and_budget(cuda, oracle_lib):
+    tr = _tiny(seed=8, n_slices=2, pairs_per_slice=20000, hosts=1 << 10, planted=2, lo=2000, hi=3000)
+    p = dict(k=2, r=4, c=8, s=8, u=1, log2g=10, theta=128.0, seed=2)
+    g, o = make_pair({**p, "tuple_budget": 10}, oracle_lib)
+    run_trace(g, o, tr.aip, tr.bip, restore=False)
+    compare_restore(g, o)
+    g2, o2 = make_pair(p, oracle_lib)
+    run_trace(g2, o2, tr.aip, tr.bip, restore=False)
+    rc, cs, m = compare_restore(g2, o2)
+    assert rc == 0 and m > 1
+    compare_restore(g2, o2, cap=m - 1)
+    assert g2.tuple_count() == o2.tuple_count()
