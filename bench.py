@@ -36,6 +36,22 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per scan launch from the committed counter runs, or None when
+    the kernel source has changed since they were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "ingest_link_pmc.json")) as fh:
+            rec = json.load(fh)
+        with open(os.path.join(ROOT, "paper_1807_01527_amd", "csrc", "kernels.hip"), "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None
+    if not sha.startswith(rec["kernels_hip_sha256_prefix"]):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(tr, truth_hosts, budget_s: float = 20.0) -> dict:
     """The oracle as it stands, single-threaded on a host core, over the first
     slices of the same trace until about budget_s of work is done."""
@@ -70,6 +86,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slices", type=int, default=10)
     ap.add_argument("--pairs", type=int, default=5_000_000)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus above 1 is not supported"}))
@@ -80,7 +98,7 @@ def main():
     import torch
 
     from paper_1807_01527_amd import traffic
-    from paper_1807_01527_amd.binding import AT_OK, AtPool
+    from paper_1807_01527_amd.binding import AtPool, probe_scatter
 
     t0 = time.perf_counter()
     tr = traffic.generate(traffic.config_link(seed=0, n_slices=args.slices, pairs_per_slice=args.pairs))
@@ -166,9 +184,39 @@ def main():
         "mean_rel_err": {"plain": float(rel.mean()), "learned": None, "hosts": int(truth_h.size)},
         "roofline": {"kernel": "k_ingest (fused pair hash + r byte scatter)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_pair": 8 + LINK["r"],
+                     "traffic": measured_traffic(), "bytes_per_pair": 8 + LINK["r"],
                      "avg_launch_ms": float(ingest_ms.mean()), "pairs_per_launch": per_launch},
     }
+    # scatter roofline: the same input stream and r byte stores per pair at
+    # uniformly random positions of a pool-sized buffer
+    probe_buf = torch.empty(pool.pool_bytes, dtype=torch.uint8, device=dev)
+    pr = []
+    for rep in range(2):
+        for t in range(S):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            probe_scatter(probe_buf, aip_d[t], bip_d[t], args.pairs, LINK["r"], stream=stream)
+            e1.record(stream)
+            if rep:
+                pr.append((e0, e1))
+    torch.cuda.synchronize()
+    probe_ms = float(np.mean([a.elapsed_time(b) for a, b in pr]))
+    del probe_buf
+    out["scatter_probe"] = {
+        "what": "uniform random byte stores, r per pair, into a buffer of the pool's size, same input stream",
+        "mpps": per_launch / (probe_ms / 1e3) / 1e6, "avg_launch_ms": probe_ms,
+        "stores_per_s": LINK["r"] * per_launch / (probe_ms / 1e3),
+        "ingest_frac_of_probe": (per_launch / avg_ingest_s) / (per_launch / (probe_ms / 1e3)),
+    }
+    if args.copy_probe:
+        x = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = {"read": x.numel(), "write": y.numel(), "launches": 3}
+        del x, y
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(tr, truth_h)

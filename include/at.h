@@ -182,6 +182,15 @@ int at_estimate_dev(at_ctx *h, const uint32_t *aip_dev, uint64_t n, double *est_
 /* Number of column tuples U that at_restore would enumerate (see above). */
 int at_tuple_count(at_ctx *h, uint64_t *U);
 
+/* Measurement probe, not part of the method: n items (n a multiple of 4,
+ * a_dev/b_dev 16-byte aligned device arrays of n uint32, read like the pair
+ * scan reads its input) each store r (1, 2, 4 or 8) bytes at uniformly random
+ * positions of dst_dev (device, `bytes` a power of two).  It gives the
+ * random-byte-store throughput of a buffer of the pool's size, the roofline
+ * of at_ingest_slice.  Asynchronous on hip_stream. */
+int at_probe_scatter(uint8_t *dst_dev, uint64_t bytes, const uint32_t *a_dev, const uint32_t *b_dev,
+                     uint64_t n, uint32_t r, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,6 +52,7 @@ SIGNATURES = {
     "at_estimate_detail": (C.c_int, [_vp, _u32p, C.c_uint64, _f64p, _u8p, _u32p]),
     "at_estimate_dev": (C.c_int, [_vp, _vp, C.c_uint64, _vp, _vp, _vp]),
     "at_tuple_count": (C.c_int, [_vp, _u64p]),
+    "at_probe_scatter": (C.c_int, [_vp, C.c_uint64, _vp, _vp, C.c_uint64, C.c_uint32, _vp]),
 }
 
 _lib = None
@@ -96,6 +97,16 @@ def _dev_ptr(t) -> int:
 def _check(rc: int, where: str):
     if rc != AT_OK:
         raise AtError(rc, where)
+
+
+def probe_scatter(dst_dev, a_dev, b_dev, n: int, r: int, stream=None):
+    """Uniform random byte-store probe (see at_probe_scatter)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(load().at_probe_scatter(C.c_void_p(_dev_ptr(dst_dev)), dst_dev.numel() * dst_dev.element_size(),
+                                   C.c_void_p(_dev_ptr(a_dev)), C.c_void_p(_dev_ptr(b_dev)), n, r,
+                                   C.c_void_p(stream.cuda_stream)), "at_probe_scatter")
 
 
 class AtPool:

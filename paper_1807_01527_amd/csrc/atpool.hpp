@@ -53,4 +53,7 @@ hipError_t launch_estimate(const uint8_t* pool, const uint64_t* aat, const uint3
                            const Geometry& G, uint32_t c0q, uint32_t kq, double* est, uint8_t* flags,
                            uint32_t* nat, hipStream_t st);
 
+hipError_t launch_scatter_probe(uint8_t* dst, uint64_t bytes, const uint32_t* a, const uint32_t* b, uint64_t n,
+                                uint32_t r, hipStream_t st);
+
 }  // namespace atp

@@ -456,4 +456,16 @@ int at_constants(const at_ctx* h, uint64_t* out8) {
     return AT_OK;
 }
 
+int at_probe_scatter(uint8_t* dst_dev, uint64_t bytes, const uint32_t* a_dev, const uint32_t* b_dev, uint64_t n,
+                     uint32_t r, void* hip_stream) {
+    if (!dst_dev || !a_dev || !b_dev || bytes == 0 || (bytes & (bytes - 1)) || (n % 4) ||
+        ((reinterpret_cast<uintptr_t>(a_dev) | reinterpret_cast<uintptr_t>(b_dev)) & 15u))
+        return AT_E_INVAL;
+    if (!(r == 1 || r == 2 || r == 4 || r == 8)) return AT_E_INVAL;
+    if (!device_accessible(dst_dev) || !device_accessible(a_dev) || !device_accessible(b_dev)) return AT_E_INVAL;
+    return atp::launch_scatter_probe(dst_dev, bytes, a_dev, b_dev, n, r, (hipStream_t)hip_stream) == hipSuccess
+               ? AT_OK
+               : AT_E_DEVICE;
+}
+
 }  // extern "C"

@@ -481,6 +481,37 @@ __global__ __launch_bounds__(kBlock) void k_estimate(const uint8_t* __restrict__
     }
 }
 
+
+// ---------------------------------------------------------------- probes
+// Scatter roofline probe: the same input stream as the pair scan (8 B per
+// item, 16-byte vector loads) and the same number of byte stores per item,
+// but at uniformly random positions of a buffer of `bytes` (a power of two)
+// -- the memory-side cost of the scan without its hashing and skew.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_scatter_probe(uint8_t* __restrict__ dst, uint64_t mask,
+                                                          const uint32_t* __restrict__ a_in,
+                                                          const uint32_t* __restrict__ b_in, uint64_t n) {
+    const uint64_t n4 = n / 4;
+    const uint4* a4 = reinterpret_cast<const uint4*>(a_in);
+    const uint4* b4 = reinterpret_cast<const uint4*>(b_in);
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += (uint64_t)gridDim.x * blockDim.x) {
+        uint4 a = a4[q], b = b4[q];
+        uint32_t av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            uint64_t h = mix64(((uint64_t)av[e] << 32) | bv[e]);
+#pragma unroll
+            for (int j = 0; j < R; j++) dst[mix64(h + j) & mask] = (uint8_t)j;
+        }
+    }
+}
+
 uint32_t grid_for(uint64_t items, uint32_t cap) {
     uint64_t b = (items + kBlock - 1) / kBlock;
     if (b < 1) b = 1;
@@ -645,6 +676,20 @@ hipError_t launch_estimate(const uint8_t* pool, const uint64_t* aat, const uint3
             return hipErrorInvalidValue;
     }
 #undef AT_EST_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_probe(uint8_t* dst, uint64_t bytes, const uint32_t* a, const uint32_t* b, uint64_t n,
+                                uint32_t r, hipStream_t st) {
+    if (n < 4) return hipSuccess;
+    const uint32_t grid = grid_for(n / 4, 1u << 20);
+    switch (r) {
+        case 1: hipLaunchKernelGGL(k_scatter_probe<1>, dim3(grid), dim3(kBlock), 0, st, dst, bytes - 1, a, b, n); break;
+        case 2: hipLaunchKernelGGL(k_scatter_probe<2>, dim3(grid), dim3(kBlock), 0, st, dst, bytes - 1, a, b, n); break;
+        case 4: hipLaunchKernelGGL(k_scatter_probe<4>, dim3(grid), dim3(kBlock), 0, st, dst, bytes - 1, a, b, n); break;
+        case 8: hipLaunchKernelGGL(k_scatter_probe<8>, dim3(grid), dim3(kBlock), 0, st, dst, bytes - 1, a, b, n); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
