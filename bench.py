@@ -36,6 +36,108 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
+SERVE_SHAPE = dict(r=4, c=9, s=8, u=1, log2g=12, theta=1024.0)   # 2^24 ATs per link
+
+
+def serve_phase(dev, n_links: int = 16, slices: int = 10, period_scale: float = 0.1, seed: int = 0, mlp=None):
+    """Streaming workload: n_links links, k drawn from {5, 10, 30}, per-slice
+    pair counts lognormal (median 2M, sigma 1, clipped to [100k, 20M]), slice
+    periods U[50, 200] ms times period_scale with a random phase, chunks of
+    65536 pairs arriving uniformly within each slice.  A producer thread
+    submits events on that schedule while the main thread runs server steps.
+    Latency is taken per slice from its end call to its result on the host."""
+    import threading
+
+    import torch
+
+    from paper_1807_01527_amd import traffic_gpu as tg
+    from paper_1807_01527_amd.binding import Server
+
+    rng = np.random.default_rng(seed)
+    ks = rng.choice([5, 10, 30], n_links)
+    sizes = np.clip(np.exp(np.log(2e6) + rng.standard_normal((n_links, slices))), 1e5, 2e7).astype(np.int64) // 4 * 4
+    stream_len = 20_000_000
+    streams = []
+    for li in range(n_links):
+        a, b, planted = tg.link_stream(seed * 1000 + li, stream_len, dev)
+        streams.append((a, b, planted))
+    torch.cuda.synchronize()
+    pool_bytes = (1 << (SERVE_SHAPE["c"] + SERVE_SHAPE["u"])) * SERVE_SHAPE["r"] * (1 << SERVE_SHAPE["log2g"])
+    srv = Server(hbm_budget=n_links * (pool_bytes + (8 << 20)), max_links=n_links, cand_cap=2048, watch_cap=64,
+                 **SERVE_SHAPE)
+    if mlp is not None:
+        srv.set_mlp(mlp)
+    ids = []
+    for li in range(n_links):
+        lid, adm = srv.open_link(int(ks[li]), seed * 1000 + li)
+        srv.set_watch(lid, streams[li][2])
+        ids.append(lid)
+    # event timeline
+    chunk = 65536
+    events = []
+    for li in range(n_links):
+        period = rng.uniform(50.0, 200.0) * period_scale * 1e-3
+        t = rng.uniform(0, period)
+        pos = 0
+        for sl in range(slices):
+            n = int(sizes[li, sl])
+            nch = (n + chunk - 1) // chunk
+            times = np.sort(rng.uniform(t, t + period, nch))
+            for c in range(nch):
+                lo = c * chunk
+                hi = min(n, lo + chunk)
+                start = (pos + lo) % (stream_len - chunk)
+                events.append((times[c], li, "chunk", start, hi - lo))
+            events.append((t + period, li, "end", int(ks[li]), 0))
+            pos += n
+            t += period
+    events.sort(key=lambda e: (e[0], e[1], e[2] == "end"))
+    total_pairs = int(sizes.sum())
+    done = threading.Event()
+
+    def producer():
+        t0 = time.perf_counter()
+        for (ts, li, kind, x, n) in events:
+            wait = ts - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            a, b, _ = streams[li]
+            if kind == "chunk":
+                srv.submit(ids[li], a[x:x + n], b[x:x + n])
+            else:
+                srv.end_slice(ids[li], x)
+        done.set()
+
+    results = []
+    th = threading.Thread(target=producer)
+    t_start = time.perf_counter()
+    th.start()
+    step_ms = []
+    while True:
+        t0 = time.perf_counter()
+        srv.step()
+        step_ms.append(1e3 * (time.perf_counter() - t0))
+        results += srv.results()
+        if done.is_set() and all(srv.link_state(lid)[2] == 0 for lid in ids):
+            break
+    th.join()
+    wall = time.perf_counter() - t_start
+    st = srv.stats()
+    lat = np.array([r["latency_ms"] for r in results])
+    srv.destroy()
+    return {
+        "workload": f"{n_links} links, k from {{5,10,30}}, 2^24-AT pools (c=9,s=8,u=1,g=4096,r=4), {slices} slices "
+                    f"per link, lognormal slice sizes (median 2M, sigma 1, [100k, 20M]), 64k-pair chunks, slice "
+                    f"periods U[50,200] ms x {period_scale}",
+        "closes": len(results), "pairs": total_pairs, "wall_s": wall, "mpps_offered": total_pairs / wall / 1e6,
+        "steps": st["steps"], "step_ms_p50": float(np.percentile(step_ms, 50)),
+        "slice_close_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+        "restore_rc_counts": {str(k): int(v) for k, v in zip(*np.unique([r["restore_rc"] for r in results],
+                                                                          return_counts=True))},
+    }
+
+
 def measured_traffic():
     """HBM bytes per scan launch from the committed counter runs, or None when
     the kernel source has changed since they were taken."""
@@ -86,6 +188,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slices", type=int, default=10)
     ap.add_argument("--pairs", type=int, default=5_000_000)
+    ap.add_argument("--no-serve", action="store_true", help="skip the streaming-server phase")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -98,7 +201,8 @@ def main():
     import torch
 
     from paper_1807_01527_amd import traffic
-    from paper_1807_01527_amd.binding import AtPool, probe_scatter
+    from paper_1807_01527_amd import learned
+    from paper_1807_01527_amd.binding import AtPool, Mlp, probe_scatter
 
     t0 = time.perf_counter()
     tr = traffic.generate(traffic.config_link(seed=0, n_slices=args.slices, pairs_per_slice=args.pairs))
@@ -112,6 +216,8 @@ def main():
     bip_d = [torch.from_numpy(b.view(np.int32)).to(dev) for b in tr.bip]
     stream = torch.cuda.current_stream()
     pool = AtPool(**LINK, stream=stream)
+    weights = learned.load_weights("link")
+    mlp = Mlp(weights) if weights is not None else None
     S = tr.n_slices
     K = LINK["k"]
     cap = 1 << 20
@@ -130,10 +236,14 @@ def main():
             c0 = time.perf_counter()
             pool.close(K)
             rc, sip, est, fl, m = pool.restore(cap=cap)
-            e_plain, f_plain = pool.estimate_plain(truth_h)
+            if mlp is not None:
+                e_learn, f_learn, e_plain = pool.estimate_learned(mlp, truth_h)
+            else:
+                e_plain, f_plain = pool.estimate_plain(truth_h)
+                e_learn = None
             lat.append(time.perf_counter() - c0)
             ev.append((e0, e1))
-            last = (rc, m, e_plain, f_plain)
+            last = (rc, m, e_plain, e_learn)
         if record is not None:
             torch.cuda.synchronize()
             record["ingest_ms"].extend(a.elapsed_time(b) for a, b in ev)
@@ -156,8 +266,9 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
     ingest_ms = np.array(rec["ingest_ms"])
     close_ms = np.array(rec["close_ms"])
-    rc, m, e_plain, f_plain = rec["last"]
+    rc, m, e_plain, e_learn = rec["last"]
     rel = np.abs(e_plain - truth_n) / truth_n
+    rel_l = np.abs(e_learn - truth_n) / truth_n if e_learn is not None else None
     per_launch = args.pairs
     avg_ingest_s = float(ingest_ms.mean()) / 1e3
     alg_bytes = (8 + LINK["r"]) * per_launch
@@ -179,9 +290,12 @@ def main():
                    "pool_ats": pool.pool_bytes, "parallelism": "single GPU"},
         "ingest_mpps": per_launch / avg_ingest_s / 1e6,
         "slice_close_ms": {"p50": float(np.percentile(close_ms, 50)), "p99": float(np.percentile(close_ms, 99)),
-                           "includes": "close + restore + estimate of the true super points, host wall clock"},
+                           "includes": "close + restore + plain and learned estimates of the true super points, "
+                                       "host wall clock"},
         "restore": {"rc": int(rc), "n_out": int(m), "note": "AT_E_BUDGET (-6) at this load: every ATV is super"},
-        "mean_rel_err": {"plain": float(rel.mean()), "learned": None, "hosts": int(truth_h.size)},
+        "mean_rel_err": {"plain": float(rel.mean()), "learned": float(rel_l.mean()) if rel_l is not None else None,
+                         "hosts": int(truth_h.size),
+                         "over": "true super points of the window (exact distinct count >= 1024)"},
         "roofline": {"kernel": "k_ingest (fused pair hash + r byte scatter)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(), "bytes_per_pair": 8 + LINK["r"],
@@ -217,6 +331,16 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = {"read": x.numel(), "write": y.numel(), "launches": 3}
         del x, y
+    if not args.no_serve:
+        log("streaming-server phase ...")
+        pool.destroy()
+        del aip_d, bip_d
+        torch.cuda.empty_cache()
+        smlp = None
+        w_small = learned.load_weights("serve")
+        if w_small is not None:
+            smlp = Mlp(w_small)
+        out["serving"] = serve_phase(dev, mlp=smlp)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(tr, truth_h)

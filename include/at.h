@@ -59,7 +59,7 @@ typedef struct {
     uint32_t c;            /* log2 of the columns per row, 1..20               */
     uint32_t s;            /* column stride in LBS bits, 1..c                  */
     uint32_t u;            /* log2 of the frames, 0..16                        */
-    uint32_t log2g;        /* log2 of the ATs per ATV, 4..16                   */
+    uint32_t log2g;        /* log2 of the ATs per ATV, 4..15                   */
     double theta;          /* super point threshold, > 0                       */
     uint64_t seed;         /* derives the mangling multiplier and the BH hash  */
     uint64_t tuple_budget; /* restore guard on column tuples; 0 means 2^32     */
@@ -181,6 +181,148 @@ int at_estimate_dev(at_ctx *h, const uint32_t *aip_dev, uint64_t n, double *est_
 
 /* Number of column tuples U that at_restore would enumerate (see above). */
 int at_tuple_count(at_ctx *h, uint64_t *U);
+
+/* ------------------------------------------------------ learned correction
+ * Not in the paper: a small network that corrects the plain estimate from the
+ * host's occupancy-by-age profile, with the plain estimate kept as fallback.
+ *
+ * Features of a host (AT_FEATURES = 64 floats), over the last closed window:
+ * with e_i the largest age (ACT distance) of the host's r ATs at position i
+ * when all r are active for the full window k (Alg 1 with k' = k),
+ *   f[d]  = #{i : e_i = d} / g        for d < min(k, 61)   (0 above)
+ *   f[61] = min(ln(1 + max(plain, 0)), 20) / 16, plain = the Eq 4 estimate
+ *   f[62] = k / 64
+ *   f[63] = mean over rows of AAT(k', row, frame) / (g * 2^c).
+ * The prefix sum of f[0..k'-1] times g is NAT(k') of Alg 5.
+ *
+ * Network: 64 -> 64 -> 64 -> 1, ReLU.  Its output y corrects the plain
+ * estimate's log feature: z = y + 16 * f[61] estimates ln n.  Parameters
+ * (AT_MLP_NPARAM floats, FP32 master copy): W1[64][64] (row = output unit),
+ * b1[64], W2[64][64], b2[64], w3[64], b3.  Features, weights and hidden
+ * activations are rounded to bfloat16 (nearest even); products accumulate in
+ * FP32 on the matrix cores.  Training minimises the mean squared error of ln n
+ * with Adam (beta1 0.9, beta2 0.999, eps 1e-8) on FP32 master weights.
+ * Learned estimate = exp(z) when z is finite and within
+ * [ln 16 - 0.5, ln 2^18 + 0.5], else the plain estimate with AT_F_FALLBACK. */
+typedef struct at_mlp at_mlp;
+#define AT_FEATURES 64
+#define AT_MLP_NPARAM 8385
+
+/* Features, plain estimates and their flags of n hosts (device arrays: aip_dev
+ * n uint32; feat_dev n*64 float row-major; est_dev, flags_dev may be NULL).
+ * Asynchronous on the handle's stream; valid in the same state as
+ * at_estimate (AT_E_STATE otherwise). */
+int at_features(at_ctx *h, const uint32_t *aip_dev, uint64_t n, float *feat_dev, double *est_dev,
+                uint8_t *flags_dev);
+
+/* A network on the given stream with all parameters zero.  AT_E_NOMEM. */
+int at_mlp_create(void *hip_stream, at_mlp **out);
+int at_mlp_destroy(at_mlp *m);
+/* Copy AT_MLP_NPARAM host floats in (resets the optimiser) or out.  Sync. */
+int at_mlp_set_params(at_mlp *m, const float *host_params);
+int at_mlp_get_params(at_mlp *m, float *host_params);
+/* y_dev[i] = network(x_dev[i*64 .. i*64+63]) for i < n.  Asynchronous. */
+int at_mlp_forward(at_mlp *m, const float *x_dev, uint64_t n, float *y_dev);
+/* Gradient of mean((y - t)^2) over the n rows (t: the target of y, i.e.
+ * ln n - 16 * f[61] for the learned correction) into grad_dev (AT_MLP_NPARAM
+ * floats, device, may be NULL); the loss to *loss_host if not NULL (then
+ * synchronous). */
+int at_mlp_grad(at_mlp *m, const float *x_dev, const float *t_dev, uint64_t n, float *grad_dev,
+                float *loss_host);
+/* One Adam step with the given gradient (device) and learning rate. */
+int at_mlp_apply_grad(at_mlp *m, const float *grad_dev, float lr);
+/* Gradient + Adam step on one batch; loss as in at_mlp_grad (before the step). */
+int at_mlp_train_step(at_mlp *m, const float *x_dev, const float *t_dev, uint64_t n, float lr,
+                      float *loss_host);
+/* Learned estimates of n hosts with fallback (host arrays; plain_out, the
+ * plain Eq 4 estimates, may be NULL).  Synchronous.  Flags: AT_F_SAT and
+ * AT_F_NEG of the plain estimate, AT_F_FALLBACK, AT_F_SUPER of the returned
+ * estimate. */
+int at_estimate_learned(at_ctx *h, at_mlp *m, const uint32_t *aip_host, uint64_t n, double *est_out,
+                        uint8_t *flags_out, double *plain_out);
+/* The same on device arrays, asynchronous (plain_dev may be NULL). */
+int at_estimate_learned_dev(at_ctx *h, at_mlp *m, const uint32_t *aip_dev, uint64_t n, double *est_dev,
+                            uint8_t *flags_dev, double *plain_dev);
+
+/* ------------------------------------------------------ streaming server
+ * Not in the paper: many links served by one device.  Every admitted link's
+ * pool stays resident in device memory; links are admitted while the sum of
+ * their footprints fits the HBM budget, later ones wait in FIFO order and are
+ * admitted as others close.  Producers queue chunks of pairs and slice ends
+ * per link at any time (thread-safe); each at_serve_step turns everything
+ * queued so far into one batched step: the slices that open are preserved
+ * and every queued chunk of every link is scanned in one launch, while the
+ * slices whose chunks were all scanned in earlier steps are closed, restored
+ * and estimated in a concurrent branch.  The step is a hipGraph captured
+ * once and replayed with a new descriptor table each time.
+ *
+ * All links of a server share the geometry shape (r, c, s, u, log2g, theta);
+ * k and seed are per link.  Per closed slice the server returns the restore
+ * outcome (AT_OK with up to cand_cap sorted candidates, AT_E_BUDGET with U,
+ * or AT_E_OVERFLOW with m), the plain and learned estimates of the candidates
+ * and of the link's watch hosts, and the latency from the slice end call to
+ * the result being on the host. */
+typedef struct at_serve at_serve;
+
+typedef struct {
+    uint64_t hbm_budget;   /* bytes of device memory the links may hold       */
+    uint32_t max_links;    /* links resident at once, 1..64                    */
+    uint32_t cand_cap;     /* restore candidates returned per close, 1..2048   */
+    uint32_t watch_cap;    /* watch hosts per link, 0..4096                    */
+    uint32_t r, c, s, u;   /* shared geometry (u <= 8)                         */
+    uint32_t log2g;
+    double theta;
+} at_serve_config;
+
+typedef struct {
+    uint32_t link;         /* link id                                          */
+    uint32_t kprime;       /* window of the close                              */
+    uint64_t slice;        /* index of the closed slice                        */
+    int32_t restore_rc;    /* AT_OK, AT_E_BUDGET or AT_E_OVERFLOW              */
+    uint32_t n_cand;       /* candidates returned (0 unless restore_rc AT_OK)  */
+    uint64_t n_out;        /* m candidates, or U when AT_E_BUDGET              */
+    uint32_t n_watch;      /* watch-host estimates returned                    */
+    uint32_t pad;
+    double latency_ms;     /* slice end call -> result on the host             */
+    double step_ms;        /* device time of the step that closed it          */
+} at_serve_result;
+
+int at_serve_create(const at_serve_config *cfg, at_serve **out);
+int at_serve_destroy(at_serve *s);
+/* Network used for the learned estimates (NULL: learned = plain, flagged
+ * AT_F_FALLBACK).  The network must outlive its use by the server. */
+int at_serve_set_mlp(at_serve *s, at_mlp *m);
+/* Register a link: admitted at once (*admitted = 1) if its footprint fits the
+ * budget and nobody waits, else queued (*admitted = 0).  AT_E_NOMEM if it can
+ * never fit. */
+int at_serve_open_link(at_serve *s, uint32_t k, uint64_t seed, uint64_t tuple_budget, uint32_t *link_id,
+                       int *admitted);
+/* state: 0 waiting, 1 active, 2 closed; slices closed; queued events. */
+int at_serve_link_state(at_serve *s, uint32_t link_id, int *state, uint64_t *slices_closed,
+                        uint64_t *pending);
+/* Release a link's memory (after the running step) and admit waiting links. */
+int at_serve_close_link(at_serve *s, uint32_t link_id);
+/* Hosts estimated at every close of the link (host array, <= watch_cap). */
+int at_serve_set_watch(at_serve *s, uint32_t link_id, const uint32_t *hosts_host, uint32_t n);
+/* Queue a chunk of the link's current slice (device arrays of n uint32,
+ * contents complete; they must stay valid until the step that scans them
+ * returns).  AT_E_STATE unless the link is active. */
+int at_serve_submit(at_serve *s, uint32_t link_id, const uint32_t *aip_dev, const uint32_t *bip_dev,
+                    uint64_t n);
+/* Queue the end of the link's current slice with window k' (1 <= k' <= k). */
+int at_serve_end_slice(at_serve *s, uint32_t link_id, uint32_t kprime);
+/* Run one batched step (synchronous); *n_results = slices closed by it. */
+int at_serve_step(at_serve *s, uint32_t *n_results);
+/* Pop the oldest result; arrays may be NULL; AT_E_STATE when none is ready,
+ * AT_E_OVERFLOW when the capacities are too small (nothing popped). */
+int at_serve_next_result(at_serve *s, at_serve_result *out, uint32_t *cand, double *cand_plain,
+                         double *cand_learned, uint8_t *cand_flags, uint32_t cand_cap, double *watch_plain,
+                         double *watch_learned, uint8_t *watch_flags, uint32_t watch_cap);
+/* out[0] steps run, out[1] pairs scanned, out[2] bytes held by links,
+ * out[3] links waiting for admission. */
+int at_serve_stats(at_serve *s, uint64_t *out4);
+/* Synchronous copy of an active link's pool to the host. */
+int at_serve_read_pool(at_serve *s, uint32_t link_id, uint8_t *host_out);
 
 /* Measurement probe, not part of the method: n items (n a multiple of 4,
  * a_dev/b_dev 16-byte aligned device arrays of n uint32, read like the pair

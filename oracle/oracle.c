@@ -475,10 +475,14 @@ int oat_restore(const oat *o, uint32_t *out, uint64_t cap, uint64_t *n_out)
     return rc;
 }
 
-/* Occupancy-by-age features of a host: e_i = the largest age over its r ATs
- * at position i (infinite if any is inactive for the full window k);
- * feat[d] = #{i : e_i = d} / g for d < k, feat[62] = k/64, feat[63] = mean of
- * the rows' active fractions P_j. */
+/* Occupancy-by-age features of a host (inputs of the learned correction):
+ * e_i = the largest age over its r ATs at position i, or none if any of them
+ * is inactive for the full window k;
+ *   feat[d]  = #{i : e_i = d} / g                 for d < min(k, 61)
+ *   feat[61] = min(ln(1 + max(plain, 0)), 20) / 16  (plain = Eq 4 estimate)
+ *   feat[62] = k / 64
+ *   feat[63] = (P_0 + ... + P_{r-1}) / r           (P_j as in Eq 4)
+ * The histogram's prefix sums are NAT for every window k' <= k. */
 int oat_features(const oat *o, const uint32_t *aip, uint64_t n, float *feat)
 {
     if (!o) return OAT_E_INVAL;
@@ -503,9 +507,14 @@ int oat_features(const oat *o, const uint32_t *aip, uint64_t n, float *feat)
             }
             if (!inactive) hist[e]++;
         }
+        uint8_t fl;
+        double plain = estimate_one(o, z, nat_of(o, z, x), &fl);
         float *f = feat + q * 64;
         for (uint32_t d = 0; d < 64; d++) f[d] = 0.0f;
-        for (uint32_t d = 0; d < k && d < 62; d++) f[d] = (float)((double)hist[d] / (double)o->g);
+        for (uint32_t d = 0; d < k && d < 61; d++) f[d] = (float)((double)hist[d] / (double)o->g);
+        double lp = log(1.0 + (plain > 0 ? plain : 0.0));
+        if (!(lp < 20.0)) lp = 20.0;
+        f[61] = (float)(lp / 16.0);
         f[62] = (float)((double)k / 64.0);
         double denom_cells = (double)((uint64_t)o->g * o->ncol);
         double s = 0;

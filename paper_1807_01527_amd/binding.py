@@ -53,7 +53,50 @@ SIGNATURES = {
     "at_estimate_dev": (C.c_int, [_vp, _vp, C.c_uint64, _vp, _vp, _vp]),
     "at_tuple_count": (C.c_int, [_vp, _u64p]),
     "at_probe_scatter": (C.c_int, [_vp, C.c_uint64, _vp, _vp, C.c_uint64, C.c_uint32, _vp]),
+    "at_features": (C.c_int, [_vp, _vp, C.c_uint64, _vp, _vp, _vp]),
+    "at_mlp_create": (C.c_int, [_vp, C.POINTER(_vp)]),
+    "at_mlp_destroy": (C.c_int, [_vp]),
+    "at_mlp_set_params": (C.c_int, [_vp, _f32p]),
+    "at_mlp_get_params": (C.c_int, [_vp, _f32p]),
+    "at_mlp_forward": (C.c_int, [_vp, _vp, C.c_uint64, _vp]),
+    "at_mlp_grad": (C.c_int, [_vp, _vp, _vp, C.c_uint64, _vp, _f32p]),
+    "at_mlp_apply_grad": (C.c_int, [_vp, _vp, C.c_float]),
+    "at_mlp_train_step": (C.c_int, [_vp, _vp, _vp, C.c_uint64, C.c_float, _f32p]),
+    "at_estimate_learned": (C.c_int, [_vp, _vp, _u32p, C.c_uint64, _f64p, _u8p, _f64p]),
+    "at_estimate_learned_dev": (C.c_int, [_vp, _vp, _vp, C.c_uint64, _vp, _vp, _vp]),
 }
+MLP_NPARAM = 8385
+FEATURES = 64
+
+
+class ServeConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("max_links", C.c_uint32), ("cand_cap", C.c_uint32),
+                ("watch_cap", C.c_uint32), ("r", C.c_uint32), ("c", C.c_uint32), ("s", C.c_uint32),
+                ("u", C.c_uint32), ("log2g", C.c_uint32), ("theta", C.c_double)]
+
+
+class ServeResult(C.Structure):
+    _fields_ = [("link", C.c_uint32), ("kprime", C.c_uint32), ("slice", C.c_uint64), ("restore_rc", C.c_int32),
+                ("n_cand", C.c_uint32), ("n_out", C.c_uint64), ("n_watch", C.c_uint32), ("pad", C.c_uint32),
+                ("latency_ms", C.c_double), ("step_ms", C.c_double)]
+
+
+SIGNATURES.update({
+    "at_serve_create": (C.c_int, [C.POINTER(ServeConfig), C.POINTER(_vp)]),
+    "at_serve_destroy": (C.c_int, [_vp]),
+    "at_serve_set_mlp": (C.c_int, [_vp, _vp]),
+    "at_serve_open_link": (C.c_int, [_vp, C.c_uint32, C.c_uint64, C.c_uint64, _u32p, C.POINTER(C.c_int)]),
+    "at_serve_link_state": (C.c_int, [_vp, C.c_uint32, C.POINTER(C.c_int), _u64p, _u64p]),
+    "at_serve_close_link": (C.c_int, [_vp, C.c_uint32]),
+    "at_serve_set_watch": (C.c_int, [_vp, C.c_uint32, _u32p, C.c_uint32]),
+    "at_serve_submit": (C.c_int, [_vp, C.c_uint32, _vp, _vp, C.c_uint64]),
+    "at_serve_end_slice": (C.c_int, [_vp, C.c_uint32, C.c_uint32]),
+    "at_serve_step": (C.c_int, [_vp, _u32p]),
+    "at_serve_next_result": (C.c_int, [_vp, C.POINTER(ServeResult), _u32p, _f64p, _f64p, _u8p, C.c_uint32,
+                                       _f64p, _f64p, _u8p, C.c_uint32]),
+    "at_serve_stats": (C.c_int, [_vp, _u64p]),
+    "at_serve_read_pool": (C.c_int, [_vp, C.c_uint32, _u8p]),
+})
 
 _lib = None
 
@@ -234,7 +277,188 @@ class AtPool:
         _check(self.lib.at_constants(self._handle(), _p(out, C.c_uint64)), "at_constants")
         return dict(zip(["p", "A", "Ainv", "alpha", "beta", "T", "W", "blk_a"], map(int, out)))
 
+    def features(self, aip_dev, feat_dev, est_dev=None, flags_dev=None):
+        n = aip_dev.numel()
+        ptr = lambda t: C.c_void_p(_dev_ptr(t)) if t is not None else C.c_void_p(0)  # noqa: E731
+        _check(self.lib.at_features(self._handle(), ptr(aip_dev), n, ptr(feat_dev), ptr(est_dev), ptr(flags_dev)),
+               "at_features")
+
+    def estimate_learned(self, mlp: "Mlp", aip_host: np.ndarray):
+        """Returns (learned estimates, flags, plain estimates)."""
+        aip = np.ascontiguousarray(aip_host, np.uint32)
+        est = np.zeros(aip.size, np.float64)
+        fl = np.zeros(aip.size, np.uint8)
+        plain = np.zeros(aip.size, np.float64)
+        _check(self.lib.at_estimate_learned(self._handle(), mlp._handle(), _p(aip, C.c_uint32), aip.size,
+                                            _p(est, C.c_double), _p(fl, C.c_uint8), _p(plain, C.c_double)),
+               "at_estimate_learned")
+        return est, fl, plain
+
+    def estimate_learned_dev(self, mlp: "Mlp", aip_dev, est_dev, flags_dev, plain_dev=None):
+        ptr = lambda t: C.c_void_p(_dev_ptr(t)) if t is not None else C.c_void_p(0)  # noqa: E731
+        _check(self.lib.at_estimate_learned_dev(self._handle(), mlp._handle(), ptr(aip_dev), aip_dev.numel(),
+                                                ptr(est_dev), ptr(flags_dev), ptr(plain_dev)),
+               "at_estimate_learned_dev")
+
     def tuple_count(self) -> int:
         U = C.c_uint64()
         _check(self.lib.at_tuple_count(self._handle(), C.byref(U)), "at_tuple_count")
         return int(U.value)
+
+
+class Mlp:
+    """The learned-correction network (at_mlp_*): 64 -> 64 -> 64 -> 1."""
+
+    def __init__(self, params: Optional[np.ndarray] = None, stream=None):
+        import torch
+        self.lib = load()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(self.lib.at_mlp_create(C.c_void_p(self.stream.cuda_stream), C.byref(h)), "at_mlp_create")
+        self.h = h
+        if params is not None:
+            self.set_params(params)
+
+    def _handle(self):
+        if not self.h:
+            raise AtError(AT_E_STATE, "network destroyed")
+        return self.h
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            self.lib.at_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def set_params(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, np.float32)
+        if p.size != MLP_NPARAM:
+            raise ValueError("expected %d parameters" % MLP_NPARAM)
+        _check(self.lib.at_mlp_set_params(self._handle(), _p(p, C.c_float)), "at_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(MLP_NPARAM, np.float32)
+        _check(self.lib.at_mlp_get_params(self._handle(), _p(p, C.c_float)), "at_mlp_get_params")
+        return p
+
+    def forward(self, x_dev, y_dev):
+        n = x_dev.shape[0]
+        _check(self.lib.at_mlp_forward(self._handle(), C.c_void_p(_dev_ptr(x_dev)), n, C.c_void_p(_dev_ptr(y_dev))),
+               "at_mlp_forward")
+
+    def grad(self, x_dev, t_dev, grad_dev=None, want_loss: bool = True):
+        loss = C.c_float()
+        _check(self.lib.at_mlp_grad(self._handle(), C.c_void_p(_dev_ptr(x_dev)), C.c_void_p(_dev_ptr(t_dev)),
+                                    x_dev.shape[0], C.c_void_p(_dev_ptr(grad_dev)) if grad_dev is not None else None,
+                                    C.byref(loss) if want_loss else None), "at_mlp_grad")
+        return float(loss.value) if want_loss else None
+
+    def apply_grad(self, grad_dev, lr: float):
+        _check(self.lib.at_mlp_apply_grad(self._handle(), C.c_void_p(_dev_ptr(grad_dev)), lr), "at_mlp_apply_grad")
+
+    def train_step(self, x_dev, t_dev, lr: float, want_loss: bool = False):
+        loss = C.c_float()
+        _check(self.lib.at_mlp_train_step(self._handle(), C.c_void_p(_dev_ptr(x_dev)), C.c_void_p(_dev_ptr(t_dev)),
+                                          x_dev.shape[0], lr, C.byref(loss) if want_loss else None),
+               "at_mlp_train_step")
+        return float(loss.value) if want_loss else None
+
+
+class Server:
+    """Streaming server (at_serve_*): many links, batched steps, one graph."""
+
+    def __init__(self, hbm_budget: int, max_links: int, r: int, c: int, s: int, u: int, log2g: int,
+                 theta: float = 1024.0, cand_cap: int = 2048, watch_cap: int = 256):
+        self.lib = load()
+        cfg = ServeConfig(hbm_budget, max_links, cand_cap, watch_cap, r, c, s, u, log2g, theta)
+        h = C.c_void_p()
+        _check(self.lib.at_serve_create(C.byref(cfg), C.byref(h)), "at_serve_create")
+        self.h = h
+        self.cand_cap, self.watch_cap = cand_cap, watch_cap
+        self.pool_bytes = (1 << (c + u)) * r * (1 << log2g)
+        self._keep = []
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            self.lib.at_serve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def set_mlp(self, mlp: Optional["Mlp"]):
+        _check(self.lib.at_serve_set_mlp(self.h, mlp._handle() if mlp is not None else None), "at_serve_set_mlp")
+        self._mlp = mlp
+
+    def open_link(self, k: int, seed: int, tuple_budget: int = 0) -> Tuple[int, bool]:
+        lid = C.c_uint32()
+        adm = C.c_int()
+        _check(self.lib.at_serve_open_link(self.h, k, seed, tuple_budget, C.byref(lid), C.byref(adm)),
+               "at_serve_open_link")
+        return int(lid.value), bool(adm.value)
+
+    def link_state(self, lid: int) -> Tuple[int, int, int]:
+        st, t, pend = C.c_int(), C.c_uint64(), C.c_uint64()
+        _check(self.lib.at_serve_link_state(self.h, lid, C.byref(st), C.byref(t), C.byref(pend)),
+               "at_serve_link_state")
+        return int(st.value), int(t.value), int(pend.value)
+
+    def close_link(self, lid: int):
+        _check(self.lib.at_serve_close_link(self.h, lid), "at_serve_close_link")
+
+    def set_watch(self, lid: int, hosts: np.ndarray):
+        hw = np.ascontiguousarray(hosts, np.uint32)
+        _check(self.lib.at_serve_set_watch(self.h, lid, _p(hw, C.c_uint32), hw.size), "at_serve_set_watch")
+
+    def submit(self, lid: int, aip_dev, bip_dev, n: Optional[int] = None) -> int:
+        n = aip_dev.numel() if n is None else n
+        return self.lib.at_serve_submit(self.h, lid, C.c_void_p(_dev_ptr(aip_dev)), C.c_void_p(_dev_ptr(bip_dev)), n)
+
+    def end_slice(self, lid: int, kprime: int) -> int:
+        return self.lib.at_serve_end_slice(self.h, lid, kprime)
+
+    def step(self) -> int:
+        n = C.c_uint32()
+        _check(self.lib.at_serve_step(self.h, C.byref(n)), "at_serve_step")
+        return int(n.value)
+
+    def results(self):
+        """Pop every ready result as dicts."""
+        out = []
+        cc, wc = self.cand_cap, self.watch_cap
+        cand = np.zeros(cc, np.uint32)
+        ce, cl = np.zeros(cc), np.zeros(cc)
+        cf = np.zeros(cc, np.uint8)
+        wp, wl = np.zeros(max(wc, 1)), np.zeros(max(wc, 1))
+        wf = np.zeros(max(wc, 1), np.uint8)
+        while True:
+            r = ServeResult()
+            rc = self.lib.at_serve_next_result(self.h, C.byref(r), _p(cand, C.c_uint32), _p(ce, C.c_double),
+                                               _p(cl, C.c_double), _p(cf, C.c_uint8), cc, _p(wp, C.c_double),
+                                               _p(wl, C.c_double), _p(wf, C.c_uint8), wc)
+            if rc == AT_E_STATE:
+                return out
+            _check(rc, "at_serve_next_result")
+            nc, nw = r.n_cand, r.n_watch
+            out.append(dict(link=r.link, kprime=r.kprime, slice=r.slice, restore_rc=r.restore_rc, n_out=r.n_out,
+                            cand=cand[:nc].copy(), cand_plain=ce[:nc].copy(), cand_learned=cl[:nc].copy(),
+                            cand_flags=cf[:nc].copy(), watch_plain=wp[:nw].copy(), watch_learned=wl[:nw].copy(),
+                            watch_flags=wf[:nw].copy(), latency_ms=r.latency_ms, step_ms=r.step_ms))
+
+    def stats(self) -> dict:
+        o = np.zeros(4, np.uint64)
+        _check(self.lib.at_serve_stats(self.h, _p(o, C.c_uint64)), "at_serve_stats")
+        return dict(steps=int(o[0]), pairs=int(o[1]), bytes=int(o[2]), waiting=int(o[3]))
+
+    def read_pool(self, lid: int) -> np.ndarray:
+        out = np.zeros(self.pool_bytes, np.uint8)
+        _check(self.lib.at_serve_read_pool(self.h, lid, _p(out, C.c_uint8)), "at_serve_read_pool")
+        return out

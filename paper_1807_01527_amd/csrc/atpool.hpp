@@ -34,6 +34,17 @@ struct Geometry {
     double theta;
 };
 
+// Lazy preserve work of one slice opening: the byte ranges of the two blocks
+// whose timestamp becomes 0 and k, and the (one or two, disjoint) spans of
+// 4-byte words covering them.
+struct PreserveSpans {
+    uint32_t r0lo, r0hi;  // byte range of the block with timestamp 0
+    uint32_t r1lo, r1hi;  // byte range of the block with timestamp k
+    uint32_t w0lo, nw0;   // word span 0
+    uint32_t w1lo, nw1;   // word span 1 (may be empty)
+};
+PreserveSpans preserve_spans(const Geometry& G, uint32_t c0);
+
 // ---- launchers (kernels.hip); all asynchronous on `st` ---------------------
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* p, uint32_t n, hipStream_t st);
@@ -53,7 +64,145 @@ hipError_t launch_estimate(const uint8_t* pool, const uint64_t* aat, const uint3
                            const Geometry& G, uint32_t c0q, uint32_t kq, double* est, uint8_t* flags,
                            uint32_t* nat, hipStream_t st);
 
+hipError_t launch_features(const uint8_t* pool, const uint64_t* aat, const uint32_t* aip, uint64_t n,
+                           const Geometry& G, uint32_t c0q, uint32_t kq, float* feat, double* est, uint8_t* flags,
+                           hipStream_t st);
+
+// ---- learned correction (mlp.hip) ------------------------------------------
+constexpr uint32_t kMlpDim = 64;
+constexpr uint32_t kOffW1 = 0;
+constexpr uint32_t kOffB1 = kMlpDim * kMlpDim;
+constexpr uint32_t kOffW2 = kOffB1 + kMlpDim;
+constexpr uint32_t kOffB2 = kOffW2 + kMlpDim * kMlpDim;
+constexpr uint32_t kOffW3 = kOffB2 + kMlpDim;
+constexpr uint32_t kOffB3 = kOffW3 + kMlpDim;
+constexpr uint32_t kMlpParams = kOffB3 + 1;  // 8385
+constexpr uint32_t kMlpChunk = 512;          // rows per weight-gradient partial
+
+struct MlpDev {  // operands of the device network
+    const uint16_t* W1b;
+    const float* b1;
+    const uint16_t* W2b;
+    const float* b2;
+    const uint16_t* w3b;
+    const float* b3;
+    const uint16_t* W2Tb;
+};
+
+struct MlpOut {  // bf16 operand copies refreshed from the FP32 master weights
+    uint16_t* W1b;
+    uint16_t* W2b;
+    uint16_t* W2Tb;
+    uint16_t* w3b;
+};
+
+struct MlpScratch {  // training activations, feature-major [64][nrows]
+    uint16_t *XT, *H1T, *H2T, *dH1T, *dH2T;
+    float *y, *dy, *partial, *grad;
+};
+
+struct AdamConst {
+    float lr, b1, b2, one_minus_b1, one_minus_b2, c1, c2, eps;
+};
+
+hipError_t launch_mlp_forward(const float* X, uint64_t n, const MlpDev& P, float* y, hipStream_t st);
+hipError_t launch_mlp_train_fwd_bwd(const float* X, const float* t, uint64_t n, uint64_t nrows, const MlpDev& P,
+                                    const MlpScratch& S, hipStream_t st);
+hipError_t launch_mlp_loss(const float* y, const float* t, uint64_t n, float* out, hipStream_t st);
+hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, const AdamConst& C, const MlpOut& O,
+                           hipStream_t st);
+hipError_t launch_mlp_refresh(const float* w, const MlpOut& O, hipStream_t st);
+hipError_t launch_learned_combine(const float* y, const float* feat, const double* plain, const uint8_t* pflags,
+                                  uint64_t n, double zlo, double zhi, double theta, double* est, uint8_t* flags,
+                                  hipStream_t st);
+
 hipError_t launch_scatter_probe(uint8_t* dst, uint64_t bytes, const uint32_t* a, const uint32_t* b, uint64_t n,
                                 uint32_t r, hipStream_t st);
+
+// ---- serving: many links in one launch (kernels.hip, driven by serve.hip) --
+constexpr uint32_t kServeMaxLinks = 64;
+constexpr uint32_t kServeMaxChunks = 2048;
+constexpr uint32_t kServeUnit = 256;  // pairs per wave work unit (4 per lane)
+
+struct LinkSlot {  // device-resident description of one admitted link
+    Geometry G;
+    uint8_t* pool;
+    uint32_t* w;
+    uint64_t* aat;
+    uint32_t* sa;
+    uint32_t* sa_cnt;
+    uint32_t* cand;           // restore candidates (capacity cand_cap)
+    uint64_t* frame_prefix;   // 2^u + 1 restore items per frame, prefix
+    const uint32_t* watch;    // hosts always estimated at close
+    uint32_t n_watch;
+    uint32_t pad;
+    uint64_t tuple_budget;
+};
+
+struct OpenDesc {
+    uint32_t slot, c0;
+    PreserveSpans S;
+};
+struct ChunkDesc {
+    const uint32_t* aip;
+    const uint32_t* bip;
+    uint64_t n;
+    uint64_t unit0;  // first work unit of the chunk in the step's unit space
+    uint32_t slot, c0, vec, pad;
+};
+struct CloseDesc {
+    uint32_t slot, c0, kq, pad;
+};
+
+struct StepDesc {  // one serving step, copied to the device before each replay
+    uint32_t n_open, n_chunks, n_close, pad;
+    uint64_t n_units;
+    uint64_t open_prefix[kServeMaxLinks + 1];
+    OpenDesc open[kServeMaxLinks];
+    CloseDesc close[kServeMaxLinks];
+    ChunkDesc chunk[kServeMaxChunks];
+};
+
+struct CloseOut {  // per close of a step
+    uint64_t U;          // column tuples (Alg 4 enumeration size)
+    uint64_t m;          // candidates found
+    uint64_t items;      // restore join work items
+    unsigned long long cnt;
+    int32_t rc;          // AT_OK, AT_E_BUDGET or AT_E_OVERFLOW
+    uint32_t n_cand;     // sorted candidates written to the host list
+    uint32_t host_off;   // first entry in the step's host list
+    uint32_t n_hosts;    // candidates + watch hosts
+};
+
+struct ServeState {
+    CloseOut out[kServeMaxLinks];
+    uint64_t item_prefix[kServeMaxLinks + 1];
+    uint64_t n_hosts;
+    uint64_t pad;
+};
+
+struct ServeBufs {  // device buffers of one server's step graph
+    const StepDesc* desc;
+    const LinkSlot* slots;
+    ServeState* state;
+    uint32_t* hosts;   // host list: per close, sorted candidates then watch hosts
+    float* feat;       // hosts x 64
+    double* est;       // plain estimates
+    uint8_t* pflags;   // plain flags
+    float* y;          // network output
+    double* est_l;     // learned estimates
+    uint8_t* flags_l;  // returned flags
+    uint64_t max_hosts;
+    uint32_t cand_cap;
+    uint32_t pad;
+};
+
+hipError_t launch_serve_ingest_branch(const ServeBufs& B, const Geometry& shape, hipStream_t st);
+hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, uint64_t n_atv, hipStream_t st);
+hipError_t launch_mlp_forward_devn(const float* X, const uint64_t* n_dev, uint64_t nrows_max, const MlpDev& P, float* y,
+                                   hipStream_t st);
+hipError_t launch_learned_combine_devn(const float* y, const float* feat, const double* plain, const uint8_t* pflags,
+                                       const uint64_t* n_dev, uint64_t n_max, double zlo, double zhi, double theta,
+                                       double* est, uint8_t* flags, hipStream_t st);
 
 }  // namespace atp

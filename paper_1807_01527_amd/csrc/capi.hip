@@ -38,6 +38,9 @@ struct at_ctx {
     double* q_est = nullptr;
     uint8_t* q_flags = nullptr;
     uint32_t* q_nat = nullptr;
+    float* q_feat = nullptr;      // n x 64 features
+    float* q_y = nullptr;         // network outputs
+    double* q_plain = nullptr;
     uint64_t q_cap = 0;
     // slice clock
     uint64_t t = 0;
@@ -74,7 +77,7 @@ int validate(const at_params& p) {
     if (p.c + p.s * (p.r - 1) < W) return AT_E_INVAL;  // completeness
     if (p.c * p.r <= W) return AT_E_INVAL;             // redundancy
     if (p.s * (p.r - 1) >= W) return AT_E_INVAL;
-    if (p.log2g < 4 || p.log2g > 16) return AT_E_INVAL;
+    if (p.log2g < 4 || p.log2g > 15) return AT_E_INVAL;
     if (!(p.theta > 0) || !std::isfinite(p.theta)) return AT_E_INVAL;
     if ((uint64_t)p.c + p.u + p.log2g > 36) return AT_E_INVAL;  // pool <= r * 64 GiB
     return AT_OK;
@@ -137,7 +140,7 @@ int dev_alloc(T** p, uint64_t count) {
 
 void free_all(at_ctx* h) {
     void* bufs[] = {h->pool, h->w, h->aat, h->sa, h->sa_cnt, h->counter, h->prefix, h->cand,
-                    h->q_aip, h->q_est, h->q_flags, h->q_nat};
+                    h->q_aip, h->q_est, h->q_flags, h->q_nat, h->q_feat, h->q_y, h->q_plain};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -170,14 +173,21 @@ int ensure_query(at_ctx* h, uint64_t n) {
     if (h->q_est) (void)hipFree(h->q_est);
     if (h->q_flags) (void)hipFree(h->q_flags);
     if (h->q_nat) (void)hipFree(h->q_nat);
+    if (h->q_feat) (void)hipFree(h->q_feat);
+    if (h->q_y) (void)hipFree(h->q_y);
+    if (h->q_plain) (void)hipFree(h->q_plain);
     h->q_aip = nullptr;
     h->q_est = nullptr;
     h->q_flags = nullptr;
     h->q_nat = nullptr;
+    h->q_feat = nullptr;
+    h->q_y = nullptr;
+    h->q_plain = nullptr;
     h->q_cap = 0;
     int rc;
     if ((rc = dev_alloc(&h->q_aip, cap)) || (rc = dev_alloc(&h->q_est, cap)) || (rc = dev_alloc(&h->q_flags, cap)) ||
-        (rc = dev_alloc(&h->q_nat, cap)))
+        (rc = dev_alloc(&h->q_nat, cap)) || (rc = dev_alloc(&h->q_feat, cap * 64)) || (rc = dev_alloc(&h->q_y, cap)) ||
+        (rc = dev_alloc(&h->q_plain, cap)))
         return rc;
     h->q_cap = cap;
     return AT_OK;
@@ -466,6 +476,225 @@ int at_probe_scatter(uint8_t* dst_dev, uint64_t bytes, const uint32_t* a_dev, co
     return atp::launch_scatter_probe(dst_dev, bytes, a_dev, b_dev, n, r, (hipStream_t)hip_stream) == hipSuccess
                ? AT_OK
                : AT_E_DEVICE;
+}
+
+}  // extern "C"
+
+// ============================================================== learned correction
+
+struct at_mlp {
+    hipStream_t stream = nullptr;
+    float* w = nullptr;  // FP32 master parameters (kMlpParams)
+    float* m = nullptr;  // Adam moments
+    float* v = nullptr;
+    uint16_t* W1b = nullptr;
+    uint16_t* W2b = nullptr;
+    uint16_t* W2Tb = nullptr;
+    uint16_t* w3b = nullptr;
+    float* loss = nullptr;
+    uint64_t step = 0;
+    atp::MlpScratch S{};
+    uint64_t s_rows = 0;
+};
+
+namespace {
+
+atp::MlpDev mlp_dev(const at_mlp* M) {
+    return atp::MlpDev{M->W1b, M->w + atp::kOffB1, M->W2b, M->w + atp::kOffB2, M->w3b, M->w + atp::kOffB3, M->W2Tb};
+}
+
+atp::MlpOut mlp_out(at_mlp* M) { return atp::MlpOut{M->W1b, M->W2b, M->W2Tb, M->w3b}; }
+
+void mlp_free_scratch(at_mlp* M) {
+    void* b[] = {M->S.XT, M->S.H1T, M->S.H2T, M->S.dH1T, M->S.dH2T, M->S.y, M->S.dy, M->S.partial, M->S.grad};
+    for (void* p : b)
+        if (p) (void)hipFree(p);
+    M->S = atp::MlpScratch{};
+    M->s_rows = 0;
+}
+
+int mlp_ensure(at_mlp* M, uint64_t nrows) {
+    if (nrows <= M->s_rows) return AT_OK;
+    mlp_free_scratch(M);
+    int rc;
+    const uint64_t T = 64 * nrows;
+    if ((rc = dev_alloc(&M->S.XT, T)) || (rc = dev_alloc(&M->S.H1T, T)) || (rc = dev_alloc(&M->S.H2T, T)) ||
+        (rc = dev_alloc(&M->S.dH1T, T)) || (rc = dev_alloc(&M->S.dH2T, T)) || (rc = dev_alloc(&M->S.y, nrows)) ||
+        (rc = dev_alloc(&M->S.dy, nrows)) || (rc = dev_alloc(&M->S.partial, nrows / atp::kMlpChunk * atp::kMlpParams)) ||
+        (rc = dev_alloc(&M->S.grad, atp::kMlpParams))) {
+        mlp_free_scratch(M);
+        return rc;
+    }
+    M->s_rows = nrows;
+    return AT_OK;
+}
+
+// forward + backward + reduction into M->S.grad (and optionally the loss)
+int mlp_grad(at_mlp* M, const float* x_dev, const float* t_dev, uint64_t n) {
+    const uint64_t nrows = (n + atp::kMlpChunk - 1) / atp::kMlpChunk * atp::kMlpChunk;
+    int rc = mlp_ensure(M, nrows);
+    if (rc) return rc;
+    hipError_t e = atp::launch_mlp_train_fwd_bwd(x_dev, t_dev, n, nrows, mlp_dev(M), M->S, M->stream);
+    return e == hipSuccess ? AT_OK : AT_E_DEVICE;
+}
+
+int mlp_adam(at_mlp* M, const float* grad, float lr) {
+    M->step += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    atp::AdamConst C{lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2),
+                     (float)(1.0 - std::pow(b1, (double)M->step)), (float)(1.0 - std::pow(b2, (double)M->step)), 1e-8f};
+    return atp::launch_mlp_adam(M->w, M->m, M->v, grad, C, mlp_out(M), M->stream) == hipSuccess ? AT_OK : AT_E_DEVICE;
+}
+
+int read_loss(at_mlp* M, const float* t_dev, uint64_t n, float* loss_host) {
+    hipError_t e = atp::launch_mlp_loss(M->S.y, t_dev, n, M->loss, M->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(loss_host, M->loss, sizeof(float), hipMemcpyDeviceToHost, M->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(M->stream);
+    return dev_err(e);
+}
+
+}  // namespace
+
+namespace atp {
+bool mlp_operands(const at_mlp* m, MlpDev* out) {
+    if (!m) return false;
+    *out = mlp_dev(m);
+    return true;
+}
+}  // namespace atp
+
+extern "C" {
+
+int at_mlp_create(void* hip_stream, at_mlp** out) {
+    if (!out) return AT_E_INVAL;
+    *out = nullptr;
+    at_mlp* M = new (std::nothrow) at_mlp();
+    if (!M) return AT_E_NOMEM;
+    M->stream = (hipStream_t)hip_stream;
+    int rc;
+    if ((rc = dev_alloc(&M->w, atp::kMlpParams)) || (rc = dev_alloc(&M->m, atp::kMlpParams)) ||
+        (rc = dev_alloc(&M->v, atp::kMlpParams)) || (rc = dev_alloc(&M->W1b, 64 * 64)) ||
+        (rc = dev_alloc(&M->W2b, 64 * 64)) || (rc = dev_alloc(&M->W2Tb, 64 * 64)) || (rc = dev_alloc(&M->w3b, 64)) ||
+        (rc = dev_alloc(&M->loss, 1))) {
+        at_mlp_destroy(M);
+        return rc;
+    }
+    std::vector<float> zero(atp::kMlpParams, 0.0f);
+    hipError_t e = hipMemcpyAsync(M->w, zero.data(), zero.size() * 4, hipMemcpyHostToDevice, M->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(M->m, zero.data(), zero.size() * 4, hipMemcpyHostToDevice, M->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(M->v, zero.data(), zero.size() * 4, hipMemcpyHostToDevice, M->stream);
+    if (e == hipSuccess) e = atp::launch_mlp_refresh(M->w, mlp_out(M), M->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(M->stream);
+    if (e != hipSuccess) {
+        at_mlp_destroy(M);
+        return AT_E_DEVICE;
+    }
+    *out = M;
+    return AT_OK;
+}
+
+int at_mlp_destroy(at_mlp* M) {
+    if (!M) return AT_OK;
+    (void)hipStreamSynchronize(M->stream);
+    mlp_free_scratch(M);
+    void* b[] = {M->w, M->m, M->v, M->W1b, M->W2b, M->W2Tb, M->w3b, M->loss};
+    for (void* p : b)
+        if (p) (void)hipFree(p);
+    delete M;
+    return AT_OK;
+}
+
+int at_mlp_set_params(at_mlp* M, const float* host_params) {
+    if (!M || !host_params) return AT_E_INVAL;
+    std::vector<float> zero(atp::kMlpParams, 0.0f);
+    hipError_t e = hipMemcpyAsync(M->w, host_params, atp::kMlpParams * 4, hipMemcpyHostToDevice, M->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(M->m, zero.data(), zero.size() * 4, hipMemcpyHostToDevice, M->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(M->v, zero.data(), zero.size() * 4, hipMemcpyHostToDevice, M->stream);
+    if (e == hipSuccess) e = atp::launch_mlp_refresh(M->w, mlp_out(M), M->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(M->stream);
+    M->step = 0;
+    return dev_err(e);
+}
+
+int at_mlp_get_params(at_mlp* M, float* host_params) {
+    if (!M || !host_params) return AT_E_INVAL;
+    hipError_t e = hipMemcpyAsync(host_params, M->w, atp::kMlpParams * 4, hipMemcpyDeviceToHost, M->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(M->stream);
+    return dev_err(e);
+}
+
+int at_mlp_forward(at_mlp* M, const float* x_dev, uint64_t n, float* y_dev) {
+    if (!M || (n && (!x_dev || !y_dev))) return AT_E_INVAL;
+    return atp::launch_mlp_forward(x_dev, n, mlp_dev(M), y_dev, M->stream) == hipSuccess ? AT_OK : AT_E_DEVICE;
+}
+
+int at_mlp_grad(at_mlp* M, const float* x_dev, const float* t_dev, uint64_t n, float* grad_dev, float* loss_host) {
+    if (!M || !x_dev || !t_dev || n == 0) return AT_E_INVAL;
+    int rc = mlp_grad(M, x_dev, t_dev, n);
+    if (rc) return rc;
+    if (grad_dev) {
+        hipError_t e = hipMemcpyAsync(grad_dev, M->S.grad, atp::kMlpParams * 4, hipMemcpyDeviceToDevice, M->stream);
+        if (e != hipSuccess) return AT_E_DEVICE;
+    }
+    return loss_host ? read_loss(M, t_dev, n, loss_host) : AT_OK;
+}
+
+int at_mlp_apply_grad(at_mlp* M, const float* grad_dev, float lr) {
+    if (!M || !grad_dev || !(lr > 0)) return AT_E_INVAL;
+    return mlp_adam(M, grad_dev, lr);
+}
+
+int at_mlp_train_step(at_mlp* M, const float* x_dev, const float* t_dev, uint64_t n, float lr, float* loss_host) {
+    if (!M || !x_dev || !t_dev || n == 0 || !(lr > 0)) return AT_E_INVAL;
+    int rc = mlp_grad(M, x_dev, t_dev, n);
+    if (rc) return rc;
+    if (loss_host && (rc = read_loss(M, t_dev, n, loss_host))) return rc;
+    return mlp_adam(M, M->S.grad, lr);
+}
+
+int at_features(at_ctx* h, const uint32_t* aip_dev, uint64_t n, float* feat_dev, double* est_dev, uint8_t* flags_dev) {
+    if (!h || (n && (!aip_dev || !feat_dev))) return AT_E_INVAL;
+    if (!h->queryable) return AT_E_STATE;
+    hipError_t e = atp::launch_features(h->pool, h->aat, aip_dev, n, h->G, h->c0_query, h->kq, feat_dev, est_dev,
+                                        flags_dev, h->stream);
+    return e == hipSuccess ? AT_OK : AT_E_DEVICE;
+}
+
+int at_estimate_learned_dev(at_ctx* h, at_mlp* M, const uint32_t* aip_dev, uint64_t n, double* est_dev,
+                            uint8_t* flags_dev, double* plain_dev) {
+    if (!h || !M || (n && (!aip_dev || !est_dev || !flags_dev))) return AT_E_INVAL;
+    if (!h->queryable) return AT_E_STATE;
+    if (n == 0) return AT_OK;
+    int rc = ensure_query(h, n);
+    if (rc) return rc;
+    double* plain = plain_dev ? plain_dev : h->q_plain;
+    hipError_t e = atp::launch_features(h->pool, h->aat, aip_dev, n, h->G, h->c0_query, h->kq, h->q_feat, plain,
+                                        h->q_flags, h->stream);
+    if (e == hipSuccess) e = atp::launch_mlp_forward(h->q_feat, n, mlp_dev(M), h->q_y, h->stream);
+    if (e == hipSuccess)
+        e = atp::launch_learned_combine(h->q_y, h->q_feat, plain, h->q_flags, n, std::log(16.0) - 0.5,
+                                        std::log(262144.0) + 0.5, h->p.theta, est_dev, flags_dev, h->stream);
+    return e == hipSuccess ? AT_OK : AT_E_DEVICE;
+}
+
+int at_estimate_learned(at_ctx* h, at_mlp* M, const uint32_t* aip_host, uint64_t n, double* est_out,
+                        uint8_t* flags_out, double* plain_out) {
+    if (!h || !M || (n && (!aip_host || !est_out || !flags_out))) return AT_E_INVAL;
+    if (!h->queryable) return AT_E_STATE;
+    if (n == 0) return AT_OK;
+    int rc = ensure_query(h, n);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(h->q_aip, aip_host, n * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return AT_E_DEVICE;
+    // est and flags of the learned path land in q_est / q_nat (as bytes); plain in q_plain
+    rc = at_estimate_learned_dev(h, M, h->q_aip, n, h->q_est, reinterpret_cast<uint8_t*>(h->q_nat), h->q_plain);
+    if (rc) return rc;
+    e = hipMemcpyAsync(est_out, h->q_est, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(flags_out, h->q_nat, n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && plain_out)
+        e = hipMemcpyAsync(plain_out, h->q_plain, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return dev_err(e);
 }
 
 }  // extern "C"

@@ -94,13 +94,6 @@ __global__ void k_zero_u64(unsigned long long* p, uint32_t n) {
 // alone, which is exactly what Alg 2 does to it.  Work items are 4-byte words
 // of one or two disjoint word spans per ATV; bytes outside the due blocks are
 // written back unchanged.
-struct PreserveSpans {
-    uint32_t r0lo, r0hi;  // byte range of the block with timestamp 0
-    uint32_t r1lo, r1hi;  // byte range of the block with timestamp k
-    uint32_t w0lo, nw0;   // word span 0
-    uint32_t w1lo, nw1;   // word span 1 (may be empty)
-};
-
 __global__ __launch_bounds__(kBlock) void k_preserve(uint8_t* __restrict__ pool, uint64_t n_atv,
                                                      uint32_t log2g, uint32_t k, PreserveSpans S) {
     const uint32_t per_atv = S.nw0 + S.nw1;
@@ -482,6 +475,497 @@ __global__ __launch_bounds__(kBlock) void k_estimate(const uint8_t* __restrict__
 }
 
 
+// ---------------------------------------------------------------- a7: features
+// Occupancy-by-age features of a host (one wave per host): e_i = largest age
+// over the host's r ATs at position i when all are active for the full
+// window k.  feat[d] = #{i : e_i = d}/g (d < min(k, 61)); feat[61] =
+// min(ln(1 + max(plain, 0)), 20)/16 with plain the Eq 4 estimate for the
+// close's k'; feat[62] = k/64; feat[63] = mean over rows of AAT/(g*2^c).  The
+// histogram's prefix below k' is NAT(k'), so the plain estimate comes along.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_features(const uint8_t* __restrict__ pool, const uint64_t* __restrict__ aat,
+                                                     const uint32_t* __restrict__ aips, uint64_t n, Geometry G,
+                                                     uint32_t c0q, uint32_t kq, float* __restrict__ feat,
+                                                     double* __restrict__ est, uint8_t* __restrict__ flags) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint8_t* act_lut = smem;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(smem + ((G.g + 15u) & ~15u)) + (threadIdx.x >> 6) * 128;
+    fill_act_lut(act_lut, c0q, G);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
+    for (uint64_t h = wave; h < n; h += nwaves) {
+        hist[lane] = 0;  // ages reach k - 1 <= 126: two bins per lane
+        hist[lane + 64] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t a = aips[h];
+        const uint32_t f = mangle(a, G.A);
+        const uint32_t z = f & G.umask;
+        const uint64_t L = (uint64_t)(f >> G.u);
+        const uint64_t LL = L | (L << G.W);
+        const uint8_t* rows[R];
+#pragma unroll
+        for (int j = 0; j < R; j++) {
+            uint32_t x = column(LL, G.sh[j], G.ncol_mask);
+            rows[j] = pool + (((((uint64_t)z * R + j) << G.c) + x) << G.log2g);
+        }
+        for (uint32_t off = lane * 16; off < G.g; off += 64 * 16) {
+            const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
+            uint4 d[R];
+#pragma unroll
+            for (int j = 0; j < R; j++) d[j] = *reinterpret_cast<const uint4*>(rows[j] + off);
+#pragma unroll
+            for (int b = 0; b < 16; b++) {
+                const uint32_t sh = 8 * (b & 3);
+                const uint32_t actb = ((b < 4 ? ac.x : b < 8 ? ac.y : b < 12 ? ac.z : ac.w) >> sh) & 0xFFu;
+                uint32_t e = 0, ok = 1;
+#pragma unroll
+                for (int j = 0; j < R; j++) {
+                    const uint32_t at = ((b < 4 ? d[j].x : b < 8 ? d[j].y : b < 12 ? d[j].z : d[j].w) >> sh) & 0xFFu;
+                    const uint32_t dist = actb >= at ? actb - at : actb + G.twok - at;
+                    ok &= (at != G.twok) & (dist < G.k);
+                    e = dist > e ? dist : e;
+                }
+                if (ok) atomicAdd(&hist[e], 1u);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t hv = hist[lane];
+        uint32_t nat = (lane < kq ? hv : 0u) + (lane + 64 < kq ? hist[lane + 64] : 0u);
+        for (uint32_t o = 32; o > 0; o >>= 1) nat += __shfl_xor(nat, o, 64);
+        uint8_t fl = 0;
+        double e_plain = 0.0;
+        if (lane == 0) e_plain = eq4(nat, z, aat, G, &fl);
+        e_plain = __shfl(e_plain, 0, 64);
+        const uint32_t nd = G.k < 61 ? G.k : 61;
+        float fv = lane < nd ? (float)((double)hv / (double)G.g) : 0.0f;
+        if (lane == 61) {
+            double lp = log(1.0 + (e_plain > 0 ? e_plain : 0.0));
+            if (!(lp < 20.0)) lp = 20.0;
+            fv = (float)(lp / 16.0);
+        } else if (lane == 62) {
+            fv = (float)((double)G.k / 64.0);
+        } else if (lane == 63) {
+            const double cells = (double)((uint64_t)G.g << G.c);
+            double s = 0.0;
+            for (uint32_t j = 0; j < G.r; j++) s += (double)aat[(uint64_t)z * G.r + j] / cells;
+            fv = (float)(s / (double)G.r);
+        }
+        feat[h * 64 + lane] = fv;
+        if (lane == 0) {
+            if (est) est[h] = e_plain;
+            if (flags) flags[h] = fl;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// ---------------------------------------------------------------- a9: serving
+// Batched forms of the kernels above for many links per launch.  Every grid
+// is fixed (the step graph is captured once); the work of a replay is read
+// from the step descriptor and the device-side counters.  Links of one server
+// share the geometry shape (r, c, s, u, g); k, seed and C0 are per link.
+
+__device__ __forceinline__ uint32_t upper_index(const uint64_t* prefix, uint32_t n, uint64_t x) {
+    // last i in [0, n) with prefix[i] <= x (prefix non-decreasing, prefix[0] = 0)
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_serve_preserve(const StepDesc* __restrict__ d,
+                                                           const LinkSlot* __restrict__ L) {
+    const uint32_t no = d->n_open;
+    if (no == 0) return;
+    const uint64_t total = d->open_prefix[no];
+    for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+         it += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t o = upper_index(d->open_prefix, no, it);
+        const OpenDesc& od = d->open[o];
+        const LinkSlot& ls = L[od.slot];
+        const PreserveSpans& S = od.S;
+        const uint32_t per_atv = S.nw0 + S.nw1;
+        const uint64_t rem = it - d->open_prefix[o];
+        const uint64_t atv = rem / per_atv;
+        const uint32_t wi = (uint32_t)(rem - atv * per_atv);
+        const uint32_t word = wi < S.nw0 ? S.w0lo + wi : S.w1lo + (wi - S.nw0);
+        const uint32_t k = ls.G.k, twok = ls.G.twok;
+        uint32_t* p = (uint32_t*)(ls.pool + (atv << ls.G.log2g)) + word;
+        uint32_t v = *p, nv = v;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            uint32_t pos = word * 4 + b;
+            uint32_t at = (v >> (8 * b)) & 0xFFu;
+            uint32_t out = at;
+            if (pos >= S.r0lo && pos < S.r0hi && at <= k) out = twok;
+            if (pos >= S.r1lo && pos < S.r1hi && ((at >= k && at < twok) || at == 0)) out = twok;
+            nv = (nv & ~(0xFFu << (8 * b))) | (out << (8 * b));
+        }
+        if (nv != v) *p = nv;
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_serve_ingest(const StepDesc* __restrict__ d, const LinkSlot* __restrict__ L) {
+    const uint32_t nc = d->n_chunks;
+    if (nc == 0) return;
+    const uint64_t units = d->n_units;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
+    for (uint64_t u = wave; u < units; u += nwaves) {
+        // chunk c holds units [unit0_c, unit0_c + ceil(n_c / kServeUnit))
+        uint32_t lo = 0, hi = nc;
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (d->chunk[mid].unit0 <= u) lo = mid;
+            else hi = mid;
+        }
+        const ChunkDesc& cd = d->chunk[lo];
+        const LinkSlot& ls = L[cd.slot];
+        const uint64_t q0 = (u - cd.unit0) * kServeUnit + lane * 4;
+        if (q0 >= cd.n) continue;
+        if (cd.vec && q0 + 4 <= cd.n) {
+            const uint4 a = *reinterpret_cast<const uint4*>(cd.aip + q0);
+            const uint4 b = *reinterpret_cast<const uint4*>(cd.bip + q0);
+            scan_pair<R>(ls.pool, a.x, b.x, ls.G, cd.c0);
+            scan_pair<R>(ls.pool, a.y, b.y, ls.G, cd.c0);
+            scan_pair<R>(ls.pool, a.z, b.z, ls.G, cd.c0);
+            scan_pair<R>(ls.pool, a.w, b.w, ls.G, cd.c0);
+        } else {
+            for (uint64_t q = q0; q < q0 + 4 && q < cd.n; q++) scan_pair<R>(ls.pool, cd.aip[q], cd.bip[q], ls.G, cd.c0);
+        }
+    }
+}
+
+// k'-weights of every ATV of every closing link; block timestamps are
+// computed per byte (links differ in k and C0).
+__global__ __launch_bounds__(kBlock) void k_serve_close(const StepDesc* __restrict__ d, const LinkSlot* __restrict__ L,
+                                                        uint64_t n_atv, uint32_t log2g) {
+    const uint32_t ncl = d->n_close;
+    if (ncl == 0) return;
+    const uint32_t g = 1u << log2g;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t lpa = g / 16 < 64 ? g / 16 : 64;
+    const uint32_t apw = 64 / lpa;
+    const uint32_t sub = lane / lpa, sl = lane % lpa;
+    const uint32_t steps = g / (16 * lpa);
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
+    const uint64_t total = (uint64_t)ncl * n_atv;
+    for (uint64_t base = wave * apw; base < total; base += nwaves * apw) {
+        const uint64_t gi = base + sub;
+        uint32_t cnt = 0;
+        const uint32_t ci = (uint32_t)(gi / n_atv);
+        if (gi < total) {
+            const CloseDesc& cdsc = d->close[ci];
+            const LinkSlot& ls = L[cdsc.slot];
+            const uint64_t atv = gi - (uint64_t)ci * n_atv;
+            const uint8_t* p = ls.pool + (atv << log2g);
+            for (uint32_t st = 0; st < steps; st++) {
+                const uint32_t off = (st * lpa + sl) * 16;
+                const uint4 dv = *reinterpret_cast<const uint4*>(p + off);
+                uint32_t acts[4];
+#pragma unroll
+                for (int wd = 0; wd < 4; wd++) {
+                    uint32_t a4 = 0;
+#pragma unroll
+                    for (int b = 0; b < 4; b++) a4 |= act_of(off + 4 * wd + b, cdsc.c0, ls.G) << (8 * b);
+                    acts[wd] = a4;
+                }
+                cnt += __popc(active_mask16(dv, make_uint4(acts[0], acts[1], acts[2], acts[3]), ls.G.twok, cdsc.kq));
+            }
+        }
+        for (uint32_t o = lpa / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if (sl == 0 && gi < total) L[d->close[ci].slot].w[gi - (uint64_t)ci * n_atv] = cnt;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_serve_summarize(const StepDesc* __restrict__ d,
+                                                            const LinkSlot* __restrict__ L, uint32_t ngroups) {
+    __shared__ uint32_t wave_cnt[kBlock / 64];
+    __shared__ unsigned long long wave_sum[kBlock / 64];
+    const uint32_t ci = blockIdx.x / ngroups, grp = blockIdx.x % ngroups;
+    if (ci >= d->n_close) return;
+    const LinkSlot& ls = L[d->close[ci].slot];
+    const Geometry& G = ls.G;
+    const uint64_t base = (uint64_t)grp << G.c;
+    const uint32_t ncol = G.ncol_mask + 1;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    uint64_t sum = 0;
+    uint32_t written = 0;
+    for (uint32_t x0 = 0; x0 < ncol; x0 += kBlock) {
+        const uint32_t x = x0 + threadIdx.x;
+        const uint32_t wx = x < ncol ? ls.w[base + x] : 0u;
+        const bool sup = x < ncol && wx >= G.T;
+        sum += wx;
+        const uint64_t ball = __ballot(sup);
+        const uint32_t before = __popcll(ball & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_cnt[wv] = __popcll(ball);
+        __syncthreads();
+        uint32_t off = written, tot = 0;
+        for (uint32_t q = 0; q < kBlock / 64; q++) {
+            if (q < wv) off += wave_cnt[q];
+            tot += wave_cnt[q];
+        }
+        if (sup) ls.sa[base + off + before] = x;
+        written += tot;
+        __syncthreads();
+    }
+    for (uint32_t o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if (lane == 0) wave_sum[wv] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (uint32_t q = 0; q < kBlock / 64; q++) t += wave_sum[q];
+        ls.aat[grp] = t;
+        ls.sa_cnt[grp] = written;
+    }
+}
+
+// One thread per closing link: restore items per frame, U and the budget
+// rule; then the items prefix over links (single block, thread 0).
+__global__ void k_serve_restore_prep(const StepDesc* __restrict__ d, const LinkSlot* __restrict__ L,
+                                     ServeState* __restrict__ S) {
+    const uint32_t ncl = d->n_close;
+    for (uint32_t ci = threadIdx.x; ci < ncl; ci += blockDim.x) {
+        const LinkSlot& ls = L[d->close[ci].slot];
+        const Geometry& G = ls.G;
+        const uint32_t nframe = G.umask + 1;
+        uint64_t U = 0, items = 0;
+        ls.frame_prefix[0] = 0;
+        for (uint32_t z = 0; z < nframe; z++) {
+            uint64_t prod = 1;
+            bool empty = false;
+            for (uint32_t j = 0; j < G.r; j++) {
+                const uint64_t cj = ls.sa_cnt[(uint64_t)z * G.r + j];
+                empty |= cj == 0;
+                prod = (prod == 0 || cj == 0) ? 0 : (prod > UINT64_MAX / cj ? UINT64_MAX : prod * cj);
+            }
+            U = (UINT64_MAX - U < prod) ? UINT64_MAX : U + prod;
+            uint64_t it = empty ? 0 : ls.sa_cnt[(uint64_t)z * G.r];
+            if (!empty && G.r >= 2) it *= ls.sa_cnt[(uint64_t)z * G.r + 1];
+            items += it;
+            ls.frame_prefix[z + 1] = items;
+        }
+        CloseOut& o = S->out[ci];
+        o.U = U;
+        o.rc = U > ls.tuple_budget ? AT_E_BUDGET : AT_OK;
+        o.items = o.rc == AT_OK ? items : 0;
+        o.cnt = 0;
+        o.m = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        S->item_prefix[0] = 0;
+        for (uint32_t ci = 0; ci < ncl; ci++) S->item_prefix[ci + 1] = S->item_prefix[ci] + S->out[ci].items;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_serve_restore_join(const StepDesc* __restrict__ d,
+                                                               const LinkSlot* __restrict__ L,
+                                                               ServeState* __restrict__ S, uint32_t cap) {
+    const uint32_t ncl = d->n_close;
+    if (ncl == 0) return;
+    const uint64_t total = S->item_prefix[ncl];
+    for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+         it += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t ci = upper_index(S->item_prefix, ncl, it);
+        const LinkSlot& ls = L[d->close[ci].slot];
+        const Geometry& G = ls.G;
+        const uint32_t R = G.r;
+        const uint64_t li = it - S->item_prefix[ci];
+        const uint32_t z = upper_index(ls.frame_prefix, G.umask + 1, li);
+        const uint64_t rem = li - ls.frame_prefix[z];
+        const uint32_t* cnt = ls.sa_cnt + (uint64_t)z * R;
+        const uint64_t rowbase = (uint64_t)z * R << G.c;
+        unsigned long long* counter = &S->out[ci].cnt;
+        if (R == 1) {
+            emit(place(ls.sa[rowbase + rem], G.sh[0], G), z, G, ls.cand, cap, counter);
+            continue;
+        }
+        const uint32_t c1 = cnt[1];
+        const uint32_t i0 = (uint32_t)(rem / c1), i1 = (uint32_t)(rem - (uint64_t)i0 * c1);
+        uint32_t Lb = place(ls.sa[rowbase + i0], G.sh[0], G);
+        uint32_t M = G.win[0];
+        const uint32_t P = place(ls.sa[rowbase + (1ull << G.c) + i1], G.sh[1], G);
+        if ((P ^ Lb) & M & G.win[1]) continue;
+        Lb |= P;
+        M |= G.win[1];
+        if (R == 2) {
+            emit(Lb, z, G, ls.cand, cap, counter);
+            continue;
+        }
+        uint32_t Ls[kMaxRows], Ms[kMaxRows], idx[kMaxRows];
+        uint32_t lvl = 2;
+        Ls[2] = Lb;
+        Ms[2] = M;
+        idx[2] = 0;
+        for (;;) {
+            if (idx[lvl] >= cnt[lvl]) {
+                if (lvl == 2) break;
+                lvl--;
+                idx[lvl]++;
+                continue;
+            }
+            const uint32_t Pq = place(ls.sa[rowbase + ((uint64_t)lvl << G.c) + idx[lvl]], G.sh[lvl], G);
+            if ((Pq ^ Ls[lvl]) & Ms[lvl] & G.win[lvl]) {
+                idx[lvl]++;
+                continue;
+            }
+            if (lvl == R - 1) {
+                emit(Ls[lvl] | Pq, z, G, ls.cand, cap, counter);
+                idx[lvl]++;
+            } else {
+                Ls[lvl + 1] = Ls[lvl] | Pq;
+                Ms[lvl + 1] = Ms[lvl] | G.win[lvl];
+                lvl++;
+                idx[lvl] = 0;
+            }
+        }
+    }
+}
+
+// Candidate counts, the cap rule and each close's slice of the host list.
+__global__ void k_serve_host_offsets(const StepDesc* __restrict__ d, const LinkSlot* __restrict__ L,
+                                     ServeState* __restrict__ S, uint32_t cap) {
+    if (threadIdx.x != 0) return;
+    uint64_t off = 0;
+    for (uint32_t ci = 0; ci < d->n_close; ci++) {
+        CloseOut& o = S->out[ci];
+        o.m = o.cnt;
+        uint32_t nc = 0;
+        if (o.rc == AT_OK) {
+            if (o.m > cap) o.rc = AT_E_OVERFLOW;
+            else nc = (uint32_t)o.m;
+        }
+        o.n_cand = nc;
+        o.host_off = (uint32_t)off;
+        o.n_hosts = nc + L[d->close[ci].slot].n_watch;
+        off += o.n_hosts;
+    }
+    S->n_hosts = off;
+}
+
+// One workgroup per close: sort its candidates in LDS (cap <= kTile) and
+// write them, then its watch hosts, to the host list.
+__global__ __launch_bounds__(kBlock) void k_serve_sort(const StepDesc* __restrict__ d, const LinkSlot* __restrict__ L,
+                                                       const ServeState* __restrict__ S, uint32_t* __restrict__ hosts) {
+    __shared__ uint32_t s[kTile];
+    const uint32_t ci = blockIdx.x;
+    if (ci >= d->n_close) return;
+    const CloseOut& o = S->out[ci];
+    const LinkSlot& ls = L[d->close[ci].slot];
+    const uint32_t n = o.n_cand;
+    uint32_t np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    for (uint32_t q = threadIdx.x; q < np2; q += blockDim.x) s[q] = q < n ? ls.cand[q] : 0xFFFFFFFFu;
+    __syncthreads();
+    for (uint32_t k = 2; k <= np2; k <<= 1)
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t p = threadIdx.x; p < np2 / 2; p += blockDim.x) {
+                const uint32_t li = 2 * p - (p & (j - 1));
+                cmp_swap_lds(s, li, li + j, (li & k) == 0);
+            }
+            __syncthreads();
+        }
+    for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) hosts[o.host_off + q] = s[q];
+    for (uint32_t q = threadIdx.x; q < ls.n_watch; q += blockDim.x) hosts[o.host_off + n + q] = ls.watch[q];
+}
+
+// Features and plain estimates of the host list (one wave per host).
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_serve_features(const StepDesc* __restrict__ d,
+                                                           const LinkSlot* __restrict__ L,
+                                                           const ServeState* __restrict__ S,
+                                                           const uint32_t* __restrict__ hosts, float* __restrict__ feat,
+                                                           double* __restrict__ est, uint8_t* __restrict__ pflags) {
+    __shared__ uint32_t hist_all[kBlock / 64][128];
+    uint32_t* hist = hist_all[threadIdx.x >> 6];
+    const uint32_t ncl = d->n_close;
+    if (ncl == 0) return;
+    const uint64_t nh = S->n_hosts;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
+    for (uint64_t h = wave; h < nh; h += nwaves) {
+        uint32_t ci = 0;
+        while (ci + 1 < ncl && S->out[ci + 1].host_off <= h) ci++;
+        const CloseDesc& cdsc = d->close[ci];
+        const LinkSlot& ls = L[cdsc.slot];
+        const Geometry& G = ls.G;
+        hist[lane] = 0;
+        hist[lane + 64] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t f = mangle(hosts[h], G.A);
+        const uint32_t z = f & G.umask;
+        const uint64_t Lw = (uint64_t)(f >> G.u);
+        const uint64_t LL = Lw | (Lw << G.W);
+        const uint8_t* rows[R];
+#pragma unroll
+        for (int j = 0; j < R; j++)
+            rows[j] = ls.pool + (((((uint64_t)z * R + j) << G.c) + column(LL, G.sh[j], G.ncol_mask)) << G.log2g);
+        for (uint32_t off = lane * 16; off < G.g; off += 64 * 16) {
+            uint4 dv[R];
+#pragma unroll
+            for (int j = 0; j < R; j++) dv[j] = *reinterpret_cast<const uint4*>(rows[j] + off);
+#pragma unroll
+            for (int b = 0; b < 16; b++) {
+                const uint32_t sh = 8 * (b & 3);
+                const uint32_t actb = act_of(off + b, cdsc.c0, G);
+                uint32_t e = 0, ok = 1;
+#pragma unroll
+                for (int j = 0; j < R; j++) {
+                    const uint32_t at = ((b < 4 ? dv[j].x : b < 8 ? dv[j].y : b < 12 ? dv[j].z : dv[j].w) >> sh) & 0xFFu;
+                    const uint32_t dist = actb >= at ? actb - at : actb + G.twok - at;
+                    ok &= (at != G.twok) & (dist < G.k);
+                    e = dist > e ? dist : e;
+                }
+                if (ok) atomicAdd(&hist[e], 1u);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t hv = hist[lane];
+        const uint32_t kq = cdsc.kq;
+        uint32_t nat = (lane < kq ? hv : 0u) + (lane + 64 < kq ? hist[lane + 64] : 0u);
+        for (uint32_t o = 32; o > 0; o >>= 1) nat += __shfl_xor(nat, o, 64);
+        uint8_t fl = 0;
+        double e_plain = 0.0;
+        if (lane == 0) e_plain = eq4(nat, z, ls.aat, G, &fl);
+        e_plain = __shfl(e_plain, 0, 64);
+        const uint32_t nd = G.k < 61 ? G.k : 61;
+        float fv = lane < nd ? (float)((double)hv / (double)G.g) : 0.0f;
+        if (lane == 61) {
+            double lp = log(1.0 + (e_plain > 0 ? e_plain : 0.0));
+            if (!(lp < 20.0)) lp = 20.0;
+            fv = (float)(lp / 16.0);
+        } else if (lane == 62) {
+            fv = (float)((double)G.k / 64.0);
+        } else if (lane == 63) {
+            const double cells = (double)((uint64_t)G.g << G.c);
+            double sacc = 0.0;
+            for (uint32_t j = 0; j < G.r; j++) sacc += (double)ls.aat[(uint64_t)z * G.r + j] / cells;
+            fv = (float)(sacc / (double)G.r);
+        }
+        feat[h * 64 + lane] = fv;
+        if (lane == 0) {
+            est[h] = e_plain;
+            pflags[h] = fl;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 // ---------------------------------------------------------------- probes
 // Scatter roofline probe: the same input stream as the pair scan (8 B per
 // item, 16-byte vector loads) and the same number of byte stores per item,
@@ -534,7 +1018,7 @@ hipError_t launch_zero_u64(unsigned long long* p, uint32_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_preserve(uint8_t* pool, uint64_t n_atv, const Geometry& G, uint32_t c0, hipStream_t st) {
+PreserveSpans preserve_spans(const Geometry& G, uint32_t c0) {
     // blocks whose timestamp (c0 + b) mod 2k becomes 0 and k
     const uint32_t twok = G.twok, k = G.k;
     const uint32_t b0 = (twok - c0) % twok, b1 = (3 * k - c0) % twok;
@@ -567,12 +1051,15 @@ hipError_t launch_preserve(uint8_t* pool, uint64_t n_atv, const Geometry& G, uin
             ns = 1;
         }
     }
-    if (ns == 0) return hipSuccess;
-    S.w0lo = sp[0][0];
-    S.nw0 = sp[0][1] - sp[0][0];
-    S.w1lo = ns == 2 ? sp[1][0] : 0;
-    S.nw1 = ns == 2 ? sp[1][1] - sp[1][0] : 0;
+    if (ns >= 1) { S.w0lo = sp[0][0]; S.nw0 = sp[0][1] - sp[0][0]; }
+    if (ns == 2) { S.w1lo = sp[1][0]; S.nw1 = sp[1][1] - sp[1][0]; }
+    return S;
+}
+
+hipError_t launch_preserve(uint8_t* pool, uint64_t n_atv, const Geometry& G, uint32_t c0, hipStream_t st) {
+    const PreserveSpans S = preserve_spans(G, c0);
     const uint64_t items = n_atv * (S.nw0 + S.nw1);
+    if (items == 0) return hipSuccess;
     hipLaunchKernelGGL(k_preserve, dim3(grid_for(items, 1u << 16)), dim3(kBlock), 0, st, pool, n_atv, G.log2g,
                        G.k, S);
     return hipGetLastError();
@@ -676,6 +1163,89 @@ hipError_t launch_estimate(const uint8_t* pool, const uint64_t* aat, const uint3
             return hipErrorInvalidValue;
     }
 #undef AT_EST_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_features(const uint8_t* pool, const uint64_t* aat, const uint32_t* aip, uint64_t n,
+                           const Geometry& G, uint32_t c0q, uint32_t kq, float* feat, double* est, uint8_t* flags,
+                           hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + 3) / 4;
+    if (blocks > 16384) blocks = 16384;
+    const size_t shmem = ((G.g + 15u) & ~15u) + (kBlock / 64) * 128 * sizeof(uint32_t);
+#define AT_FEAT_CASE(RR)                                                                                   \
+    case RR:                                                                                               \
+        hipLaunchKernelGGL((k_features<RR>), dim3((uint32_t)blocks), dim3(kBlock), shmem, st, pool, aat, aip, n, G, \
+                           c0q, kq, feat, est, flags);                                                     \
+        break;
+    switch (G.r) {
+        AT_FEAT_CASE(1)
+        AT_FEAT_CASE(2)
+        AT_FEAT_CASE(3)
+        AT_FEAT_CASE(4)
+        AT_FEAT_CASE(5)
+        AT_FEAT_CASE(6)
+        AT_FEAT_CASE(7)
+        AT_FEAT_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef AT_FEAT_CASE
+    return hipGetLastError();
+}
+
+constexpr uint32_t kServeGrid = 2048;  // persistent grid of the batched kernels
+
+hipError_t launch_serve_ingest_branch(const ServeBufs& B, const Geometry& shape, hipStream_t st) {
+    hipLaunchKernelGGL(k_serve_preserve, dim3(kServeGrid), dim3(kBlock), 0, st, B.desc, B.slots);
+#define AT_SERVE_ING(RR)                                                                                   \
+    case RR:                                                                                               \
+        hipLaunchKernelGGL((k_serve_ingest<RR>), dim3(kServeGrid * 2), dim3(kBlock), 0, st, B.desc, B.slots); \
+        break;
+    switch (shape.r) {
+        AT_SERVE_ING(1)
+        AT_SERVE_ING(2)
+        AT_SERVE_ING(3)
+        AT_SERVE_ING(4)
+        AT_SERVE_ING(5)
+        AT_SERVE_ING(6)
+        AT_SERVE_ING(7)
+        AT_SERVE_ING(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef AT_SERVE_ING
+    return hipGetLastError();
+}
+
+hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, uint64_t n_atv, hipStream_t st) {
+    const uint32_t ngroups = (shape.umask + 1) * shape.r;
+    hipLaunchKernelGGL(k_serve_close, dim3(kServeGrid), dim3(kBlock), 0, st, B.desc, B.slots, n_atv, shape.log2g);
+    hipLaunchKernelGGL(k_serve_summarize, dim3(kServeMaxLinks * ngroups), dim3(kBlock), 0, st, B.desc, B.slots,
+                       ngroups);
+    hipLaunchKernelGGL(k_serve_restore_prep, dim3(1), dim3(64), 0, st, B.desc, B.slots, B.state);
+    hipLaunchKernelGGL(k_serve_restore_join, dim3(kServeGrid), dim3(kBlock), 0, st, B.desc, B.slots, B.state,
+                       B.cand_cap);
+    hipLaunchKernelGGL(k_serve_host_offsets, dim3(1), dim3(64), 0, st, B.desc, B.slots, B.state, B.cand_cap);
+    hipLaunchKernelGGL(k_serve_sort, dim3(kServeMaxLinks), dim3(kBlock), 0, st, B.desc, B.slots, B.state, B.hosts);
+#define AT_SERVE_FEAT(RR)                                                                                     \
+    case RR:                                                                                                  \
+        hipLaunchKernelGGL((k_serve_features<RR>), dim3(kServeGrid), dim3(kBlock), 0, st, B.desc, B.slots, B.state, \
+                           B.hosts, B.feat, B.est, B.pflags);                                                 \
+        break;
+    switch (shape.r) {
+        AT_SERVE_FEAT(1)
+        AT_SERVE_FEAT(2)
+        AT_SERVE_FEAT(3)
+        AT_SERVE_FEAT(4)
+        AT_SERVE_FEAT(5)
+        AT_SERVE_FEAT(6)
+        AT_SERVE_FEAT(7)
+        AT_SERVE_FEAT(8)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef AT_SERVE_FEAT
     return hipGetLastError();
 }
 

@@ -1,0 +1,746 @@
+// Streaming server: many links' ATVC pools resident in device memory,
+// admitted against an HBM budget, their uneven slices batched into one step
+// graph replayed per step.
+//
+// Per step the host turns every link's queued events (chunks of pairs, slice
+// ends) into one descriptor table.  The captured graph then runs two branches
+// concurrently:
+//   ingest: batched lazy preserve of opening slices, then the batched scan of
+//           every queued chunk of every link;
+//   close:  batched close, super lists, restore (budget rule, join, sort),
+//           features + plain estimates of candidates and watch hosts, and
+//           the learned correction;
+// then copies the results to pinned host memory.  A link whose slice ends is
+// closed in the step after its last chunk was scanned, and its next slice
+// waits for that close, so the two branches never touch the same pool.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "at.h"
+#include "atpool.hpp"
+
+using atp::ChunkDesc;
+using atp::CloseDesc;
+using atp::Geometry;
+using atp::LinkSlot;
+using atp::OpenDesc;
+using atp::ServeState;
+using atp::StepDesc;
+
+namespace {
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+uint64_t splitmix(uint64_t& s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t pow_mod_p(uint64_t b, uint64_t e) {
+    const uint64_t p = atp::kPrime;
+    uint64_t r = 1;
+    b %= p;
+    while (e) {
+        if (e & 1) r = (r * b) % p;
+        b = (b * b) % p;
+        e >>= 1;
+    }
+    return r;
+}
+
+// The same derivation as a single handle's (at_create): constants from the seed.
+Geometry derive_geometry(const at_params& p) {
+    Geometry G{};
+    G.k = p.k;
+    G.twok = 2 * p.k;
+    G.r = p.r;
+    G.c = p.c;
+    G.s = p.s;
+    G.u = p.u;
+    G.W = 32 - p.u;
+    G.log2g = p.log2g;
+    G.g = 1u << p.log2g;
+    G.ncol_mask = (1u << p.c) - 1u;
+    G.umask = (1u << p.u) - 1u;
+    uint64_t st = p.seed;
+    const uint64_t x0 = splitmix(st), x1 = splitmix(st), x2 = splitmix(st);
+    const uint64_t A = (1ull << 31) + x0 % (atp::kPrime - (1ull << 31));
+    G.A = (uint32_t)A;
+    G.Ainv = (uint32_t)pow_mod_p(A, atp::kPrime - 2);
+    G.alpha = x1 | 1ull;
+    G.beta = x2;
+    G.blk_a = G.g / G.twok;
+    G.last_blk = G.twok - 1;
+    G.blk_magic = G.blk_a ? (((1ull << 32) + G.blk_a - 1) / G.blk_a) : 0;
+    G.maskW = G.W == 32 ? 0xFFFFFFFFull : ((1ull << G.W) - 1);
+    for (uint32_t j = 0; j < (uint32_t)atp::kMaxRows; j++) {
+        G.sh[j] = j < p.r ? (p.s * j) % G.W : 0;
+        if (j < p.r) {
+            uint64_t t = (uint64_t)G.ncol_mask << G.sh[j];
+            G.win[j] = (uint32_t)((t | (t >> G.W)) & G.maskW);
+        }
+    }
+    const double thr = (double)G.g - (double)G.g * std::exp(-p.theta / (double)G.g);
+    double Tc = std::ceil(thr);
+    G.T = (uint32_t)(Tc < 0 ? 0 : Tc);
+    G.theta = p.theta;
+    return G;
+}
+
+template <typename T>
+int dalloc(T** p, uint64_t count) {
+    *p = nullptr;
+    hipError_t e = hipMalloc((void**)p, (count ? count : 1) * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? AT_E_NOMEM : AT_E_DEVICE;
+    }
+    return AT_OK;
+}
+
+enum LinkState { L_WAITING = 0, L_ACTIVE = 1, L_CLOSED = 2 };
+
+struct Event {
+    bool end;
+    const uint32_t* aip;
+    const uint32_t* bip;
+    uint64_t n;
+    uint32_t kprime;
+    double t_arrival;
+};
+
+struct Link {
+    uint32_t id = 0;
+    int state = L_WAITING;
+    at_params p{};
+    Geometry G{};
+    uint64_t bytes = 0;
+    int slot = -1;
+    // device buffers
+    uint8_t* pool = nullptr;
+    uint32_t* w = nullptr;
+    uint64_t* aat = nullptr;
+    uint32_t* sa = nullptr;
+    uint32_t* sa_cnt = nullptr;
+    uint32_t* cand = nullptr;
+    uint64_t* frame_prefix = nullptr;
+    uint32_t* watch = nullptr;
+    uint32_t n_watch = 0;
+    // clock
+    uint64_t t = 0;          // slices closed
+    bool open = false;
+    uint32_t c0 = 0;
+    std::deque<Event> q;
+    uint64_t consumed = 0;   // events consumed (chunks + ends)
+};
+
+struct Result {
+    at_serve_result r;
+    std::vector<uint32_t> cand;
+    std::vector<double> cand_est, cand_learned;
+    std::vector<uint8_t> cand_flags;
+    std::vector<double> watch_plain, watch_learned;
+    std::vector<uint8_t> watch_flags;
+};
+
+}  // namespace
+
+struct at_serve {
+    at_serve_config cfg{};
+    hipStream_t s0 = nullptr, s1 = nullptr;  // s0: scan branch and graph launch; s1: close branch
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::mutex step_mu;  // held while device state may be in use (steps, admissions, watch lists)
+    std::mutex mu;       // guards the host-side queues; never held while the GPU works
+    std::vector<Link*> links;             // by id
+    std::deque<uint32_t> waiting;         // admission FIFO
+    std::vector<int> slot_used;           // slot -> link id or -1
+    uint64_t used_bytes = 0;
+    uint64_t per_link_bytes = 0;
+    Geometry shape{};
+    uint64_t n_atv = 0;
+    // device
+    StepDesc* d_desc = nullptr;
+    LinkSlot* d_slots = nullptr;
+    ServeState* d_state = nullptr;
+    uint32_t* d_hosts = nullptr;
+    float* d_feat = nullptr;
+    double* d_est = nullptr;
+    uint8_t* d_pflags = nullptr;
+    float* d_y = nullptr;
+    double* d_estl = nullptr;
+    uint8_t* d_flagsl = nullptr;
+    uint64_t max_hosts = 0;
+    // pinned host
+    StepDesc* h_desc = nullptr;
+    ServeState* h_state = nullptr;
+    uint32_t* h_hosts = nullptr;
+    double* h_est = nullptr;
+    double* h_estl = nullptr;
+    uint8_t* h_flagsl = nullptr;
+    // graph
+    at_mlp* mlp = nullptr;
+    const void* mlp_key = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // results
+    std::deque<Result> results;
+    uint64_t steps = 0;
+    double last_step_ms = 0.0;
+    uint64_t pairs_ingested = 0;
+};
+
+namespace atp {
+// MLP operands of a network (capi.hip)
+bool mlp_operands(const at_mlp* m, MlpDev* out);
+}
+
+namespace {
+
+void free_link_device(Link* L) {
+    void* b[] = {L->pool, L->w, L->aat, L->sa, L->sa_cnt, L->cand, L->frame_prefix, L->watch};
+    for (void* p : b)
+        if (p) (void)hipFree(p);
+    L->pool = nullptr;
+    L->w = nullptr;
+    L->aat = nullptr;
+    L->sa = nullptr;
+    L->sa_cnt = nullptr;
+    L->cand = nullptr;
+    L->frame_prefix = nullptr;
+    L->watch = nullptr;
+}
+
+uint64_t link_bytes(const at_serve* S) {
+    const uint64_t ngroups = (uint64_t)(S->shape.umask + 1) * S->shape.r;
+    return (S->n_atv << S->shape.log2g) + S->n_atv * 8 + ngroups * 12 + (uint64_t)S->cfg.cand_cap * 4 +
+           ((uint64_t)S->shape.umask + 2) * 8 + (uint64_t)S->cfg.watch_cap * 4;
+}
+
+// Allocate and initialise a link's pool; publish its slot.  Caller holds mu.
+int admit(at_serve* S, Link* L) {
+    int slot = -1;
+    for (uint32_t i = 0; i < S->slot_used.size(); i++)
+        if (S->slot_used[i] < 0) {
+            slot = (int)i;
+            break;
+        }
+    if (slot < 0) return AT_E_NOMEM;
+    const uint64_t ngroups = (uint64_t)(S->shape.umask + 1) * S->shape.r;
+    int rc;
+    if ((rc = dalloc(&L->pool, S->n_atv << S->shape.log2g)) || (rc = dalloc(&L->w, S->n_atv)) ||
+        (rc = dalloc(&L->aat, ngroups)) || (rc = dalloc(&L->sa, S->n_atv)) || (rc = dalloc(&L->sa_cnt, ngroups)) ||
+        (rc = dalloc(&L->cand, S->cfg.cand_cap)) || (rc = dalloc(&L->frame_prefix, S->shape.umask + 2)) ||
+        (rc = dalloc(&L->watch, S->cfg.watch_cap))) {
+        free_link_device(L);
+        return rc;
+    }
+    hipError_t e = atp::launch_fill_u8(L->pool, S->n_atv << S->shape.log2g, (uint8_t)L->G.twok, S->s0);
+    LinkSlot ls{};
+    ls.G = L->G;
+    ls.pool = L->pool;
+    ls.w = L->w;
+    ls.aat = L->aat;
+    ls.sa = L->sa;
+    ls.sa_cnt = L->sa_cnt;
+    ls.cand = L->cand;
+    ls.frame_prefix = L->frame_prefix;
+    ls.watch = L->watch;
+    ls.n_watch = 0;
+    ls.tuple_budget = L->p.tuple_budget ? L->p.tuple_budget : (1ull << 32);
+    if (e == hipSuccess) e = hipMemcpyAsync(S->d_slots + slot, &ls, sizeof(ls), hipMemcpyHostToDevice, S->s0);
+    if (e == hipSuccess) e = hipStreamSynchronize(S->s0);
+    if (e != hipSuccess) {
+        free_link_device(L);
+        return AT_E_DEVICE;
+    }
+    L->slot = slot;
+    L->n_watch = 0;
+    S->slot_used[slot] = (int)L->id;
+    L->state = L_ACTIVE;
+    S->used_bytes += L->bytes;
+    return AT_OK;
+}
+
+void admit_waiting(at_serve* S) {
+    while (!S->waiting.empty()) {
+        Link* L = S->links[S->waiting.front()];
+        if (S->used_bytes + L->bytes > S->cfg.hbm_budget) break;
+        if (admit(S, L) != AT_OK) break;
+        S->waiting.pop_front();
+    }
+}
+
+int capture_graph(at_serve* S) {
+    atp::ServeBufs B{};
+    B.desc = S->d_desc;
+    B.slots = S->d_slots;
+    B.state = S->d_state;
+    B.hosts = S->d_hosts;
+    B.feat = S->d_feat;
+    B.est = S->d_est;
+    B.pflags = S->d_pflags;
+    B.y = S->d_y;
+    B.est_l = S->d_estl;
+    B.flags_l = S->d_flagsl;
+    B.max_hosts = S->max_hosts;
+    B.cand_cap = S->cfg.cand_cap;
+    atp::MlpDev P{};
+    const bool have_mlp = S->mlp && atp::mlp_operands(S->mlp, &P);
+    if (S->exec) {
+        (void)hipGraphExecDestroy(S->exec);
+        S->exec = nullptr;
+    }
+    if (S->graph) {
+        (void)hipGraphDestroy(S->graph);
+        S->graph = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(S->s0, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return AT_E_DEVICE;
+    hipError_t ec = hipMemcpyAsync(S->d_desc, S->h_desc, sizeof(StepDesc), hipMemcpyHostToDevice, S->s0);
+    if (ec == hipSuccess) ec = hipEventRecord(S->ev_fork, S->s0);
+    if (ec == hipSuccess) ec = hipStreamWaitEvent(S->s1, S->ev_fork, 0);
+    // branch 1: close of slices whose chunks were all scanned in earlier steps
+    if (ec == hipSuccess) ec = atp::launch_serve_close_branch(B, S->shape, S->n_atv, S->s1);
+    if (ec == hipSuccess && have_mlp)
+        ec = atp::launch_mlp_forward_devn(S->d_feat, &S->d_state->n_hosts, S->max_hosts, P, S->d_y, S->s1);
+    if (ec == hipSuccess && have_mlp)
+        ec = atp::launch_learned_combine_devn(S->d_y, S->d_feat, S->d_est, S->d_pflags, &S->d_state->n_hosts,
+                                              S->max_hosts, std::log(16.0) - 0.5, std::log(262144.0) + 0.5,
+                                              S->cfg.theta, S->d_estl, S->d_flagsl, S->s1);
+    if (ec == hipSuccess)
+        ec = hipMemcpyAsync(S->h_state, S->d_state, sizeof(ServeState), hipMemcpyDeviceToHost, S->s1);
+    if (ec == hipSuccess)
+        ec = hipMemcpyAsync(S->h_hosts, S->d_hosts, S->max_hosts * 4, hipMemcpyDeviceToHost, S->s1);
+    if (ec == hipSuccess) ec = hipMemcpyAsync(S->h_est, S->d_est, S->max_hosts * 8, hipMemcpyDeviceToHost, S->s1);
+    if (ec == hipSuccess && have_mlp)
+        ec = hipMemcpyAsync(S->h_estl, S->d_estl, S->max_hosts * 8, hipMemcpyDeviceToHost, S->s1);
+    if (ec == hipSuccess)
+        ec = hipMemcpyAsync(S->h_flagsl, have_mlp ? S->d_flagsl : S->d_pflags, S->max_hosts, hipMemcpyDeviceToHost,
+                            S->s1);
+    if (ec == hipSuccess) ec = hipEventRecord(S->ev_join, S->s1);
+    // branch 0: open + scan
+    if (ec == hipSuccess) ec = atp::launch_serve_ingest_branch(B, S->shape, S->s0);
+    if (ec == hipSuccess) ec = hipStreamWaitEvent(S->s0, S->ev_join, 0);
+    e = hipStreamEndCapture(S->s0, &S->graph);
+    if (ec != hipSuccess || e != hipSuccess) {
+        if (S->graph) (void)hipGraphDestroy(S->graph);
+        S->graph = nullptr;
+        (void)hipGetLastError();
+        return AT_E_DEVICE;
+    }
+    e = hipGraphInstantiate(&S->exec, S->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        S->exec = nullptr;
+        return AT_E_DEVICE;
+    }
+    S->mlp_key = have_mlp ? (const void*)S->mlp : nullptr;
+    return AT_OK;
+}
+
+void free_server(at_serve* S) {
+    if (S->exec) (void)hipGraphExecDestroy(S->exec);
+    if (S->graph) (void)hipGraphDestroy(S->graph);
+    for (Link* L : S->links) {
+        if (L) {
+            free_link_device(L);
+            delete L;
+        }
+    }
+    void* d[] = {S->d_desc, S->d_slots, S->d_state, S->d_hosts, S->d_feat, S->d_est, S->d_pflags, S->d_y, S->d_estl,
+                 S->d_flagsl};
+    for (void* p : d)
+        if (p) (void)hipFree(p);
+    void* h[] = {S->h_desc, S->h_state, S->h_hosts, S->h_est, S->h_estl, S->h_flagsl};
+    for (void* p : h)
+        if (p) (void)hipHostFree(p);
+    if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
+    if (S->ev_join) (void)hipEventDestroy(S->ev_join);
+    if (S->s1) (void)hipStreamDestroy(S->s1);
+    if (S->s0) (void)hipStreamDestroy(S->s0);
+}
+
+}  // namespace
+
+extern "C" {
+
+int at_serve_create(const at_serve_config* cfg, at_serve** out) {
+    if (!out || !cfg) return AT_E_INVAL;
+    *out = nullptr;
+    at_params shp{};
+    shp.k = 1;
+    shp.r = cfg->r;
+    shp.c = cfg->c;
+    shp.s = cfg->s;
+    shp.u = cfg->u;
+    shp.log2g = cfg->log2g;
+    shp.theta = cfg->theta;
+    if (cfg->max_links < 1 || cfg->max_links > atp::kServeMaxLinks || cfg->cand_cap < 1 || cfg->cand_cap > 2048 ||
+        cfg->u > 8 || cfg->watch_cap > 4096)
+        return AT_E_INVAL;
+    {  // the geometry rules of at_create
+        const uint32_t W = 32 - shp.u;
+        if (shp.r < 1 || shp.r > (uint32_t)atp::kMaxRows || shp.c < 1 || shp.c > 20 || shp.s < 1 || shp.s > shp.c ||
+            shp.c > W || shp.c + shp.s * (shp.r - 1) < W || shp.c * shp.r <= W || shp.s * (shp.r - 1) >= W ||
+            shp.log2g < 4 || shp.log2g > 15 || !(shp.theta > 0))
+            return AT_E_INVAL;
+    }
+    at_serve* S = new (std::nothrow) at_serve();
+    if (!S) return AT_E_NOMEM;
+    S->cfg = *cfg;
+    S->shape = derive_geometry(shp);
+    S->n_atv = ((uint64_t)(S->shape.umask + 1) * S->shape.r) << S->shape.c;
+    S->per_link_bytes = link_bytes(S);
+    S->slot_used.assign(cfg->max_links, -1);
+    S->max_hosts = (uint64_t)cfg->max_links * (cfg->cand_cap + cfg->watch_cap);
+    int rc = AT_OK;
+    hipError_t e = hipStreamCreateWithFlags(&S->s0, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s1, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) rc = AT_E_DEVICE;
+    if (!rc && ((rc = dalloc(&S->d_desc, 1)) || (rc = dalloc(&S->d_slots, atp::kServeMaxLinks)) ||
+                (rc = dalloc(&S->d_state, 1)) || (rc = dalloc(&S->d_hosts, S->max_hosts)) ||
+                (rc = dalloc(&S->d_feat, S->max_hosts * 64)) || (rc = dalloc(&S->d_est, S->max_hosts)) ||
+                (rc = dalloc(&S->d_pflags, S->max_hosts)) || (rc = dalloc(&S->d_y, S->max_hosts)) ||
+                (rc = dalloc(&S->d_estl, S->max_hosts)) || (rc = dalloc(&S->d_flagsl, S->max_hosts)))) {
+    }
+    if (!rc) {
+        if (hipHostMalloc((void**)&S->h_desc, sizeof(StepDesc), 0) != hipSuccess ||
+            hipHostMalloc((void**)&S->h_state, sizeof(ServeState), 0) != hipSuccess ||
+            hipHostMalloc((void**)&S->h_hosts, S->max_hosts * 4, 0) != hipSuccess ||
+            hipHostMalloc((void**)&S->h_est, S->max_hosts * 8, 0) != hipSuccess ||
+            hipHostMalloc((void**)&S->h_estl, S->max_hosts * 8, 0) != hipSuccess ||
+            hipHostMalloc((void**)&S->h_flagsl, S->max_hosts, 0) != hipSuccess)
+            rc = AT_E_NOMEM;
+    }
+    if (rc) {
+        free_server(S);
+        delete S;
+        return rc;
+    }
+    memset(S->h_desc, 0, sizeof(StepDesc));
+    *out = S;
+    return AT_OK;
+}
+
+int at_serve_destroy(at_serve* S) {
+    if (!S) return AT_OK;
+    { std::lock_guard<std::mutex> sg(S->step_mu); }
+    (void)hipStreamSynchronize(S->s0);
+    (void)hipStreamSynchronize(S->s1);
+    free_server(S);
+    delete S;
+    return AT_OK;
+}
+
+int at_serve_set_mlp(at_serve* S, at_mlp* m) {
+    if (!S) return AT_E_INVAL;
+    std::lock_guard<std::mutex> sg(S->step_mu);
+    std::lock_guard<std::mutex> g(S->mu);
+    S->mlp = m;
+    return AT_OK;
+}
+
+int at_serve_open_link(at_serve* S, uint32_t k, uint64_t seed, uint64_t tuple_budget, uint32_t* link_id,
+                       int* admitted) {
+    if (!S || !link_id) return AT_E_INVAL;
+    if (k < 1 || k > 127) return AT_E_INVAL;
+    std::lock_guard<std::mutex> sg(S->step_mu);
+    std::lock_guard<std::mutex> g(S->mu);
+    Link* L = new (std::nothrow) Link();
+    if (!L) return AT_E_NOMEM;
+    L->id = (uint32_t)S->links.size();
+    L->p.k = k;
+    L->p.r = S->cfg.r;
+    L->p.c = S->cfg.c;
+    L->p.s = S->cfg.s;
+    L->p.u = S->cfg.u;
+    L->p.log2g = S->cfg.log2g;
+    L->p.theta = S->cfg.theta;
+    L->p.seed = seed;
+    L->p.tuple_budget = tuple_budget;
+    L->G = derive_geometry(L->p);
+    L->bytes = S->per_link_bytes;
+    S->links.push_back(L);
+    *link_id = L->id;
+    if (L->bytes > S->cfg.hbm_budget) {
+        L->state = L_CLOSED;
+        return AT_E_NOMEM;
+    }
+    if (S->waiting.empty() && S->used_bytes + L->bytes <= S->cfg.hbm_budget) {
+        int rc = admit(S, L);
+        if (rc == AT_OK) {
+            if (admitted) *admitted = 1;
+            return AT_OK;
+        }
+    }
+    L->state = L_WAITING;
+    S->waiting.push_back(L->id);
+    if (admitted) *admitted = 0;
+    return AT_OK;
+}
+
+int at_serve_link_state(at_serve* S, uint32_t link_id, int* state, uint64_t* slices_closed, uint64_t* pending) {
+    if (!S) return AT_E_INVAL;
+    std::lock_guard<std::mutex> g(S->mu);
+    if (link_id >= S->links.size()) return AT_E_INVAL;
+    const Link* L = S->links[link_id];
+    if (state) *state = L->state;
+    if (slices_closed) *slices_closed = L->t;
+    if (pending) *pending = L->q.size();
+    return AT_OK;
+}
+
+int at_serve_close_link(at_serve* S, uint32_t link_id) {
+    if (!S) return AT_E_INVAL;
+    std::lock_guard<std::mutex> sg(S->step_mu);
+    std::lock_guard<std::mutex> g(S->mu);
+    if (link_id >= S->links.size()) return AT_E_INVAL;
+    Link* L = S->links[link_id];
+    if (L->state == L_CLOSED) return AT_E_STATE;
+    if (L->state == L_WAITING) {
+        for (auto it = S->waiting.begin(); it != S->waiting.end(); ++it)
+            if (*it == link_id) {
+                S->waiting.erase(it);
+                break;
+            }
+    } else {
+        (void)hipStreamSynchronize(S->s0);
+        S->slot_used[L->slot] = -1;
+        free_link_device(L);
+        S->used_bytes -= L->bytes;
+        L->slot = -1;
+    }
+    L->state = L_CLOSED;
+    L->q.clear();
+    admit_waiting(S);
+    return AT_OK;
+}
+
+int at_serve_set_watch(at_serve* S, uint32_t link_id, const uint32_t* hosts_host, uint32_t n) {
+    if (!S || (n && !hosts_host)) return AT_E_INVAL;
+    std::lock_guard<std::mutex> sg(S->step_mu);
+    std::lock_guard<std::mutex> g(S->mu);
+    if (link_id >= S->links.size() || n > S->cfg.watch_cap) return AT_E_INVAL;
+    Link* L = S->links[link_id];
+    if (L->state != L_ACTIVE) return AT_E_STATE;
+    hipError_t e = hipSuccess;
+    if (n) e = hipMemcpyAsync(L->watch, hosts_host, n * 4, hipMemcpyHostToDevice, S->s0);
+    const size_t off = offsetof(LinkSlot, n_watch);
+    uint32_t nw = n;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(reinterpret_cast<uint8_t*>(S->d_slots + L->slot) + off, &nw, sizeof(nw),
+                           hipMemcpyHostToDevice, S->s0);
+    if (e == hipSuccess) e = hipStreamSynchronize(S->s0);
+    if (e != hipSuccess) return AT_E_DEVICE;
+    L->n_watch = n;
+    return AT_OK;
+}
+
+int at_serve_submit(at_serve* S, uint32_t link_id, const uint32_t* aip_dev, const uint32_t* bip_dev, uint64_t n) {
+    if (!S || (n && (!aip_dev || !bip_dev))) return AT_E_INVAL;
+    std::lock_guard<std::mutex> g(S->mu);
+    if (link_id >= S->links.size()) return AT_E_INVAL;
+    Link* L = S->links[link_id];
+    if (L->state != L_ACTIVE) return AT_E_STATE;
+    if (n == 0) return AT_OK;
+    L->q.push_back(Event{false, aip_dev, bip_dev, n, 0, 0.0});
+    return AT_OK;
+}
+
+int at_serve_end_slice(at_serve* S, uint32_t link_id, uint32_t kprime) {
+    if (!S) return AT_E_INVAL;
+    const double t = now_ms();
+    std::lock_guard<std::mutex> g(S->mu);
+    if (link_id >= S->links.size()) return AT_E_INVAL;
+    Link* L = S->links[link_id];
+    if (L->state != L_ACTIVE) return AT_E_STATE;
+    if (kprime < 1 || kprime > L->p.k) return AT_E_INVAL;
+    L->q.push_back(Event{true, nullptr, nullptr, 0, kprime, t});
+    return AT_OK;
+}
+
+int at_serve_step(at_serve* S, uint32_t* n_results) {
+    if (!S) return AT_E_INVAL;
+    if (n_results) *n_results = 0;
+    std::lock_guard<std::mutex> sg(S->step_mu);
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (!S->exec || S->mlp_key != (const void*)S->mlp) {
+        int rc = capture_graph(S);
+        if (rc) return rc;
+    }
+    StepDesc& D = *S->h_desc;
+    D.n_open = D.n_chunks = D.n_close = 0;
+    D.n_units = 0;
+    D.open_prefix[0] = 0;
+    struct CloseRec {
+        Link* L;
+        uint32_t kq;
+        double t_arrival;
+        uint64_t slice;
+    };
+    std::vector<CloseRec> closes;
+    uint64_t pairs = 0;
+    for (Link* L : S->links) {
+        if (!L || L->state != L_ACTIVE || L->q.empty()) continue;
+        const Event& first = L->q.front();
+        if (first.end && L->open) {
+            // every chunk of this slice was scanned in an earlier step: close it now
+            CloseDesc& c = D.close[D.n_close++];
+            c.slot = (uint32_t)L->slot;
+            c.c0 = L->c0;
+            c.kq = first.kprime;
+            closes.push_back(CloseRec{L, first.kprime, first.t_arrival, L->t});
+            continue;
+        }
+        // open the slice if needed, then queue its chunks (stopping at its end)
+        if (!L->open) {
+            OpenDesc& o = D.open[D.n_open];
+            o.slot = (uint32_t)L->slot;
+            o.c0 = (uint32_t)(L->t % L->G.twok);
+            o.S = atp::preserve_spans(L->G, o.c0);
+            D.open_prefix[D.n_open + 1] = D.open_prefix[D.n_open] + S->n_atv * (o.S.nw0 + o.S.nw1);
+            D.n_open++;
+            L->open = true;
+            L->c0 = o.c0;
+        }
+        for (auto it = L->q.begin(); it != L->q.end() && !it->end; ++it) {
+            if (D.n_chunks == atp::kServeMaxChunks) break;
+            if (it->aip == nullptr) continue;  // already scanned in this step loop
+            ChunkDesc& cd = D.chunk[D.n_chunks++];
+            cd.aip = it->aip;
+            cd.bip = it->bip;
+            cd.n = it->n;
+            cd.unit0 = D.n_units;
+            cd.slot = (uint32_t)L->slot;
+            cd.c0 = L->c0;
+            cd.vec = ((reinterpret_cast<uintptr_t>(it->aip) | reinterpret_cast<uintptr_t>(it->bip)) & 15u) == 0;
+            D.n_units += (it->n + atp::kServeUnit - 1) / atp::kServeUnit;
+            pairs += it->n;
+            it->aip = nullptr;  // mark as handed to this step
+        }
+    }
+    lk.unlock();
+
+    const double t0 = now_ms();
+    hipError_t e = hipGraphLaunch(S->exec, S->s0);
+    if (e == hipSuccess) e = hipStreamSynchronize(S->s0);
+    const double t1 = now_ms();
+    if (e != hipSuccess) return AT_E_DEVICE;
+
+    lk.lock();
+    S->steps++;
+    S->last_step_ms = t1 - t0;
+    S->pairs_ingested += pairs;
+    // retire scanned chunks and closed slices
+    for (Link* L : S->links) {
+        if (!L || L->state != L_ACTIVE) continue;
+        while (!L->q.empty() && !L->q.front().end && L->q.front().aip == nullptr) {
+            L->q.pop_front();
+            L->consumed++;
+        }
+    }
+    uint32_t produced = 0;
+    for (uint32_t ci = 0; ci < closes.size(); ci++) {
+        const CloseRec& cr = closes[ci];
+        const atp::CloseOut& o = S->h_state->out[ci];
+        Result R{};
+        R.r.link = cr.L->id;
+        R.r.kprime = cr.kq;
+        R.r.slice = cr.slice;
+        R.r.restore_rc = o.rc;
+        R.r.n_out = o.rc == AT_E_BUDGET ? o.U : o.m;
+        R.r.n_cand = o.n_cand;
+        R.r.n_watch = o.n_hosts - o.n_cand;
+        R.r.latency_ms = t1 - cr.t_arrival;
+        R.r.step_ms = t1 - t0;
+        const bool have_mlp = S->mlp_key != nullptr;
+        for (uint32_t q = 0; q < o.n_hosts; q++) {
+            const uint64_t h = (uint64_t)o.host_off + q;
+            const double plain = S->h_est[h];
+            const double learned = have_mlp ? S->h_estl[h] : plain;
+            const uint8_t fl = S->h_flagsl[h] | (have_mlp ? 0 : (uint8_t)AT_F_FALLBACK);
+            if (q < o.n_cand) {
+                R.cand.push_back(S->h_hosts[h]);
+                R.cand_est.push_back(plain);
+                R.cand_learned.push_back(learned);
+                R.cand_flags.push_back(fl);
+            } else {
+                R.watch_plain.push_back(plain);
+                R.watch_learned.push_back(learned);
+                R.watch_flags.push_back(fl);
+            }
+        }
+        S->results.push_back(std::move(R));
+        Link* L = cr.L;
+        L->q.pop_front();  // the end event
+        L->consumed++;
+        L->t += 1;
+        L->open = false;
+        produced++;
+    }
+    if (n_results) *n_results = produced;
+    return AT_OK;
+}
+
+int at_serve_next_result(at_serve* S, at_serve_result* out, uint32_t* cand, double* cand_plain,
+                         double* cand_learned, uint8_t* cand_flags, uint32_t cand_cap, double* watch_plain,
+                         double* watch_learned, uint8_t* watch_flags, uint32_t watch_cap) {
+    if (!S || !out) return AT_E_INVAL;
+    std::lock_guard<std::mutex> g(S->mu);
+    if (S->results.empty()) return AT_E_STATE;
+    Result& R = S->results.front();
+    if (R.cand.size() > cand_cap || R.watch_plain.size() > watch_cap) return AT_E_OVERFLOW;
+    *out = R.r;
+    for (size_t i = 0; i < R.cand.size(); i++) {
+        if (cand) cand[i] = R.cand[i];
+        if (cand_plain) cand_plain[i] = R.cand_est[i];
+        if (cand_learned) cand_learned[i] = R.cand_learned[i];
+        if (cand_flags) cand_flags[i] = R.cand_flags[i];
+    }
+    for (size_t i = 0; i < R.watch_plain.size(); i++) {
+        if (watch_plain) watch_plain[i] = R.watch_plain[i];
+        if (watch_learned) watch_learned[i] = R.watch_learned[i];
+        if (watch_flags) watch_flags[i] = R.watch_flags[i];
+    }
+    S->results.pop_front();
+    return AT_OK;
+}
+
+int at_serve_stats(at_serve* S, uint64_t* out4) {
+    if (!S || !out4) return AT_E_INVAL;
+    std::lock_guard<std::mutex> g(S->mu);
+    out4[0] = S->steps;
+    out4[1] = S->pairs_ingested;
+    out4[2] = S->used_bytes;
+    out4[3] = S->waiting.size();
+    return AT_OK;
+}
+
+int at_serve_read_pool(at_serve* S, uint32_t link_id, uint8_t* host_out) {
+    if (!S || !host_out) return AT_E_INVAL;
+    std::lock_guard<std::mutex> sg(S->step_mu);
+    std::lock_guard<std::mutex> g(S->mu);
+    if (link_id >= S->links.size()) return AT_E_INVAL;
+    Link* L = S->links[link_id];
+    if (L->state != L_ACTIVE) return AT_E_STATE;
+    hipError_t e = hipMemcpyAsync(host_out, L->pool, S->n_atv << S->shape.log2g, hipMemcpyDeviceToHost, S->s0);
+    if (e == hipSuccess) e = hipStreamSynchronize(S->s0);
+    return e == hipSuccess ? AT_OK : AT_E_DEVICE;
+}
+
+}  // extern "C"

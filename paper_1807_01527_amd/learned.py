@@ -1,0 +1,209 @@
+"""Learned correction of the plain estimate: training set, training and evaluation.
+
+Everything on the path runs in the HIP library:
+- the traces are ingested by at_ingest_slice / at_close_slice;
+- the features come from at_features;
+- training runs at_mlp_train_step (bf16 matrix-core forward/backward + Adam);
+- inference runs at_estimate_learned.
+
+This module only orchestrates.  Labels are the exact distinct counts of the
+synthetic traces.
+
+    python -m paper_1807_01527_amd.learned --geom small --samples 1000000 --out weights/small.npy
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import math
+import os
+import sys
+import time
+from typing import Dict, Optional
+
+import numpy as np
+
+from . import traffic
+from .binding import MLP_NPARAM, AtPool, Mlp
+
+GEOMS = {
+    # the small configuration's literal pool: 2^20 ATs, k = 4
+    "small": dict(k=4, r=4, c=9, s=8, u=0, log2g=9, theta=1024.0),
+    # the realistic link's pool: 2^26 ATs, k = 10
+    "link": dict(k=10, r=4, c=9, s=7, u=3, log2g=12, theta=1024.0),
+    # the serving links' pools: 2^24 ATs, k from {5, 10, 30} (one network for all)
+    "serve": dict(k=30, r=4, c=9, s=8, u=1, log2g=12, theta=1024.0),
+}
+KS = {"serve": (5, 10, 30)}
+WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+
+
+def pool_ats(geom: dict) -> int:
+    return (1 << (geom["c"] + geom["u"])) * geom["r"] * (1 << geom["log2g"])
+
+
+def trace_shape(name: str):
+    from .traffic_gpu import TraceShape
+    g = GEOMS[name]
+    if name == "small":
+        return TraceShape(slices=g["k"], pool_ats=pool_ats(g), rows=g["r"], hosts=1 << 16, zipf_s=1.1)
+    if name == "serve":
+        return TraceShape(slices=g["k"], pool_ats=pool_ats(g), rows=g["r"], hosts=1 << 16, zipf_s=1.1,
+                          max_planted=200, bg_samples=400)
+    return TraceShape(slices=g["k"], pool_ats=pool_ats(g), rows=g["r"], hosts=1 << 22, zipf_s=1.2,
+                      lam_lo=0.3, lam_hi=3.0, max_planted=400, bg_samples=3000, hi=1 << 18)
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-uniform weights, zero biases; a small output layer so the network
+    starts near the plain estimate."""
+    rng = np.random.default_rng(seed)
+    lim = math.sqrt(6.0 / 64)
+    W1 = rng.uniform(-lim, lim, (64, 64))
+    W2 = rng.uniform(-lim, lim, (64, 64))
+    w3 = rng.uniform(-lim, lim, 64) * 0.1
+    return np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), w3, [0.0]]).astype(np.float32)
+
+
+def build_dataset(name: str, n_samples: int, seed: int = 1, log=print):
+    """(features [N, 64] float32, ln n [N] float32) as device tensors."""
+    import torch
+    from .traffic_gpu import make_trace
+    geom = GEOMS[name]
+    shape = trace_shape(name)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    X, T = [], []
+    have = 0
+    trace = 0
+    t0 = time.perf_counter()
+    while have < n_samples:
+        k = KS[name][trace % len(KS[name])] if name in KS else geom["k"]
+        aips, bips, hosts, counts = make_trace(dataclasses.replace(shape, slices=k), seed, trace, dev)
+        pool = AtPool(**{**geom, "k": k}, seed=seed * 100003 + trace)
+        for t in range(k):
+            if aips[t].numel():
+                pool.ingest(aips[t], bips[t])
+            pool.close(k)
+        if hosts.size:
+            hd = torch.from_numpy(hosts.view(np.int32)).to(dev)
+            feat = torch.empty((hosts.size, 64), dtype=torch.float32, device=dev)
+            pool.features(hd, feat)
+            X.append(feat)
+            T.append(torch.from_numpy(np.log(counts.astype(np.float64)).astype(np.float32)).to(dev))
+            have += hosts.size
+        pool.destroy()
+        trace += 1
+        if trace % 200 == 0:
+            log(f"  dataset {name}: {trace} traces, {have} samples, {time.perf_counter() - t0:.1f}s")
+    torch.cuda.synchronize()
+    return torch.cat(X)[:n_samples].contiguous(), torch.cat(T)[:n_samples].contiguous()
+
+
+def residual_target(X, T):
+    """The network predicts ln n minus the plain estimate's log feature."""
+    return (T - 16.0 * X[:, 61]).contiguous()
+
+
+def train(mlp: Mlp, X, T, epochs: int = 40, batch: int = 4096, lr: float = 2e-3, seed: int = 0, log=print):
+    """T holds ln n; the network is fit to its residual over 16*f[61]."""
+    import torch
+    n = X.shape[0]
+    T = residual_target(X, T)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    losses = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(X.device)
+        lr_ep = lr * (0.5 * (1 + math.cos(math.pi * ep / epochs)) * 0.95 + 0.05)
+        tot, cnt = 0.0, 0
+        for s in range(0, n - batch + 1, batch):
+            idx = perm[s:s + batch]
+            xb = X.index_select(0, idx).contiguous()
+            tb = T.index_select(0, idx).contiguous()
+            want = (s // batch) % 50 == 0
+            loss = mlp.train_step(xb, tb, lr_ep, want_loss=want)
+            if want:
+                tot += loss
+                cnt += 1
+        losses.append(tot / max(cnt, 1))
+        log(f"  epoch {ep + 1}/{epochs}: loss {losses[-1]:.5f} (lr {lr_ep:.2e})")
+    return losses
+
+
+def evaluate(name: str, mlp: Optional[Mlp], seeds=range(10)) -> Dict[str, float]:
+    """Mean relative error over the true super points (exact count >= theta
+    in the window) of the plain and the learned estimates, on traces of the
+    configuration's own traffic shape."""
+    import torch
+    geom = GEOMS[name]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    rel_p, rel_l, fb = [], [], 0
+    for sd in seeds:
+        k = KS[name][sd % len(KS[name])] if name in KS else geom["k"]
+        if name == "small":
+            tr = traffic.generate(traffic.config_small(seed=sd))
+        elif name == "serve":
+            cfg = traffic.config_small(seed=sd)
+            cfg.n_slices, cfg.pairs_per_slice = k, 1_000_000 // k * 4 // 4
+            tr = traffic.generate(cfg)
+        else:
+            tr = traffic.generate(traffic.config_link(seed=sd))
+        pool = AtPool(**{**geom, "k": k}, seed=sd)
+        for t in range(tr.n_slices):
+            pool.ingest(torch.from_numpy(tr.aip[t].view(np.int32)).to(dev),
+                        torch.from_numpy(tr.bip[t].view(np.int32)).to(dev))
+            pool.close(k)
+        lo = max(0, tr.n_slices - k)
+        h, n = traffic.window_counts(tr.aip[lo:], tr.bip[lo:], min_count=int(geom["theta"]))
+        if mlp is not None:
+            est_l, fl, plain = pool.estimate_learned(mlp, h)
+            rel_l.append(np.abs(est_l - n) / n)
+            fb += int(np.count_nonzero(fl & 4))
+        else:
+            plain, _ = pool.estimate_plain(h)
+        rel_p.append(np.abs(plain - n) / n)
+        pool.destroy()
+    out = {"plain": float(np.mean(np.concatenate(rel_p))), "hosts": int(sum(x.size for x in rel_p))}
+    if mlp is not None:
+        out["learned"] = float(np.mean(np.concatenate(rel_l)))
+        out["fallbacks"] = fb
+    return out
+
+
+def load_weights(name: str) -> Optional[np.ndarray]:
+    path = os.path.join(WEIGHTS_DIR, f"{name}.npy")
+    if not os.path.exists(path):
+        return None
+    p = np.load(path, allow_pickle=False).astype(np.float32)
+    return p if p.size == MLP_NPARAM else None
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--geom", choices=sorted(GEOMS), default="small")
+    ap.add_argument("--samples", type=int, default=1_000_000)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--eval-seeds", type=int, default=10)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+    log = lambda m: print(m, flush=True)  # noqa: E731
+    t0 = time.perf_counter()
+    X, T = build_dataset(args.geom, args.samples, seed=args.seed, log=log)
+    log(f"dataset: {X.shape[0]} samples in {time.perf_counter() - t0:.1f}s")
+    mlp = Mlp(init_params(args.seed))
+    t1 = time.perf_counter()
+    train(mlp, X, T, epochs=args.epochs, log=log)
+    torch.cuda.synchronize()
+    log(f"training: {time.perf_counter() - t1:.1f}s")
+    if args.out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        np.save(args.out, mlp.get_params())
+    res = evaluate(args.geom, mlp, seeds=range(args.eval_seeds))
+    log(f"evaluation ({args.geom} traffic, seeds 0..{args.eval_seeds - 1}): {res}")
+    return res
+
+
+if __name__ == "__main__":
+    sys.exit(0 if main() else 1)

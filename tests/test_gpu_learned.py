@@ -1,0 +1,40 @@
+"""The learned correction, trained on the GPU by the library's own kernels,
+lowers the mean relative error of the plain estimator over the true super
+points of the small configuration's traffic (window exact counts >= theta)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_01527_amd import binding
+    binding.load()
+    return torch
+
+
+def test_committed_weights_beat_plain(torch_cuda):
+    from paper_1807_01527_amd import learned
+    from paper_1807_01527_amd.binding import Mlp
+    w = learned.load_weights("small")
+    assert w is not None, "paper_1807_01527_amd/weights/small.npy missing"
+    res = learned.evaluate("small", Mlp(w), seeds=range(10, 16))
+    print(res)
+    assert res["hosts"] > 300
+    assert res["learned"] < 0.8 * res["plain"]
+
+
+def test_training_from_scratch_beats_plain(torch_cuda):
+    from paper_1807_01527_amd import learned
+    from paper_1807_01527_amd.binding import Mlp
+    X, T = learned.build_dataset("small", 200_000, seed=7, log=lambda m: None)
+    net = Mlp(learned.init_params(7))
+    losses = learned.train(net, X, T, epochs=40, log=lambda m: None)
+    assert losses[-1] < 0.5 * losses[0]
+    res = learned.evaluate("small", net, seeds=range(20, 24))
+    print(res)
+    assert res["learned"] < res["plain"]

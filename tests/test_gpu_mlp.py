@@ -1,0 +1,181 @@
+"""Learned correction on the GPU vs its CPU reference, through the C ABI.
+
+Features: bit-exact except f[61] (a log of the FP64 plain estimate, within one
+float32 ulp).  Network: same bf16 rounding points as the reference; the matrix
+cores accumulate in FP32 in their own order, so outputs and gradients agree to
+the tolerances stated below, derived from bf16's 2^-8 relative step.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+from paper_1807_01527_amd import traffic
+
+from ._parity import make_pair, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_01527_amd import binding
+    binding.load()
+    return torch
+
+
+def _dev_f32(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+@pytest.mark.parametrize("geom,tr_kw", [
+    (dict(k=4, r=4, c=9, s=8, u=0, log2g=9, theta=1024.0, seed=0), dict(seed=0)),
+    (dict(k=5, r=3, c=11, s=10, u=3, log2g=7, theta=64.0, seed=3), dict(seed=2, n_slices=9, pairs_per_slice=4000)),
+    (dict(k=13, r=4, c=8, s=8, u=1, log2g=4, theta=16.0, seed=4), dict(seed=3, n_slices=20, pairs_per_slice=2000)),
+])
+def test_features_match_oracle(torch_cuda, oracle_lib, geom, tr_kw):
+    torch = torch_cuda
+    if geom["log2g"] == 9:
+        tr = traffic.generate(traffic.config_small(seed=0))
+    else:
+        tr = traffic.generate(traffic.config_tiny(**tr_kw))
+    g, o = make_pair(geom, oracle_lib)
+    for t in range(tr.n_slices):
+        g.ingest(to_dev(tr.aip[t]), to_dev(tr.bip[t]))
+        o.ingest(tr.aip[t], tr.bip[t])
+        kp = 1 + t % geom["k"]
+        g.close(kp)
+        o.close(kp)
+    hosts = np.unique(np.concatenate([tr.planted_hosts, tr.aip[-1][:3000]]))
+    f_o = o.features(hosts)
+    feat = torch.empty((hosts.size, 64), dtype=torch.float32, device="cuda")
+    est = torch.empty(hosts.size, dtype=torch.float64, device="cuda")
+    fl = torch.empty(hosts.size, dtype=torch.uint8, device="cuda")
+    g.features(to_dev(hosts), feat, est, fl)
+    f_g = feat.cpu().numpy()
+    cols = [c for c in range(64) if c != 61]
+    assert np.array_equal(f_g[:, cols], f_o[:, cols])
+    ulp = np.spacing(np.abs(f_o[:, 61]).astype(np.float32))
+    assert np.all(np.abs(f_g[:, 61] - f_o[:, 61]) <= ulp)
+    e_o, fl_o, nat_o = o.estimate(hosts)
+    assert np.array_equal(fl.cpu().numpy(), fl_o)
+    assert np.allclose(est.cpu().numpy(), e_o, rtol=1e-12, atol=0, equal_nan=False)
+    # the histogram's prefix below k' is NAT(k')
+    kq = o.clock()["kq"]
+    assert np.array_equal(np.rint(f_o[:, :kq].astype(np.float64).sum(1) * g.g).astype(np.int64), nat_o)
+
+
+def _rand_problem(seed, n):
+    rng = np.random.default_rng(seed)
+    p = ref.init_params(seed) + rng.normal(0, 0.05, ref.NPARAM)
+    p[ref.OFF_B1:ref.OFF_W2] = rng.normal(0, 0.3, 64)
+    p[ref.OFF_B2:ref.OFF_W3] = rng.normal(0, 0.3, 64)
+    X = rng.random((n, 64)).astype(np.float32)
+    X[:, 40:] *= rng.random((n, 24)) < 0.3
+    t = rng.uniform(2.8, 12.5, n).astype(np.float32)
+    return p.astype(np.float32), X, t
+
+
+@pytest.mark.parametrize("n", [1, 63, 1000, 4096, 5000])
+def test_forward_matches_reference(torch_cuda, n):
+    torch = torch_cuda
+    from paper_1807_01527_amd.binding import Mlp
+    p, X, _ = _rand_problem(n, n)
+    net = Mlp(p)
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    net.forward(_dev_f32(torch, X), y)
+    y_g = y.cpu().numpy()
+    y_r, _ = ref.forward_bf16(p, X)
+    d = np.abs(y_g.astype(np.float64) - y_r)
+    # FP32 accumulation order may move a hidden unit by one bf16 step (2^-8
+    # relative) now and then; the output moves by far less than that scale
+    assert d.max() <= 2e-2 * (1 + np.abs(y_r).max()), d.max()
+    assert np.median(d) <= 1e-5 * (1 + np.abs(y_r).max())
+    np.testing.assert_array_equal(net.get_params(), p)
+
+
+@pytest.mark.parametrize("n", [512, 3000, 4096])
+def test_gradients_match_reference(torch_cuda, n):
+    torch = torch_cuda
+    from paper_1807_01527_amd.binding import Mlp
+    p, X, t = _rand_problem(100 + n, n)
+    net = Mlp(p)
+    grad = torch.empty(ref.NPARAM, dtype=torch.float32, device="cuda")
+    loss = net.grad(_dev_f32(torch, X), _dev_f32(torch, t), grad)
+    g_g = grad.cpu().numpy().astype(np.float64)
+    g_r, loss_r = ref.backward_bf16(p, X, t)
+    assert abs(loss - loss_r) <= 1e-3 * loss_r
+    sl = {"W1": slice(ref.OFF_W1, ref.OFF_B1), "b1": slice(ref.OFF_B1, ref.OFF_W2),
+          "W2": slice(ref.OFF_W2, ref.OFF_B2), "b2": slice(ref.OFF_B2, ref.OFF_W3),
+          "w3": slice(ref.OFF_W3, ref.OFF_B3), "b3": slice(ref.OFF_B3, ref.OFF_B3 + 1)}
+    for name, s in sl.items():
+        num = np.linalg.norm(g_g[s] - g_r[s])
+        den = np.linalg.norm(g_r[s])
+        assert num <= 1e-2 * den + 1e-7, (name, num, den)
+
+
+def test_adam_matches_reference(torch_cuda):
+    torch = torch_cuda
+    from paper_1807_01527_amd.binding import Mlp
+    rng = np.random.default_rng(7)
+    p = ref.init_params(7).astype(np.float32)
+    net = Mlp(p)
+    m = np.zeros(ref.NPARAM, np.float32)
+    v = np.zeros(ref.NPARAM, np.float32)
+    pr = p.copy()
+    for step in range(1, 4):
+        g = (rng.standard_normal(ref.NPARAM) * 0.01).astype(np.float32)
+        net.apply_grad(_dev_f32(torch, g), 1e-3)
+        pr, m, v = ref.adam(pr, m, v, g, step, 1e-3)
+        np.testing.assert_allclose(net.get_params(), pr, rtol=2e-7, atol=1e-9)
+
+
+def test_training_reduces_loss(torch_cuda):
+    torch = torch_cuda
+    from paper_1807_01527_amd.binding import Mlp
+    rng = np.random.default_rng(9)
+    n = 8192
+    X = rng.random((n, 64)).astype(np.float32)
+    t = (4 + 6 * X[:, 0] + 2 * X[:, 1] * X[:, 2]).astype(np.float32)   # a smooth target
+    net = Mlp(ref.init_params(1))
+    xd, td = _dev_f32(torch, X), _dev_f32(torch, t)
+    first = net.grad(xd, td)
+    for _ in range(300):
+        net.train_step(xd[:4096], td[:4096], 3e-3)
+        net.train_step(xd[4096:], td[4096:], 3e-3)
+    last = net.grad(xd, td)
+    assert last < 0.05 * first, (first, last)
+
+
+def test_learned_estimate_and_fallback(torch_cuda, oracle_lib):
+    """With a constant network (all weights 0, output bias b3) the learned
+    estimate is exp(b3 + 16*f[61]) inside the trained range, else the plain
+    estimate with AT_F_FALLBACK."""
+    torch = torch_cuda
+    from paper_1807_01527_amd.binding import Mlp
+    tr = traffic.generate(traffic.config_tiny(seed=5, n_slices=3, pairs_per_slice=20000, hosts=1 << 10))
+    geom = dict(k=3, r=4, c=8, s=8, u=1, log2g=8, theta=200.0, seed=1)
+    g, o = make_pair(geom, oracle_lib)
+    for t in range(3):
+        g.ingest(to_dev(tr.aip[t]), to_dev(tr.bip[t]))
+        g.close(3)
+    hosts = np.unique(tr.aip[-1][:500])
+    feat = torch.empty((hosts.size, 64), dtype=torch.float32, device="cuda")
+    g.features(to_dev(hosts), feat)
+    f61 = feat.cpu().numpy()[:, 61].astype(np.float64)
+    e_plain, f_plain, _ = g.estimate(hosts)
+    for b3 in (0.0, -0.7, 0.4, -30.0, 30.0):
+        p = np.zeros(ref.NPARAM, np.float32)
+        p[ref.OFF_B3] = b3
+        net = Mlp(p)
+        est, fl, plain = g.estimate_learned(net, hosts)
+        np.testing.assert_array_equal(plain, e_plain)
+        z = np.float64(np.float32(b3)) + 16.0 * f61
+        inside = (z >= np.log(16.0) - 0.5) & (z <= np.log(262144.0) + 0.5)
+        np.testing.assert_allclose(est[inside], np.exp(z[inside]), rtol=1e-14)
+        np.testing.assert_array_equal(est[~inside], plain[~inside])
+        assert np.array_equal((fl & 4) != 0, ~inside)
+        assert np.array_equal((fl & 8) != 0, est >= geom["theta"])
+        assert np.array_equal(fl & 3, f_plain & 3)

@@ -1,0 +1,187 @@
+"""Streaming server: every link's results in the mix equal the same link
+served alone and the single-link API run eagerly on the same chunks.
+
+Integers (restore outcome, candidate lists, pools) must be bit-exact, FP64
+estimates equal to 1e-12 relative.  Many steps are run, so every comparison
+also checks a graph replay against eager execution.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+from paper_1807_01527_amd import traffic
+
+from ._parity import to_dev
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = dict(r=4, c=9, s=8, u=1, log2g=10, theta=512.0)
+CAND_CAP = 2048
+WATCH_CAP = 64
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_01527_amd import binding
+    binding.load()
+    return torch
+
+
+def _link_events(lid_seed: int, k: int, n_slices: int, rng):
+    """Uneven slices (some empty) cut into ragged chunks; returns the device
+    tensors to keep alive, the event list and the watch hosts."""
+    tr = traffic.generate(traffic.config_tiny(seed=lid_seed, n_slices=n_slices, pairs_per_slice=60000,
+                                              hosts=1 << 11, planted=4, lo=600, hi=3000))
+    keep, events = [], []
+    for t in range(n_slices):
+        n = 0 if rng.random() < 0.15 else int(rng.integers(1, tr.aip[t].size + 1))
+        a, b = tr.aip[t][:n], tr.bip[t][:n]
+        if n:
+            da, db = to_dev(a), to_dev(b)
+            keep += [da, db]
+            cuts = np.sort(rng.integers(0, n + 1, int(rng.integers(0, 4))))
+            bounds = [0, *cuts.tolist(), n]
+            for lo, hi in zip(bounds[:-1], bounds[1:]):
+                if hi > lo:
+                    events.append(("chunk", da[lo:hi], db[lo:hi], a[lo:hi], b[lo:hi]))
+        events.append(("end", int(rng.integers(1, k + 1))))
+    watch = np.unique(np.concatenate([tr.planted_hosts, tr.aip[0][:40]]))[:WATCH_CAP]
+    return keep, events, watch
+
+
+def _reference(k, seed, events, watch, net):
+    """The single-link API, eager, on the same chunks."""
+    from paper_1807_01527_amd.binding import AtPool
+    g = AtPool(k=k, seed=seed, **SHAPE)
+    out = []
+    for ev in events:
+        if ev[0] == "chunk":
+            g.ingest(ev[1], ev[2])
+            continue
+        g.close(ev[1])
+        rc, cand, _, _, m = g.restore(cap=CAND_CAP)
+        rec = dict(restore_rc=rc, n_out=m, cand=cand if rc == 0 else np.zeros(0, np.uint32))
+        if rc == 0 and cand.size:
+            rec["cand_learned"], rec["cand_flags"], rec["cand_plain"] = g.estimate_learned(net, cand)
+        else:
+            rec["cand_learned"] = rec["cand_plain"] = np.zeros(0)
+            rec["cand_flags"] = np.zeros(0, np.uint8)
+        rec["watch_learned"], rec["watch_flags"], rec["watch_plain"] = g.estimate_learned(net, watch)
+        out.append(rec)
+    pool = g.read_pool()
+    g.destroy()
+    return out, pool
+
+
+def _serve(links, net, seed=0, steps_every=3):
+    """Feed every link's events interleaved at random into one server."""
+    from paper_1807_01527_amd.binding import Server
+    srv = Server(hbm_budget=1 << 34, max_links=16, cand_cap=CAND_CAP, watch_cap=WATCH_CAP, **SHAPE)
+    srv.set_mlp(net)
+    ids = []
+    for ln in links:
+        lid, adm = srv.open_link(ln["k"], ln["seed"])
+        assert adm
+        srv.set_watch(lid, ln["watch"])
+        ids.append(lid)
+    rng = np.random.default_rng(seed)
+    cursor = [0] * len(links)
+    results = {lid: [] for lid in ids}
+    n_sub = 0
+    while any(c < len(ln["events"]) for c, ln in zip(cursor, links)):
+        i = int(rng.integers(0, len(links)))
+        if cursor[i] >= len(links[i]["events"]):
+            continue
+        ev = links[i]["events"][cursor[i]]
+        cursor[i] += 1
+        rc = srv.submit(ids[i], ev[1], ev[2]) if ev[0] == "chunk" else srv.end_slice(ids[i], ev[1])
+        assert rc == 0
+        n_sub += 1
+        if n_sub % steps_every == 0:
+            srv.step()
+            for r in srv.results():
+                results[r["link"]].append(r)
+    for _ in range(4 * max(len(ln["events"]) for ln in links)):
+        if all(srv.link_state(lid)[2] == 0 for lid in ids):
+            break
+        srv.step()
+        for r in srv.results():
+            results[r["link"]].append(r)
+    pools = {lid: srv.read_pool(lid) for lid in ids}
+    stats = srv.stats()
+    srv.destroy()
+    return ids, results, pools, stats
+
+
+def _compare(got, want, where):
+    assert len(got) == len(want), where
+    for s, (g, w) in enumerate(zip(got, want)):
+        tag = f"{where} slice {s}"
+        assert g["slice"] == s, tag
+        assert g["restore_rc"] == w["restore_rc"], tag
+        assert g["n_out"] == w["n_out"], tag
+        assert np.array_equal(g["cand"], w["cand"]), tag
+        for key in ("cand_plain", "cand_learned", "watch_plain", "watch_learned"):
+            a, b = np.asarray(g[key]), np.asarray(w[key])
+            assert a.shape == b.shape, (tag, key)
+            assert np.array_equal(np.isfinite(a), np.isfinite(b)), (tag, key)
+            fin = np.isfinite(b)
+            assert np.all(np.abs(a[fin] - b[fin]) <= 1e-12 * np.abs(b[fin])), (tag, key)
+        assert np.array_equal(g["cand_flags"], w["cand_flags"]), tag
+        assert np.array_equal(g["watch_flags"], w["watch_flags"]), tag
+        assert g["latency_ms"] > 0
+
+
+def _links(n, rng, n_slices=7):
+    links, keep = [], []
+    for i in range(n):
+        k = [5, 10, 30][i % 3]
+        kp, ev, watch = _link_events(100 + i, k, n_slices, rng)
+        keep += kp
+        links.append(dict(k=k, seed=1000 + i, events=ev, watch=watch))
+    return links, keep
+
+
+def test_mix_equals_alone_and_single_link_api(torch_cuda):
+    from paper_1807_01527_amd.binding import Mlp
+    rng = np.random.default_rng(0)
+    links, keep = _links(8, rng)
+    net = Mlp(ref.init_params(5).astype(np.float32) * np.float32(0.5))
+    ids, res, pools, stats = _serve(links, net, seed=1)
+    assert stats["steps"] > 10 and stats["waiting"] == 0
+    for i, (lid, ln) in enumerate(zip(ids, links)):
+        want, pool = _reference(ln["k"], ln["seed"], ln["events"], ln["watch"], net)
+        _compare(res[lid], want, f"link {i} in the mix")
+        assert np.array_equal(pools[lid], pool), f"link {i}: pool differs"
+    # one link alone in its own server gives the same results as in the mix
+    ids1, res1, pools1, _ = _serve([links[2]], net, seed=7, steps_every=1)
+    _compare(res1[ids1[0]], res[ids[2]], "link 2 alone vs mix")
+    assert np.array_equal(pools1[ids1[0]], pools[ids[2]])
+
+
+def test_admission_by_budget(torch_cuda):
+    from paper_1807_01527_amd.binding import AT_E_STATE, Server
+    probe = Server(hbm_budget=1 << 34, max_links=4, cand_cap=256, watch_cap=8, **SHAPE)
+    pool_bytes = probe.pool_bytes
+    probe.destroy()
+    srv = Server(hbm_budget=int(2.5 * pool_bytes), max_links=8, cand_cap=256, watch_cap=8, **SHAPE)
+    got = [srv.open_link(5, s) for s in range(4)]
+    assert [a for _, a in got] == [True, True, False, False]
+    assert srv.stats()["waiting"] == 2
+    a = to_dev(np.arange(64, dtype=np.uint32))
+    assert srv.submit(got[2][0], a, a) == AT_E_STATE
+    assert srv.submit(got[0][0], a, a) == 0
+    assert srv.end_slice(got[0][0], 5) == 0
+    srv.step()
+    srv.step()
+    assert [r["link"] for r in srv.results()] == [got[0][0]]
+    srv.close_link(got[0][0])                        # frees a pool: the first waiting link gets it
+    assert srv.link_state(got[2][0])[0] == 1 and srv.link_state(got[3][0])[0] == 0
+    assert srv.stats()["waiting"] == 1
+    assert srv.submit(got[2][0], a, a) == 0
+    srv.close_link(got[1][0])
+    assert srv.link_state(got[3][0])[0] == 1 and srv.stats()["waiting"] == 0
+    srv.destroy()
