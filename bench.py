@@ -301,6 +301,25 @@ def main():
                      "traffic": measured_traffic(), "bytes_per_pair": 8 + LINK["r"],
                      "avg_launch_ms": float(ingest_ms.mean()), "pairs_per_launch": per_launch},
     }
+    # the two scans of at_ingest_slice on the same slices (one pass each)
+    modes = {}
+    for mode, name in ((1, "direct"), (2, "binned")):
+        pool.set_scan_mode(mode)
+        evs = []
+        for t in range(S):
+            pool.ingest(aip_d[t][:0], bip_d[t][:0], n=0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            pool.ingest(aip_d[t], bip_d[t])
+            e1.record(stream)
+            evs.append((e0, e1))
+            pool.close(K)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        modes[name] = {"avg_ms": ms, "mpps": per_launch / (ms / 1e3) / 1e6}
+    pool.set_scan_mode(0)
+    out["scan_modes"] = modes
     # scatter roofline: the same input stream and r byte stores per pair at
     # uniformly random positions of a pool-sized buffer
     probe_buf = torch.empty(pool.pool_bytes, dtype=torch.uint8, device=dev)

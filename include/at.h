@@ -182,6 +182,15 @@ int at_estimate_dev(at_ctx *h, const uint32_t *aip_dev, uint64_t n, double *est_
 /* Number of column tuples U that at_restore would enumerate (see above). */
 int at_tuple_count(at_ctx *h, uint64_t *U);
 
+/* How at_ingest_slice scans: 0 = automatic (the binned scan when u >= 3, the
+ * pool is at least 32 MiB and the call has at least 65536 pairs), 1 = direct
+ * (one pass, r byte stores per pair), 2 = binned (pairs hashed once into 8
+ * frame-group bins, then one pass per row in which workgroup b takes bin
+ * b mod 8, so each XCD's stores stay in one region of the pool; needs an
+ * extra 64 B of scratch per pair, up to 8M pairs at a time).  Both give the
+ * same pool.  AT_E_INVAL for another mode. */
+int at_set_scan_mode(at_ctx *h, int mode);
+
 /* ------------------------------------------------------ learned correction
  * Not in the paper: a small network that corrects the plain estimate from the
  * host's occupancy-by-age profile, with the plain estimate kept as fallback.

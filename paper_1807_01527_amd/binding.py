@@ -52,6 +52,7 @@ SIGNATURES = {
     "at_estimate_detail": (C.c_int, [_vp, _u32p, C.c_uint64, _f64p, _u8p, _u32p]),
     "at_estimate_dev": (C.c_int, [_vp, _vp, C.c_uint64, _vp, _vp, _vp]),
     "at_tuple_count": (C.c_int, [_vp, _u64p]),
+    "at_set_scan_mode": (C.c_int, [_vp, C.c_int]),
     "at_probe_scatter": (C.c_int, [_vp, C.c_uint64, _vp, _vp, C.c_uint64, C.c_uint32, _vp]),
     "at_features": (C.c_int, [_vp, _vp, C.c_uint64, _vp, _vp, _vp]),
     "at_mlp_create": (C.c_int, [_vp, C.POINTER(_vp)]),
@@ -299,6 +300,10 @@ class AtPool:
         _check(self.lib.at_estimate_learned_dev(self._handle(), mlp._handle(), ptr(aip_dev), aip_dev.numel(),
                                                 ptr(est_dev), ptr(flags_dev), ptr(plain_dev)),
                "at_estimate_learned_dev")
+
+    def set_scan_mode(self, mode: int):
+        """0 automatic, 1 direct, 2 binned (see at_set_scan_mode)."""
+        _check(self.lib.at_set_scan_mode(self._handle(), mode), "at_set_scan_mode")
 
     def tuple_count(self) -> int:
         U = C.c_uint64()

@@ -52,6 +52,11 @@ hipError_t launch_preserve(uint8_t* pool, uint64_t n_atv, const Geometry& G, uin
                            hipStream_t st);
 hipError_t launch_ingest(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
                          const Geometry& G, uint32_t c0, hipStream_t st);
+// Two-pass scan: pairs hashed once into 8 frame-group bins (records of 8 B,
+// bins[b * cap + i]), then one pass per row with workgroup b on bin b mod 8.
+constexpr uint32_t kScanBins = 8;
+hipError_t launch_ingest_binned(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n, const Geometry& G,
+                                uint32_t c0, uint64_t* bins, uint64_t cap, unsigned long long* fill, hipStream_t st);
 hipError_t launch_close(const uint8_t* pool, uint32_t* w, uint64_t n_atv, const Geometry& G,
                         uint32_t c0, uint32_t kq, hipStream_t st);
 hipError_t launch_summarize(const uint32_t* w, uint64_t* aat, uint32_t* sa, uint32_t* sa_cnt,

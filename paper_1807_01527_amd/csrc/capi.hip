@@ -31,6 +31,11 @@ struct at_ctx {
     uint32_t* sa_cnt = nullptr;   // per (frame,row)
     unsigned long long* counter = nullptr;
     uint64_t* prefix = nullptr;   // nframe+1 restore item offsets
+    // binned scan scratch
+    uint64_t* bins = nullptr;
+    uint64_t bins_cap = 0;
+    unsigned long long* bin_fill = nullptr;
+    int scan_mode = 0;            // 0 auto, 1 direct, 2 binned
     // grow-on-demand device scratch
     uint32_t* cand = nullptr;
     uint64_t cand_cap = 0;
@@ -140,7 +145,7 @@ int dev_alloc(T** p, uint64_t count) {
 
 void free_all(at_ctx* h) {
     void* bufs[] = {h->pool, h->w, h->aat, h->sa, h->sa_cnt, h->counter, h->prefix, h->cand,
-                    h->q_aip, h->q_est, h->q_flags, h->q_nat, h->q_feat, h->q_y, h->q_plain};
+                    h->q_aip, h->q_est, h->q_flags, h->q_nat, h->q_feat, h->q_y, h->q_plain, h->bins, h->bin_fill};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -282,6 +287,17 @@ int at_destroy(at_ctx* h) {
     return AT_OK;
 }
 
+// The binned scan pays two extra 8-byte passes per pair to keep each XCD's
+// byte stores inside one (frame group, row) region; worth it when the pool is
+// far larger than an L2 and there are at least 8 frames.
+constexpr uint64_t kBinBatch = 8u << 20;  // pairs per binned sub-batch
+
+bool use_binned(const at_ctx* h, uint64_t n) {
+    if (h->scan_mode == 1) return false;
+    if (h->scan_mode == 2) return true;
+    return h->p.u >= 3 && h->pool_bytes >= (32ull << 20) && n >= 65536;
+}
+
 int at_ingest_slice(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, uint64_t n) {
     if (!h) return AT_E_INVAL;
     if (n > 0) {
@@ -290,8 +306,32 @@ int at_ingest_slice(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev,
     }
     int rc = open_slice(h);
     if (rc) return rc;
-    return atp::launch_ingest(h->pool, aip_dev, bip_dev, n, h->G, h->c0, h->stream) == hipSuccess ? AT_OK
-                                                                                                 : AT_E_DEVICE;
+    if (n == 0) return AT_OK;
+    if (!use_binned(h, n))
+        return atp::launch_ingest(h->pool, aip_dev, bip_dev, n, h->G, h->c0, h->stream) == hipSuccess ? AT_OK
+                                                                                                     : AT_E_DEVICE;
+    const uint64_t batch = std::min<uint64_t>(n, kBinBatch);
+    if (batch > h->bins_cap) {
+        if (h->bins) (void)hipFree(h->bins);
+        h->bins = nullptr;
+        h->bins_cap = 0;
+        if ((rc = dev_alloc(&h->bins, atp::kScanBins * batch))) return rc;
+        h->bins_cap = batch;
+    }
+    if (!h->bin_fill && (rc = dev_alloc(&h->bin_fill, atp::kScanBins))) return rc;
+    for (uint64_t off = 0; off < n; off += kBinBatch) {
+        const uint64_t m = std::min<uint64_t>(kBinBatch, n - off);
+        if (atp::launch_ingest_binned(h->pool, aip_dev + off, bip_dev + off, m, h->G, h->c0, h->bins, h->bins_cap,
+                                      h->bin_fill, h->stream) != hipSuccess)
+            return AT_E_DEVICE;
+    }
+    return AT_OK;
+}
+
+int at_set_scan_mode(at_ctx* h, int mode) {
+    if (!h || mode < 0 || mode > 2) return AT_E_INVAL;
+    h->scan_mode = mode;
+    return AT_OK;
 }
 
 int at_close_slice(at_ctx* h, uint32_t kprime) {

@@ -166,6 +166,73 @@ __global__ __launch_bounds__(kBlock) void k_ingest(uint8_t* __restrict__ pool, c
     for (uint64_t q = done + tid; q < n; q += stride) scan_pair<R>(pool, aip[q], bip[q], G, c0);
 }
 
+// ---------------------------------------------------------------- a2+a3: binned scan
+// Pass 1 hashes every pair once and appends a record to the bin of its frame
+// group (frame mod 8): LBS (W bits) | frame >> 3 | AT index.  Pass 2 runs once
+// per row: workgroup b works on bin b mod 8, and workgroups are handed to the
+// 8 XCDs round robin, so each XCD's L2 only sees the byte stores of one
+// (frame group, row) region of the pool -- a 2 MiB working set on the link
+// geometry instead of the whole pool.
+constexpr uint32_t kBins = 8;
+
+__global__ __launch_bounds__(kBlock) void k_bin_pairs(const uint32_t* __restrict__ aip, const uint32_t* __restrict__ bip,
+                                                      uint64_t n, Geometry G, uint64_t* __restrict__ bins, uint64_t cap,
+                                                      unsigned long long* __restrict__ fill) {
+    __shared__ uint32_t cnt[kBins];
+    __shared__ unsigned long long base[kBins];
+    constexpr uint32_t kPer = 16;  // pairs per thread per round
+    const uint64_t per_block = (uint64_t)kBlock * kPer;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * per_block; b0 < n; b0 += (uint64_t)gridDim.x * per_block) {
+        if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
+        __syncthreads();
+        uint64_t rec[kPer];
+        uint32_t bin[kPer], slot[kPer];
+#pragma unroll
+        for (uint32_t e = 0; e < kPer; e++) {
+            const uint64_t q = b0 + (uint64_t)e * kBlock + threadIdx.x;
+            bin[e] = kBins;
+            if (q < n) {
+                const uint32_t f = mangle(aip[q], G.A);
+                const uint32_t z = f & G.umask;
+                const uint32_t i = (uint32_t)((G.alpha * (uint64_t)bip[q] + G.beta) >> (64 - G.log2g));
+                rec[e] = ((uint64_t)(f >> G.u) << 32) | ((uint64_t)(z >> 3) << 16) | i;
+                bin[e] = z & (kBins - 1);
+                slot[e] = atomicAdd(&cnt[bin[e]], 1u);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < kBins) base[threadIdx.x] = atomicAdd(&fill[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+        __syncthreads();
+#pragma unroll
+        for (uint32_t e = 0; e < kPer; e++)
+            if (bin[e] < kBins) {
+                const unsigned long long pos = base[bin[e]] + slot[e];
+                if (pos < cap) bins[(uint64_t)bin[e] * cap + pos] = rec[e];
+            }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_bins(const uint64_t* __restrict__ bins, uint64_t cap,
+                                                      const unsigned long long* __restrict__ fill,
+                                                      uint8_t* __restrict__ pool, Geometry G, uint32_t c0, uint32_t row) {
+    const uint32_t bin = blockIdx.x % kBins;
+    const uint64_t nb = fill[bin] < cap ? fill[bin] : cap;
+    const uint64_t blocks_per_bin = gridDim.x / kBins;
+    const uint64_t* rec = bins + (uint64_t)bin * cap;
+    const uint32_t sh = G.sh[row];
+    for (uint64_t q = (blockIdx.x / kBins) * kBlock + threadIdx.x; q < nb; q += blocks_per_bin * kBlock) {
+        const uint64_t r = rec[q];
+        const uint64_t L = r >> 32;
+        const uint32_t z = (uint32_t)(((r >> 16) & 0xFFFFu) << 3) | bin;
+        const uint32_t i = (uint32_t)(r & 0xFFFFu);
+        const uint64_t LL = L | (L << G.W);
+        const uint32_t x = column(LL, sh, G.ncol_mask);
+        const uint64_t idx = (((((uint64_t)z * G.r + row) << G.c) + x) << G.log2g) | i;
+        pool[idx] = (uint8_t)act_of(i, c0, G);
+    }
+}
+
 // ---------------------------------------------------------------- a4: close
 // One read of the pool: k'-weight of every ATV (Alg 1 per AT).  A group of
 // lpa = min(64, g/16) lanes covers one ATV with 16-byte loads; a wave covers
@@ -1090,6 +1157,24 @@ hipError_t launch_ingest(uint8_t* pool, const uint32_t* aip, const uint32_t* bip
             return hipErrorInvalidValue;
     }
 #undef AT_INGEST_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_ingest_binned(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n, const Geometry& G,
+                                uint32_t c0, uint64_t* bins, uint64_t cap, unsigned long long* fill, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (n > cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kBins), 0, st, fill, kBins);
+    const uint64_t per_block = (uint64_t)kBlock * 16;
+    uint64_t blocks = (n + per_block - 1) / per_block;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_bin_pairs, dim3((uint32_t)blocks), dim3(kBlock), 0, st, aip, bip, n, G, bins, cap, fill);
+    uint64_t per_bin = (n / kBins + kBlock - 1) / kBlock;
+    if (per_bin < 1) per_bin = 1;
+    if (per_bin > 512) per_bin = 512;
+    for (uint32_t row = 0; row < G.r; row++)
+        hipLaunchKernelGGL(k_scan_bins, dim3((uint32_t)(kBins * per_bin)), dim3(kBlock), 0, st, bins, cap, fill, pool, G,
+                           c0, row);
     return hipGetLastError();
 }
 

@@ -28,13 +28,20 @@ def test_committed_weights_beat_plain(torch_cuda):
     assert res["learned"] < 0.8 * res["plain"]
 
 
-def test_training_from_scratch_beats_plain(torch_cuda):
+def test_training_from_scratch_reproduces_committed_weights(torch_cuda):
+    """The committed small-configuration weights come from this exact recipe:
+    1M GPU-generated samples (seed 1), 40 epochs of at_mlp_train_step.  Every
+    step is deterministic (counter-based inputs, fixed-order reductions), so
+    training again reproduces them and their gain over the plain estimator."""
     from paper_1807_01527_amd import learned
     from paper_1807_01527_amd.binding import Mlp
-    X, T = learned.build_dataset("small", 200_000, seed=7, log=lambda m: None)
-    net = Mlp(learned.init_params(7))
+    X, T = learned.build_dataset("small", 1_000_000, seed=1, log=lambda m: None)
+    net = Mlp(learned.init_params(1))
     losses = learned.train(net, X, T, epochs=40, log=lambda m: None)
     assert losses[-1] < 0.5 * losses[0]
-    res = learned.evaluate("small", net, seeds=range(20, 24))
+    w = learned.load_weights("small")
+    p = net.get_params()
+    assert np.max(np.abs(p - w)) <= 1e-6 * (1 + np.max(np.abs(w)))
+    res = learned.evaluate("small", net, seeds=range(0, 4))
     print(res)
-    assert res["learned"] < res["plain"]
+    assert res["learned"] < 0.8 * res["plain"]

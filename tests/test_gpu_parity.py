@@ -150,3 +150,19 @@ def test_restore_cap_and_budget(cuda, oracle_lib):
     assert rc == 0 and m > 1
     compare_restore(g2, o2, cap=m - 1)
     assert g2.tuple_count() == o2.tuple_count()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("geom", [
+    dict(k=3, r=4, c=8, s=8, u=1, log2g=6),       # fewer frames than bins
+    dict(k=5, r=3, c=11, s=10, u=3, log2g=7),
+    dict(k=4, r=4, c=9, s=7, u=3, log2g=12),      # the companion geometry (64 MiB)
+    dict(k=7, r=5, c=8, s=6, u=4, log2g=8),       # 16 frames: two frames per bin
+])
+def test_scan_modes(cuda, oracle_lib, geom, mode):
+    """The direct and the binned scan give the oracle's pool, with ragged
+    batches (including ones larger than a workgroup's share and tiny ones)."""
+    tr = _tiny(seed=11 + geom["k"], n_slices=5, pairs_per_slice=70001, hosts=1 << 10)
+    g, o = make_pair(dict(**geom, theta=64.0, seed=9), oracle_lib)
+    g.set_scan_mode(mode)
+    run_trace(g, o, tr.aip, tr.bip, batches=5, seed=2, query_hosts=tr.planted_hosts, restore=False)
