@@ -20,7 +20,7 @@ struct oat {
     uint32_t blk_a;   /* ATs in each of the first 2k-1 blocks */
     uint32_t T;       /* super-ATV threshold (integer)        */
     uint64_t n_atv, pool_size;
-    uint8_t *at;
+    uint16_t *at;     /* one 16-bit word per AT: values 0..2k, 2k <= 65534 */
     uint64_t t;       /* index of the current (or next) slice */
     int open;         /* slice t has been opened              */
     int queryable;    /* a closed window is held in the pool  */
@@ -189,7 +189,7 @@ int oat_create(const oat_params *p, oat **out)
     if (!p || !out) return OAT_E_INVAL;
     *out = NULL;
     uint32_t W = 32 - p->u;
-    if (p->u >= 32 || p->k < 1 || p->k > 127 || p->r < 1 || p->r > 64) return OAT_E_INVAL;
+    if (p->u >= 32 || p->k < 1 || p->k > 32767 || p->r < 1 || p->r > 64) return OAT_E_INVAL;
     if (p->s < 1 || p->s > p->c || p->c > W || p->c > 24) return OAT_E_INVAL;
     if (p->c + p->s * (p->r - 1) < W) return OAT_E_INVAL;       /* completeness */
     if (p->c * p->r <= W) return OAT_E_INVAL;                   /* redundancy   */
@@ -222,7 +222,7 @@ int oat_create(const oat_params *p, oat **out)
     o->T = (uint32_t)Tc;
     o->n_atv = (uint64_t)o->nframe * p->r * o->ncol;
     o->pool_size = o->n_atv * o->g;
-    o->at = (uint8_t *)malloc(o->pool_size);
+    o->at = (uint16_t *)malloc(o->pool_size * sizeof(uint16_t));
     o->w = (uint32_t *)calloc(o->n_atv, sizeof(uint32_t));
     o->aat = (uint64_t *)calloc((size_t)o->nframe * p->r, sizeof(uint64_t));
     o->super = (uint8_t *)calloc(o->n_atv, 1);
@@ -231,7 +231,7 @@ int oat_create(const oat_params *p, oat **out)
         return OAT_E_NOMEM;
     }
     /* InitAT: every AT starts inactive (value 2k) */
-    memset(o->at, (int)(2 * p->k), o->pool_size);
+    for (uint64_t q = 0; q < o->pool_size; q++) o->at[q] = (uint16_t)(2 * p->k);
     o->t = 0;
     o->open = 0;
     o->queryable = 0;
@@ -256,9 +256,9 @@ static void open_slice(oat *o)
     uint32_t k = o->p.k;
     o->c0 = (uint32_t)(o->t % (2 * k));
     for (uint64_t v = 0; v < o->n_atv; v++) {
-        uint8_t *atv = o->at + v * o->g;
+        uint16_t *atv = o->at + v * o->g;
         for (uint32_t i = 0; i < o->g; i++)
-            atv[i] = (uint8_t)oat_preserve_at(k, act_of(o, o->c0, i), atv[i]);
+            atv[i] = (uint16_t)oat_preserve_at(k, act_of(o, o->c0, i), atv[i]);
     }
     o->open = 1;
     o->queryable = 0;
@@ -277,7 +277,7 @@ int oat_ingest(oat *o, const uint32_t *aip, const uint32_t *bip, uint64_t n)
         uint32_t act = act_of(o, o->c0, i);
         for (uint32_t j = 0; j < o->p.r; j++) {
             uint64_t v = atv_index(o, z, j, x[j]);
-            o->at[v * o->g + i] = (uint8_t)act;
+            o->at[v * o->g + i] = (uint16_t)act;
         }
     }
     return OAT_OK;
@@ -295,7 +295,7 @@ int oat_close(oat *o, uint32_t kprime)
         for (uint32_t j = 0; j < o->p.r; j++)
             for (uint32_t x = 0; x < o->ncol; x++) {
                 uint64_t v = atv_index(o, z, j, x);
-                const uint8_t *atv = o->at + v * o->g;
+                const uint16_t *atv = o->at + v * o->g;
                 uint32_t w = 0;
                 for (uint32_t i = 0; i < o->g; i++)
                     w += (uint32_t)oat_check_at(o->p.k, act_of(o, o->c0, i), atv[i], kprime);
@@ -311,6 +311,31 @@ int oat_close(oat *o, uint32_t kprime)
     return OAT_OK;
 }
 
+/* Summaries of the window ending at the last closed slice for another k'
+ * (1 <= k' <= k): same timestamps, same ACT, Alg 1 with the new k'.  The
+ * clock does not move; later queries use this k'. */
+int oat_requery(oat *o, uint32_t kprime)
+{
+    if (!o) return OAT_E_INVAL;
+    if (!o->queryable) return OAT_E_STATE;
+    if (kprime < 1 || kprime > o->p.k) return OAT_E_INVAL;
+    memset(o->aat, 0, sizeof(uint64_t) * (size_t)o->nframe * o->p.r);
+    for (uint32_t z = 0; z < o->nframe; z++)
+        for (uint32_t j = 0; j < o->p.r; j++)
+            for (uint32_t x = 0; x < o->ncol; x++) {
+                uint64_t v = atv_index(o, z, j, x);
+                const uint16_t *atv = o->at + v * o->g;
+                uint32_t w = 0;
+                for (uint32_t i = 0; i < o->g; i++)
+                    w += (uint32_t)oat_check_at(o->p.k, act_of(o, o->c0_query, i), atv[i], kprime);
+                o->w[v] = w;
+                o->aat[(uint64_t)z * o->p.r + j] += w;
+                o->super[v] = (w >= o->T);
+            }
+    o->kq = kprime;
+    return OAT_OK;
+}
+
 /* Alg 5: NAT(aip) = number of positions i active in all r ATVs of aip. */
 static uint32_t nat_of(const oat *o, uint32_t z, const uint32_t *x)
 {
@@ -319,7 +344,7 @@ static uint32_t nat_of(const oat *o, uint32_t z, const uint32_t *x)
         int all = 1;
         for (uint32_t j = 0; j < o->p.r; j++) {
             uint64_t v = atv_index(o, z, j, x[j]);
-            uint8_t at = o->at[v * o->g + i];
+            uint16_t at = o->at[v * o->g + i];
             if (!oat_check_at(o->p.k, act_of(o, o->c0_query, i), at, o->kq)) {
                 all = 0;
                 break;
@@ -488,16 +513,17 @@ int oat_features(const oat *o, const uint32_t *aip, uint64_t n, float *feat)
     if (!o) return OAT_E_INVAL;
     if (!o->queryable) return OAT_E_STATE;
     uint32_t k = o->p.k, x[64], z;
-    uint32_t hist[128];
+    uint32_t *hist = (uint32_t *)malloc(k * sizeof(uint32_t)); /* ages 0..k-1 */
+    if (!hist) return OAT_E_NOMEM;
     for (uint64_t q = 0; q < n; q++) {
         oat_rrh(o, aip[q], &z, x);
-        memset(hist, 0, sizeof(hist));
+        memset(hist, 0, k * sizeof(uint32_t));
         for (uint32_t i = 0; i < o->g; i++) {
             uint32_t act = act_of(o, o->c0_query, i);
             uint32_t e = 0;
             int inactive = 0;
             for (uint32_t j = 0; j < o->p.r; j++) {
-                uint8_t at = o->at[atv_index(o, z, j, x[j]) * o->g + i];
+                uint16_t at = o->at[atv_index(o, z, j, x[j]) * o->g + i];
                 if (!oat_check_at(k, act, at, k)) {
                     inactive = 1;
                     break;
@@ -521,11 +547,12 @@ int oat_features(const oat *o, const uint32_t *aip, uint64_t n, float *feat)
         for (uint32_t j = 0; j < o->p.r; j++) s += (double)o->aat[(uint64_t)z * o->p.r + j] / denom_cells;
         f[63] = (float)(s / (double)o->p.r);
     }
+    free(hist);
     return OAT_OK;
 }
 
 uint64_t oat_pool_size(const oat *o) { return o->pool_size; }
-const uint8_t *oat_pool(const oat *o) { return o->at; }
+const uint16_t *oat_pool(const oat *o) { return o->at; }
 uint64_t oat_n_atv(const oat *o) { return o->n_atv; }
 const uint32_t *oat_weights(const oat *o) { return o->w; }
 const uint64_t *oat_aat(const oat *o) { return o->aat; }

@@ -22,6 +22,8 @@
  *     ATs, the last holds the rest (Section 3).
  *   - slice lifecycle: open(t) sets C0 = t mod 2k and runs preserveAT,
  *     pairs are scanned, close(t) summarises the window ending at t.
+ *   - an AT holds 2k+1 values (ceil(log2(2k+1)) bits, Section 3); the oracle
+ *     keeps every AT in a 16-bit word, so k <= 32767.
  */
 #ifndef ASSE_ORACLE_H
 #define ASSE_ORACLE_H
@@ -33,7 +35,7 @@ extern "C" {
 #endif
 
 typedef struct {
-    uint32_t k;            /* slices per window, 1..127                    */
+    uint32_t k;            /* slices per window, 1..32767                  */
     uint32_t r, c, s, u;   /* rows, log2 columns, column stride, log2 frames */
     uint32_t log2g;        /* ATs per ATV = 2^log2g                        */
     double theta;          /* super point threshold                         */
@@ -75,6 +77,7 @@ uint32_t oat_block_of(const oat *o, uint32_t i);
 /* Slice lifecycle: scan pairs, close a slice, query the closed window. */
 int oat_ingest(oat *o, const uint32_t *aip, const uint32_t *bip, uint64_t n);
 int oat_close(oat *o, uint32_t kprime);
+int oat_requery(oat *o, uint32_t kprime);
 int oat_estimate(const oat *o, const uint32_t *aip, uint64_t n, double *est,
                  uint8_t *flags, uint32_t *nat);
 int oat_restore(const oat *o, uint32_t *out, uint64_t cap, uint64_t *n_out);
@@ -83,7 +86,7 @@ int oat_features(const oat *o, const uint32_t *aip, uint64_t n, float *feat /* n
 
 /* Introspection. */
 uint64_t oat_pool_size(const oat *o);
-const uint8_t *oat_pool(const oat *o);
+const uint16_t *oat_pool(const oat *o);          /* AT values, one word each */
 uint64_t oat_n_atv(const oat *o);
 const uint32_t *oat_weights(const oat *o);     /* per ATV, last close       */
 const uint64_t *oat_aat(const oat *o);         /* per (frame, row)          */

@@ -53,6 +53,7 @@ def lib():
             "oat_block_of": (C.c_uint32, [vp, C.c_uint32]),
             "oat_ingest": (C.c_int, [vp, u32p, u32p, C.c_uint64]),
             "oat_close": (C.c_int, [vp, C.c_uint32]),
+            "oat_requery": (C.c_int, [vp, C.c_uint32]),
             "oat_estimate": (C.c_int, [vp, u32p, C.c_uint64, f64p, u8p, u32p]),
             "oat_restore": (C.c_int, [vp, u32p, C.c_uint64, u64p]),
             "oat_tuple_count": (C.c_int, [vp, u64p]),
@@ -183,6 +184,10 @@ class Oracle:
     def close(self, kprime: Optional[int] = None) -> int:
         return lib().oat_close(self.h, self.k if kprime is None else kprime)
 
+    def requery(self, kprime: int) -> int:
+        """Summarise the closed window again for another k' (clock unchanged)."""
+        return lib().oat_requery(self.h, kprime)
+
     def estimate(self, aip: np.ndarray):
         aip = np.ascontiguousarray(aip, np.uint32)
         est = np.zeros(aip.size, np.float64)
@@ -228,8 +233,9 @@ class Oracle:
         return int(lib().oat_n_atv(self.h))
 
     def pool(self) -> np.ndarray:
+        """AT values (uint16, one per AT, ATV-major)."""
         ptr = lib().oat_pool(self.h)
-        return np.ctypeslib.as_array(C.cast(ptr, C.POINTER(C.c_uint8)), (self.pool_size,)).copy()
+        return np.ctypeslib.as_array(C.cast(ptr, C.POINTER(C.c_uint16)), (self.pool_size,)).copy()
 
     def weights(self) -> np.ndarray:
         ptr = lib().oat_weights(self.h)

@@ -173,7 +173,8 @@ def test_rejects_invalid_geometry(oracle_lib):
     assert Or.try_create(**{**ok, "s": 7}) == oracle_lib.E_INVAL      # not complete
     assert Or.try_create(**{**ok, "u": 4, "c": 7, "s": 7}) == oracle_lib.E_INVAL  # c*r <= W
     assert Or.try_create(**{**ok, "k": 0}) == oracle_lib.E_INVAL
-    assert Or.try_create(**{**ok, "k": 128}) == oracle_lib.E_INVAL
+    assert Or.try_create(**{**ok, "k": 32768}) == oracle_lib.E_INVAL   # 2k must fit a 16-bit AT
+    assert Or.try_create(**{**ok, "k": 32767}) == 0
     assert Or.try_create(**{**ok, "s": 10}) == oracle_lib.E_INVAL     # s > c
     assert Or.try_create(**{**ok, "log2g": 0}) == oracle_lib.E_INVAL
     assert Or.try_create(**{**ok, "theta": 0.0}) == oracle_lib.E_INVAL
@@ -235,19 +236,23 @@ def _positions(o, aip, bip):
     return out
 
 
-@pytest.mark.parametrize("k,log2g", [(1, 4), (2, 4), (3, 4), (5, 4), (9, 5), (13, 4), (4, 3)])
+@pytest.mark.parametrize("k,log2g", [(1, 4), (2, 4), (3, 4), (5, 4), (9, 5), (13, 4), (4, 3), (150, 9), (300, 4)])
 def test_lazy_timestamps_match_exact_timestamps(oracle_lib, k, log2g):
     """After every slice, checkAT(at, k') for every AT and every k' <= k equals
     'set within the last k' slices' from 64-bit exact timestamps (a timestamp
     vector).  Slices include empty ones and run past several ACT wraps; k=13 with
-    g=16 and k=9/g=32 cover g < 2k."""
+    g=16 and k=9/g=32 cover g < 2k.  k = 150 and the paper's k = 300 need ATs
+    wider than a byte (2k >= 256); for them one wrap is run and a spread of
+    k' values is checked."""
     o = oracle_lib.Oracle(k=k, r=4, c=8, s=8, u=1, log2g=log2g, seed=k)
     g = 1 << log2g
     ts = np.full(o.pool_size, -(10**9), np.int64)
     rng = np.random.default_rng(k * 100 + log2g)
     hosts = rng.integers(0, 2**32, 6, dtype=np.uint64).astype(np.uint32)
     blocks = np.array([o.block_of(i) for i in range(g)])
-    for t in range(5 * k + 7):
+    wide = k > 20
+    kps = sorted({1, 2, k // 3, k // 2, k - 1, k}) if wide else range(1, k + 1)
+    for t in range(2 * k + 25 if wide else 5 * k + 7):
         n = 0 if t % 4 == 3 else int(rng.integers(1, 40))
         if n:
             aip = hosts[rng.integers(0, hosts.size, n)]
@@ -260,10 +265,12 @@ def test_lazy_timestamps_match_exact_timestamps(oracle_lib, k, log2g):
         c0 = t % (2 * k)
         act = (c0 + blocks) % (2 * k)
         touched = np.nonzero(ts > t - 2 * k - 2)[0]
+        if wide and touched.size > 300:
+            touched = touched[rng.integers(0, touched.size, 300)]
         sample = np.unique(np.concatenate([touched, rng.integers(0, o.pool_size, 200)]))
         for idx in sample.tolist():
             a = int(act[idx % g])
-            for kp in range(1, k + 1):
+            for kp in kps:
                 assert oracle_lib.check_at(k, a, int(pool[idx]), kp) == (ts[idx] >= t - kp + 1), \
                     (t, idx, kp, int(pool[idx]), int(ts[idx]))
         w = o.weights()
@@ -440,3 +447,60 @@ def test_generator_shapes():
     h, c = traffic.window_counts(tr.aip, tr.bip)
     d = dict(zip(h.tolist(), c.tolist()))
     assert [d[a] for a in tr.planted_hosts.tolist()] == tr.planted_card.tolist()
+
+
+@pytest.mark.parametrize("k", [3, 5, 10])
+def test_ace_comparator_same_windows_k_times_more_updates(oracle_lib, k):
+    """The aging counters the paper compares against (ACE, Section 2.3: set to
+    c = k when visited, decremented at every slice end, active for k' while
+    above k - k') mark exactly the same ATs active as the asynchronous
+    timestamps, but every counter is rewritten at every slice, while the
+    timestamps' preserve touches two blocks of 2k per ATV: k times fewer."""
+    o = oracle_lib.Oracle(k=k, r=4, c=8, s=8, u=1, log2g=6, seed=k)
+    g = o.g
+    ace = np.zeros(o.pool_size, np.int64)
+    rng = np.random.default_rng(k)
+    hosts = rng.integers(0, 2**32, 5, dtype=np.uint64).astype(np.uint32)
+    blocks = np.array([o.block_of(i) for i in range(g)])
+    touched = []
+    for t in range(4 * k + 3):
+        if t > 0:
+            ace = np.maximum(ace - 1, 0)          # ACE: every counter ages at the slice end
+        aip = hosts[rng.integers(0, hosts.size, 30)]
+        bip = rng.integers(0, 2**32, 30, dtype=np.uint64).astype(np.uint32)
+        o.ingest(aip, bip)
+        for atv, i in _positions(o, aip, bip):
+            ace[atv * g + i] = k
+        o.close(k)
+        pool = o.pool()
+        act = (t % (2 * k) + blocks) % (2 * k)
+        c0 = t % (2 * k)
+        due = {(2 * k - c0) % (2 * k), (3 * k - c0) % (2 * k)}
+        touched.append(int(np.isin(blocks, list(due)).sum()) * o.n_atv)
+        for kp in range(1, k + 1):
+            at_active = np.array([oracle_lib.check_at(k, int(act[idx % g]), int(pool[idx]), kp)
+                                  for idx in range(0, o.pool_size, 7)])
+            assert np.array_equal(at_active, ace[::7] > k - kp)
+    assert abs(np.mean(touched) / o.pool_size - 1.0 / k) < 0.5 / k
+
+
+def test_requery_equals_close_with_that_window(oracle_lib):
+    """Re-summarising the closed window for k' gives what closing with k'
+    would have given (two oracles fed the same pairs)."""
+    tr = traffic.generate(traffic.config_tiny(seed=12, n_slices=6, pairs_per_slice=4000, hosts=1 << 9))
+    k = 5
+    for kp in range(1, k + 1):
+        a = oracle_lib.Oracle(k=k, r=4, c=8, s=8, u=1, log2g=6, seed=1)
+        b = oracle_lib.Oracle(k=k, r=4, c=8, s=8, u=1, log2g=6, seed=1)
+        for t in range(tr.n_slices):
+            a.ingest(tr.aip[t], tr.bip[t])
+            b.ingest(tr.aip[t], tr.bip[t])
+            a.close(k)
+            b.close(kp)
+        assert a.requery(kp) == 0
+        assert np.array_equal(a.weights(), b.weights()) and np.array_equal(a.aat(), b.aat())
+        hosts = np.unique(tr.aip[-1][:200])
+        ea, fa, na = a.estimate(hosts)
+        eb, fb, nb = b.estimate(hosts)
+        assert np.array_equal(na, nb) and np.array_equal(fa, fb) and np.array_equal(ea, eb)
+    assert a.requery(0) == oracle_lib.E_INVAL and a.requery(k + 1) == oracle_lib.E_INVAL
