@@ -46,8 +46,6 @@ def serve_phase(dev, n_links: int = 16, slices: int = 10, period_scale: float = 
     65536 pairs arriving uniformly within each slice.  A producer thread
     submits events on that schedule while the main thread runs server steps.
     Latency is taken per slice from its end call to its result on the host."""
-    import threading
-
     import torch
 
     from paper_1807_01527_amd import traffic_gpu as tg
@@ -69,7 +67,9 @@ def serve_phase(dev, n_links: int = 16, slices: int = 10, period_scale: float = 
         srv.set_mlp(mlp)
     ids = []
     for li in range(n_links):
-        lid, adm = srv.open_link(int(ks[li]), seed * 1000 + li)
+        # a tuple budget of 2^24: at these loads windows with more column tuples
+        # answer AT_E_BUDGET at once instead of running a long join
+        lid, adm = srv.open_link(int(ks[li]), seed * 1000 + li, tuple_budget=1 << 24)
         srv.set_watch(lid, streams[li][2])
         ids.append(lid)
     # event timeline
@@ -93,34 +93,31 @@ def serve_phase(dev, n_links: int = 16, slices: int = 10, period_scale: float = 
             t += period
     events.sort(key=lambda e: (e[0], e[1], e[2] == "end"))
     total_pairs = int(sizes.sum())
-    done = threading.Event()
-
-    def producer():
-        t0 = time.perf_counter()
-        for (ts, li, kind, x, n) in events:
-            wait = ts - (time.perf_counter() - t0)
-            if wait > 0:
-                time.sleep(wait)
-            a, b, _ = streams[li]
-            if kind == "chunk":
-                srv.submit(ids[li], a[x:x + n], b[x:x + n])
-            else:
-                srv.end_slice(ids[li], x)
-        done.set()
-
+    # device pointers of every event, computed before the clock starts
+    lib = srv.lib
+    plan = []
+    for (ts, li, kind, x, n) in events:
+        a, b, _ = streams[li]
+        if kind == "chunk":
+            plan.append((ts, 0, ids[li], a[x:].data_ptr(), b[x:].data_ptr(), n))
+        else:
+            plan.append((ts, 1, ids[li], x, 0, 0))
+    import ctypes as C
     results = []
-    th = threading.Thread(target=producer)
+    srv.start()                     # the server steps on its own native thread
     t_start = time.perf_counter()
-    th.start()
-    step_ms = []
-    while True:
-        t0 = time.perf_counter()
-        srv.step()
-        step_ms.append(1e3 * (time.perf_counter() - t0))
-        results += srv.results()
-        if done.is_set() and all(srv.link_state(lid)[2] == 0 for lid in ids):
-            break
-    th.join()
+    for (ts, kind, lid, x, y, n) in plan:
+        wait = ts - (time.perf_counter() - t_start)
+        if wait > 0:
+            time.sleep(wait)
+        if kind == 0:
+            lib.at_serve_submit(srv.h, lid, C.c_void_p(x), C.c_void_p(y), n)
+        else:
+            lib.at_serve_end_slice(srv.h, lid, x)
+    while not all(srv.link_state(lid)[2] == 0 for lid in ids):
+        time.sleep(0.0005)
+    srv.stop()
+    results += srv.results()
     wall = time.perf_counter() - t_start
     st = srv.stats()
     lat = np.array([r["latency_ms"] for r in results])
@@ -130,12 +127,42 @@ def serve_phase(dev, n_links: int = 16, slices: int = 10, period_scale: float = 
                     f"per link, lognormal slice sizes (median 2M, sigma 1, [100k, 20M]), 64k-pair chunks, slice "
                     f"periods U[50,200] ms x {period_scale}",
         "closes": len(results), "pairs": total_pairs, "wall_s": wall, "mpps_offered": total_pairs / wall / 1e6,
-        "steps": st["steps"], "step_ms_p50": float(np.percentile(step_ms, 50)),
+        "steps": st["steps"],
         "slice_close_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                            "max": float(lat.max())},
         "restore_rc_counts": {str(k): int(v) for k, v in zip(*np.unique([r["restore_rc"] for r in results],
                                                                           return_counts=True))},
     }
+
+
+def scatter_sweep(n: int = 5_000_000):
+    """Random byte-store throughput against buffer size: n items with r = 1 and
+    r = 4 uniformly random stores each, the input read as the scan reads it."""
+    import torch
+
+    from paper_1807_01527_amd import traffic_gpu as tg
+    from paper_1807_01527_amd.binding import probe_scatter
+    dev = torch.device("cuda", 0)
+    a = tg.as_u32_device(tg.rand_u32(1, 1, n, dev))
+    b = tg.as_u32_device(tg.rand_u32(1, 2, n, dev))
+    rows = []
+    for mb in (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024):
+        buf = torch.empty(mb << 20, dtype=torch.uint8, device=dev)
+        for r in (1, 4):
+            for _ in range(2):
+                probe_scatter(buf, a, b, n, r)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                probe_scatter(buf, a, b, n, r)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 5
+            rows.append({"buffer_mib": mb, "r": r, "us": 1e3 * ms, "gstores_per_s": n * r / ms / 1e6})
+            log(f"{mb:5d} MiB r={r}: {1e3 * ms:8.1f} us {n * r / ms / 1e6:7.1f} Gstores/s")
+        del buf
+    print(json.dumps({"scatter_sweep": rows}), flush=True)
 
 
 def measured_traffic():
@@ -189,6 +216,8 @@ def main():
     ap.add_argument("--slices", type=int, default=10)
     ap.add_argument("--pairs", type=int, default=5_000_000)
     ap.add_argument("--no-serve", action="store_true", help="skip the streaming-server phase")
+    ap.add_argument("--scatter-sweep", action="store_true",
+                    help="only sweep the random byte-store probe over buffer sizes (1 MiB .. 1 GiB) and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -200,9 +229,13 @@ def main():
 
     import torch
 
+    if args.scatter_sweep:
+        scatter_sweep()
+        return
+
     from paper_1807_01527_amd import traffic
     from paper_1807_01527_amd import learned
-    from paper_1807_01527_amd.binding import AtPool, Mlp, probe_scatter
+    from paper_1807_01527_amd.binding import AtPool, Mlp, probe_ace_age, probe_scatter
 
     t0 = time.perf_counter()
     tr = traffic.generate(traffic.config_link(seed=0, n_slices=args.slices, pairs_per_slice=args.pairs))
@@ -273,6 +306,11 @@ def main():
     avg_ingest_s = float(ingest_ms.mean()) / 1e3
     alg_bytes = (8 + LINK["r"]) * per_launch
     achieved = alg_bytes / avg_ingest_s / 1e9
+    # at_ingest_slice's automatic choice: the binned scan for 8+ frames, pools
+    # of 32 MiB and more and batches of 64Ki pairs and more, else the direct one
+    binned = LINK["u"] >= 3 and pool.pool_bytes >= (32 << 20) and per_launch >= 65536
+    scan_kernels = ("k_bin_pairs + k_scan_bins (binned scan: XCD-local frame bins, then the r byte stores)"
+                    if binned else "k_ingest (fused pair hash + r byte scatter)")
     out = {
         "metric": "Mpps ingested + slice-close p99 ms; mean rel. error plain vs learned at θ=1024",
         "value": total_pairs / elapsed / 1e6,
@@ -296,7 +334,7 @@ def main():
         "mean_rel_err": {"plain": float(rel.mean()), "learned": float(rel_l.mean()) if rel_l is not None else None,
                          "hosts": int(truth_h.size),
                          "over": "true super points of the window (exact distinct count >= 1024)"},
-        "roofline": {"kernel": "k_ingest (fused pair hash + r byte scatter)", "bound": "hbm",
+        "roofline": {"kernel": scan_kernels, "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(), "bytes_per_pair": 8 + LINK["r"],
                      "avg_launch_ms": float(ingest_ms.mean()), "pairs_per_launch": per_launch},
@@ -342,6 +380,30 @@ def main():
         "stores_per_s": LINK["r"] * per_launch / (probe_ms / 1e3),
         "ingest_frac_of_probe": (per_launch / avg_ingest_s) / (per_launch / (probe_ms / 1e3)),
     }
+    # the paper's comparison of slice maintenance: aging counters (ACE) rewrite
+    # the whole pool at every slice end, asynchronous timestamps preserve two
+    # blocks of every ATV (measured on the opening call of each slice)
+    ace_buf = torch.full((pool.pool_bytes,), 7, dtype=torch.uint8, device=dev)
+    pres, ages = [], []
+    for t in range(S):
+        e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+        e0.record(stream)
+        pool.ingest(aip_d[t][:0], bip_d[t][:0], n=0)
+        e1.record(stream)
+        e2.record(stream)
+        probe_ace_age(ace_buf, stream=stream)
+        e3.record(stream)
+        pool.ingest(aip_d[t], bip_d[t])
+        pool.close(K)
+        pres.append((e0, e1))
+        ages.append((e2, e3))
+    torch.cuda.synchronize()
+    pm = float(np.mean([a.elapsed_time(b) for a, b in pres]))
+    am = float(np.mean([a.elapsed_time(b) for a, b in ages]))
+    del ace_buf
+    out["slice_maintenance"] = {"at_lazy_preserve_ms": pm, "ace_aging_ms": am, "ratio": am / pm,
+                                "note": f"per slice, {pool.pool_bytes >> 20} MiB pool, k={K}: the timestamps touch "
+                                        f"2 of 2k blocks per ATV, the aging counters all of them"}
     if args.copy_probe:
         x = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         y = torch.empty_like(x)

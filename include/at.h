@@ -16,10 +16,13 @@
  * thread-safe; distinct handles may be used from different threads.  Every
  * call returns AT_OK (0) or a negative error code; at_strerror() names it.
  *
- * Pool layout (device, owned by the handle): one byte per AT,
+ * Pool layout (device, owned by the handle): one AT per element,
  *   AT[((z*r + y)*2^c + x)*g + i]
  * for frame z < 2^u, row y < r, column x < 2^c and AT position i < g, so each
- * ATV (g ATs) is contiguous.  An AT holds 0..2k; 2k means inactive.
+ * ATV (g ATs) is contiguous.  An AT holds 0..2k; 2k means inactive.  That is
+ * ceil(log2(2k+1)) bits (Section 3), stored in one byte while 2k < 256
+ * (k <= 127) and in a little-endian 16-bit word otherwise (the paper's own run
+ * uses k = 300).
  */
 #ifndef AT_H
 #define AT_H
@@ -54,7 +57,7 @@ enum {
 };
 
 typedef struct {
-    uint32_t k;            /* slices per window, 1..127 (one byte per AT)      */
+    uint32_t k;            /* slices per window, 1..32767 (byte ATs to 127)    */
     uint32_t r;            /* rows: ATVs per host, 1..8                        */
     uint32_t c;            /* log2 of the columns per row, 1..20               */
     uint32_t s;            /* column stride in LBS bits, 1..c                  */
@@ -66,8 +69,9 @@ typedef struct {
 } at_params;
 
 /*
- * at_create -- allocate a pool of 2^(c+u) * r * 2^log2g bytes on the current
- * HIP device and set every AT to 2k (InitAT, Section 3).
+ * at_create -- allocate a pool of 2^(c+u) * r * 2^log2g ATs (1 byte each for
+ * k <= 127, 2 bytes beyond) on the current HIP device and set every AT to 2k
+ * (InitAT, Section 3).
  *
  * The geometry must allow the reversible hash of Section 4.1 (W = 32 - u):
  *   1 <= s <= c <= W,  c + s*(r-1) >= W (completeness: every bit of LBS lands
@@ -109,6 +113,19 @@ int at_ingest_slice(at_ctx *h, const uint32_t *aip_dev, const uint32_t *bip_dev,
  */
 int at_close_slice(at_ctx *h, uint32_t kprime);
 
+/* at_close_slice for several windows at once (the paper's "any k' <= k from
+ * one state", Section 3): one read of the pool yields the k'-weights of every
+ * ATV for each of the n windows kprimes[0..n-1] (1 <= n <= AT_MAX_WINDOWS,
+ * each 1 <= k' <= k), then AAT and super lists per window.  Queries use
+ * kprimes[0] until at_select_window picks another.  AT_E_INVAL otherwise. */
+#define AT_MAX_WINDOWS 8
+int at_close_slice_multi(at_ctx *h, const uint32_t *kprimes, uint32_t n);
+
+/* Make estimates, restores and at_read_summary use the window k' of the last
+ * close (one of its kprimes).  AT_E_STATE without a queryable window,
+ * AT_E_INVAL if k' was not summarised. */
+int at_select_window(at_ctx *h, uint32_t kprime);
+
 /*
  * at_estimate -- cardinality of each of n hosts over the window summarised by
  * the last close (Alg 5 and Eq 4, Section 4.3): NAT = ATs active in all r of
@@ -149,10 +166,12 @@ int at_destroy(at_ctx *h);
 /* Text for an error code. */
 const char *at_strerror(int rc);
 
-/* Pool size in bytes and number of ATVs. */
+/* Pool size in bytes and number of ATVs (bytes per AT = pool_bytes /
+ * (n_atv * g): 1 for k <= 127, else 2). */
 int at_pool_info(const at_ctx *h, uint64_t *pool_bytes, uint64_t *n_atv);
 
-/* Synchronous copy of the whole pool (pool_bytes) to a host buffer. */
+/* Synchronous copy of the whole pool (pool_bytes, the layout above) to a host
+ * buffer. */
 int at_read_pool(at_ctx *h, uint8_t *host_out);
 
 /* Synchronous copy of the last close's summaries: per-ATV weights (n_atv
@@ -303,7 +322,7 @@ int at_serve_destroy(at_serve *s);
 int at_serve_set_mlp(at_serve *s, at_mlp *m);
 /* Register a link: admitted at once (*admitted = 1) if its footprint fits the
  * budget and nobody waits, else queued (*admitted = 0).  AT_E_NOMEM if it can
- * never fit. */
+ * never fit.  Served links use byte ATs: 1 <= k <= 127, else AT_E_INVAL. */
 int at_serve_open_link(at_serve *s, uint32_t k, uint64_t seed, uint64_t tuple_budget, uint32_t *link_id,
                        int *admitted);
 /* state: 0 waiting, 1 active, 2 closed; slices closed; queued events. */
@@ -322,6 +341,11 @@ int at_serve_submit(at_serve *s, uint32_t link_id, const uint32_t *aip_dev, cons
 int at_serve_end_slice(at_serve *s, uint32_t link_id, uint32_t kprime);
 /* Run one batched step (synchronous); *n_results = slices closed by it. */
 int at_serve_step(at_serve *s, uint32_t *n_results);
+/* Start a native thread that runs steps back to back while any link has
+ * queued work and sleeps otherwise (AT_E_STATE if already running); stop
+ * drains the queues, joins the thread and returns the first step error. */
+int at_serve_start(at_serve *s);
+int at_serve_stop(at_serve *s);
 /* Pop the oldest result; arrays may be NULL; AT_E_STATE when none is ready,
  * AT_E_OVERFLOW when the capacities are too small (nothing popped). */
 int at_serve_next_result(at_serve *s, at_serve_result *out, uint32_t *cand, double *cand_plain,
@@ -332,6 +356,14 @@ int at_serve_next_result(at_serve *s, at_serve_result *out, uint32_t *cand, doub
 int at_serve_stats(at_serve *s, uint64_t *out4);
 /* Synchronous copy of an active link's pool to the host. */
 int at_serve_read_pool(at_serve *s, uint32_t link_id, uint8_t *host_out);
+
+/* Comparator probe: one aging pass of ACE counters (the sliding-window
+ * counters the paper compares asynchronous timestamps against, Section 2.3):
+ * every nonzero byte of counters_dev (device, `bytes` a multiple of 16,
+ * 16-byte aligned) is decremented by one, as ACE requires at every slice end.
+ * Timed against the lazy preserve of at_ingest_slice on a pool of the same
+ * size it measures the k-fold saving the paper claims.  Asynchronous. */
+int at_probe_ace_age(uint8_t *counters_dev, uint64_t bytes, void *hip_stream);
 
 /* Measurement probe, not part of the method: n items (n a multiple of 4,
  * a_dev/b_dev 16-byte aligned device arrays of n uint32, read like the pair

@@ -40,6 +40,8 @@ SIGNATURES = {
     "at_create": (C.c_int, [C.POINTER(Params), _vp, C.POINTER(_vp)]),
     "at_ingest_slice": (C.c_int, [_vp, _vp, _vp, C.c_uint64]),
     "at_close_slice": (C.c_int, [_vp, C.c_uint32]),
+    "at_close_slice_multi": (C.c_int, [_vp, _u32p, C.c_uint32]),
+    "at_select_window": (C.c_int, [_vp, C.c_uint32]),
     "at_estimate": (C.c_int, [_vp, _u32p, C.c_uint64, _f64p, _u8p]),
     "at_restore": (C.c_int, [_vp, _u32p, _f64p, _u8p, C.c_uint64, _u64p]),
     "at_destroy": (C.c_int, [_vp]),
@@ -54,6 +56,7 @@ SIGNATURES = {
     "at_tuple_count": (C.c_int, [_vp, _u64p]),
     "at_set_scan_mode": (C.c_int, [_vp, C.c_int]),
     "at_probe_scatter": (C.c_int, [_vp, C.c_uint64, _vp, _vp, C.c_uint64, C.c_uint32, _vp]),
+    "at_probe_ace_age": (C.c_int, [_vp, C.c_uint64, _vp]),
     "at_features": (C.c_int, [_vp, _vp, C.c_uint64, _vp, _vp, _vp]),
     "at_mlp_create": (C.c_int, [_vp, C.POINTER(_vp)]),
     "at_mlp_destroy": (C.c_int, [_vp]),
@@ -93,6 +96,8 @@ SIGNATURES.update({
     "at_serve_submit": (C.c_int, [_vp, C.c_uint32, _vp, _vp, C.c_uint64]),
     "at_serve_end_slice": (C.c_int, [_vp, C.c_uint32, C.c_uint32]),
     "at_serve_step": (C.c_int, [_vp, _u32p]),
+    "at_serve_start": (C.c_int, [_vp]),
+    "at_serve_stop": (C.c_int, [_vp]),
     "at_serve_next_result": (C.c_int, [_vp, C.POINTER(ServeResult), _u32p, _f64p, _f64p, _u8p, C.c_uint32,
                                        _f64p, _f64p, _u8p, C.c_uint32]),
     "at_serve_stats": (C.c_int, [_vp, _u64p]),
@@ -153,6 +158,15 @@ def probe_scatter(dst_dev, a_dev, b_dev, n: int, r: int, stream=None):
                                    C.c_void_p(stream.cuda_stream)), "at_probe_scatter")
 
 
+def probe_ace_age(counters_dev, stream=None):
+    """One ACE aging pass over a device byte buffer (see at_probe_ace_age)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(load().at_probe_ace_age(C.c_void_p(_dev_ptr(counters_dev)), counters_dev.numel(),
+                                   C.c_void_p(stream.cuda_stream)), "at_probe_ace_age")
+
+
 class AtPool:
     """One link: an ATVC pool in device memory, driven on a HIP stream."""
 
@@ -173,6 +187,7 @@ class AtPool:
         pb, na = C.c_uint64(), C.c_uint64()
         _check(self.lib.at_pool_info(self.h, C.byref(pb), C.byref(na)), "at_pool_info")
         self.pool_bytes, self.n_atv = int(pb.value), int(na.value)
+        self.at_bytes = self.pool_bytes // (self.n_atv * self.g)   # 1, or 2 for k > 127
 
     @staticmethod
     def try_create(**kw) -> int:
@@ -217,6 +232,13 @@ class AtPool:
     def close(self, kprime: Optional[int] = None):
         _check(self.lib.at_close_slice(self._handle(), self.k if kprime is None else kprime), "at_close_slice")
 
+    def close_multi(self, kprimes):
+        kp = np.ascontiguousarray(kprimes, np.uint32)
+        _check(self.lib.at_close_slice_multi(self._handle(), _p(kp, C.c_uint32), kp.size), "at_close_slice_multi")
+
+    def select_window(self, kprime: int):
+        _check(self.lib.at_select_window(self._handle(), kprime), "at_select_window")
+
     def estimate(self, aip_host: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
         aip = np.ascontiguousarray(aip_host, np.uint32)
         est = np.zeros(aip.size, np.float64)
@@ -257,9 +279,10 @@ class AtPool:
 
     # ---- introspection --------------------------------------------------
     def read_pool(self) -> np.ndarray:
+        """AT values, uint8 (k <= 127) or uint16, ATV-major."""
         out = np.zeros(self.pool_bytes, np.uint8)
         _check(self.lib.at_read_pool(self._handle(), _p(out, C.c_uint8)), "at_read_pool")
-        return out
+        return out.view(np.uint16) if self.at_bytes == 2 else out
 
     def read_summary(self) -> Tuple[np.ndarray, np.ndarray]:
         w = np.zeros(self.n_atv, np.uint32)
@@ -434,6 +457,13 @@ class Server:
         n = C.c_uint32()
         _check(self.lib.at_serve_step(self.h, C.byref(n)), "at_serve_step")
         return int(n.value)
+
+    def start(self):
+        """Run steps on a native thread while work is queued."""
+        _check(self.lib.at_serve_start(self.h), "at_serve_start")
+
+    def stop(self):
+        _check(self.lib.at_serve_stop(self.h), "at_serve_stop")
 
     def results(self):
         """Pop every ready result as dicts."""

@@ -25,7 +25,7 @@ struct Geometry {
     uint32_t A, Ainv;        // mangling multiplier and its inverse mod p
     uint32_t blk_a;          // ATs in each of the first 2k-1 blocks (may be 0)
     uint32_t last_blk;       // 2k-1
-    uint32_t pad0;
+    uint32_t atb;            // bytes per AT: 1 while 2k < 256, else 2
     uint64_t blk_magic;      // ceil(2^32 / blk_a): i / blk_a == (i*magic) >> 32 for i < 2^16
     uint64_t maskW;          // 2^W - 1
     uint64_t alpha, beta;    // BH multiply-add-shift
@@ -34,33 +34,46 @@ struct Geometry {
     double theta;
 };
 
-// Lazy preserve work of one slice opening: the byte ranges of the two blocks
+// Lazy preserve work of one slice opening: the AT ranges of the two blocks
 // whose timestamp becomes 0 and k, and the (one or two, disjoint) spans of
-// 4-byte words covering them.
+// 16-byte chunks covering them.
 struct PreserveSpans {
-    uint32_t r0lo, r0hi;  // byte range of the block with timestamp 0
-    uint32_t r1lo, r1hi;  // byte range of the block with timestamp k
-    uint32_t w0lo, nw0;   // word span 0
-    uint32_t w1lo, nw1;   // word span 1 (may be empty)
+    uint32_t r0lo, r0hi;  // AT range of the block with timestamp 0
+    uint32_t r1lo, r1hi;  // AT range of the block with timestamp k
+    uint32_t w0lo, nw0;   // span 0 of 16-byte chunks covering the ranges
+    uint32_t w1lo, nw1;   // span 1 (may be empty; disjoint from span 0)
 };
 PreserveSpans preserve_spans(const Geometry& G, uint32_t c0);
 
 // ---- launchers (kernels.hip); all asynchronous on `st` ---------------------
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t st);
+// n_at ATs of a pool (G.atb bytes each) set to the inactive value 2k
+hipError_t launch_fill_pool(uint8_t* pool, uint64_t n_at, const Geometry& G, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* p, uint32_t n, hipStream_t st);
 hipError_t launch_preserve(uint8_t* pool, uint64_t n_atv, const Geometry& G, uint32_t c0,
                            hipStream_t st);
 hipError_t launch_ingest(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
                          const Geometry& G, uint32_t c0, hipStream_t st);
-// Two-pass scan: pairs hashed once into 8 frame-group bins (records of 8 B,
-// bins[b * cap + i]), then one pass per row with workgroup b on bin b mod 8.
+// Two-pass scan: pairs hashed once into 8 frame-group bins of 64 sub-runs
+// each (8-byte records), then one pass per row with workgroup b on bin b mod 8.
+// Scratch: bins of 8 * 64 * binned_sub_cap(n) records, fill of 512 counters.
 constexpr uint32_t kScanBins = 8;
+constexpr uint32_t kScanSubs = 64;
+uint64_t binned_sub_cap(uint64_t n);
 hipError_t launch_ingest_binned(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n, const Geometry& G,
-                                uint32_t c0, uint64_t* bins, uint64_t cap, unsigned long long* fill, hipStream_t st);
-hipError_t launch_close(const uint8_t* pool, uint32_t* w, uint64_t n_atv, const Geometry& G,
-                        uint32_t c0, uint32_t kq, hipStream_t st);
-hipError_t launch_summarize(const uint32_t* w, uint64_t* aat, uint32_t* sa, uint32_t* sa_cnt,
-                            const Geometry& G, hipStream_t st);
+                                uint32_t c0, uint64_t* bins, uint64_t sub_cap, unsigned long long* fill,
+                                hipStream_t st);
+// Windows summarised by one close: weights for window j land in
+// w[j * n_atv ...], AAT in aat[j * groups ...], super lists likewise.
+constexpr uint32_t kMaxWindows = 8;
+struct CloseWindows {
+    uint32_t n;
+    uint32_t kq[kMaxWindows];
+};
+hipError_t launch_close(const uint8_t* pool, uint32_t* w, uint64_t n_atv, const Geometry& G, uint32_t c0,
+                        const CloseWindows& Wn, hipStream_t st);
+hipError_t launch_summarize(const uint32_t* w, uint64_t* aat, uint32_t* sa, uint32_t* sa_cnt, const Geometry& G,
+                            uint64_t n_atv, uint32_t nwin, hipStream_t st);
 hipError_t launch_restore_join(const uint32_t* sa, const uint32_t* sa_cnt, const uint64_t* pair_prefix,
                                uint64_t n_items, const Geometry& G, uint32_t* cand, uint64_t cap,
                                unsigned long long* counter, hipStream_t st);
@@ -121,6 +134,7 @@ hipError_t launch_learned_combine(const float* y, const float* feat, const doubl
                                   uint64_t n, double zlo, double zhi, double theta, double* est, uint8_t* flags,
                                   hipStream_t st);
 
+hipError_t launch_ace_age(uint8_t* p, uint64_t bytes, hipStream_t st);
 hipError_t launch_scatter_probe(uint8_t* dst, uint64_t bytes, const uint32_t* a, const uint32_t* b, uint64_t n,
                                 uint32_t r, hipStream_t st);
 

@@ -25,7 +25,15 @@ struct at_ctx {
     uint32_t nframe = 0, ngroups = 0;  // frames and (frame,row) groups
     // device state
     uint8_t* pool = nullptr;
-    uint32_t* w = nullptr;        // per ATV weight of the last close
+    // summaries of up to kMaxWindows windows of the last close ...
+    uint32_t* w_all = nullptr;
+    uint64_t* aat_all = nullptr;
+    uint32_t* sa_all = nullptr;
+    uint32_t* sa_cnt_all = nullptr;
+    uint32_t nwin = 0;
+    uint32_t win_kq[atp::kMaxWindows] = {};
+    // ... and the one queries use
+    uint32_t* w = nullptr;        // per ATV weight
     uint64_t* aat = nullptr;      // per (frame,row)
     uint32_t* sa = nullptr;       // per (frame,row): ascending super columns
     uint32_t* sa_cnt = nullptr;   // per (frame,row)
@@ -76,7 +84,7 @@ uint64_t pow_mod_p(uint64_t b, uint64_t e) {
 }
 
 int validate(const at_params& p) {
-    if (p.u > 16 || p.k < 1 || p.k > 127 || p.r < 1 || p.r > (uint32_t)atp::kMaxRows) return AT_E_INVAL;
+    if (p.u > 16 || p.k < 1 || p.k > 32767 || p.r < 1 || p.r > (uint32_t)atp::kMaxRows) return AT_E_INVAL;
     const uint32_t W = 32 - p.u;
     if (p.c < 1 || p.c > 20 || p.s < 1 || p.s > p.c || p.c > W) return AT_E_INVAL;
     if (p.c + p.s * (p.r - 1) < W) return AT_E_INVAL;  // completeness
@@ -92,6 +100,7 @@ Geometry derive(const at_params& p) {
     Geometry G{};
     G.k = p.k;
     G.twok = 2 * p.k;
+    G.atb = G.twok < 256 ? 1 : 2;  // AT bytes: 2k + 1 values per AT
     G.r = p.r;
     G.c = p.c;
     G.s = p.s;
@@ -144,7 +153,7 @@ int dev_alloc(T** p, uint64_t count) {
 }
 
 void free_all(at_ctx* h) {
-    void* bufs[] = {h->pool, h->w, h->aat, h->sa, h->sa_cnt, h->counter, h->prefix, h->cand,
+    void* bufs[] = {h->pool, h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->counter, h->prefix, h->cand,
                     h->q_aip, h->q_est, h->q_flags, h->q_nat, h->q_feat, h->q_y, h->q_plain, h->bins, h->bin_fill};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -258,23 +267,28 @@ int at_create(const at_params* p, void* hip_stream, at_ctx** out) {
     h->nframe = 1u << p->u;
     h->ngroups = h->nframe * p->r;
     h->n_atv = (uint64_t)h->ngroups << p->c;
-    h->pool_bytes = h->n_atv << p->log2g;
-    if ((rc = dev_alloc(&h->pool, h->pool_bytes)) || (rc = dev_alloc(&h->w, h->n_atv)) ||
-        (rc = dev_alloc(&h->aat, h->ngroups)) || (rc = dev_alloc(&h->sa, h->n_atv)) ||
-        (rc = dev_alloc(&h->sa_cnt, h->ngroups)) || (rc = dev_alloc(&h->counter, 1)) ||
+    h->pool_bytes = (h->n_atv << p->log2g) * h->G.atb;
+    const uint64_t W = atp::kMaxWindows;
+    if ((rc = dev_alloc(&h->pool, h->pool_bytes)) || (rc = dev_alloc(&h->w_all, W * h->n_atv)) ||
+        (rc = dev_alloc(&h->aat_all, W * h->ngroups)) || (rc = dev_alloc(&h->sa_all, W * h->n_atv)) ||
+        (rc = dev_alloc(&h->sa_cnt_all, W * h->ngroups)) || (rc = dev_alloc(&h->counter, 1)) ||
         (rc = dev_alloc(&h->prefix, h->nframe + 1))) {
         free_all(h);
         delete h;
         return rc;
     }
     // InitAT (Section 3): every AT starts inactive
-    hipError_t e = atp::launch_fill_u8(h->pool, h->pool_bytes, (uint8_t)h->G.twok, h->stream);
+    hipError_t e = atp::launch_fill_pool(h->pool, h->n_atv << p->log2g, h->G, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         free_all(h);
         delete h;
         return AT_E_DEVICE;
     }
+    h->w = h->w_all;
+    h->aat = h->aat_all;
+    h->sa = h->sa_all;
+    h->sa_cnt = h->sa_cnt_all;
     *out = h;
     return AT_OK;
 }
@@ -310,15 +324,15 @@ int at_ingest_slice(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev,
     if (!use_binned(h, n))
         return atp::launch_ingest(h->pool, aip_dev, bip_dev, n, h->G, h->c0, h->stream) == hipSuccess ? AT_OK
                                                                                                      : AT_E_DEVICE;
-    const uint64_t batch = std::min<uint64_t>(n, kBinBatch);
-    if (batch > h->bins_cap) {
+    const uint64_t sub_cap = atp::binned_sub_cap(std::min<uint64_t>(n, kBinBatch));
+    if (sub_cap > h->bins_cap) {
         if (h->bins) (void)hipFree(h->bins);
         h->bins = nullptr;
         h->bins_cap = 0;
-        if ((rc = dev_alloc(&h->bins, atp::kScanBins * batch))) return rc;
-        h->bins_cap = batch;
+        if ((rc = dev_alloc(&h->bins, (uint64_t)atp::kScanBins * atp::kScanSubs * sub_cap))) return rc;
+        h->bins_cap = sub_cap;
     }
-    if (!h->bin_fill && (rc = dev_alloc(&h->bin_fill, atp::kScanBins))) return rc;
+    if (!h->bin_fill && (rc = dev_alloc(&h->bin_fill, atp::kScanBins * atp::kScanSubs))) return rc;
     for (uint64_t off = 0; off < n; off += kBinBatch) {
         const uint64_t m = std::min<uint64_t>(kBinBatch, n - off);
         if (atp::launch_ingest_binned(h->pool, aip_dev + off, bip_dev + off, m, h->G, h->c0, h->bins, h->bins_cap,
@@ -334,20 +348,54 @@ int at_set_scan_mode(at_ctx* h, int mode) {
     return AT_OK;
 }
 
-int at_close_slice(at_ctx* h, uint32_t kprime) {
-    if (!h) return AT_E_INVAL;
-    if (kprime < 1 || kprime > h->p.k) return AT_E_INVAL;
+namespace {
+void use_window(at_ctx* h, uint32_t j) {
+    h->w = h->w_all + (uint64_t)j * h->n_atv;
+    h->aat = h->aat_all + (uint64_t)j * h->ngroups;
+    h->sa = h->sa_all + (uint64_t)j * h->n_atv;
+    h->sa_cnt = h->sa_cnt_all + (uint64_t)j * h->ngroups;
+    h->kq = h->win_kq[j];
+}
+}  // namespace
+
+int at_close_slice_multi(at_ctx* h, const uint32_t* kprimes, uint32_t n) {
+    if (!h || !kprimes || n < 1 || n > atp::kMaxWindows) return AT_E_INVAL;
+    atp::CloseWindows Wn{};
+    Wn.n = n;
+    for (uint32_t j = 0; j < n; j++) {
+        if (kprimes[j] < 1 || kprimes[j] > h->p.k) return AT_E_INVAL;
+        Wn.kq[j] = kprimes[j];
+    }
     int rc = open_slice(h);
     if (rc) return rc;
-    hipError_t e = atp::launch_close(h->pool, h->w, h->n_atv, h->G, h->c0, kprime, h->stream);
-    if (e == hipSuccess) e = atp::launch_summarize(h->w, h->aat, h->sa, h->sa_cnt, h->G, h->stream);
+    hipError_t e = atp::launch_close(h->pool, h->w_all, h->n_atv, h->G, h->c0, Wn, h->stream);
+    if (e == hipSuccess)
+        e = atp::launch_summarize(h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->G, h->n_atv, n, h->stream);
     if (e != hipSuccess) return AT_E_DEVICE;
+    h->nwin = n;
+    for (uint32_t j = 0; j < n; j++) h->win_kq[j] = kprimes[j];
     h->c0_query = h->c0;
-    h->kq = kprime;
+    use_window(h, 0);
     h->t += 1;
     h->open = false;
     h->queryable = true;
     return AT_OK;
+}
+
+int at_close_slice(at_ctx* h, uint32_t kprime) {
+    if (!h) return AT_E_INVAL;
+    return at_close_slice_multi(h, &kprime, 1);
+}
+
+int at_select_window(at_ctx* h, uint32_t kprime) {
+    if (!h) return AT_E_INVAL;
+    if (!h->queryable) return AT_E_STATE;
+    for (uint32_t j = 0; j < h->nwin; j++)
+        if (h->win_kq[j] == kprime) {
+            use_window(h, j);
+            return AT_OK;
+        }
+    return AT_E_INVAL;
 }
 
 int at_estimate_dev(at_ctx* h, const uint32_t* aip_dev, uint64_t n, double* est_dev, uint8_t* flags_dev,
@@ -504,6 +552,13 @@ int at_constants(const at_ctx* h, uint64_t* out8) {
     out8[6] = h->G.W;
     out8[7] = h->G.blk_a;
     return AT_OK;
+}
+
+int at_probe_ace_age(uint8_t* counters_dev, uint64_t bytes, void* hip_stream) {
+    if (!counters_dev || bytes == 0 || (bytes % 16) || (reinterpret_cast<uintptr_t>(counters_dev) & 15u))
+        return AT_E_INVAL;
+    if (!device_accessible(counters_dev)) return AT_E_INVAL;
+    return atp::launch_ace_age(counters_dev, bytes, (hipStream_t)hip_stream) == hipSuccess ? AT_OK : AT_E_DEVICE;
 }
 
 int at_probe_scatter(uint8_t* dst_dev, uint64_t bytes, const uint32_t* a_dev, const uint32_t* b_dev, uint64_t n,

@@ -1,9 +1,12 @@
 // gfx950 kernels of the ATVC hot path: slice open (lazy preserve), pair scan,
 // slice close (window weights, AAT, super lists), restore join, sort, and
-// the per-host estimate.  Wave64 throughout; one byte per AT.
+// the per-host estimate.  Wave64 throughout.  An AT is one byte while
+// 2k < 256 and a 16-bit word beyond (the AT type T of the pool kernels); the
+// streaming server's kernels use byte ATs.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "atpool.hpp"
 
@@ -44,42 +47,66 @@ __device__ __forceinline__ uint32_t column(uint64_t LL, uint32_t sh, uint32_t ma
     return (uint32_t)(LL >> sh) & mask;
 }
 
-// Alg 1 on one byte: inactive value 2k, otherwise active when the distance
+// Alg 1 on one AT: inactive value 2k, otherwise active when the distance
 // from the block's timestamp is below k'.
 __device__ __forceinline__ uint32_t is_active(uint32_t at, uint32_t act, uint32_t twok, uint32_t kq) {
     uint32_t d = act >= at ? act - at : act + twok - at;
     return (at != twok) & (d < kq);
 }
 
-__device__ __forceinline__ uint32_t active_mask4(uint32_t atw, uint32_t actw, uint32_t twok, uint32_t kq) {
+// ATs of type T in a 32-bit word and in a 16-byte chunk; AT b of a word.
+template <typename T>
+constexpr uint32_t kPerWord = 4 / sizeof(T);
+template <typename T>
+constexpr uint32_t kPerChunk = 16 / sizeof(T);
+template <typename T>
+__device__ __forceinline__ uint32_t at_in_word(uint32_t w, uint32_t b) {
+    return sizeof(T) == 1 ? (w >> (8 * b)) & 0xFFu : (w >> (16 * b)) & 0xFFFFu;
+}
+__device__ __forceinline__ uint32_t word_of(const uint4& v, uint32_t q) {
+    return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w;
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t active_mask_word(uint32_t atw, uint32_t actw, uint32_t twok, uint32_t kq) {
     uint32_t m = 0;
 #pragma unroll
-    for (int b = 0; b < 4; b++)
-        m |= is_active((atw >> (8 * b)) & 0xFFu, (actw >> (8 * b)) & 0xFFu, twok, kq) << b;
+    for (uint32_t b = 0; b < kPerWord<T>; b++)
+        m |= is_active(at_in_word<T>(atw, b), at_in_word<T>(actw, b), twok, kq) << b;
     return m;
 }
 
+// bit e set when AT e of the chunk is active for k'
+template <typename T>
+__device__ __forceinline__ uint32_t active_mask_chunk(uint4 at, uint4 act, uint32_t twok, uint32_t kq) {
+    constexpr uint32_t N = kPerWord<T>;
+    return active_mask_word<T>(at.x, act.x, twok, kq) | (active_mask_word<T>(at.y, act.y, twok, kq) << N) |
+           (active_mask_word<T>(at.z, act.z, twok, kq) << (2 * N)) |
+           (active_mask_word<T>(at.w, act.w, twok, kq) << (3 * N));
+}
+
 __device__ __forceinline__ uint32_t active_mask16(uint4 at, uint4 act, uint32_t twok, uint32_t kq) {
-    return active_mask4(at.x, act.x, twok, kq) | (active_mask4(at.y, act.y, twok, kq) << 4) |
-           (active_mask4(at.z, act.z, twok, kq) << 8) | (active_mask4(at.w, act.w, twok, kq) << 12);
+    return active_mask_chunk<uint8_t>(at, act, twok, kq);
 }
 
 // per-position block timestamp table for the slice whose first block has C0
-__device__ void fill_act_lut(uint8_t* lut, uint32_t c0, const Geometry& G) {
-    for (uint32_t i = threadIdx.x; i < G.g; i += blockDim.x) lut[i] = (uint8_t)act_of(i, c0, G);
+template <typename T>
+__device__ void fill_act_lut(T* lut, uint32_t c0, const Geometry& G) {
+    for (uint32_t i = threadIdx.x; i < G.g; i += blockDim.x) lut[i] = (T)act_of(i, c0, G);
     __syncthreads();
 }
 
 // ---------------------------------------------------------------- utilities
 
-__global__ void k_fill_u8(uint8_t* __restrict__ p, uint64_t n, uint8_t v) {
+// n bytes set to the repeated 32-bit word v4 (n a multiple of 4 unless every
+// byte of v4 is the same)
+__global__ void k_fill_u8(uint8_t* __restrict__ p, uint64_t n, uint32_t v4) {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 16;
-    uint32_t v4 = v * 0x01010101u;
     uint4 vv = make_uint4(v4, v4, v4, v4);
     for (uint64_t o = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16; o < n; o += stride) {
         if (o + 16 <= n) *(uint4*)(p + o) = vv;
         else
-            for (uint64_t q = o; q < n; q++) p[q] = v;
+            for (uint64_t q = o; q < n; q++) p[q] = (uint8_t)(v4 >> (8 * (q & 3)));
     }
 }
 
@@ -91,31 +118,51 @@ __global__ void k_zero_u64(unsigned long long* p, uint32_t n) {
 // ---------------------------------------------------------------- a1: open
 // Alg 2 applied lazily: of the 2k blocks of every ATV only the two whose
 // timestamp becomes 0 or k can change (Section 3); every other AT is left
-// alone, which is exactly what Alg 2 does to it.  Work items are 4-byte words
-// of one or two disjoint word spans per ATV; bytes outside the due blocks are
-// written back unchanged.
+// alone, which is exactly what Alg 2 does to it.  Work items are 16-byte
+// chunks of one or two disjoint chunk spans per ATV; ATs outside the due
+// blocks are written back unchanged.  pos0 is the AT index of the word's
+// first AT.
+template <typename T = uint8_t>
+__device__ __forceinline__ uint32_t preserve_word(uint32_t v, uint32_t pos0, const PreserveSpans& S, uint32_t k,
+                                                  uint32_t twok) {
+    constexpr uint32_t B = 8 * sizeof(T);
+    constexpr uint32_t M = sizeof(T) == 1 ? 0xFFu : 0xFFFFu;
+    uint32_t nv = v;
+#pragma unroll
+    for (uint32_t b = 0; b < kPerWord<T>; b++) {
+        const uint32_t pos = pos0 + b;
+        const uint32_t at = at_in_word<T>(v, b);
+        uint32_t out = at;
+        if (pos >= S.r0lo && pos < S.r0hi && at <= k) out = twok;
+        if (pos >= S.r1lo && pos < S.r1hi && ((at >= k && at < twok) || at == 0)) out = twok;
+        nv = (nv & ~(M << (B * b))) | (out << (B * b));
+    }
+    return nv;
+}
+
+// One 16-byte chunk of a due range per thread: every chunk is independent, so
+// the pass streams at memory speed.  ATs of a chunk outside the due blocks
+// are written back unchanged.
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_preserve(uint8_t* __restrict__ pool, uint64_t n_atv,
                                                      uint32_t log2g, uint32_t k, PreserveSpans S) {
-    const uint32_t per_atv = S.nw0 + S.nw1;
-    const uint64_t total = n_atv * per_atv;
+    const uint32_t per = S.nw0 + S.nw1;  // 16-byte chunks per ATV
+    const uint64_t total = n_atv * per;
     const uint32_t twok = 2 * k;
     for (uint64_t it = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
          it += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t atv = it / per_atv;
-        uint32_t wi = (uint32_t)(it - atv * per_atv);
-        uint32_t word = wi < S.nw0 ? S.w0lo + wi : S.w1lo + (wi - S.nw0);
-        uint32_t* p = (uint32_t*)(pool + (atv << log2g)) + word;
-        uint32_t v = *p, nv = v;
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            uint32_t pos = word * 4 + b;
-            uint32_t at = (v >> (8 * b)) & 0xFFu;
-            uint32_t out = at;
-            if (pos >= S.r0lo && pos < S.r0hi && at <= k) out = twok;
-            if (pos >= S.r1lo && pos < S.r1hi && ((at >= k && at < twok) || at == 0)) out = twok;
-            nv = (nv & ~(0xFFu << (8 * b))) | (out << (8 * b));
-        }
-        if (nv != v) *p = nv;
+        const uint64_t atv = total < (1ull << 32) ? (uint32_t)it / per : it / per;
+        const uint32_t ci = (uint32_t)(it - atv * per);
+        const uint32_t chunk = ci < S.nw0 ? S.w0lo + ci : S.w1lo + (ci - S.nw0);
+        uint4* p = reinterpret_cast<uint4*>(pool + ((atv << log2g) * sizeof(T))) + chunk;
+        const uint4 v = *p;
+        constexpr uint32_t CA = kPerChunk<T>, N = kPerWord<T>;
+        uint4 nv;
+        nv.x = preserve_word<T>(v.x, chunk * CA, S, k, twok);
+        nv.y = preserve_word<T>(v.y, chunk * CA + N, S, k, twok);
+        nv.z = preserve_word<T>(v.z, chunk * CA + 2 * N, S, k, twok);
+        nv.w = preserve_word<T>(v.w, chunk * CA + 3 * N, S, k, twok);
+        if (nv.x != v.x || nv.y != v.y || nv.z != v.z || nv.w != v.w) *p = nv;
     }
 }
 
@@ -124,15 +171,15 @@ __global__ __launch_bounds__(kBlock) void k_preserve(uint8_t* __restrict__ pool,
 // bits, columns from LBS, AT index BH(bip), value = that AT's block timestamp.
 // The r byte stores need no atomics: every writer of an AT in a slice stores
 // the same value.
-template <int R>
-__device__ __forceinline__ void scan_pair(uint8_t* __restrict__ pool, uint32_t a, uint32_t b,
+template <int R, typename T>
+__device__ __forceinline__ void scan_pair(T* __restrict__ pool, uint32_t a, uint32_t b,
                                           const Geometry& G, uint32_t c0) {
     uint32_t f = mangle(a, G.A);
     uint32_t z = f & G.umask;
     uint64_t L = (uint64_t)(f >> G.u);
     uint64_t LL = L | (L << G.W);
     uint32_t i = (uint32_t)((G.alpha * (uint64_t)b + G.beta) >> (64 - G.log2g));
-    uint8_t v = (uint8_t)act_of(i, c0, G);
+    const T v = (T)act_of(i, c0, G);
     uint64_t zr = (uint64_t)z * R;
 #pragma unroll
     for (int j = 0; j < R; j++) {
@@ -142,8 +189,8 @@ __device__ __forceinline__ void scan_pair(uint8_t* __restrict__ pool, uint32_t a
     }
 }
 
-template <int R, bool VEC>
-__global__ __launch_bounds__(kBlock) void k_ingest(uint8_t* __restrict__ pool, const uint32_t* __restrict__ aip,
+template <int R, bool VEC, typename T>
+__global__ __launch_bounds__(kBlock) void k_ingest(T* __restrict__ pool, const uint32_t* __restrict__ aip,
                                                    const uint32_t* __restrict__ bip, uint64_t n, Geometry G,
                                                    uint32_t c0) {
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -174,15 +221,22 @@ __global__ __launch_bounds__(kBlock) void k_ingest(uint8_t* __restrict__ pool, c
 // (frame group, row) region of the pool -- a 2 MiB working set on the link
 // geometry instead of the whole pool.
 constexpr uint32_t kBins = 8;
+constexpr uint32_t kSubs = 64;        // sub-runs per bin: spreads the run reservations over 512 counters
+constexpr uint32_t kBinTile = 2048;   // pairs per block round
 
+// Bin b, sub-run s holds records bins[(b * kSubs + s) * sub_cap + j], j < fill[b * kSubs + s];
+// a block with index B only appends to sub-run B mod kSubs.  With n <= 8192
+// tiles every block takes at most one tile, so a sub-run receives at most
+// ceil(ceil(n / kBinTile) / kSubs) tiles <= n / kSubs + 32 + kBinTile pairs;
+// sub_cap = ceil(n / kSubs) + 2 kBinTile covers that.
 __global__ __launch_bounds__(kBlock) void k_bin_pairs(const uint32_t* __restrict__ aip, const uint32_t* __restrict__ bip,
-                                                      uint64_t n, Geometry G, uint64_t* __restrict__ bins, uint64_t cap,
-                                                      unsigned long long* __restrict__ fill) {
+                                                      uint64_t n, Geometry G, uint64_t* __restrict__ bins,
+                                                      uint64_t sub_cap, unsigned long long* __restrict__ fill) {
+    constexpr uint32_t kPer = kBinTile / kBlock;
     __shared__ uint32_t cnt[kBins];
     __shared__ unsigned long long base[kBins];
-    constexpr uint32_t kPer = 16;  // pairs per thread per round
-    const uint64_t per_block = (uint64_t)kBlock * kPer;
-    for (uint64_t b0 = (uint64_t)blockIdx.x * per_block; b0 < n; b0 += (uint64_t)gridDim.x * per_block) {
+    const uint32_t sub = blockIdx.x % kSubs;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * kBinTile; b0 < n; b0 += (uint64_t)gridDim.x * kBinTile) {
         if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
         __syncthreads();
         uint64_t rec[kPer];
@@ -201,78 +255,148 @@ __global__ __launch_bounds__(kBlock) void k_bin_pairs(const uint32_t* __restrict
             }
         }
         __syncthreads();
-        if (threadIdx.x < kBins) base[threadIdx.x] = atomicAdd(&fill[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+        if (threadIdx.x < kBins)
+            base[threadIdx.x] =
+                cnt[threadIdx.x] ? atomicAdd(&fill[threadIdx.x * kSubs + sub], (unsigned long long)cnt[threadIdx.x])
+                                 : 0ull;
         __syncthreads();
 #pragma unroll
         for (uint32_t e = 0; e < kPer; e++)
             if (bin[e] < kBins) {
                 const unsigned long long pos = base[bin[e]] + slot[e];
-                if (pos < cap) bins[(uint64_t)bin[e] * cap + pos] = rec[e];
+                if (pos < sub_cap) bins[((uint64_t)bin[e] * kSubs + sub) * sub_cap + pos] = rec[e];
             }
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_bins(const uint64_t* __restrict__ bins, uint64_t cap,
+// The 64 sub-runs of a bin are scanned as one index space: each sub-run's
+// length is rounded up to a multiple of 4 (sub_cap is one too), so a group of
+// four consecutive indices never straddles two sub-runs; indices past a
+// sub-run's fill are skipped.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scan_bins(const uint64_t* __restrict__ bins, uint64_t sub_cap,
                                                       const unsigned long long* __restrict__ fill,
-                                                      uint8_t* __restrict__ pool, Geometry G, uint32_t c0, uint32_t row) {
+                                                      T* __restrict__ pool, Geometry G, uint32_t c0, uint32_t row) {
+    __shared__ unsigned long long pre[kSubs + 1];  // prefix of the rounded sub-run lengths
+    __shared__ unsigned long long len[kSubs];      // records in each sub-run
     const uint32_t bin = blockIdx.x % kBins;
-    const uint64_t nb = fill[bin] < cap ? fill[bin] : cap;
-    const uint64_t blocks_per_bin = gridDim.x / kBins;
-    const uint64_t* rec = bins + (uint64_t)bin * cap;
+    const uint64_t bpb = gridDim.x / kBins;  // blocks per bin
+    const uint64_t me = blockIdx.x / kBins;
+    if (threadIdx.x < 64) {
+        static_assert(kSubs == 64, "one lane per sub-run");
+        const uint32_t s = threadIdx.x;
+        const unsigned long long f = fill[bin * kSubs + s];
+        const unsigned long long nb = f < sub_cap ? f : sub_cap;
+        len[s] = nb;
+        unsigned long long v = (nb + 3) & ~3ull;
+        for (uint32_t o = 1; o < 64; o <<= 1) {
+            const unsigned long long t = __shfl_up(v, o, 64);
+            if (s >= o) v += t;
+        }
+        pre[s + 1] = v;
+        if (s == 0) pre[0] = 0;
+    }
+    __syncthreads();
+    const uint64_t total = pre[kSubs];
     const uint32_t sh = G.sh[row];
-    for (uint64_t q = (blockIdx.x / kBins) * kBlock + threadIdx.x; q < nb; q += blocks_per_bin * kBlock) {
-        const uint64_t r = rec[q];
-        const uint64_t L = r >> 32;
-        const uint32_t z = (uint32_t)(((r >> 16) & 0xFFFFu) << 3) | bin;
-        const uint32_t i = (uint32_t)(r & 0xFFFFu);
-        const uint64_t LL = L | (L << G.W);
-        const uint32_t x = column(LL, sh, G.ncol_mask);
-        const uint64_t idx = (((((uint64_t)z * G.r + row) << G.c) + x) << G.log2g) | i;
-        pool[idx] = (uint8_t)act_of(i, c0, G);
+    const uint64_t zr = (uint64_t)G.r;
+    for (uint64_t q0 = (me * kBlock + threadIdx.x) * 4; q0 < total; q0 += bpb * kBlock * 4) {
+        uint32_t s = 0;  // last sub-run with pre[s] <= q0
+#pragma unroll
+        for (uint32_t step = 32; step > 0; step >>= 1)
+            if (pre[s + step] <= q0) s += step;
+        const uint64_t local = q0 - pre[s];
+        const uint64_t nb = len[s];
+        const uint64_t* rec = bins + ((uint64_t)bin * kSubs + s) * sub_cap + local;
+        uint64_t r4[4];
+        if (local + 4 <= nb) {
+            const ulonglong2 a = *reinterpret_cast<const ulonglong2*>(rec);
+            const ulonglong2 b = *reinterpret_cast<const ulonglong2*>(rec + 2);
+            r4[0] = a.x;
+            r4[1] = a.y;
+            r4[2] = b.x;
+            r4[3] = b.y;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; e++) r4[e] = local + e < nb ? rec[e] : ~0ull;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const uint64_t r = r4[e];
+            if (r == ~0ull) continue;  // never a record: frame bits 16..31 stay below 0xFFFF
+            const uint64_t L = r >> 32;
+            const uint32_t z = (uint32_t)(((r >> 16) & 0xFFFFu) << 3) | bin;
+            const uint32_t i = (uint32_t)(r & 0xFFFFu);
+            const uint64_t LL = L | (L << G.W);
+            const uint32_t x = column(LL, sh, G.ncol_mask);
+            const uint64_t idx = (((((uint64_t)z * zr + row) << G.c) + x) << G.log2g) | i;
+            pool[idx] = (T)act_of(i, c0, G);
+        }
     }
 }
 
 // ---------------------------------------------------------------- a4: close
-// One read of the pool: k'-weight of every ATV (Alg 1 per AT).  A group of
-// lpa = min(64, g/16) lanes covers one ATV with 16-byte loads; a wave covers
-// 64/lpa ATVs per step.  Block timestamps come from an LDS table of g bytes.
-__global__ __launch_bounds__(kBlock) void k_close(const uint8_t* __restrict__ pool, uint32_t* __restrict__ w,
-                                                  uint64_t n_atv, Geometry G, uint32_t c0, uint32_t kq) {
-    extern __shared__ __align__(16) uint8_t act_lut[];
+// One read of the pool: k'-weight of every ATV (Alg 1 per AT) for each of
+// the Wn.n windows.  A group of lpa = min(64, g/CA) lanes covers one ATV with
+// 16-byte loads of CA ATs; a wave covers 64/lpa ATVs per step.  Block
+// timestamps come from an LDS table of g ATs.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_close(const T* __restrict__ pool, uint32_t* __restrict__ w,
+                                                  uint64_t n_atv, Geometry G, uint32_t c0, CloseWindows Wn) {
+    extern __shared__ __align__(16) uint8_t smem_close[];
+    T* act_lut = reinterpret_cast<T*>(smem_close);
     fill_act_lut(act_lut, c0, G);
+    constexpr uint32_t CA = kPerChunk<T>;
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t lpa = G.g / 16 < 64 ? G.g / 16 : 64;
+    const uint32_t lpa = G.g / CA < 64 ? G.g / CA : 64;
     const uint32_t apw = 64 / lpa;
     const uint32_t sub = lane / lpa, sl = lane % lpa;
-    const uint32_t steps = G.g / (16 * lpa);
+    const uint32_t steps = G.g / (CA * lpa);
     const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
     for (uint64_t base = wave * apw; base < n_atv; base += nwaves * apw) {
-        uint64_t atv = base + sub;
-        uint32_t cnt = 0;
+        const uint64_t atv = base + sub;
+        uint32_t cnt[kMaxWindows];
+#pragma unroll
+        for (uint32_t j = 0; j < kMaxWindows; j++) cnt[j] = 0;
         if (atv < n_atv) {
-            const uint8_t* p = pool + (atv << G.log2g);
+            const T* p = pool + (atv << G.log2g);
             for (uint32_t st = 0; st < steps; st++) {
-                uint32_t off = (st * lpa + sl) * 16;
-                uint4 d = *reinterpret_cast<const uint4*>(p + off);
-                uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
-                cnt += __popc(active_mask16(d, ac, G.twok, kq));
+                const uint32_t off = (st * lpa + sl) * CA;
+                const uint4 d = *reinterpret_cast<const uint4*>(p + off);
+                const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
+                if (Wn.n == 1) {
+                    cnt[0] += __popc(active_mask_chunk<T>(d, ac, G.twok, Wn.kq[0]));
+                } else {
+#pragma unroll
+                    for (uint32_t j = 0; j < kMaxWindows; j++)
+                        if (j < Wn.n) cnt[j] += __popc(active_mask_chunk<T>(d, ac, G.twok, Wn.kq[j]));
+                }
             }
         }
-        for (uint32_t o = lpa / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-        if (sl == 0 && atv < n_atv) w[atv] = cnt;
+#pragma unroll
+        for (uint32_t j = 0; j < kMaxWindows; j++) {
+            if (j >= Wn.n) break;
+            uint32_t c = cnt[j];
+            for (uint32_t o = lpa / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+            if (sl == 0 && atv < n_atv) w[(uint64_t)j * n_atv + atv] = c;
+        }
     }
 }
 
 // One workgroup per (frame, row): AAT = sum of the row's weights, and the
 // ascending list of super columns (weight >= T) with its length.
-__global__ __launch_bounds__(kBlock) void k_summarize(const uint32_t* __restrict__ w, uint64_t* __restrict__ aat,
-                                                      uint32_t* __restrict__ sa, uint32_t* __restrict__ sa_cnt,
-                                                      Geometry G) {
+__global__ __launch_bounds__(kBlock) void k_summarize(const uint32_t* __restrict__ w_all, uint64_t* __restrict__ aat_all,
+                                                      uint32_t* __restrict__ sa_all, uint32_t* __restrict__ sa_cnt_all,
+                                                      Geometry G, uint64_t n_atv, uint32_t ngroups) {
     __shared__ uint32_t wave_cnt[kBlock / 64];
     __shared__ unsigned long long wave_sum[kBlock / 64];
     const uint32_t grp = blockIdx.x;
+    const uint32_t* w = w_all + (uint64_t)blockIdx.y * n_atv;   // window blockIdx.y
+    uint64_t* aat = aat_all + (uint64_t)blockIdx.y * ngroups;
+    uint32_t* sa = sa_all + (uint64_t)blockIdx.y * n_atv;
+    uint32_t* sa_cnt = sa_cnt_all + (uint64_t)blockIdx.y * ngroups;
     const uint64_t base = (uint64_t)grp << G.c;
     const uint32_t ncol = G.ncol_mask + 1;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
@@ -497,13 +621,15 @@ __device__ double eq4(uint32_t nat, uint32_t z, const uint64_t* __restrict__ aat
     return est;
 }
 
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_estimate(const uint8_t* __restrict__ pool, const uint64_t* __restrict__ aat,
+template <int R, typename T>
+__global__ __launch_bounds__(kBlock) void k_estimate(const T* __restrict__ pool, const uint64_t* __restrict__ aat,
                                                      const uint32_t* __restrict__ aips, uint64_t n, Geometry G,
                                                      uint32_t c0q, uint32_t kq, double* __restrict__ est,
                                                      uint8_t* __restrict__ flags, uint32_t* __restrict__ nat_out) {
-    extern __shared__ __align__(16) uint8_t act_lut[];
+    extern __shared__ __align__(16) uint8_t smem_est[];
+    T* act_lut = reinterpret_cast<T*>(smem_est);
     fill_act_lut(act_lut, c0q, G);
+    constexpr uint32_t CA = kPerChunk<T>;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
@@ -513,20 +639,20 @@ __global__ __launch_bounds__(kBlock) void k_estimate(const uint8_t* __restrict__
         const uint32_t z = f & G.umask;
         const uint64_t L = (uint64_t)(f >> G.u);
         const uint64_t LL = L | (L << G.W);
-        const uint8_t* rows[R];
+        const T* rows[R];
 #pragma unroll
         for (int j = 0; j < R; j++) {
             uint32_t x = column(LL, G.sh[j], G.ncol_mask);
             rows[j] = pool + (((((uint64_t)z * R + j) << G.c) + x) << G.log2g);
         }
         uint32_t cnt = 0;
-        for (uint32_t off = lane * 16; off < G.g; off += 64 * 16) {
+        for (uint32_t off = lane * CA; off < G.g; off += 64 * CA) {
             const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
-            uint32_t m = 0xFFFFu;
+            uint32_t m = ~0u;
 #pragma unroll
             for (int j = 0; j < R; j++) {
                 uint4 d = *reinterpret_cast<const uint4*>(rows[j] + off);
-                m &= active_mask16(d, ac, G.twok, kq);
+                m &= active_mask_chunk<T>(d, ac, G.twok, kq);
             }
             cnt += __popc(m);
         }
@@ -547,23 +673,25 @@ __global__ __launch_bounds__(kBlock) void k_estimate(const uint8_t* __restrict__
 // over the host's r ATs at position i when all are active for the full
 // window k.  feat[d] = #{i : e_i = d}/g (d < min(k, 61)); feat[61] =
 // min(ln(1 + max(plain, 0)), 20)/16 with plain the Eq 4 estimate for the
-// close's k'; feat[62] = k/64; feat[63] = mean over rows of AAT/(g*2^c).  The
-// histogram's prefix below k' is NAT(k'), so the plain estimate comes along.
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_features(const uint8_t* __restrict__ pool, const uint64_t* __restrict__ aat,
+// close's k'; feat[62] = k/64; feat[63] = mean over rows of AAT/(g*2^c).
+// NAT(k') = #{i : e_i < k'} is counted in the same pass, so the plain
+// estimate comes along.  The LDS histogram keeps ages below 64.
+template <int R, typename T>
+__global__ __launch_bounds__(kBlock) void k_features(const T* __restrict__ pool, const uint64_t* __restrict__ aat,
                                                      const uint32_t* __restrict__ aips, uint64_t n, Geometry G,
                                                      uint32_t c0q, uint32_t kq, float* __restrict__ feat,
                                                      double* __restrict__ est, uint8_t* __restrict__ flags) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    uint8_t* act_lut = smem;
-    uint32_t* hist = reinterpret_cast<uint32_t*>(smem + ((G.g + 15u) & ~15u)) + (threadIdx.x >> 6) * 128;
+    extern __shared__ __align__(16) uint8_t smem_feat[];
+    T* act_lut = reinterpret_cast<T*>(smem_feat);
+    uint32_t* hist =
+        reinterpret_cast<uint32_t*>(smem_feat + ((G.g * sizeof(T) + 15u) & ~15u)) + (threadIdx.x >> 6) * 64;
     fill_act_lut(act_lut, c0q, G);
+    constexpr uint32_t CA = kPerChunk<T>, N = kPerWord<T>;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
     for (uint64_t h = wave; h < n; h += nwaves) {
-        hist[lane] = 0;  // ages reach k - 1 <= 126: two bins per lane
-        hist[lane + 64] = 0;
+        hist[lane] = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         const uint32_t a = aips[h];
@@ -571,36 +699,38 @@ __global__ __launch_bounds__(kBlock) void k_features(const uint8_t* __restrict__
         const uint32_t z = f & G.umask;
         const uint64_t L = (uint64_t)(f >> G.u);
         const uint64_t LL = L | (L << G.W);
-        const uint8_t* rows[R];
+        const T* rows[R];
 #pragma unroll
         for (int j = 0; j < R; j++) {
             uint32_t x = column(LL, G.sh[j], G.ncol_mask);
             rows[j] = pool + (((((uint64_t)z * R + j) << G.c) + x) << G.log2g);
         }
-        for (uint32_t off = lane * 16; off < G.g; off += 64 * 16) {
+        uint32_t nat = 0;
+        for (uint32_t off = lane * CA; off < G.g; off += 64 * CA) {
             const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
             uint4 d[R];
 #pragma unroll
             for (int j = 0; j < R; j++) d[j] = *reinterpret_cast<const uint4*>(rows[j] + off);
 #pragma unroll
-            for (int b = 0; b < 16; b++) {
-                const uint32_t sh = 8 * (b & 3);
-                const uint32_t actb = ((b < 4 ? ac.x : b < 8 ? ac.y : b < 12 ? ac.z : ac.w) >> sh) & 0xFFu;
+            for (uint32_t b = 0; b < CA; b++) {
+                const uint32_t actb = at_in_word<T>(word_of(ac, b / N), b % N);
                 uint32_t e = 0, ok = 1;
 #pragma unroll
                 for (int j = 0; j < R; j++) {
-                    const uint32_t at = ((b < 4 ? d[j].x : b < 8 ? d[j].y : b < 12 ? d[j].z : d[j].w) >> sh) & 0xFFu;
+                    const uint32_t at = at_in_word<T>(word_of(d[j], b / N), b % N);
                     const uint32_t dist = actb >= at ? actb - at : actb + G.twok - at;
                     ok &= (at != G.twok) & (dist < G.k);
                     e = dist > e ? dist : e;
                 }
-                if (ok) atomicAdd(&hist[e], 1u);
+                if (ok) {
+                    nat += e < kq;
+                    if (e < 64) atomicAdd(&hist[e], 1u);
+                }
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         const uint32_t hv = hist[lane];
-        uint32_t nat = (lane < kq ? hv : 0u) + (lane + 64 < kq ? hist[lane + 64] : 0u);
         for (uint32_t o = 32; o > 0; o >>= 1) nat += __shfl_xor(nat, o, 64);
         uint8_t fl = 0;
         double e_plain = 0.0;
@@ -661,21 +791,17 @@ __global__ __launch_bounds__(kBlock) void k_serve_preserve(const StepDesc* __res
         const uint32_t per_atv = S.nw0 + S.nw1;
         const uint64_t rem = it - d->open_prefix[o];
         const uint64_t atv = rem / per_atv;
-        const uint32_t wi = (uint32_t)(rem - atv * per_atv);
-        const uint32_t word = wi < S.nw0 ? S.w0lo + wi : S.w1lo + (wi - S.nw0);
+        const uint32_t ci = (uint32_t)(rem - atv * per_atv);
+        const uint32_t chunk = ci < S.nw0 ? S.w0lo + ci : S.w1lo + (ci - S.nw0);
         const uint32_t k = ls.G.k, twok = ls.G.twok;
-        uint32_t* p = (uint32_t*)(ls.pool + (atv << ls.G.log2g)) + word;
-        uint32_t v = *p, nv = v;
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            uint32_t pos = word * 4 + b;
-            uint32_t at = (v >> (8 * b)) & 0xFFu;
-            uint32_t out = at;
-            if (pos >= S.r0lo && pos < S.r0hi && at <= k) out = twok;
-            if (pos >= S.r1lo && pos < S.r1hi && ((at >= k && at < twok) || at == 0)) out = twok;
-            nv = (nv & ~(0xFFu << (8 * b))) | (out << (8 * b));
-        }
-        if (nv != v) *p = nv;
+        uint4* p = reinterpret_cast<uint4*>(ls.pool + (atv << ls.G.log2g)) + chunk;
+        const uint4 v = *p;
+        uint4 nv;
+        nv.x = preserve_word(v.x, chunk * 16, S, k, twok);
+        nv.y = preserve_word(v.y, chunk * 16 + 4, S, k, twok);
+        nv.z = preserve_word(v.z, chunk * 16 + 8, S, k, twok);
+        nv.w = preserve_word(v.w, chunk * 16 + 12, S, k, twok);
+        if (nv.x != v.x || nv.y != v.y || nv.z != v.z || nv.w != v.w) *p = nv;
     }
 }
 
@@ -1033,6 +1159,27 @@ __global__ __launch_bounds__(kBlock) void k_serve_features(const StepDesc* __res
     }
 }
 
+// Comparator: the aging counters of ACE (Section 2.3) must all be decremented
+// at every slice end -- one read and one write of the whole pool -- where the
+// asynchronous timestamps only touch two blocks of each ATV (k_preserve).
+__global__ __launch_bounds__(kBlock) void k_ace_age(uint8_t* __restrict__ p, uint64_t n16) {
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n16; q += (uint64_t)gridDim.x * blockDim.x) {
+        uint4 v = reinterpret_cast<uint4*>(p)[q];
+        uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            uint32_t x = w[e], out = 0;
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                uint32_t c = (x >> (8 * b)) & 0xFFu;
+                out |= (c ? c - 1 : 0u) << (8 * b);
+            }
+            w[e] = out;
+        }
+        reinterpret_cast<uint4*>(p)[q] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
 // ---------------------------------------------------------------- probes
 // Scatter roofline probe: the same input stream as the pair scan (8 B per
 // item, 16-byte vector loads) and the same number of byte stores per item,
@@ -1069,13 +1216,56 @@ uint32_t grid_for(uint64_t items, uint32_t cap) {
     return (uint32_t)(b < cap ? b : cap);
 }
 
+
+// Calls f(std::integral_constant<int, R>{}, T{}) for the handle's row count R
+// (1..8) and AT type T (uint8_t, or uint16_t when G.atb == 2).
+template <typename T, typename F>
+hipError_t with_rows(uint32_t r, F&& f) {
+    switch (r) {
+        case 1: f(std::integral_constant<int, 1>{}, T{}); break;
+        case 2: f(std::integral_constant<int, 2>{}, T{}); break;
+        case 3: f(std::integral_constant<int, 3>{}, T{}); break;
+        case 4: f(std::integral_constant<int, 4>{}, T{}); break;
+        case 5: f(std::integral_constant<int, 5>{}, T{}); break;
+        case 6: f(std::integral_constant<int, 6>{}, T{}); break;
+        case 7: f(std::integral_constant<int, 7>{}, T{}); break;
+        case 8: f(std::integral_constant<int, 8>{}, T{}); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename F>
+hipError_t with_rows_at(const Geometry& G, F&& f) {
+    if (G.atb == 2) return with_rows<uint16_t>(G.r, f);
+    if (G.atb == 1) return with_rows<uint8_t>(G.r, f);
+    return hipErrorInvalidValue;
+}
+
+template <typename F>
+hipError_t with_at(const Geometry& G, F&& f) {
+    if (G.atb == 2) f(uint16_t{});
+    else if (G.atb == 1) f(uint8_t{});
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // ============================================================== launchers
 
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for((n + 15) / 16, 1u << 16)), dim3(kBlock), 0, st, p, n, v);
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for((n + 15) / 16, 1u << 16)), dim3(kBlock), 0, st, p, n,
+                       v * 0x01010101u);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_pool(uint8_t* pool, uint64_t n_at, const Geometry& G, hipStream_t st) {
+    if (n_at == 0) return hipSuccess;
+    const uint64_t bytes = n_at * G.atb;
+    const uint32_t v4 = G.atb == 2 ? G.twok * 0x00010001u : G.twok * 0x01010101u;
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for((bytes + 15) / 16, 1u << 16)), dim3(kBlock), 0, st, pool, bytes, v4);
     return hipGetLastError();
 }
 
@@ -1102,18 +1292,20 @@ PreserveSpans preserve_spans(const Geometry& G, uint32_t c0) {
     PreserveSpans S{};
     range(b0, S.r0lo, S.r0hi);
     range(b1, S.r1lo, S.r1hi);
-    // word spans of the two byte ranges, merged when they touch a common word
+    // 16-byte chunk spans (ca ATs each) of the two AT ranges, merged when
+    // they share a chunk
+    const uint32_t ca = 16 / G.atb;
     uint32_t sp[2][2];
     int ns = 0;
-    if (S.r0hi > S.r0lo) { sp[ns][0] = S.r0lo / 4; sp[ns][1] = (S.r0hi + 3) / 4; ns++; }
-    if (S.r1hi > S.r1lo) { sp[ns][0] = S.r1lo / 4; sp[ns][1] = (S.r1hi + 3) / 4; ns++; }
+    if (S.r0hi > S.r0lo) { sp[ns][0] = S.r0lo / ca; sp[ns][1] = (S.r0hi + ca - 1) / ca; ns++; }
+    if (S.r1hi > S.r1lo) { sp[ns][0] = S.r1lo / ca; sp[ns][1] = (S.r1hi + ca - 1) / ca; ns++; }
     if (ns == 2) {
         if (sp[0][0] > sp[1][0]) {
             uint32_t t0 = sp[0][0], t1 = sp[0][1];
             sp[0][0] = sp[1][0]; sp[0][1] = sp[1][1];
             sp[1][0] = t0; sp[1][1] = t1;
         }
-        if (sp[1][0] <= sp[0][1]) {  // overlapping or adjacent word spans
+        if (sp[1][0] <= sp[0][1]) {  // overlapping or adjacent chunk spans
             sp[0][1] = sp[1][1] > sp[0][1] ? sp[1][1] : sp[0][1];
             ns = 1;
         }
@@ -1127,9 +1319,11 @@ hipError_t launch_preserve(uint8_t* pool, uint64_t n_atv, const Geometry& G, uin
     const PreserveSpans S = preserve_spans(G, c0);
     const uint64_t items = n_atv * (S.nw0 + S.nw1);
     if (items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_preserve, dim3(grid_for(items, 1u << 16)), dim3(kBlock), 0, st, pool, n_atv, G.log2g,
-                       G.k, S);
-    return hipGetLastError();
+    return with_at(G, [&](auto t) {
+        using T = decltype(t);
+        hipLaunchKernelGGL(k_preserve<T>, dim3(grid_for(items, 1u << 16)), dim3(kBlock), 0, st, pool, n_atv, G.log2g,
+                           G.k, S);
+    });
 }
 
 hipError_t launch_ingest(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n, const Geometry& G,
@@ -1137,61 +1331,59 @@ hipError_t launch_ingest(uint8_t* pool, const uint32_t* aip, const uint32_t* bip
     if (n == 0) return hipSuccess;
     const bool vec = ((reinterpret_cast<uintptr_t>(aip) | reinterpret_cast<uintptr_t>(bip)) & 15u) == 0;
     const uint32_t grid = grid_for(vec ? (n + 3) / 4 : n, 1u << 20);
-#define AT_INGEST_CASE(RR)                                                                              \
-    case RR:                                                                                            \
-        if (vec)                                                                                        \
-            hipLaunchKernelGGL((k_ingest<RR, true>), dim3(grid), dim3(kBlock), 0, st, pool, aip, bip, n, G, c0); \
-        else                                                                                            \
-            hipLaunchKernelGGL((k_ingest<RR, false>), dim3(grid), dim3(kBlock), 0, st, pool, aip, bip, n, G, c0); \
-        break;
-    switch (G.r) {
-        AT_INGEST_CASE(1)
-        AT_INGEST_CASE(2)
-        AT_INGEST_CASE(3)
-        AT_INGEST_CASE(4)
-        AT_INGEST_CASE(5)
-        AT_INGEST_CASE(6)
-        AT_INGEST_CASE(7)
-        AT_INGEST_CASE(8)
-        default:
-            return hipErrorInvalidValue;
-    }
-#undef AT_INGEST_CASE
-    return hipGetLastError();
+    return with_rows_at(G, [&](auto rc, auto t) {
+        constexpr int R = decltype(rc)::value;
+        using T = decltype(t);
+        T* p = reinterpret_cast<T*>(pool);
+        if (vec)
+            hipLaunchKernelGGL((k_ingest<R, true, T>), dim3(grid), dim3(kBlock), 0, st, p, aip, bip, n, G, c0);
+        else
+            hipLaunchKernelGGL((k_ingest<R, false, T>), dim3(grid), dim3(kBlock), 0, st, p, aip, bip, n, G, c0);
+    });
 }
 
+uint64_t binned_sub_cap(uint64_t n) { return ((n + kSubs - 1) / kSubs + 2 * kBinTile + 3) & ~3ull; }
+
 hipError_t launch_ingest_binned(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n, const Geometry& G,
-                                uint32_t c0, uint64_t* bins, uint64_t cap, unsigned long long* fill, hipStream_t st) {
+                                uint32_t c0, uint64_t* bins, uint64_t sub_cap, unsigned long long* fill,
+                                hipStream_t st) {
     if (n == 0) return hipSuccess;
-    if (n > cap) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(kBins), 0, st, fill, kBins);
-    const uint64_t per_block = (uint64_t)kBlock * 16;
-    uint64_t blocks = (n + per_block - 1) / per_block;
+    if (binned_sub_cap(n) > sub_cap || n > (uint64_t)8192 * kBinTile) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_zero_u64, dim3((kBins * kSubs + kBlock - 1) / kBlock), dim3(kBlock), 0, st, fill,
+                       kBins * kSubs);
+    uint64_t blocks = (n + kBinTile - 1) / kBinTile;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_bin_pairs, dim3((uint32_t)blocks), dim3(kBlock), 0, st, aip, bip, n, G, bins, cap, fill);
-    uint64_t per_bin = (n / kBins + kBlock - 1) / kBlock;
+    blocks = (blocks + kSubs - 1) / kSubs * kSubs;  // every sub-run gets the same number of blocks
+    hipLaunchKernelGGL(k_bin_pairs, dim3((uint32_t)blocks), dim3(kBlock), 0, st, aip, bip, n, G, bins, sub_cap, fill);
+    uint64_t per_bin = (n / kBins + 4 * kBlock - 1) / (4 * kBlock);
     if (per_bin < 1) per_bin = 1;
     if (per_bin > 512) per_bin = 512;
-    for (uint32_t row = 0; row < G.r; row++)
-        hipLaunchKernelGGL(k_scan_bins, dim3((uint32_t)(kBins * per_bin)), dim3(kBlock), 0, st, bins, cap, fill, pool, G,
-                           c0, row);
-    return hipGetLastError();
+    return with_at(G, [&](auto t) {
+        using T = decltype(t);
+        for (uint32_t row = 0; row < G.r; row++)
+            hipLaunchKernelGGL(k_scan_bins<T>, dim3((uint32_t)(kBins * per_bin)), dim3(kBlock), 0, st, bins, sub_cap,
+                               fill, reinterpret_cast<T*>(pool), G, c0, row);
+    });
 }
 
 hipError_t launch_close(const uint8_t* pool, uint32_t* w, uint64_t n_atv, const Geometry& G, uint32_t c0,
-                        uint32_t kq, hipStream_t st) {
-    const uint32_t lpa = G.g / 16 < 64 ? G.g / 16 : 64;
+                        const CloseWindows& Wn, hipStream_t st) {
+    const uint32_t ca = 16 / G.atb;  // ATs per 16-byte chunk
+    const uint32_t lpa = G.g / ca < 64 ? G.g / ca : 64;
     const uint64_t atv_per_block = (kBlock / 64) * (64 / lpa);
     uint64_t blocks = (n_atv + atv_per_block - 1) / atv_per_block;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_close, dim3((uint32_t)blocks), dim3(kBlock), G.g, st, pool, w, n_atv, G, c0, kq);
-    return hipGetLastError();
+    return with_at(G, [&](auto t) {
+        using T = decltype(t);
+        hipLaunchKernelGGL(k_close<T>, dim3((uint32_t)blocks), dim3(kBlock), G.g * sizeof(T), st,
+                           reinterpret_cast<const T*>(pool), w, n_atv, G, c0, Wn);
+    });
 }
 
 hipError_t launch_summarize(const uint32_t* w, uint64_t* aat, uint32_t* sa, uint32_t* sa_cnt, const Geometry& G,
-                            hipStream_t st) {
+                            uint64_t n_atv, uint32_t nwin, hipStream_t st) {
     const uint32_t groups = (G.umask + 1) * G.r;
-    hipLaunchKernelGGL(k_summarize, dim3(groups), dim3(kBlock), 0, st, w, aat, sa, sa_cnt, G);
+    hipLaunchKernelGGL(k_summarize, dim3(groups, nwin), dim3(kBlock), 0, st, w, aat, sa, sa_cnt, G, n_atv, groups);
     return hipGetLastError();
 }
 
@@ -1230,25 +1422,12 @@ hipError_t launch_estimate(const uint8_t* pool, const uint64_t* aat, const uint3
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + 3) / 4;
     if (blocks > 16384) blocks = 16384;
-#define AT_EST_CASE(RR)                                                                                  \
-    case RR:                                                                                             \
-        hipLaunchKernelGGL((k_estimate<RR>), dim3((uint32_t)blocks), dim3(kBlock), G.g, st, pool, aat, aip, n, G, \
-                           c0q, kq, est, flags, nat);                                                    \
-        break;
-    switch (G.r) {
-        AT_EST_CASE(1)
-        AT_EST_CASE(2)
-        AT_EST_CASE(3)
-        AT_EST_CASE(4)
-        AT_EST_CASE(5)
-        AT_EST_CASE(6)
-        AT_EST_CASE(7)
-        AT_EST_CASE(8)
-        default:
-            return hipErrorInvalidValue;
-    }
-#undef AT_EST_CASE
-    return hipGetLastError();
+    return with_rows_at(G, [&](auto rc, auto t) {
+        constexpr int R = decltype(rc)::value;
+        using T = decltype(t);
+        hipLaunchKernelGGL((k_estimate<R, T>), dim3((uint32_t)blocks), dim3(kBlock), G.g * sizeof(T), st,
+                           reinterpret_cast<const T*>(pool), aat, aip, n, G, c0q, kq, est, flags, nat);
+    });
 }
 
 hipError_t launch_features(const uint8_t* pool, const uint64_t* aat, const uint32_t* aip, uint64_t n,
@@ -1257,26 +1436,13 @@ hipError_t launch_features(const uint8_t* pool, const uint64_t* aat, const uint3
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + 3) / 4;
     if (blocks > 16384) blocks = 16384;
-    const size_t shmem = ((G.g + 15u) & ~15u) + (kBlock / 64) * 128 * sizeof(uint32_t);
-#define AT_FEAT_CASE(RR)                                                                                   \
-    case RR:                                                                                               \
-        hipLaunchKernelGGL((k_features<RR>), dim3((uint32_t)blocks), dim3(kBlock), shmem, st, pool, aat, aip, n, G, \
-                           c0q, kq, feat, est, flags);                                                     \
-        break;
-    switch (G.r) {
-        AT_FEAT_CASE(1)
-        AT_FEAT_CASE(2)
-        AT_FEAT_CASE(3)
-        AT_FEAT_CASE(4)
-        AT_FEAT_CASE(5)
-        AT_FEAT_CASE(6)
-        AT_FEAT_CASE(7)
-        AT_FEAT_CASE(8)
-        default:
-            return hipErrorInvalidValue;
-    }
-#undef AT_FEAT_CASE
-    return hipGetLastError();
+    const size_t shmem = ((G.g * G.atb + 15u) & ~15u) + (kBlock / 64) * 64 * sizeof(uint32_t);
+    return with_rows_at(G, [&](auto rc, auto t) {
+        constexpr int R = decltype(rc)::value;
+        using T = decltype(t);
+        hipLaunchKernelGGL((k_features<R, T>), dim3((uint32_t)blocks), dim3(kBlock), shmem, st,
+                           reinterpret_cast<const T*>(pool), aat, aip, n, G, c0q, kq, feat, est, flags);
+    });
 }
 
 constexpr uint32_t kServeGrid = 2048;  // persistent grid of the batched kernels
@@ -1331,6 +1497,12 @@ hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, 
             return hipErrorInvalidValue;
     }
 #undef AT_SERVE_FEAT
+    return hipGetLastError();
+}
+
+hipError_t launch_ace_age(uint8_t* p, uint64_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ace_age, dim3(grid_for(bytes / 16, 1u << 16)), dim3(kBlock), 0, st, p, bytes / 16);
     return hipGetLastError();
 }
 

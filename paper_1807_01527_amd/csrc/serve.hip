@@ -15,8 +15,11 @@
 // waits for that close, so the two branches never touch the same pool.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <thread>
 #include <cstdint>
 #include <cstring>
 #include <deque>
@@ -66,6 +69,7 @@ Geometry derive_geometry(const at_params& p) {
     Geometry G{};
     G.k = p.k;
     G.twok = 2 * p.k;
+    G.atb = G.twok < 256 ? 1 : 2;  // AT bytes: 2k + 1 values per AT
     G.r = p.r;
     G.c = p.c;
     G.s = p.s;
@@ -196,6 +200,13 @@ struct at_serve {
     const void* mlp_key = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // native stepping thread
+    std::thread worker;
+    std::condition_variable cv;
+    bool stop = false;
+    bool running = false;
+    int device = 0;
+    int worker_rc = AT_OK;
     // results
     std::deque<Result> results;
     uint64_t steps = 0;
@@ -437,8 +448,11 @@ int at_serve_create(const at_serve_config* cfg, at_serve** out) {
     return AT_OK;
 }
 
+int at_serve_stop(at_serve* S);
+
 int at_serve_destroy(at_serve* S) {
     if (!S) return AT_OK;
+    at_serve_stop(S);
     { std::lock_guard<std::mutex> sg(S->step_mu); }
     (void)hipStreamSynchronize(S->s0);
     (void)hipStreamSynchronize(S->s1);
@@ -559,6 +573,7 @@ int at_serve_submit(at_serve* S, uint32_t link_id, const uint32_t* aip_dev, cons
     if (L->state != L_ACTIVE) return AT_E_STATE;
     if (n == 0) return AT_OK;
     L->q.push_back(Event{false, aip_dev, bip_dev, n, 0, 0.0});
+    S->cv.notify_one();
     return AT_OK;
 }
 
@@ -571,6 +586,7 @@ int at_serve_end_slice(at_serve* S, uint32_t link_id, uint32_t kprime) {
     if (L->state != L_ACTIVE) return AT_E_STATE;
     if (kprime < 1 || kprime > L->p.k) return AT_E_INVAL;
     L->q.push_back(Event{true, nullptr, nullptr, 0, kprime, t});
+    S->cv.notify_one();
     return AT_OK;
 }
 
@@ -695,6 +711,64 @@ int at_serve_step(at_serve* S, uint32_t* n_results) {
     }
     if (n_results) *n_results = produced;
     return AT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+bool has_work(const at_serve* S) {  // caller holds mu
+    for (const Link* L : S->links)
+        if (L && L->state == L_ACTIVE && !L->q.empty()) return true;
+    return false;
+}
+
+void worker_loop(at_serve* S) {
+    (void)hipSetDevice(S->device);
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait(lk, [&] { return S->stop || has_work(S); });
+            if (S->stop && !has_work(S)) return;
+        }
+        uint32_t n = 0;
+        int rc = at_serve_step(S, &n);
+        if (rc != AT_OK) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->worker_rc = rc;
+            return;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int at_serve_start(at_serve* S) {
+    if (!S) return AT_E_INVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->running) return AT_E_STATE;
+    if (hipGetDevice(&S->device) != hipSuccess) return AT_E_DEVICE;
+    S->stop = false;
+    S->worker_rc = AT_OK;
+    S->worker = std::thread(worker_loop, S);
+    S->running = true;
+    return AT_OK;
+}
+
+int at_serve_stop(at_serve* S) {
+    if (!S) return AT_E_INVAL;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (!S->running) return AT_OK;
+        S->stop = true;
+    }
+    S->cv.notify_all();
+    S->worker.join();
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->running = false;
+    return S->worker_rc;
 }
 
 int at_serve_next_result(at_serve* S, at_serve_result* out, uint32_t* cand, double* cand_plain,

@@ -169,14 +169,20 @@ def make_trace(shape: TraceShape, seed: int, trace: int, device) -> Tuple[List[t
 
 
 def link_stream(seed: int, n_pairs: int, device, hosts: int = 1 << 16, zipf_s: float = 1.1, planted: int = 32,
-                lo: int = 1500, hi: int = 8000) -> Tuple[torch.Tensor, torch.Tensor, np.ndarray]:
-    """A long pair stream of one link (small-configuration content: Zipf
-    background, uniform 32-bit bips, planted hosts with U[lo, hi] distinct
-    bips spread uniformly over the stream).  Returns int32 aip and bip device
-    tensors and the planted hosts.  Consecutive sub-ranges serve as slices."""
+                lo: int = 1500, hi: int = 8000, card_dist: str = "uniform") -> Tuple[torch.Tensor, torch.Tensor,
+                                                                                     np.ndarray]:
+    """A long pair stream of one link (by default small-configuration content:
+    Zipf background, uniform 32-bit bips, planted hosts with U[lo, hi]
+    distinct bips spread uniformly over the stream; card_dist="loguniform"
+    draws the planted cardinalities log-uniformly over [lo, hi]).  Returns
+    int32 aip and bip device tensors and the planted hosts.  Consecutive
+    sub-ranges serve as slices."""
     base = 0x9000
     u = rand_unit(seed, base, planted, device).cpu().numpy()
-    card = (lo + np.floor(u * (hi - lo + 1))).astype(np.int64)
+    if card_dist == "loguniform":
+        card = np.floor(np.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))).astype(np.int64)
+    else:
+        card = (lo + np.floor(u * (hi - lo + 1))).astype(np.int64)
     n_pl = int(card.sum())
     n_bg = max(n_pairs - n_pl, 0)
     hid = torch.repeat_interleave(torch.arange(planted, device=device), torch.from_numpy(card).to(device))

@@ -98,3 +98,23 @@ def run_trace(gpu, orc, aip_slices, bip_slices, kprimes=None, batches=3, seed=0,
             compare_estimates(gpu, orc, hosts, where)
         if restore:
             compare_restore(gpu, orc, cap=cap, where=where)
+
+
+def compare_serve_results(got, want, where):
+    """Per closed slice: a served link's results against the single-link API's."""
+    assert len(got) == len(want), where
+    for s, (g, w) in enumerate(zip(got, want)):
+        tag = f"{where} slice {s}"
+        assert g["slice"] == s, tag
+        assert g["restore_rc"] == w["restore_rc"], tag
+        assert g["n_out"] == w["n_out"], tag
+        assert np.array_equal(g["cand"], w["cand"]), tag
+        for key in ("cand_plain", "cand_learned", "watch_plain", "watch_learned"):
+            a, b = np.asarray(g[key]), np.asarray(w[key])
+            assert a.shape == b.shape, (tag, key)
+            assert np.array_equal(np.isfinite(a), np.isfinite(b)), (tag, key)
+            fin = np.isfinite(b)
+            assert np.all(np.abs(a[fin] - b[fin]) <= 1e-12 * np.abs(b[fin])), (tag, key)
+        assert np.array_equal(g["cand_flags"], w["cand_flags"]), tag
+        assert np.array_equal(g["watch_flags"], w["watch_flags"]), tag
+        assert g["latency_ms"] > 0

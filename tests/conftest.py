@@ -10,7 +10,7 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
-    config.addinivalue_line("markers", "slow: exhaustive CPU pin (seconds to a minute)")
+    config.addinivalue_line("markers", "slow: long-running (exhaustive CPU pins, full-size GPU workloads)")
 
 
 @pytest.fixture(scope="session")

@@ -39,7 +39,7 @@ def test_strerror_and_null_handles():
     dict(k=4, r=4, c=9, s=7, u=0, log2g=9),      # c + s(r-1) < W: incomplete
     dict(k=4, r=4, c=7, s=7, u=4, log2g=9),      # c*r <= W: no redundancy
     dict(k=0, r=4, c=9, s=8, u=0, log2g=9),
-    dict(k=128, r=4, c=9, s=8, u=0, log2g=9),
+    dict(k=32768, r=4, c=9, s=8, u=0, log2g=9),  # 2k no longer fits a 16-bit AT
     dict(k=4, r=9, c=9, s=4, u=0, log2g=9),      # more rows than supported
     dict(k=4, r=4, c=9, s=10, u=0, log2g=9),     # s > c
     dict(k=4, r=4, c=9, s=8, u=0, log2g=3),      # g below 16

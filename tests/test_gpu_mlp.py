@@ -34,10 +34,12 @@ def _dev_f32(torch, a):
     (dict(k=4, r=4, c=9, s=8, u=0, log2g=9, theta=1024.0, seed=0), dict(seed=0)),
     (dict(k=5, r=3, c=11, s=10, u=3, log2g=7, theta=64.0, seed=3), dict(seed=2, n_slices=9, pairs_per_slice=4000)),
     (dict(k=13, r=4, c=8, s=8, u=1, log2g=4, theta=16.0, seed=4), dict(seed=3, n_slices=20, pairs_per_slice=2000)),
+    # 16-bit ATs (k > 127), ages beyond the histogram's 64 bins
+    (dict(k=150, r=4, c=8, s=8, u=1, log2g=9, theta=64.0, seed=6), dict(seed=5, n_slices=170, pairs_per_slice=1500)),
 ])
 def test_features_match_oracle(torch_cuda, oracle_lib, geom, tr_kw):
     torch = torch_cuda
-    if geom["log2g"] == 9:
+    if "n_slices" not in tr_kw:
         tr = traffic.generate(traffic.config_small(seed=0))
     else:
         tr = traffic.generate(traffic.config_tiny(**tr_kw))
@@ -64,6 +66,7 @@ def test_features_match_oracle(torch_cuda, oracle_lib, geom, tr_kw):
     assert np.allclose(est.cpu().numpy(), e_o, rtol=1e-12, atol=0, equal_nan=False)
     # the histogram's prefix below k' is NAT(k')
     kq = o.clock()["kq"]
+    assert kq <= 61
     assert np.array_equal(np.rint(f_o[:, :kq].astype(np.float64).sum(1) * g.g).astype(np.int64), nat_o)
 
 

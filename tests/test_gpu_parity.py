@@ -113,7 +113,7 @@ def test_error_paths(cuda, oracle_lib):
     from paper_1807_01527_amd import binding
     from paper_1807_01527_amd.binding import AtError, AtPool
     bad = [dict(k=4, r=4, c=9, s=7, u=0, log2g=9), dict(k=0, r=4, c=9, s=8, u=0, log2g=9),
-           dict(k=128, r=4, c=9, s=8, u=0, log2g=9), dict(k=4, r=4, c=7, s=7, u=4, log2g=9),
+           dict(k=32768, r=4, c=9, s=8, u=0, log2g=9), dict(k=4, r=4, c=7, s=7, u=4, log2g=9),
            dict(k=4, r=4, c=9, s=8, u=0, log2g=9, theta=0.0)]
     for p in bad:
         assert AtPool.try_create(**p) == binding.AT_E_INVAL
@@ -166,3 +166,84 @@ def test_scan_modes(cuda, oracle_lib, geom, mode):
     g, o = make_pair(dict(**geom, theta=64.0, seed=9), oracle_lib)
     g.set_scan_mode(mode)
     run_trace(g, o, tr.aip, tr.bip, batches=5, seed=2, query_hosts=tr.planted_hosts, restore=False)
+
+
+def test_ace_age_probe(cuda):
+    """The comparator's aging pass decrements every nonzero counter by one."""
+    import torch
+    from paper_1807_01527_amd.binding import probe_ace_age
+    rng = np.random.default_rng(3)
+    v = rng.integers(0, 256, 1 << 20).astype(np.uint8)
+    d = torch.from_numpy(v.copy()).cuda()
+    probe_ace_age(d)
+    torch.cuda.synchronize()
+    assert np.array_equal(d.cpu().numpy(), np.maximum(v.astype(np.int64) - 1, 0).astype(np.uint8))
+
+
+@pytest.mark.parametrize("geom", [
+    dict(k=6, r=4, c=8, s=8, u=1, log2g=7),
+    dict(k=10, r=4, c=9, s=7, u=3, log2g=10),
+    dict(k=150, r=4, c=8, s=8, u=1, log2g=9),     # 16-bit ATs
+])
+def test_close_multi_windows(cuda, oracle_lib, geom):
+    """One close summarising several windows k' (Section 3: every k' <= k is
+    answerable from the same state) equals the oracle re-summarised for each
+    k', and leaves the pool and clock as a single-window close does."""
+    from paper_1807_01527_amd import binding
+    from paper_1807_01527_amd.binding import AtError
+    k = geom["k"]
+    tr = _tiny(seed=21 + k, n_slices=k + 4, pairs_per_slice=9001, hosts=1 << 10, planted=4, lo=300, hi=2000)
+    g, o = make_pair(dict(**geom, theta=256.0, seed=4), oracle_lib)
+    wins = sorted({1, 2, k // 2, k - 1, k})[:8]
+    for t in range(tr.n_slices):
+        g.ingest(to_dev(tr.aip[t]), to_dev(tr.bip[t]))
+        o.ingest(tr.aip[t], tr.bip[t])
+        order = wins[::-1] if t % 2 else wins
+        g.close_multi(order)
+        o.close(order[0])
+        compare_state(g, o, f"slice {t}")
+        if t < k - 1 and t != tr.n_slices - 1:
+            continue
+        hosts = np.unique(np.concatenate([tr.planted_hosts, tr.aip[t][:64]]))
+        for kp in order[1:] + order[:1]:
+            g.select_window(kp)
+            assert o.requery(kp) == 0
+            where = f"slice {t} window {kp}"
+            compare_state(g, o, where, pool=False)
+            compare_summary(g, o, where)
+            compare_estimates(g, o, hosts, where)
+            compare_restore(g, o, where=where)
+    with pytest.raises(AtError) as e:
+        g.select_window(k + 1 if k + 1 not in wins else 99)
+    assert e.value.rc == binding.AT_E_INVAL
+    for bad in ([], [k + 1], [0], list(range(1, 10))):
+        with pytest.raises(AtError) as e:
+            g.close_multi(bad)
+        assert e.value.rc == binding.AT_E_INVAL
+    g.ingest(to_dev(tr.aip[0][:10]), to_dev(tr.bip[0][:10]))
+    with pytest.raises(AtError) as e:
+        g.select_window(k)
+    assert e.value.rc == binding.AT_E_STATE
+    g.destroy()
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("geom,slices", [
+    (dict(k=150, r=4, c=8, s=8, u=1, log2g=9), 310),    # blocks of 1 AT and a 213-AT last block
+    (dict(k=300, r=4, c=8, s=8, u=3, log2g=4), 610),    # the paper's k; g < 2k: one block holds every AT
+    (dict(k=200, r=4, c=9, s=8, u=3, log2g=8), 40),     # 8 frames, a larger pool, no wrap
+])
+def test_wide_ats(cuda, oracle_lib, geom, slices, mode):
+    """k > 127 needs 2k+1 > 256 AT values: 16-bit ATs.  The two long runs go
+    past a full turn of the block clock (2k slices), with empty slices and a
+    cycle of windows k'; both scans; pool, summaries, estimates and restore
+    after every slice."""
+    k = geom["k"]
+    tr = _tiny(seed=k + mode, n_slices=slices, pairs_per_slice=1500, hosts=1 << 9, planted=3, lo=200, hi=900)
+    aip, bip = list(tr.aip), list(tr.bip)
+    for t in range(5, slices, 37):
+        aip[t], bip[t] = aip[t][:0], bip[t][:0]
+    g, o = make_pair(dict(**geom, theta=64.0, seed=7), oracle_lib)
+    assert g.at_bytes == 2 and g.pool_bytes == 2 * o.pool_size
+    g.set_scan_mode(mode)
+    run_trace(g, o, aip, bip, kprimes=[k, 1, k // 2, k - 1, 7], batches=3, seed=3, query_hosts=tr.planted_hosts)

@@ -11,7 +11,7 @@ import pytest
 from oracle import mlp as ref
 from paper_1807_01527_amd import traffic
 
-from ._parity import to_dev
+from ._parity import compare_serve_results as _compare, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -76,8 +76,9 @@ def _reference(k, seed, events, watch, net):
     return out, pool
 
 
-def _serve(links, net, seed=0, steps_every=3):
-    """Feed every link's events interleaved at random into one server."""
+def _serve(links, net, seed=0, steps_every=3, native=False):
+    """Feed every link's events interleaved at random into one server, stepping
+    it from here every few events, or from its native thread."""
     from paper_1807_01527_amd.binding import Server
     srv = Server(hbm_budget=1 << 34, max_links=16, cand_cap=CAND_CAP, watch_cap=WATCH_CAP, **SHAPE)
     srv.set_mlp(net)
@@ -91,6 +92,8 @@ def _serve(links, net, seed=0, steps_every=3):
     cursor = [0] * len(links)
     results = {lid: [] for lid in ids}
     n_sub = 0
+    if native:
+        srv.start()
     while any(c < len(ln["events"]) for c, ln in zip(cursor, links)):
         i = int(rng.integers(0, len(links)))
         if cursor[i] >= len(links[i]["events"]):
@@ -100,10 +103,14 @@ def _serve(links, net, seed=0, steps_every=3):
         rc = srv.submit(ids[i], ev[1], ev[2]) if ev[0] == "chunk" else srv.end_slice(ids[i], ev[1])
         assert rc == 0
         n_sub += 1
-        if n_sub % steps_every == 0:
+        if not native and n_sub % steps_every == 0:
             srv.step()
             for r in srv.results():
                 results[r["link"]].append(r)
+    if native:
+        srv.stop()                  # drains every queued event, then joins the thread
+        for r in srv.results():
+            results[r["link"]].append(r)
     for _ in range(4 * max(len(ln["events"]) for ln in links)):
         if all(srv.link_state(lid)[2] == 0 for lid in ids):
             break
@@ -114,25 +121,6 @@ def _serve(links, net, seed=0, steps_every=3):
     stats = srv.stats()
     srv.destroy()
     return ids, results, pools, stats
-
-
-def _compare(got, want, where):
-    assert len(got) == len(want), where
-    for s, (g, w) in enumerate(zip(got, want)):
-        tag = f"{where} slice {s}"
-        assert g["slice"] == s, tag
-        assert g["restore_rc"] == w["restore_rc"], tag
-        assert g["n_out"] == w["n_out"], tag
-        assert np.array_equal(g["cand"], w["cand"]), tag
-        for key in ("cand_plain", "cand_learned", "watch_plain", "watch_learned"):
-            a, b = np.asarray(g[key]), np.asarray(w[key])
-            assert a.shape == b.shape, (tag, key)
-            assert np.array_equal(np.isfinite(a), np.isfinite(b)), (tag, key)
-            fin = np.isfinite(b)
-            assert np.all(np.abs(a[fin] - b[fin]) <= 1e-12 * np.abs(b[fin])), (tag, key)
-        assert np.array_equal(g["cand_flags"], w["cand_flags"]), tag
-        assert np.array_equal(g["watch_flags"], w["watch_flags"]), tag
-        assert g["latency_ms"] > 0
 
 
 def _links(n, rng, n_slices=7):
@@ -160,6 +148,11 @@ def test_mix_equals_alone_and_single_link_api(torch_cuda):
     ids1, res1, pools1, _ = _serve([links[2]], net, seed=7, steps_every=1)
     _compare(res1[ids1[0]], res[ids[2]], "link 2 alone vs mix")
     assert np.array_equal(pools1[ids1[0]], pools[ids[2]])
+    # the same mix stepped by the server's native thread while events arrive
+    ids2, res2, pools2, stats2 = _serve(links, net, seed=3, native=True)
+    for i, (a, b) in enumerate(zip(ids2, ids)):
+        _compare(res2[a], res[b], f"link {i} native stepping")
+        assert np.array_equal(pools2[a], pools[b])
 
 
 def test_admission_by_budget(torch_cuda):
