@@ -192,8 +192,10 @@ def test_close_multi_windows(cuda, oracle_lib, geom):
     from paper_1807_01527_amd import binding
     from paper_1807_01527_amd.binding import AtError
     k = geom["k"]
-    tr = _tiny(seed=21 + k, n_slices=k + 4, pairs_per_slice=9001, hosts=1 << 10, planted=4, lo=300, hi=2000)
-    g, o = make_pair(dict(**geom, theta=256.0, seed=4), oracle_lib)
+    per_slice = 9001 if k <= 10 else 1200
+    tr = _tiny(seed=21 + k, n_slices=k + 4, pairs_per_slice=per_slice, hosts=1 << 10, planted=4, lo=300, hi=2000)
+    # the budget keeps the oracle's tuple enumeration short; both sides apply it
+    g, o = make_pair(dict(**geom, theta=256.0, seed=4, tuple_budget=1 << 22), oracle_lib)
     wins = sorted({1, 2, k // 2, k - 1, k})[:8]
     for t in range(tr.n_slices):
         g.ingest(to_dev(tr.aip[t]), to_dev(tr.bip[t]))
@@ -243,7 +245,7 @@ def test_wide_ats(cuda, oracle_lib, geom, slices, mode):
     aip, bip = list(tr.aip), list(tr.bip)
     for t in range(5, slices, 37):
         aip[t], bip[t] = aip[t][:0], bip[t][:0]
-    g, o = make_pair(dict(**geom, theta=64.0, seed=7), oracle_lib)
+    g, o = make_pair(dict(**geom, theta=64.0, seed=7, tuple_budget=1 << 22), oracle_lib)
     assert g.at_bytes == 2 and g.pool_bytes == 2 * o.pool_size
     g.set_scan_mode(mode)
     run_trace(g, o, aip, bip, kprimes=[k, 1, k // 2, k - 1, 7], batches=3, seed=3, query_hosts=tr.planted_hosts)
