@@ -201,13 +201,19 @@ int at_estimate_dev(at_ctx *h, const uint32_t *aip_dev, uint64_t n, double *est_
 /* Number of column tuples U that at_restore would enumerate (see above). */
 int at_tuple_count(at_ctx *h, uint64_t *U);
 
-/* How at_ingest_slice scans: 0 = automatic (the binned scan when u >= 3, the
- * pool is at least 32 MiB and the call has at least 65536 pairs), 1 = direct
- * (one pass, r byte stores per pair), 2 = binned (pairs hashed once into 8
- * frame-group bins, then one pass per row in which workgroup b takes bin
- * b mod 8, so each XCD's stores stay in one region of the pool; needs an
- * extra 64 B of scratch per pair, up to 8M pairs at a time).  Both give the
- * same pool.  AT_E_INVAL for another mode. */
+/* How at_ingest_slice scans (every mode gives the same pool):
+ *   1 = direct: one pass, r AT stores per pair straight into the pool;
+ *   2 = binned: pairs hashed once into 8 frame-group bins, then one pass per
+ *       row in which workgroup b takes bin b mod 8, so each XCD's stores stay
+ *       in one region of the pool (an extra 64 B of scratch per pair);
+ *   3 = tiled: the pool in 64 KiB tiles; the calls' AT stores are counted and
+ *       grouped per tile (2 B of scratch per store), then one workgroup per
+ *       tile applies them in LDS and writes the tile back.  Needs a pool of
+ *       whole tiles, at most 4096 of them (AT_E_INVAL otherwise);
+ *   0 = automatic: tiled when the pool tiles and the call's r*n stores reach
+ *       a twelfth of the pool's bytes, else binned when u >= 3, the pool is at
+ *       least 32 MiB and the call has at least 65536 pairs, else direct.
+ * Batches of up to 8M pairs at a time.  AT_E_INVAL for another mode. */
 int at_set_scan_mode(at_ctx *h, int mode);
 
 /* ------------------------------------------------------ learned correction

@@ -325,7 +325,7 @@ class AtPool:
                "at_estimate_learned_dev")
 
     def set_scan_mode(self, mode: int):
-        """0 automatic, 1 direct, 2 binned (see at_set_scan_mode)."""
+        """0 automatic, 1 direct, 2 binned, 3 tiled (see at_set_scan_mode)."""
         _check(self.lib.at_set_scan_mode(self._handle(), mode), "at_set_scan_mode")
 
     def tuple_count(self) -> int:

@@ -63,6 +63,27 @@ uint64_t binned_sub_cap(uint64_t n);
 hipError_t launch_ingest_binned(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n, const Geometry& G,
                                 uint32_t c0, uint64_t* bins, uint64_t sub_cap, unsigned long long* fill,
                                 hipStream_t st);
+// Tiled scan: the pool in 64 KiB tiles (at most 4096); the pairs' AT stores
+// are counted and grouped per tile (16-bit in-tile indices), then one
+// workgroup per tile applies them in LDS and writes the tile back.
+struct TileSizes {
+    uint32_t n_tiles, nb;  // tiles, blocks of the count/scatter passes
+    uint64_t recs, table;  // records (n * r), n_tiles * nb
+};
+struct TileBufs {
+    uint16_t* rec;          // rec_cap records
+    uint32_t* cnt;          // table_cap
+    uint32_t* pre;          // table_cap
+    uint32_t* tot;          // 4096
+    uint32_t* base;         // 4097
+    uint64_t rec_cap, table_cap;
+};
+bool tiled_fits(uint64_t pool_bytes);
+TileSizes tiled_sizes(uint64_t n, uint64_t pool_bytes, const Geometry& G);
+size_t tiled_lds_bytes();  // dynamic LDS of the scatter pass
+hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
+                               uint64_t pool_bytes, const Geometry& G, uint32_t c0, const TileBufs& B,
+                               hipStream_t st);
 // Windows summarised by one close: weights for window j land in
 // w[j * n_atv ...], AAT in aat[j * groups ...], super lists likewise.
 constexpr uint32_t kMaxWindows = 8;

@@ -43,7 +43,9 @@ struct at_ctx {
     uint64_t* bins = nullptr;
     uint64_t bins_cap = 0;
     unsigned long long* bin_fill = nullptr;
-    int scan_mode = 0;            // 0 auto, 1 direct, 2 binned
+    atp::TileBufs tb{};           // tiled-scan scratch (grown on demand)
+    bool tiled_ok = false;        // the device has the LDS the tiled scan needs
+    int scan_mode = 0;            // 0 auto, 1 direct, 2 binned, 3 tiled
     // grow-on-demand device scratch
     uint32_t* cand = nullptr;
     uint64_t cand_cap = 0;
@@ -154,7 +156,8 @@ int dev_alloc(T** p, uint64_t count) {
 
 void free_all(at_ctx* h) {
     void* bufs[] = {h->pool, h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->counter, h->prefix, h->cand,
-                    h->q_aip, h->q_est, h->q_flags, h->q_nat, h->q_feat, h->q_y, h->q_plain, h->bins, h->bin_fill};
+                    h->q_aip, h->q_est, h->q_flags, h->q_nat, h->q_feat, h->q_y, h->q_plain, h->bins, h->bin_fill,
+                    h->tb.rec, h->tb.cnt, h->tb.pre, h->tb.tot, h->tb.base};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -289,6 +292,9 @@ int at_create(const at_params* p, void* hip_stream, at_ctx** out) {
     h->aat = h->aat_all;
     h->sa = h->sa_all;
     h->sa_cnt = h->sa_cnt_all;
+    int lds = 0;
+    h->tiled_ok = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess &&
+                  (size_t)lds >= atp::tiled_lds_bytes() + 1024;
     *out = h;
     return AT_OK;
 }
@@ -306,10 +312,44 @@ int at_destroy(at_ctx* h) {
 // far larger than an L2 and there are at least 8 frames.
 constexpr uint64_t kBinBatch = 8u << 20;  // pairs per binned sub-batch
 
-bool use_binned(const at_ctx* h, uint64_t n) {
-    if (h->scan_mode == 1) return false;
-    if (h->scan_mode == 2) return true;
-    return h->p.u >= 3 && h->pool_bytes >= (32ull << 20) && n >= 65536;
+// The tiled scan reads and writes the whole pool once per call, so it pays
+// when the call's r*n byte stores are many next to the pool: each random
+// store costs a partial-line write-back of about 30 bytes otherwise.
+enum ScanPath { kDirect = 1, kBinned = 2, kTiled = 3 };
+
+int scan_path(const at_ctx* h, uint64_t n) {
+    if (h->scan_mode != 0) return h->scan_mode;
+    if (h->tiled_ok && atp::tiled_fits(h->pool_bytes) && n * h->p.r * 12 >= h->pool_bytes) return kTiled;
+    if (h->p.u >= 3 && h->pool_bytes >= (32ull << 20) && n >= 65536) return kBinned;
+    return kDirect;
+}
+
+int ingest_tiled(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, uint64_t n) {
+    int rc;
+    const atp::TileSizes z = atp::tiled_sizes(std::min<uint64_t>(n, kBinBatch), h->pool_bytes, h->G);
+    if (z.recs > h->tb.rec_cap) {
+        if (h->tb.rec) (void)hipFree(h->tb.rec);
+        h->tb.rec = nullptr;
+        h->tb.rec_cap = 0;
+        if ((rc = dev_alloc(&h->tb.rec, z.recs))) return rc;
+        h->tb.rec_cap = z.recs;
+    }
+    if (z.table > h->tb.table_cap) {
+        if (h->tb.cnt) (void)hipFree(h->tb.cnt);
+        if (h->tb.pre) (void)hipFree(h->tb.pre);
+        h->tb.cnt = h->tb.pre = nullptr;
+        h->tb.table_cap = 0;
+        if ((rc = dev_alloc(&h->tb.cnt, z.table)) || (rc = dev_alloc(&h->tb.pre, z.table))) return rc;
+        h->tb.table_cap = z.table;
+    }
+    if (!h->tb.tot && ((rc = dev_alloc(&h->tb.tot, 4096)) || (rc = dev_alloc(&h->tb.base, 4097)))) return rc;
+    for (uint64_t off = 0; off < n; off += kBinBatch) {
+        const uint64_t m = std::min<uint64_t>(kBinBatch, n - off);
+        if (atp::launch_ingest_tiled(h->pool, aip_dev + off, bip_dev + off, m, h->pool_bytes, h->G, h->c0, h->tb,
+                                     h->stream) != hipSuccess)
+            return AT_E_DEVICE;
+    }
+    return AT_OK;
 }
 
 int at_ingest_slice(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, uint64_t n) {
@@ -321,7 +361,9 @@ int at_ingest_slice(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev,
     int rc = open_slice(h);
     if (rc) return rc;
     if (n == 0) return AT_OK;
-    if (!use_binned(h, n))
+    const int path = scan_path(h, n);
+    if (path == kTiled) return ingest_tiled(h, aip_dev, bip_dev, n);
+    if (path == kDirect)
         return atp::launch_ingest(h->pool, aip_dev, bip_dev, n, h->G, h->c0, h->stream) == hipSuccess ? AT_OK
                                                                                                      : AT_E_DEVICE;
     const uint64_t sub_cap = atp::binned_sub_cap(std::min<uint64_t>(n, kBinBatch));
@@ -343,7 +385,8 @@ int at_ingest_slice(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev,
 }
 
 int at_set_scan_mode(at_ctx* h, int mode) {
-    if (!h || mode < 0 || mode > 2) return AT_E_INVAL;
+    if (!h || mode < 0 || mode > 3) return AT_E_INVAL;
+    if (mode == 3 && !(h->tiled_ok && atp::tiled_fits(h->pool_bytes))) return AT_E_INVAL;
     h->scan_mode = mode;
     return AT_OK;
 }

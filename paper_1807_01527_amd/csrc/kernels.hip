@@ -336,6 +336,203 @@ __global__ __launch_bounds__(kBlock) void k_scan_bins(const uint64_t* __restrict
     }
 }
 
+// ---------------------------------------------------------------- a2+a3: tiled scan
+// The pool is cut into tiles of 64 KiB (whole ATVs).  Pass 1 hashes every pair
+// and counts, per block of kTileRecs records (r per pair), the AT stores that
+// land in each tile.  A scan over blocks per tile and a scan of the tile totals
+// give every (tile, block) run its place.  Pass 2 hashes again, groups the
+// block's records (an AT's index inside its tile, 16 bits) by tile in LDS and
+// writes each run contiguously.  Pass 3 runs one workgroup per tile: the tile
+// is read into LDS, every record sets its AT to that AT's block timestamp,
+// and the tile is written back.  The random stores hit LDS; HBM sees streams.
+constexpr uint32_t kTileBytes = 1u << 16;
+constexpr uint32_t kTileRecs = 16384;  // records per block in passes 1 and 2
+constexpr uint32_t kMaxTiles = 4096;
+constexpr uint32_t kApplyBlock = 1024;
+
+template <int R>
+__device__ __forceinline__ void pair_targets(uint32_t a, uint32_t b, const Geometry& G, uint64_t* idx) {
+    const uint32_t f = mangle(a, G.A);
+    const uint32_t z = f & G.umask;
+    const uint64_t L = (uint64_t)(f >> G.u);
+    const uint64_t LL = L | (L << G.W);
+    const uint32_t i = (uint32_t)((G.alpha * (uint64_t)b + G.beta) >> (64 - G.log2g));
+    const uint64_t zr = (uint64_t)z * R;
+#pragma unroll
+    for (int j = 0; j < R; j++) {
+        const uint32_t x = column(LL, G.sh[j], G.ncol_mask);
+        idx[j] = ((((zr + j) << G.c) + x) << G.log2g) | i;
+    }
+}
+
+// Pass 1: per block, counts of its records per tile -> cnt[tile * nb + block].
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restrict__ aip,
+                                                       const uint32_t* __restrict__ bip, uint64_t n, Geometry G,
+                                                       uint32_t ts, uint32_t n_tiles, uint32_t* __restrict__ cnt,
+                                                       uint32_t nb) {
+    __shared__ uint32_t hist[kMaxTiles];
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += kBlock) hist[t] = 0;
+    __syncthreads();
+    constexpr uint32_t P = kTileRecs / R;
+    const uint64_t lo = (uint64_t)blockIdx.x * P;
+    const uint64_t hi = lo + P < n ? lo + P : n;
+    for (uint64_t q = lo + threadIdx.x; q < hi; q += kBlock) {
+        uint64_t idx[R];
+        pair_targets<R>(aip[q], bip[q], G, idx);
+#pragma unroll
+        for (int j = 0; j < R; j++) atomicAdd(&hist[(uint32_t)(idx[j] >> ts)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += kBlock) cnt[(uint64_t)t * nb + blockIdx.x] = hist[t];
+}
+
+// Exclusive scan of one block's values held as v (one per thread, kBlock
+// threads); returns the thread's prefix and leaves the block total in *total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* kBlock/64 + 1 */,
+                                                         uint32_t* total) {
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) scratch[wv] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (uint32_t w = 0; w < kBlock / 64; w++) {
+            const uint32_t t = scratch[w];
+            scratch[w] = s;
+            s += t;
+        }
+        scratch[kBlock / 64] = s;
+    }
+    __syncthreads();
+    const uint32_t r = scratch[wv] + x - v;
+    *total = scratch[kBlock / 64];
+    __syncthreads();
+    return r;
+}
+
+// Per tile (one block each): exclusive prefix of its counts over the blocks
+// -> pre[tile * nb + block], and the tile's total.
+__global__ __launch_bounds__(kBlock) void k_tile_colscan(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ pre,
+                                                         uint32_t nb, uint32_t* __restrict__ tot) {
+    __shared__ uint32_t scratch[kBlock / 64 + 1];
+    const uint64_t row = (uint64_t)blockIdx.x * nb;
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kBlock) {
+        const uint32_t b = b0 + threadIdx.x;
+        const uint32_t v = b < nb ? cnt[row + b] : 0u;
+        uint32_t sum;
+        const uint32_t p = block_exclusive_scan(v, scratch, &sum);
+        if (b < nb) pre[row + b] = carry + p;
+        carry += sum;
+    }
+    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+// One block: exclusive prefix of the tile totals -> base[0..n_tiles].
+__global__ __launch_bounds__(kBlock) void k_tile_totscan(const uint32_t* __restrict__ tot, uint32_t n_tiles,
+                                                         uint32_t* __restrict__ base) {
+    __shared__ uint32_t scratch[kBlock / 64 + 1];
+    uint32_t carry = 0;
+    for (uint32_t t0 = 0; t0 < n_tiles; t0 += kBlock) {
+        const uint32_t t = t0 + threadIdx.x;
+        const uint32_t v = t < n_tiles ? tot[t] : 0u;
+        uint32_t sum;
+        const uint32_t p = block_exclusive_scan(v, scratch, &sum);
+        if (t < n_tiles) base[t] = carry + p;
+        carry += sum;
+    }
+    if (threadIdx.x == 0) base[n_tiles] = carry;
+}
+
+// Pass 2: the block's records grouped by tile in LDS, then written run by run.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_tile_scatter(const uint32_t* __restrict__ aip,
+                                                         const uint32_t* __restrict__ bip, uint64_t n, Geometry G,
+                                                         uint32_t ts, uint32_t n_tiles,
+                                                         const uint32_t* __restrict__ cnt,
+                                                         const uint32_t* __restrict__ pre,
+                                                         const uint32_t* __restrict__ base, uint32_t nb,
+                                                         uint16_t* __restrict__ rec) {
+    extern __shared__ __align__(16) uint8_t smem_tile[];
+    uint16_t* st_local = reinterpret_cast<uint16_t*>(smem_tile);
+    uint16_t* st_tile = st_local + kTileRecs;
+    uint32_t* cur = reinterpret_cast<uint32_t*>(st_tile + kTileRecs);  // n_tiles
+    uint32_t* gbase = cur + kMaxTiles;                                    // n_tiles
+    __shared__ uint32_t scratch[kBlock / 64 + 1];
+    const uint32_t b = blockIdx.x;
+    // block-local run starts: exclusive scan of this block's counts, kMaxTiles
+    // / kBlock consecutive tiles per thread
+    constexpr uint32_t TPT = kMaxTiles / kBlock;
+    uint32_t c[TPT], s = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < TPT; e++) {
+        const uint32_t t = threadIdx.x * TPT + e;
+        c[e] = t < n_tiles ? cnt[(uint64_t)t * nb + b] : 0u;
+        s += c[e];
+    }
+    uint32_t total;
+    uint32_t st = block_exclusive_scan(s, scratch, &total);
+#pragma unroll
+    for (uint32_t e = 0; e < TPT; e++) {
+        const uint32_t t = threadIdx.x * TPT + e;
+        if (t < n_tiles) {
+            cur[t] = st;
+            gbase[t] = base[t] + pre[(uint64_t)t * nb + b] - st;  // modulo 2^32; exact once a slot is added
+        }
+        st += c[e];
+    }
+    __syncthreads();
+    constexpr uint32_t P = kTileRecs / R;
+    const uint64_t lo = (uint64_t)b * P;
+    const uint64_t hi = lo + P < n ? lo + P : n;
+    const uint32_t lmask = (1u << ts) - 1u;
+    for (uint64_t q = lo + threadIdx.x; q < hi; q += kBlock) {
+        uint64_t idx[R];
+        pair_targets<R>(aip[q], bip[q], G, idx);
+#pragma unroll
+        for (int j = 0; j < R; j++) {
+            const uint32_t t = (uint32_t)(idx[j] >> ts);
+            const uint32_t slot = atomicAdd(&cur[t], 1u);
+            st_local[slot] = (uint16_t)((uint32_t)idx[j] & lmask);
+            st_tile[slot] = (uint16_t)t;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < total; i += kBlock) {
+        const uint32_t t = st_tile[i];
+        rec[gbase[t] + i] = st_local[i];
+    }
+}
+
+// Pass 3: one workgroup per tile applies the tile's records in LDS.
+template <typename T>
+__global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict__ pool,
+                                                            const uint16_t* __restrict__ rec,
+                                                            const uint32_t* __restrict__ base, Geometry G,
+                                                            uint32_t c0) {
+    extern __shared__ __align__(16) uint8_t smem_apply[];
+    const uint32_t t = blockIdx.x;
+    const uint32_t lo = base[t], hi = base[t + 1];
+    if (lo == hi) return;  // nothing lands here: the tile stays as it is
+    uint4* lds = reinterpret_cast<uint4*>(smem_apply);
+    uint4* src = reinterpret_cast<uint4*>(pool + (uint64_t)t * kTileBytes);
+    for (uint32_t i = threadIdx.x; i < kTileBytes / 16; i += kApplyBlock) lds[i] = src[i];
+    __syncthreads();
+    T* tl = reinterpret_cast<T*>(smem_apply);
+    const uint32_t gmask = G.g - 1u;
+    for (uint32_t q = lo + threadIdx.x; q < hi; q += kApplyBlock) {
+        const uint32_t loc = rec[q];
+        tl[loc] = (T)act_of(loc & gmask, c0, G);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kTileBytes / 16; i += kApplyBlock) src[i] = lds[i];
+}
+
 // ---------------------------------------------------------------- a4: close
 // One read of the pool: k'-weight of every ATV (Alg 1 per AT) for each of
 // the Wn.n windows.  A group of lpa = min(64, g/CA) lanes covers one ATV with
@@ -1363,6 +1560,52 @@ hipError_t launch_ingest_binned(uint8_t* pool, const uint32_t* aip, const uint32
         for (uint32_t row = 0; row < G.r; row++)
             hipLaunchKernelGGL(k_scan_bins<T>, dim3((uint32_t)(kBins * per_bin)), dim3(kBlock), 0, st, bins, sub_cap,
                                fill, reinterpret_cast<T*>(pool), G, c0, row);
+    });
+}
+
+bool tiled_fits(uint64_t pool_bytes) {
+    return pool_bytes % kTileBytes == 0 && pool_bytes / kTileBytes >= 1 && pool_bytes / kTileBytes <= kMaxTiles;
+}
+
+TileSizes tiled_sizes(uint64_t n, uint64_t pool_bytes, const Geometry& G) {
+    TileSizes z{};
+    z.n_tiles = (uint32_t)(pool_bytes / kTileBytes);
+    z.nb = (uint32_t)((n + kTileRecs / G.r - 1) / (kTileRecs / G.r));
+    z.recs = n * G.r;
+    z.table = (uint64_t)z.n_tiles * z.nb;
+    return z;
+}
+
+size_t tiled_lds_bytes() { return 2 * kTileRecs * sizeof(uint16_t) + 2 * kMaxTiles * sizeof(uint32_t); }
+
+hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
+                               uint64_t pool_bytes, const Geometry& G, uint32_t c0, const TileBufs& B,
+                               hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (!tiled_fits(pool_bytes)) return hipErrorInvalidValue;
+    const TileSizes z = tiled_sizes(n, pool_bytes, G);
+    if (z.recs > B.rec_cap || z.table > B.table_cap) return hipErrorInvalidValue;
+    const uint32_t ts = 16u - (G.atb == 2 ? 1u : 0u);  // log2 of the ATs per tile
+    hipError_t e = with_rows<uint8_t>(G.r, [&](auto rc, auto) {
+        constexpr int RR = decltype(rc)::value;
+        hipLaunchKernelGGL((k_tile_count<RR>), dim3(z.nb), dim3(kBlock), 0, st, aip, bip, n, G, ts, z.n_tiles, B.cnt,
+                           z.nb);
+    });
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tile_colscan, dim3(z.n_tiles), dim3(kBlock), 0, st, B.cnt, B.pre, z.nb, B.tot);
+    hipLaunchKernelGGL(k_tile_totscan, dim3(1), dim3(kBlock), 0, st, B.tot, z.n_tiles, B.base);
+    e = with_rows<uint8_t>(G.r, [&](auto rc, auto) {
+        constexpr int RR = decltype(rc)::value;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile_scatter<RR>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)tiled_lds_bytes());
+        hipLaunchKernelGGL((k_tile_scatter<RR>), dim3(z.nb), dim3(kBlock), tiled_lds_bytes(), st, aip, bip, n, G, ts,
+                           z.n_tiles, B.cnt, B.pre, B.base, z.nb, B.rec);
+    });
+    if (e != hipSuccess) return e;
+    return with_at(G, [&](auto t) {
+        using T = decltype(t);
+        hipLaunchKernelGGL(k_tile_apply<T>, dim3(z.n_tiles), dim3(kApplyBlock), kTileBytes, st, pool, B.rec, B.base,
+                           G, c0);
     });
 }
 

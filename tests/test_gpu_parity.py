@@ -152,16 +152,17 @@ def test_restore_cap_and_budget(cuda, oracle_lib):
     assert g2.tuple_count() == o2.tuple_count()
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("geom", [
-    dict(k=3, r=4, c=8, s=8, u=1, log2g=6),       # fewer frames than bins
+    dict(k=3, r=4, c=8, s=8, u=1, log2g=6),       # fewer frames than bins; two 64 KiB tiles
     dict(k=5, r=3, c=11, s=10, u=3, log2g=7),
     dict(k=4, r=4, c=9, s=7, u=3, log2g=12),      # the companion geometry (64 MiB)
     dict(k=7, r=5, c=8, s=6, u=4, log2g=8),       # 16 frames: two frames per bin
 ])
 def test_scan_modes(cuda, oracle_lib, geom, mode):
-    """The direct and the binned scan give the oracle's pool, with ragged
-    batches (including ones larger than a workgroup's share and tiny ones)."""
+    """The direct, the binned and the tiled scan give the oracle's pool, with
+    ragged batches (including ones larger than a workgroup's share and tiny
+    ones)."""
     tr = _tiny(seed=11 + geom["k"], n_slices=5, pairs_per_slice=70001, hosts=1 << 10)
     g, o = make_pair(dict(**geom, theta=64.0, seed=9), oracle_lib)
     g.set_scan_mode(mode)
@@ -229,7 +230,7 @@ def test_close_multi_windows(cuda, oracle_lib, geom):
     g.destroy()
 
 
-@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("geom,slices", [
     (dict(k=150, r=4, c=8, s=8, u=1, log2g=9), 310),    # blocks of 1 AT and a 213-AT last block
     (dict(k=300, r=4, c=8, s=8, u=3, log2g=4), 610),    # the paper's k; g < 2k: one block holds every AT
@@ -249,3 +250,19 @@ def test_wide_ats(cuda, oracle_lib, geom, slices, mode):
     assert g.at_bytes == 2 and g.pool_bytes == 2 * o.pool_size
     g.set_scan_mode(mode)
     run_trace(g, o, aip, bip, kprimes=[k, 1, k // 2, k - 1, 7], batches=3, seed=3, query_hosts=tr.planted_hosts)
+
+
+def test_tiled_mode_needs_whole_tiles(cuda):
+    """The tiled scan needs a pool of whole 64 KiB tiles, at most 4096."""
+    from paper_1807_01527_amd import binding
+    from paper_1807_01527_amd.binding import AtError, AtPool
+    g = AtPool(k=13, r=4, c=8, s=8, u=1, log2g=4)          # 32 KiB pool
+    with pytest.raises(AtError) as e:
+        g.set_scan_mode(3)
+    assert e.value.rc == binding.AT_E_INVAL
+    g.destroy()
+    g = AtPool(k=4, r=4, c=14, s=6, u=4, log2g=12)         # 4 GiB pool: 65536 tiles
+    with pytest.raises(AtError) as e:
+        g.set_scan_mode(3)
+    assert e.value.rc == binding.AT_E_INVAL
+    g.destroy()
