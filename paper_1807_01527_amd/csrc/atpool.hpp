@@ -68,19 +68,20 @@ hipError_t launch_ingest_binned(uint8_t* pool, const uint32_t* aip, const uint32
 // workgroup per tile applies them in LDS and writes the tile back.
 struct TileSizes {
     uint32_t n_tiles, nb;  // tiles, blocks of the count/scatter passes
-    uint64_t recs, table;  // records (n * r), n_tiles * nb
+    uint32_t nchunk;       // chunks of blocks in the column scans
+    uint64_t recs, table;  // records (n * r), nb * n_tiles
 };
 struct TileBufs {
-    uint16_t* rec;          // rec_cap records
-    uint32_t* cnt;          // table_cap
-    uint32_t* pre;          // table_cap
-    uint32_t* tot;          // 4096
-    uint32_t* base;         // 4097
-    uint64_t rec_cap, table_cap;
+    uint16_t* rec;   // rec_cap records
+    uint32_t* cnt;   // table_cap: per-block tile counts
+    uint32_t* pre;   // table_cap: per-(block, tile) run starts
+    uint32_t* csum;  // chunk_cap * 4096: per-chunk column sums, then their prefixes
+    uint32_t* base;  // 4097 region starts
+    uint64_t rec_cap, table_cap, chunk_cap;
 };
 bool tiled_fits(uint64_t pool_bytes);
 TileSizes tiled_sizes(uint64_t n, uint64_t pool_bytes, const Geometry& G);
-size_t tiled_lds_bytes();  // dynamic LDS of the scatter pass
+size_t tiled_lds_bytes(uint32_t n_tiles);  // dynamic LDS of the scatter pass
 hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
                                uint64_t pool_bytes, const Geometry& G, uint32_t c0, const TileBufs& B,
                                hipStream_t st);

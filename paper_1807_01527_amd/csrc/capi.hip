@@ -157,7 +157,7 @@ int dev_alloc(T** p, uint64_t count) {
 void free_all(at_ctx* h) {
     void* bufs[] = {h->pool, h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->counter, h->prefix, h->cand,
                     h->q_aip, h->q_est, h->q_flags, h->q_nat, h->q_feat, h->q_y, h->q_plain, h->bins, h->bin_fill,
-                    h->tb.rec, h->tb.cnt, h->tb.pre, h->tb.tot, h->tb.base};
+                    h->tb.rec, h->tb.cnt, h->tb.pre, h->tb.csum, h->tb.base};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -294,7 +294,7 @@ int at_create(const at_params* p, void* hip_stream, at_ctx** out) {
     h->sa_cnt = h->sa_cnt_all;
     int lds = 0;
     h->tiled_ok = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) == hipSuccess &&
-                  (size_t)lds >= atp::tiled_lds_bytes() + 1024;
+                  (size_t)lds >= atp::tiled_lds_bytes(4096) + 1024;
     *out = h;
     return AT_OK;
 }
@@ -342,7 +342,14 @@ int ingest_tiled(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, ui
         if ((rc = dev_alloc(&h->tb.cnt, z.table)) || (rc = dev_alloc(&h->tb.pre, z.table))) return rc;
         h->tb.table_cap = z.table;
     }
-    if (!h->tb.tot && ((rc = dev_alloc(&h->tb.tot, 4096)) || (rc = dev_alloc(&h->tb.base, 4097)))) return rc;
+    if (z.nchunk > h->tb.chunk_cap) {
+        if (h->tb.csum) (void)hipFree(h->tb.csum);
+        h->tb.csum = nullptr;
+        h->tb.chunk_cap = 0;
+        if ((rc = dev_alloc(&h->tb.csum, (uint64_t)z.nchunk * 4096))) return rc;
+        h->tb.chunk_cap = z.nchunk;
+    }
+    if (!h->tb.base && (rc = dev_alloc(&h->tb.base, 4097))) return rc;
     for (uint64_t off = 0; off < n; off += kBinBatch) {
         const uint64_t m = std::min<uint64_t>(kBinBatch, n - off);
         if (atp::launch_ingest_tiled(h->pool, aip_dev + off, bip_dev + off, m, h->pool_bytes, h->G, h->c0, h->tb,

@@ -338,17 +338,21 @@ __global__ __launch_bounds__(kBlock) void k_scan_bins(const uint64_t* __restrict
 
 // ---------------------------------------------------------------- a2+a3: tiled scan
 // The pool is cut into tiles of 64 KiB (whole ATVs).  Pass 1 hashes every pair
-// and counts, per block of kTileRecs records (r per pair), the AT stores that
-// land in each tile.  A scan over blocks per tile and a scan of the tile totals
-// give every (tile, block) run its place.  Pass 2 hashes again, groups the
-// block's records (an AT's index inside its tile, 16 bits) by tile in LDS and
-// writes each run contiguously.  Pass 3 runs one workgroup per tile: the tile
-// is read into LDS, every record sets its AT to that AT's block timestamp,
-// and the tile is written back.  The random stores hit LDS; HBM sees streams.
+// and writes, per block of kTileRecs AT stores (r per pair), its count of
+// stores landing in each tile (a row of cnt).  Column scans over the blocks,
+// in chunks of kTileChunk rows, and a scan of the tile totals give every
+// (block, tile) run its place in the record array.  Pass 2 hashes again,
+// groups the block's records (an AT's index inside its tile, 16 bits) by tile
+// in LDS and writes each run contiguously.  Pass 3 runs one workgroup per
+// tile: the tile is read into LDS, every record sets its AT to the value its
+// index implies (its block timestamp), and the tile is written back.  The
+// random stores hit LDS; HBM sees streams.
 constexpr uint32_t kTileBytes = 1u << 16;
 constexpr uint32_t kTileRecs = 16384;  // records per block in passes 1 and 2
 constexpr uint32_t kMaxTiles = 4096;
+constexpr uint32_t kTileChunk = 64;    // rows (blocks) per chunk of the column scans
 constexpr uint32_t kApplyBlock = 1024;
+constexpr uint32_t kScatterBlock = 1024;  // 16 waves: the scatter block holds 96 KiB of LDS
 
 template <int R>
 __device__ __forceinline__ void pair_targets(uint32_t a, uint32_t b, const Geometry& G, uint64_t* idx) {
@@ -365,31 +369,57 @@ __device__ __forceinline__ void pair_targets(uint32_t a, uint32_t b, const Geome
     }
 }
 
-// Pass 1: per block, counts of its records per tile -> cnt[tile * nb + block].
+// Pass 1: block b's per-tile store counts -> cnt[b * n_tiles + tile].
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restrict__ aip,
                                                        const uint32_t* __restrict__ bip, uint64_t n, Geometry G,
-                                                       uint32_t ts, uint32_t n_tiles, uint32_t* __restrict__ cnt,
-                                                       uint32_t nb) {
+                                                       uint32_t ts, uint32_t n_tiles, uint32_t* __restrict__ cnt) {
     __shared__ uint32_t hist[kMaxTiles];
     for (uint32_t t = threadIdx.x; t < n_tiles; t += kBlock) hist[t] = 0;
     __syncthreads();
     constexpr uint32_t P = kTileRecs / R;
     const uint64_t lo = (uint64_t)blockIdx.x * P;
     const uint64_t hi = lo + P < n ? lo + P : n;
-    for (uint64_t q = lo + threadIdx.x; q < hi; q += kBlock) {
-        uint64_t idx[R];
-        pair_targets<R>(aip[q], bip[q], G, idx);
+    // four pairs per thread per round, loads issued before use
+    for (uint64_t q0 = lo + threadIdx.x; q0 < hi; q0 += 4 * kBlock) {
+        uint32_t a4[4], b4[4];
 #pragma unroll
-        for (int j = 0; j < R; j++) atomicAdd(&hist[(uint32_t)(idx[j] >> ts)], 1u);
+        for (int e = 0; e < 4; e++) {
+            const uint64_t q = q0 + (uint64_t)e * kBlock;
+            a4[e] = q < hi ? aip[q] : 0u;
+            b4[e] = q < hi ? bip[q] : 0u;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            if (q0 + (uint64_t)e * kBlock >= hi) break;
+            uint64_t idx[R];
+            pair_targets<R>(a4[e], b4[e], G, idx);
+#pragma unroll
+            for (int j = 0; j < R; j++) atomicAdd(&hist[(uint32_t)(idx[j] >> ts)], 1u);
+        }
     }
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < n_tiles; t += kBlock) cnt[(uint64_t)t * nb + blockIdx.x] = hist[t];
+    uint32_t* row = cnt + (uint64_t)blockIdx.x * n_tiles;
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += kBlock) row[t] = hist[t];
 }
 
-// Exclusive scan of one block's values held as v (one per thread, kBlock
+// Column sums of cnt over each chunk of kTileChunk rows -> csum[chunk][tile].
+__global__ __launch_bounds__(kBlock) void k_tile_chunksum(const uint32_t* __restrict__ cnt, uint32_t nb,
+                                                          uint32_t n_tiles, uint32_t* __restrict__ csum) {
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint32_t c = blockIdx.y;
+    const uint32_t b1 = (c + 1) * kTileChunk < nb ? (c + 1) * kTileChunk : nb;
+    uint32_t s = 0;
+#pragma unroll 8
+    for (uint32_t b = c * kTileChunk; b < b1; b++) s += cnt[(uint64_t)b * n_tiles + t];
+    csum[(uint64_t)c * n_tiles + t] = s;
+}
+
+// Exclusive scan of one block's values held as v (one per thread, NT
 // threads); returns the thread's prefix and leaves the block total in *total.
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* kBlock/64 + 1 */,
+template <uint32_t NT = kBlock>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* scratch /* NT/64 + 1 */,
                                                          uint32_t* total) {
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     uint32_t x = v;
@@ -401,109 +431,148 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t s = 0;
-        for (uint32_t w = 0; w < kBlock / 64; w++) {
+        for (uint32_t w = 0; w < NT / 64; w++) {
             const uint32_t t = scratch[w];
             scratch[w] = s;
             s += t;
         }
-        scratch[kBlock / 64] = s;
+        scratch[NT / 64] = s;
     }
     __syncthreads();
     const uint32_t r = scratch[wv] + x - v;
-    *total = scratch[kBlock / 64];
+    *total = scratch[NT / 64];
     __syncthreads();
     return r;
 }
 
-// Per tile (one block each): exclusive prefix of its counts over the blocks
-// -> pre[tile * nb + block], and the tile's total.
-__global__ __launch_bounds__(kBlock) void k_tile_colscan(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ pre,
-                                                         uint32_t nb, uint32_t* __restrict__ tot) {
-    __shared__ uint32_t scratch[kBlock / 64 + 1];
-    const uint64_t row = (uint64_t)blockIdx.x * nb;
+// One block of kScatterBlock threads: per tile, the exclusive prefix of its
+// chunk sums (in place) and its total; then the exclusive prefix of the tile
+// totals -> base[0..n_tiles].  Thread x takes tiles x, x + kScatterBlock, ...
+__global__ __launch_bounds__(kScatterBlock) void k_tile_scan(uint32_t* __restrict__ csum, uint32_t nchunk,
+                                                             uint32_t n_tiles, uint32_t* __restrict__ base) {
+    __shared__ uint32_t scratch[kScatterBlock / 64 + 1];
     uint32_t carry = 0;
-    for (uint32_t b0 = 0; b0 < nb; b0 += kBlock) {
-        const uint32_t b = b0 + threadIdx.x;
-        const uint32_t v = b < nb ? cnt[row + b] : 0u;
-        uint32_t sum;
-        const uint32_t p = block_exclusive_scan(v, scratch, &sum);
-        if (b < nb) pre[row + b] = carry + p;
-        carry += sum;
-    }
-    if (threadIdx.x == 0) tot[blockIdx.x] = carry;
-}
-
-// One block: exclusive prefix of the tile totals -> base[0..n_tiles].
-__global__ __launch_bounds__(kBlock) void k_tile_totscan(const uint32_t* __restrict__ tot, uint32_t n_tiles,
-                                                         uint32_t* __restrict__ base) {
-    __shared__ uint32_t scratch[kBlock / 64 + 1];
-    uint32_t carry = 0;
-    for (uint32_t t0 = 0; t0 < n_tiles; t0 += kBlock) {
+    for (uint32_t t0 = 0; t0 < n_tiles; t0 += kScatterBlock) {
         const uint32_t t = t0 + threadIdx.x;
-        const uint32_t v = t < n_tiles ? tot[t] : 0u;
+        uint32_t run = 0;
+        if (t < n_tiles)
+            for (uint32_t c0 = 0; c0 < nchunk; c0 += 8) {
+                uint32_t v[8];
+#pragma unroll
+                for (uint32_t u = 0; u < 8; u++)
+                    v[u] = c0 + u < nchunk ? csum[(uint64_t)(c0 + u) * n_tiles + t] : 0u;
+#pragma unroll
+                for (uint32_t u = 0; u < 8; u++)
+                    if (c0 + u < nchunk) {
+                        csum[(uint64_t)(c0 + u) * n_tiles + t] = run;
+                        run += v[u];
+                    }
+            }
         uint32_t sum;
-        const uint32_t p = block_exclusive_scan(v, scratch, &sum);
+        const uint32_t p = block_exclusive_scan<kScatterBlock>(run, scratch, &sum);
         if (t < n_tiles) base[t] = carry + p;
         carry += sum;
     }
     if (threadIdx.x == 0) base[n_tiles] = carry;
 }
 
+// Start of every (block, tile) run in the record array -> pre[b][tile].
+__global__ __launch_bounds__(kBlock) void k_tile_rowpre(const uint32_t* __restrict__ cnt,
+                                                        const uint32_t* __restrict__ cpre,
+                                                        const uint32_t* __restrict__ base, uint32_t nb,
+                                                        uint32_t n_tiles, uint32_t* __restrict__ pre) {
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint32_t c = blockIdx.y;
+    const uint32_t b1 = (c + 1) * kTileChunk < nb ? (c + 1) * kTileChunk : nb;
+    uint32_t run = base[t] + cpre[(uint64_t)c * n_tiles + t];
+#pragma unroll 8
+    for (uint32_t b = c * kTileChunk; b < b1; b++) {
+        const uint64_t o = (uint64_t)b * n_tiles + t;
+        const uint32_t v = cnt[o];
+        pre[o] = run;
+        run += v;
+    }
+}
+
 // Pass 2: the block's records grouped by tile in LDS, then written run by run.
 template <int R>
-__global__ __launch_bounds__(kBlock) void k_tile_scatter(const uint32_t* __restrict__ aip,
-                                                         const uint32_t* __restrict__ bip, uint64_t n, Geometry G,
-                                                         uint32_t ts, uint32_t n_tiles,
-                                                         const uint32_t* __restrict__ cnt,
-                                                         const uint32_t* __restrict__ pre,
-                                                         const uint32_t* __restrict__ base, uint32_t nb,
-                                                         uint16_t* __restrict__ rec) {
+__global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* __restrict__ aip,
+                                                                const uint32_t* __restrict__ bip, uint64_t n,
+                                                                Geometry G, uint32_t ts, uint32_t n_tiles,
+                                                                const uint32_t* __restrict__ pre,
+                                                                uint16_t* __restrict__ rec) {
     extern __shared__ __align__(16) uint8_t smem_tile[];
     uint16_t* st_local = reinterpret_cast<uint16_t*>(smem_tile);
     uint16_t* st_tile = st_local + kTileRecs;
-    uint32_t* cur = reinterpret_cast<uint32_t*>(st_tile + kTileRecs);  // n_tiles
-    uint32_t* gbase = cur + kMaxTiles;                                    // n_tiles
-    __shared__ uint32_t scratch[kBlock / 64 + 1];
-    const uint32_t b = blockIdx.x;
-    // block-local run starts: exclusive scan of this block's counts, kMaxTiles
-    // / kBlock consecutive tiles per thread
-    constexpr uint32_t TPT = kMaxTiles / kBlock;
-    uint32_t c[TPT], s = 0;
+    uint32_t* cur = reinterpret_cast<uint32_t*>(st_tile + kTileRecs);  // counts, then slot cursors
+    uint32_t* gbase = cur + ((n_tiles + 3u) & ~3u);                       // run start in rec minus LDS start
+    __shared__ uint32_t scratch[kScatterBlock / 64 + 1];
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += kScatterBlock) cur[t] = 0;
+    __syncthreads();
+    constexpr uint32_t P = kTileRecs / R;
+    constexpr uint32_t PPT = (P + kScatterBlock - 1) / kScatterBlock;  // pairs per thread
+    const uint64_t lo = (uint64_t)blockIdx.x * P;
+    const uint64_t hi = lo + P < n ? lo + P : n;
+    const uint32_t lmask = (1u << ts) - 1u;
+    // hash the block's pairs once; the targets stay in registers
+    uint32_t tgt[PPT][R];
+    uint32_t a4[PPT], b4[PPT];
+#pragma unroll
+    for (uint32_t e = 0; e < PPT; e++) {
+        const uint64_t q = lo + threadIdx.x + (uint64_t)e * kScatterBlock;
+        a4[e] = q < hi ? aip[q] : 0u;
+        b4[e] = q < hi ? bip[q] : 0u;
+    }
+#pragma unroll
+    for (uint32_t e = 0; e < PPT; e++) {
+        const bool ok = lo + threadIdx.x + (uint64_t)e * kScatterBlock < hi;
+        uint64_t idx[R];
+        pair_targets<R>(a4[e], b4[e], G, idx);
+#pragma unroll
+        for (int j = 0; j < R; j++) {
+            // tile in the high half, in-tile index in the low half (ts <= 16)
+            tgt[e][j] = ok ? (uint32_t)((idx[j] >> ts) << 16) | ((uint32_t)idx[j] & lmask) : ~0u;
+            if (ok) atomicAdd(&cur[tgt[e][j] >> 16], 1u);
+        }
+    }
+    __syncthreads();
+    // LDS run starts: exclusive scan of the counts, kMaxTiles / kScatterBlock
+    // consecutive tiles per thread
+    constexpr uint32_t TPT = kMaxTiles / kScatterBlock;
+    const uint32_t* prow = pre + (uint64_t)blockIdx.x * n_tiles;
+    uint32_t c[TPT], sum = 0;
 #pragma unroll
     for (uint32_t e = 0; e < TPT; e++) {
         const uint32_t t = threadIdx.x * TPT + e;
-        c[e] = t < n_tiles ? cnt[(uint64_t)t * nb + b] : 0u;
-        s += c[e];
+        c[e] = t < n_tiles ? cur[t] : 0u;
+        sum += c[e];
     }
     uint32_t total;
-    uint32_t st = block_exclusive_scan(s, scratch, &total);
+    uint32_t st = block_exclusive_scan<kScatterBlock>(sum, scratch, &total);
 #pragma unroll
     for (uint32_t e = 0; e < TPT; e++) {
         const uint32_t t = threadIdx.x * TPT + e;
         if (t < n_tiles) {
             cur[t] = st;
-            gbase[t] = base[t] + pre[(uint64_t)t * nb + b] - st;  // modulo 2^32; exact once a slot is added
+            gbase[t] = prow[t] - st;  // modulo 2^32; exact once a slot is added
         }
         st += c[e];
     }
     __syncthreads();
-    constexpr uint32_t P = kTileRecs / R;
-    const uint64_t lo = (uint64_t)b * P;
-    const uint64_t hi = lo + P < n ? lo + P : n;
-    const uint32_t lmask = (1u << ts) - 1u;
-    for (uint64_t q = lo + threadIdx.x; q < hi; q += kBlock) {
-        uint64_t idx[R];
-        pair_targets<R>(aip[q], bip[q], G, idx);
+#pragma unroll
+    for (uint32_t e = 0; e < PPT; e++) {
 #pragma unroll
         for (int j = 0; j < R; j++) {
-            const uint32_t t = (uint32_t)(idx[j] >> ts);
-            const uint32_t slot = atomicAdd(&cur[t], 1u);
-            st_local[slot] = (uint16_t)((uint32_t)idx[j] & lmask);
-            st_tile[slot] = (uint16_t)t;
+            const uint32_t v = tgt[e][j];
+            if (v == ~0u) continue;
+            const uint32_t slot = atomicAdd(&cur[v >> 16], 1u);
+            st_local[slot] = (uint16_t)(v & 0xFFFFu);
+            st_tile[slot] = (uint16_t)(v >> 16);
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < total; i += kBlock) {
+    for (uint32_t i = threadIdx.x; i < total; i += kScatterBlock) {
         const uint32_t t = st_tile[i];
         rec[gbase[t] + i] = st_local[i];
     }
@@ -525,9 +594,43 @@ __global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict_
     __syncthreads();
     T* tl = reinterpret_cast<T*>(smem_apply);
     const uint32_t gmask = G.g - 1u;
-    for (uint32_t q = lo + threadIdx.x; q < hi; q += kApplyBlock) {
-        const uint32_t loc = rec[q];
-        tl[loc] = (T)act_of(loc & gmask, c0, G);
+    // records [lo, hi): a ragged head and tail one by one, the 8-aligned body
+    // eight at a time with 16-byte loads
+    const uint32_t a8 = (lo + 7u) & ~7u, b8 = hi & ~7u;
+    if (a8 >= b8) {
+        for (uint32_t q = lo + threadIdx.x; q < hi; q += kApplyBlock) {
+            const uint32_t loc = rec[q];
+            tl[loc] = (T)act_of(loc & gmask, c0, G);
+        }
+    } else {
+        if (lo + threadIdx.x < a8) {
+            const uint32_t loc = rec[lo + threadIdx.x];
+            tl[loc] = (T)act_of(loc & gmask, c0, G);
+        }
+        if (b8 + threadIdx.x < hi) {
+            const uint32_t loc = rec[b8 + threadIdx.x];
+            tl[loc] = (T)act_of(loc & gmask, c0, G);
+        }
+        const uint4* r8 = reinterpret_cast<const uint4*>(rec + a8);
+        const uint32_t n8 = (b8 - a8) / 8;
+        // four 16-byte loads in flight per thread
+        for (uint32_t q0 = threadIdx.x; q0 < n8; q0 += 4 * kApplyBlock) {
+            uint4 v[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) {
+                const uint32_t q = q0 + u * kApplyBlock;
+                v[u] = q < n8 ? r8[q] : make_uint4(~0u, ~0u, ~0u, ~0u);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) {
+                if (q0 + u * kApplyBlock >= n8) break;
+#pragma unroll
+                for (uint32_t e = 0; e < 8; e++) {
+                    const uint32_t loc = (word_of(v[u], e / 2) >> (16 * (e & 1))) & 0xFFFFu;
+                    tl[loc] = (T)act_of(loc & gmask, c0, G);
+                }
+            }
+        }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kTileBytes / 16; i += kApplyBlock) src[i] = lds[i];
@@ -1571,12 +1674,15 @@ TileSizes tiled_sizes(uint64_t n, uint64_t pool_bytes, const Geometry& G) {
     TileSizes z{};
     z.n_tiles = (uint32_t)(pool_bytes / kTileBytes);
     z.nb = (uint32_t)((n + kTileRecs / G.r - 1) / (kTileRecs / G.r));
+    z.nchunk = (z.nb + kTileChunk - 1) / kTileChunk;
     z.recs = n * G.r;
-    z.table = (uint64_t)z.n_tiles * z.nb;
+    z.table = (uint64_t)z.nb * z.n_tiles;
     return z;
 }
 
-size_t tiled_lds_bytes() { return 2 * kTileRecs * sizeof(uint16_t) + 2 * kMaxTiles * sizeof(uint32_t); }
+size_t tiled_lds_bytes(uint32_t n_tiles) {
+    return 2 * kTileRecs * sizeof(uint16_t) + 2 * (((size_t)n_tiles + 3) & ~(size_t)3) * sizeof(uint32_t);
+}
 
 hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
                                uint64_t pool_bytes, const Geometry& G, uint32_t c0, const TileBufs& B,
@@ -1584,22 +1690,25 @@ hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_
     if (n == 0) return hipSuccess;
     if (!tiled_fits(pool_bytes)) return hipErrorInvalidValue;
     const TileSizes z = tiled_sizes(n, pool_bytes, G);
-    if (z.recs > B.rec_cap || z.table > B.table_cap) return hipErrorInvalidValue;
+    if (z.recs > B.rec_cap || z.table > B.table_cap || z.nchunk > B.chunk_cap) return hipErrorInvalidValue;
     const uint32_t ts = 16u - (G.atb == 2 ? 1u : 0u);  // log2 of the ATs per tile
+    const dim3 cols((z.n_tiles + kBlock - 1) / kBlock, z.nchunk);
     hipError_t e = with_rows<uint8_t>(G.r, [&](auto rc, auto) {
         constexpr int RR = decltype(rc)::value;
-        hipLaunchKernelGGL((k_tile_count<RR>), dim3(z.nb), dim3(kBlock), 0, st, aip, bip, n, G, ts, z.n_tiles, B.cnt,
-                           z.nb);
+        hipLaunchKernelGGL((k_tile_count<RR>), dim3(z.nb), dim3(kBlock), 0, st, aip, bip, n, G, ts, z.n_tiles,
+                           B.cnt);
     });
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile_colscan, dim3(z.n_tiles), dim3(kBlock), 0, st, B.cnt, B.pre, z.nb, B.tot);
-    hipLaunchKernelGGL(k_tile_totscan, dim3(1), dim3(kBlock), 0, st, B.tot, z.n_tiles, B.base);
+    hipLaunchKernelGGL(k_tile_chunksum, cols, dim3(kBlock), 0, st, B.cnt, z.nb, z.n_tiles, B.csum);
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScatterBlock), 0, st, B.csum, z.nchunk, z.n_tiles, B.base);
+    hipLaunchKernelGGL(k_tile_rowpre, cols, dim3(kBlock), 0, st, B.cnt, B.csum, B.base, z.nb, z.n_tiles, B.pre);
     e = with_rows<uint8_t>(G.r, [&](auto rc, auto) {
         constexpr int RR = decltype(rc)::value;
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile_scatter<RR>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)tiled_lds_bytes());
-        hipLaunchKernelGGL((k_tile_scatter<RR>), dim3(z.nb), dim3(kBlock), tiled_lds_bytes(), st, aip, bip, n, G, ts,
-                           z.n_tiles, B.cnt, B.pre, B.base, z.nb, B.rec);
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)tiled_lds_bytes(kMaxTiles));
+        hipLaunchKernelGGL((k_tile_scatter<RR>), dim3(z.nb), dim3(kScatterBlock), tiled_lds_bytes(z.n_tiles), st, aip,
+                           bip, n,
+                           G, ts, z.n_tiles, B.pre, B.rec);
     });
     if (e != hipSuccess) return e;
     return with_at(G, [&](auto t) {

@@ -197,3 +197,55 @@ def link_stream(seed: int, n_pairs: int, device, hosts: int = 1 << 16, zipf_s: f
     b = torch.cat([fmix32(ctr ^ hkey[hid]), rand_u32(seed, base + 3, n_bg, device)])
     perm = torch.argsort(rand_u64(seed, base + 4, a.numel(), device))
     return as_u32_device(a[perm]), as_u32_device(b[perm]), p_addr.cpu().numpy().astype(np.uint32)
+
+
+@dataclasses.dataclass
+class SlidingShape:
+    """Sliding-window traffic at the scale of the paper's own run (1-s slices,
+    a window of k slices).  Every slice carries `distinct` fresh background
+    pairs (aip Zipf(zipf_s) over `hosts` ranks, uniform 32-bit bips), each
+    sent `repeat` times, plus `planted` hosts whose cardinality over any full
+    window is k * m_h with m_h = floor(card_h / k) and card_h log-uniform in
+    [lo, hi]: host h adds m_h fresh bips in every slice."""
+    k: int = 300
+    distinct: int = 100_000
+    repeat: int = 10
+    hosts: int = 1 << 22
+    zipf_s: float = 1.1
+    planted: int = 1000
+    lo: int = 1024
+    hi: int = 1 << 18
+
+
+def sliding_planted(shape: SlidingShape, seed: int, device) -> Tuple[np.ndarray, np.ndarray]:
+    """Planted host addresses (uint32) and their per-slice fresh bips m_h."""
+    u = rand_unit(seed, 0xB000, shape.planted, device).cpu().numpy()
+    card = np.floor(np.exp(math.log(shape.lo) + u * (math.log(shape.hi) - math.log(shape.lo)))).astype(np.int64)
+    m = card // shape.k
+    addr_key = int(rand_u32(seed, 0xA11CE, 1, device)[0])
+    ranks = torch.arange(shape.planted, device=device, dtype=torch.int64) + shape.hosts + 1
+    return fmix32(ranks ^ addr_key).cpu().numpy().astype(np.uint32), m
+
+
+def sliding_slice(shape: SlidingShape, seed: int, t: int, device) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Pairs of slice t as int32 device tensors (shuffled)."""
+    addr_key = int(rand_u32(seed, 0xA11CE, 1, device)[0])
+    base = 0xC000 + 8 * t
+    cdf = _zipf_cdf(shape.hosts, shape.zipf_s, device)
+    ranks = torch.searchsorted(cdf, rand_unit(seed, base, shape.distinct, device), right=True)
+    ranks = ranks.clamp_(max=shape.hosts - 1) + 1
+    ba = fmix32(ranks ^ addr_key)
+    bb = rand_u32(seed, base + 1, shape.distinct, device)
+    ba, bb = ba.repeat(shape.repeat), bb.repeat(shape.repeat)
+    p_addr, m = sliding_planted(shape, seed, device)
+    mt = torch.from_numpy(m).to(device)
+    hid = torch.repeat_interleave(torch.arange(m.size, device=device), mt)
+    first = torch.from_numpy(np.concatenate([[0], np.cumsum(m)[:-1]])).to(device)
+    ctr = torch.arange(int(m.sum()), device=device, dtype=torch.int64) - first[hid]
+    hkey = rand_u32(seed, 0xB001, m.size, device)
+    pa = torch.from_numpy(p_addr.astype(np.int64)).to(device)[hid]
+    pb = fmix32((ctr + t * mt[hid]) ^ hkey[hid])           # fresh bips: counters never repeat
+    a = torch.cat([ba, pa])
+    b = torch.cat([bb, pb])
+    perm = torch.argsort(rand_u64(seed, base + 2, a.numel(), device))
+    return as_u32_device(a[perm]), as_u32_device(b[perm])
