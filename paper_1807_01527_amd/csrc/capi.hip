@@ -173,11 +173,13 @@ bool device_accessible(const void* ptr) {
            attr.type == hipMemoryTypeUnified || (attr.type == hipMemoryTypeHost && attr.devicePointer != nullptr);
 }
 
-int open_slice(at_ctx* h) {
+// Opening slice t: C0 = t mod 2k and Alg 2 on the due blocks.  With
+// `deferred` the caller runs Alg 2 itself (the tiled scan does it in LDS).
+int open_slice(at_ctx* h, bool deferred = false) {
     if (h->open) return AT_OK;
     h->c0 = (uint32_t)(h->t % h->G.twok);
-    hipError_t e = atp::launch_preserve(h->pool, h->n_atv, h->G, h->c0, h->stream);
-    if (e != hipSuccess) return AT_E_DEVICE;
+    if (!deferred && atp::launch_preserve(h->pool, h->n_atv, h->G, h->c0, h->stream) != hipSuccess)
+        return AT_E_DEVICE;
     h->open = true;
     h->queryable = false;
     return AT_OK;
@@ -324,7 +326,26 @@ int scan_path(const at_ctx* h, uint64_t n) {
     return kDirect;
 }
 
-int ingest_tiled(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, uint64_t n) {
+int ingest_tiled_buffers(at_ctx* h, uint64_t n);
+
+int ingest_tiled(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, uint64_t n, bool preserve) {
+    int rc = ingest_tiled_buffers(h, n);
+    if (rc) {
+        // the slice is open already: its preserve must not be lost
+        if (preserve && atp::launch_preserve(h->pool, h->n_atv, h->G, h->c0, h->stream) != hipSuccess)
+            return AT_E_DEVICE;
+        return rc;
+    }
+    for (uint64_t off = 0; off < n; off += kBinBatch) {
+        const uint64_t m = std::min<uint64_t>(kBinBatch, n - off);
+        if (atp::launch_ingest_tiled(h->pool, aip_dev + off, bip_dev + off, m, h->pool_bytes, h->G, h->c0, h->tb,
+                                     preserve && off == 0, h->stream) != hipSuccess)
+            return AT_E_DEVICE;
+    }
+    return AT_OK;
+}
+
+int ingest_tiled_buffers(at_ctx* h, uint64_t n) {
     int rc;
     const atp::TileSizes z = atp::tiled_sizes(std::min<uint64_t>(n, kBinBatch), h->pool_bytes, h->G);
     if (z.recs > h->tb.rec_cap) {
@@ -350,12 +371,6 @@ int ingest_tiled(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, ui
         h->tb.chunk_cap = z.nchunk;
     }
     if (!h->tb.base && (rc = dev_alloc(&h->tb.base, 4097))) return rc;
-    for (uint64_t off = 0; off < n; off += kBinBatch) {
-        const uint64_t m = std::min<uint64_t>(kBinBatch, n - off);
-        if (atp::launch_ingest_tiled(h->pool, aip_dev + off, bip_dev + off, m, h->pool_bytes, h->G, h->c0, h->tb,
-                                     h->stream) != hipSuccess)
-            return AT_E_DEVICE;
-    }
     return AT_OK;
 }
 
@@ -365,11 +380,13 @@ int at_ingest_slice(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev,
         if (!aip_dev || !bip_dev) return AT_E_INVAL;
         if (!device_accessible(aip_dev) || !device_accessible(bip_dev)) return AT_E_INVAL;
     }
-    int rc = open_slice(h);
+    const int path = n ? scan_path(h, n) : 0;
+    // a tiled call that opens the slice runs the opening preserve in its tile pass
+    const bool fuse = !h->open && path == kTiled;
+    int rc = open_slice(h, fuse);
     if (rc) return rc;
     if (n == 0) return AT_OK;
-    const int path = scan_path(h, n);
-    if (path == kTiled) return ingest_tiled(h, aip_dev, bip_dev, n);
+    if (path == kTiled) return ingest_tiled(h, aip_dev, bip_dev, n, fuse);
     if (path == kDirect)
         return atp::launch_ingest(h->pool, aip_dev, bip_dev, n, h->G, h->c0, h->stream) == hipSuccess ? AT_OK
                                                                                                      : AT_E_DEVICE;

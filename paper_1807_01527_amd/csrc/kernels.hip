@@ -578,21 +578,38 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
     }
 }
 
-// Pass 3: one workgroup per tile applies the tile's records in LDS.
+// Pass 3: one workgroup per tile applies the tile's records in LDS.  When the
+// call opens the slice (preserve != 0) Alg 2 first runs here on the two due
+// blocks of every ATV of the tile (the AT ranges of S), before any record:
+// the same order as a separate opening pass, without its extra pool traffic.
 template <typename T>
 __global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict__ pool,
                                                             const uint16_t* __restrict__ rec,
                                                             const uint32_t* __restrict__ base, Geometry G,
-                                                            uint32_t c0) {
+                                                            uint32_t c0, uint32_t preserve, PreserveSpans S) {
     extern __shared__ __align__(16) uint8_t smem_apply[];
     const uint32_t t = blockIdx.x;
     const uint32_t lo = base[t], hi = base[t + 1];
-    if (lo == hi) return;  // nothing lands here: the tile stays as it is
+    if (lo == hi && !preserve) return;  // nothing lands here: the tile stays as it is
     uint4* lds = reinterpret_cast<uint4*>(smem_apply);
     uint4* src = reinterpret_cast<uint4*>(pool + (uint64_t)t * kTileBytes);
     for (uint32_t i = threadIdx.x; i < kTileBytes / 16; i += kApplyBlock) lds[i] = src[i];
     __syncthreads();
     T* tl = reinterpret_cast<T*>(smem_apply);
+    if (preserve) {
+        const uint32_t n0 = S.r0hi - S.r0lo, n1 = S.r1hi - S.r1lo, per = n0 + n1;
+        const uint32_t atvs = (kTileBytes / sizeof(T)) >> G.log2g;
+        for (uint32_t q = threadIdx.x; q < atvs * per; q += kApplyBlock) {
+            const uint32_t v = q / per, e = q - v * per;
+            const uint32_t pos = e < n0 ? S.r0lo + e : S.r1lo + (e - n0);
+            T* a = tl + (v << G.log2g) + pos;
+            const uint32_t at = *a;
+            // Alg 2: the block whose timestamp becomes 0 clears ATs <= k, the
+            // one whose timestamp becomes k clears k..2k-1 and 0
+            if (e < n0 ? at <= G.k : ((at >= G.k && at < G.twok) || at == 0)) *a = (T)G.twok;
+        }
+        __syncthreads();
+    }
     const uint32_t gmask = G.g - 1u;
     // records [lo, hi): a ragged head and tail one by one, the 8-aligned body
     // eight at a time with 16-byte loads
@@ -662,16 +679,23 @@ __global__ __launch_bounds__(kBlock) void k_close(const T* __restrict__ pool, ui
         for (uint32_t j = 0; j < kMaxWindows; j++) cnt[j] = 0;
         if (atv < n_atv) {
             const T* p = pool + (atv << G.log2g);
-            for (uint32_t st = 0; st < steps; st++) {
-                const uint32_t off = (st * lpa + sl) * CA;
-                const uint4 d = *reinterpret_cast<const uint4*>(p + off);
-                const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
-                if (Wn.n == 1) {
-                    cnt[0] += __popc(active_mask_chunk<T>(d, ac, G.twok, Wn.kq[0]));
-                } else {
+            // four 16-byte loads in flight per lane
+            for (uint32_t st0 = 0; st0 < steps; st0 += 4) {
+                uint4 d[4];
 #pragma unroll
-                    for (uint32_t j = 0; j < kMaxWindows; j++)
-                        if (j < Wn.n) cnt[j] += __popc(active_mask_chunk<T>(d, ac, G.twok, Wn.kq[j]));
+                for (uint32_t u = 0; u < 4; u++)
+                    if (st0 + u < steps) d[u] = *reinterpret_cast<const uint4*>(p + ((st0 + u) * lpa + sl) * CA);
+#pragma unroll
+                for (uint32_t u = 0; u < 4; u++) {
+                    if (st0 + u >= steps) break;
+                    const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + ((st0 + u) * lpa + sl) * CA);
+                    if (Wn.n == 1) {
+                        cnt[0] += __popc(active_mask_chunk<T>(d[u], ac, G.twok, Wn.kq[0]));
+                    } else {
+#pragma unroll
+                        for (uint32_t j = 0; j < kMaxWindows; j++)
+                            if (j < Wn.n) cnt[j] += __popc(active_mask_chunk<T>(d[u], ac, G.twok, Wn.kq[j]));
+                    }
                 }
             }
         }
@@ -1685,7 +1709,7 @@ size_t tiled_lds_bytes(uint32_t n_tiles) {
 }
 
 hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
-                               uint64_t pool_bytes, const Geometry& G, uint32_t c0, const TileBufs& B,
+                               uint64_t pool_bytes, const Geometry& G, uint32_t c0, const TileBufs& B, bool preserve,
                                hipStream_t st) {
     if (n == 0) return hipSuccess;
     if (!tiled_fits(pool_bytes)) return hipErrorInvalidValue;
@@ -1713,8 +1737,9 @@ hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_
     if (e != hipSuccess) return e;
     return with_at(G, [&](auto t) {
         using T = decltype(t);
+        const PreserveSpans S = preserve ? preserve_spans(G, c0) : PreserveSpans{};
         hipLaunchKernelGGL(k_tile_apply<T>, dim3(z.n_tiles), dim3(kApplyBlock), kTileBytes, st, pool, B.rec, B.base,
-                           G, c0);
+                           G, c0, (uint32_t)preserve, S);
     });
 }
 
@@ -1724,7 +1749,7 @@ hipError_t launch_close(const uint8_t* pool, uint32_t* w, uint64_t n_atv, const 
     const uint32_t lpa = G.g / ca < 64 ? G.g / ca : 64;
     const uint64_t atv_per_block = (kBlock / 64) * (64 / lpa);
     uint64_t blocks = (n_atv + atv_per_block - 1) / atv_per_block;
-    if (blocks > 8192) blocks = 8192;
+    if (blocks > 1024) blocks = 1024;  // every block fills a g-AT timestamp table first: amortise it
     return with_at(G, [&](auto t) {
         using T = decltype(t);
         hipLaunchKernelGGL(k_close<T>, dim3((uint32_t)blocks), dim3(kBlock), G.g * sizeof(T), st,

@@ -1,8 +1,11 @@
 """Parity at the benchmark's full size and launch configuration.
 
 The realistic-link workload (10 slices of 5M pairs, k = 10, 2^26-AT pool)
-goes through the HIP path exactly as bench.py issues it: one open, then one
-scan launch per slice.  The oracle follows on the same pairs.  After every
+goes through the HIP path exactly as bench.py issues it: one at_ingest_slice
+call per slice, which opens the slice and scans its pairs (on the automatic
+path; at this size the tiled scan, with the opening preserve in its tile
+pass).  A second pool takes the same slices with a separate opening call
+first.  The oracle follows on the same pairs.  After every
 slice, the whole pool, the weights and the AAT are compared.  After the last
 slice, the estimates of every true super point and of a host sample are
 compared, along with the restore outcome (AT_E_BUDGET with the same U).
@@ -28,17 +31,22 @@ def link_trace():
 
 
 def test_link_workload_full_size(oracle_lib, link_trace):
+    from paper_1807_01527_amd.binding import AtPool
     tr = link_trace
     g, o = make_pair(LINK, oracle_lib)
+    g2 = AtPool(**LINK)
     for t in range(tr.n_slices):
         da, db = to_dev(tr.aip[t]), to_dev(tr.bip[t])
-        g.ingest(da[:0], db[:0], n=0)
         g.ingest(da, db)
+        g2.ingest(da[:0], db[:0], n=0)
+        g2.ingest(da, db)
         o.ingest(tr.aip[t], tr.bip[t])
         g.close(10)
+        g2.close(10)
         o.close(10)
         compare_state(g, o, f"slice {t}")
         compare_summary(g, o, f"slice {t}")
+        assert np.array_equal(g2.read_pool(), g.read_pool()), f"slice {t}: separate opening call differs"
         print(f"slice {t}: pool, weights and AAT identical", flush=True)
     h, n = traffic.window_counts(tr.aip, tr.bip, min_count=1024)
     rng = np.random.default_rng(0)
