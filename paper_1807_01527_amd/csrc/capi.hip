@@ -44,6 +44,8 @@ struct at_ctx {
     uint64_t bins_cap = 0;
     unsigned long long* bin_fill = nullptr;
     atp::TileBufs tb{};           // tiled-scan scratch (grown on demand)
+    uint8_t* pin = nullptr;       // pinned host staging of query inputs and outputs (grown on demand)
+    uint64_t pin_cap = 0;
     bool tiled_ok = false;        // the device has the LDS the tiled scan needs
     int scan_mode = 0;            // 0 auto, 1 direct, 2 binned, 3 tiled
     // grow-on-demand device scratch
@@ -158,6 +160,9 @@ void free_all(at_ctx* h) {
     void* bufs[] = {h->pool, h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->counter, h->prefix, h->cand,
                     h->q_aip, h->q_est, h->q_flags, h->q_nat, h->q_feat, h->q_y, h->q_plain, h->bins, h->bin_fill,
                     h->tb.rec, h->tb.cnt, h->tb.pre, h->tb.csum, h->tb.base};
+    if (h->pin) (void)hipHostFree(h->pin);
+    h->pin = nullptr;
+    h->pin_cap = 0;
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -218,11 +223,47 @@ uint64_t sat_mul(uint64_t a, uint64_t b) {
     return a * b;
 }
 
+// Pinned staging: copies between the caller's (pageable) host buffers and the
+// device go through it, so they run as asynchronous DMA and one call waits
+// once.  Grown on demand; one region per field.
+int ensure_pinned(at_ctx* h, uint64_t bytes) {
+    if (bytes <= h->pin_cap) return AT_OK;
+    if (h->pin) (void)hipHostFree(h->pin);
+    h->pin = nullptr;
+    h->pin_cap = 0;
+    const uint64_t cap = std::max<uint64_t>((bytes + 65535) & ~65535ull, 1u << 20);
+    if (hipHostMalloc((void**)&h->pin, cap, hipHostMallocDefault) != hipSuccess) {
+        h->pin = nullptr;
+        (void)hipGetLastError();
+        return AT_E_NOMEM;
+    }
+    h->pin_cap = cap;
+    return AT_OK;
+}
+
+// Byte offsets of the staging regions for n hosts (64-byte aligned).
+struct PinLayout {
+    uint64_t aip, est, plain, nat, flags, total;
+};
+PinLayout pin_layout(uint64_t n) {
+    auto up = [](uint64_t x) { return (x + 63) & ~63ull; };
+    PinLayout L{};
+    L.aip = 0;
+    L.est = up(L.aip + 4 * n);
+    L.plain = up(L.est + 8 * n);
+    L.nat = up(L.plain + 8 * n);
+    L.flags = up(L.nat + 4 * n);
+    L.total = up(L.flags + n);
+    return L;
+}
+
 int read_counts(at_ctx* h, std::vector<uint32_t>& cnt) {
     cnt.assign(h->ngroups, 0);
-    hipError_t e = hipMemcpyAsync(cnt.data(), h->sa_cnt, h->ngroups * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                  h->stream);
+    int rc = ensure_pinned(h, h->ngroups * sizeof(uint32_t));
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(h->pin, h->sa_cnt, h->ngroups * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) std::memcpy(cnt.data(), h->pin, h->ngroups * sizeof(uint32_t));
     return dev_err(e);
 }
 
@@ -483,19 +524,26 @@ int at_estimate_detail(at_ctx* h, const uint32_t* aip_host, uint64_t n, double* 
     if (n == 0) return AT_OK;
     if (!aip_host) return AT_E_INVAL;
     int rc = ensure_query(h, n);
+    const PinLayout L = pin_layout(n);
+    if (!rc) rc = ensure_pinned(h, L.total);
     if (rc) return rc;
-    hipError_t e = hipMemcpyAsync(h->q_aip, aip_host, n * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
+    std::memcpy(h->pin + L.aip, aip_host, n * sizeof(uint32_t));
+    hipError_t e = hipMemcpyAsync(h->q_aip, h->pin + L.aip, n * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess)
         e = atp::launch_estimate(h->pool, h->aat, h->q_aip, n, h->G, h->c0_query, h->kq, h->q_est, h->q_flags,
                                  h->q_nat, h->stream);
     if (e == hipSuccess && est_out)
-        e = hipMemcpyAsync(est_out, h->q_est, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        e = hipMemcpyAsync(h->pin + L.est, h->q_est, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess && flags_out)
-        e = hipMemcpyAsync(flags_out, h->q_flags, n, hipMemcpyDeviceToHost, h->stream);
+        e = hipMemcpyAsync(h->pin + L.flags, h->q_flags, n, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess && nat_out)
-        e = hipMemcpyAsync(nat_out, h->q_nat, n * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
+        e = hipMemcpyAsync(h->pin + L.nat, h->q_nat, n * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    return dev_err(e);
+    if (e != hipSuccess) return dev_err(e);
+    if (est_out) std::memcpy(est_out, h->pin + L.est, n * sizeof(double));
+    if (flags_out) std::memcpy(flags_out, h->pin + L.flags, n);
+    if (nat_out) std::memcpy(nat_out, h->pin + L.nat, n * sizeof(uint32_t));
+    return AT_OK;
 }
 
 int at_estimate(at_ctx* h, const uint32_t* aip_host, uint64_t n, double* est_out, uint8_t* flags_out) {
@@ -544,33 +592,43 @@ int at_restore(at_ctx* h, uint32_t* sip_out, double* est_out, uint8_t* flags_out
         if ((rc = dev_alloc(&h->cand, pow2))) return rc;
         h->cand_cap = pow2;
     }
-    hipError_t e = hipMemcpyAsync(h->prefix, prefix.data(), prefix.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
-                                  h->stream);
+    const uint64_t pre_bytes = prefix.size() * sizeof(uint64_t);
+    if ((rc = ensure_pinned(h, pre_bytes + 64))) return rc;
+    std::memcpy(h->pin + 64, prefix.data(), pre_bytes);
+    hipError_t e = hipMemcpyAsync(h->prefix, h->pin + 64, pre_bytes, hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) e = atp::launch_zero_u64(h->counter, 1, h->stream);
     if (e == hipSuccess)
         e = atp::launch_restore_join(h->sa, h->sa_cnt, h->prefix, n_items, h->G, h->cand, need, h->counter,
                                      h->stream);
     unsigned long long m = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&m, h->counter, sizeof(m), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->pin, h->counter, sizeof(m), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return dev_err(e);
+    std::memcpy(&m, h->pin, sizeof(m));
     *n_out = m;
     if (m > cap) return AT_E_OVERFLOW;
     if (m == 0) return AT_OK;
     uint64_t mp2 = 1;
     while (mp2 < m) mp2 <<= 1;
     if ((rc = ensure_query(h, m))) return rc;
+    const PinLayout L = pin_layout(m);  // candidates in the aip region
+    if ((rc = ensure_pinned(h, L.total))) return rc;
     e = atp::launch_sort_u32(h->cand, m, mp2, h->stream);
     if (e == hipSuccess && (est_out || flags_out))
         e = atp::launch_estimate(h->pool, h->aat, h->cand, m, h->G, h->c0_query, h->kq, h->q_est, h->q_flags,
                                  nullptr, h->stream);
     if (e == hipSuccess && sip_out)
-        e = hipMemcpyAsync(sip_out, h->cand, m * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
+        e = hipMemcpyAsync(h->pin + L.aip, h->cand, m * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess && est_out)
-        e = hipMemcpyAsync(est_out, h->q_est, m * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess && flags_out) e = hipMemcpyAsync(flags_out, h->q_flags, m, hipMemcpyDeviceToHost, h->stream);
+        e = hipMemcpyAsync(h->pin + L.est, h->q_est, m * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && flags_out)
+        e = hipMemcpyAsync(h->pin + L.flags, h->q_flags, m, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    return dev_err(e);
+    if (e != hipSuccess) return dev_err(e);
+    if (sip_out) std::memcpy(sip_out, h->pin + L.aip, m * sizeof(uint32_t));
+    if (est_out) std::memcpy(est_out, h->pin + L.est, m * sizeof(double));
+    if (flags_out) std::memcpy(flags_out, h->pin + L.flags, m);
+    return AT_OK;
 }
 
 int at_pool_info(const at_ctx* h, uint64_t* pool_bytes, uint64_t* n_atv) {
@@ -845,18 +903,25 @@ int at_estimate_learned(at_ctx* h, at_mlp* M, const uint32_t* aip_host, uint64_t
     if (!h->queryable) return AT_E_STATE;
     if (n == 0) return AT_OK;
     int rc = ensure_query(h, n);
+    const PinLayout L = pin_layout(n);
+    if (!rc) rc = ensure_pinned(h, L.total);
     if (rc) return rc;
-    hipError_t e = hipMemcpyAsync(h->q_aip, aip_host, n * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
+    std::memcpy(h->pin + L.aip, aip_host, n * sizeof(uint32_t));
+    hipError_t e = hipMemcpyAsync(h->q_aip, h->pin + L.aip, n * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) return AT_E_DEVICE;
     // est and flags of the learned path land in q_est / q_nat (as bytes); plain in q_plain
     rc = at_estimate_learned_dev(h, M, h->q_aip, n, h->q_est, reinterpret_cast<uint8_t*>(h->q_nat), h->q_plain);
     if (rc) return rc;
-    e = hipMemcpyAsync(est_out, h->q_est, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(flags_out, h->q_nat, n, hipMemcpyDeviceToHost, h->stream);
+    e = hipMemcpyAsync(h->pin + L.est, h->q_est, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->pin + L.flags, h->q_nat, n, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess && plain_out)
-        e = hipMemcpyAsync(plain_out, h->q_plain, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        e = hipMemcpyAsync(h->pin + L.plain, h->q_plain, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    return dev_err(e);
+    if (e != hipSuccess) return dev_err(e);
+    std::memcpy(est_out, h->pin + L.est, n * sizeof(double));
+    std::memcpy(flags_out, h->pin + L.flags, n);
+    if (plain_out) std::memcpy(plain_out, h->pin + L.plain, n * sizeof(double));
+    return AT_OK;
 }
 
 }  // extern "C"
