@@ -89,6 +89,49 @@ __device__ __forceinline__ uint32_t active_mask16(uint4 at, uint4 act, uint32_t 
     return active_mask_chunk<uint8_t>(at, act, twok, kq);
 }
 
+// Alg 1 on two ATs at a time in the 16-bit halves of a word (packed integer
+// ops).  With d = act + 2k - at in [1, 4k) (exact while 4k <= 2^16), the
+// distance is d mod 2k = min(d, d - 2k) (the second wraps high when d < 2k);
+// the AT is inactive when at = 2k or the distance reaches k', and bit 15 of
+// (x + 0x8000 - y) tests x >= y for x, y < 2^15 + y.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t w) { return __builtin_bit_cast(u16x2, w); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ uint32_t both_halves(uint32_t v) { return v | (v << 16); }
+
+// per 16-bit half: distance (in the low 15 bits) and the at = 2k flag (bit 15)
+struct Alg1Halves {
+    uint32_t dist;
+    uint32_t off;
+};
+__device__ __forceinline__ Alg1Halves alg1_halves(uint32_t at2, uint32_t act2, uint32_t twok2, uint32_t c_at) {
+    const u16x2 a = as_u16x2(at2);
+    const u16x2 d = as_u16x2(act2) + as_u16x2(twok2) - a;
+    const u16x2 m = __builtin_elementwise_min(d, d - as_u16x2(twok2));
+    return {as_u32(m), as_u32(a + as_u16x2(c_at)) & 0x80008000u};
+}
+// number of inactive ATs among the two halves for window k' (c_kq = 0x8000 - k' in both halves)
+__device__ __forceinline__ uint32_t inactive2(const Alg1Halves& h, uint32_t c_kq) {
+    return __popc(((as_u32(as_u16x2(h.dist) + as_u16x2(c_kq))) | h.off) & 0x80008000u);
+}
+// the 16-bit halves of a 16-byte chunk of ATs (bytes: even and odd bytes of every word apart)
+template <typename T>
+__device__ __forceinline__ void chunk_halves(uint4 v, uint32_t* h /* 8 or 4 */) {
+    if (sizeof(T) == 1) {
+#pragma unroll
+        for (uint32_t q = 0; q < 4; q++) {
+            const uint32_t w = word_of(v, q);
+            h[2 * q] = w & 0x00FF00FFu;
+            h[2 * q + 1] = (w >> 8) & 0x00FF00FFu;
+        }
+    } else {
+        h[0] = v.x;
+        h[1] = v.y;
+        h[2] = v.z;
+        h[3] = v.w;
+    }
+}
+
 // per-position block timestamp table for the slice whose first block has C0
 template <typename T>
 __device__ void fill_act_lut(T* lut, uint32_t c0, const Geometry& G) {
@@ -670,6 +713,10 @@ __global__ __launch_bounds__(kBlock) void k_close(const T* __restrict__ pool, ui
     const uint32_t apw = 64 / lpa;
     const uint32_t sub = lane / lpa, sl = lane % lpa;
     const uint32_t steps = G.g / (CA * lpa);
+    // the packed form counts inactive ATs; it needs 4k <= 2^16
+    const bool packed = G.twok <= 32768u;
+    const uint32_t twok2 = both_halves(G.twok), c_at = both_halves(0x8000u - G.twok);
+    const uint32_t c_kq0 = both_halves(0x8000u - Wn.kq[0]);
     const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
     for (uint64_t base = wave * apw; base < n_atv; base += nwaves * apw) {
@@ -689,7 +736,22 @@ __global__ __launch_bounds__(kBlock) void k_close(const T* __restrict__ pool, ui
                 for (uint32_t u = 0; u < 4; u++) {
                     if (st0 + u >= steps) break;
                     const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + ((st0 + u) * lpa + sl) * CA);
-                    if (Wn.n == 1) {
+                    if (packed) {
+                        constexpr uint32_t NH = 8 / sizeof(T);  // 16-bit halves per chunk
+                        uint32_t ha[NH], hc[NH];
+                        chunk_halves<T>(d[u], ha);
+                        chunk_halves<T>(ac, hc);
+#pragma unroll
+                        for (uint32_t q = 0; q < NH; q++) {
+                            const Alg1Halves hh = alg1_halves(ha[q], hc[q], twok2, c_at);
+                            cnt[0] += inactive2(hh, c_kq0);
+                            if (Wn.n > 1) {
+#pragma unroll
+                                for (uint32_t j = 1; j < kMaxWindows; j++)
+                                    if (j < Wn.n) cnt[j] += inactive2(hh, both_halves(0x8000u - Wn.kq[j]));
+                            }
+                        }
+                    } else if (Wn.n == 1) {
                         cnt[0] += __popc(active_mask_chunk<T>(d[u], ac, G.twok, Wn.kq[0]));
                     } else {
 #pragma unroll
@@ -702,7 +764,7 @@ __global__ __launch_bounds__(kBlock) void k_close(const T* __restrict__ pool, ui
 #pragma unroll
         for (uint32_t j = 0; j < kMaxWindows; j++) {
             if (j >= Wn.n) break;
-            uint32_t c = cnt[j];
+            uint32_t c = packed && atv < n_atv ? steps * CA - cnt[j] : cnt[j];  // the lane's active ATs
             for (uint32_t o = lpa / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
             if (sl == 0 && atv < n_atv) w[(uint64_t)j * n_atv + atv] = c;
         }
@@ -954,6 +1016,9 @@ __global__ __launch_bounds__(kBlock) void k_estimate(const T* __restrict__ pool,
     T* act_lut = reinterpret_cast<T*>(smem_est);
     fill_act_lut(act_lut, c0q, G);
     constexpr uint32_t CA = kPerChunk<T>;
+    const bool packed = G.twok <= 32768u;  // the packed form of Alg 1 needs 4k <= 2^16
+    const uint32_t twok2 = both_halves(G.twok), c_at = both_halves(0x8000u - G.twok);
+    const uint32_t c_kq = both_halves(0x8000u - kq);
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
@@ -970,15 +1035,50 @@ __global__ __launch_bounds__(kBlock) void k_estimate(const T* __restrict__ pool,
             rows[j] = pool + (((((uint64_t)z * R + j) << G.c) + x) << G.log2g);
         }
         uint32_t cnt = 0;
-        for (uint32_t off = lane * CA; off < G.g; off += 64 * CA) {
-            const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
-            uint32_t m = ~0u;
+        // up to four chunk positions per lane in flight, r loads each
+        for (uint32_t off0 = lane * CA; off0 < G.g; off0 += 4 * 64 * CA) {
+            uint4 d[4][R];
 #pragma unroll
-            for (int j = 0; j < R; j++) {
-                uint4 d = *reinterpret_cast<const uint4*>(rows[j] + off);
-                m &= active_mask_chunk<T>(d, ac, G.twok, kq);
+            for (uint32_t u = 0; u < 4; u++) {
+                const uint32_t off = off0 + u * 64 * CA;
+                if (off < G.g) {
+#pragma unroll
+                    for (int j = 0; j < R; j++) d[u][j] = *reinterpret_cast<const uint4*>(rows[j] + off);
+                }
             }
-            cnt += __popc(m);
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) {
+                const uint32_t off = off0 + u * 64 * CA;
+                if (off >= G.g) break;
+                const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
+                if (packed) {
+                    // positions inactive in any row, then the active rest
+                    constexpr uint32_t NH = 8 / sizeof(T);
+                    uint32_t hc[NH], inact[NH];
+                    chunk_halves<T>(ac, hc);
+#pragma unroll
+                    for (uint32_t q = 0; q < NH; q++) inact[q] = 0;
+#pragma unroll
+                    for (int j = 0; j < R; j++) {
+                        uint32_t ha[NH];
+                        chunk_halves<T>(d[u][j], ha);
+#pragma unroll
+                        for (uint32_t q = 0; q < NH; q++) {
+                            const Alg1Halves hh = alg1_halves(ha[q], hc[q], twok2, c_at);
+                            inact[q] |= (as_u32(as_u16x2(hh.dist) + as_u16x2(c_kq)) | hh.off) & 0x80008000u;
+                        }
+                    }
+                    uint32_t ni = 0;
+#pragma unroll
+                    for (uint32_t q = 0; q < NH; q++) ni += __popc(inact[q]);
+                    cnt += CA - ni;
+                } else {
+                    uint32_t m = ~0u;
+#pragma unroll
+                    for (int j = 0; j < R; j++) m &= active_mask_chunk<T>(d[u][j], ac, G.twok, kq);
+                    cnt += __popc(m);
+                }
+            }
         }
         for (uint32_t o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
         if (lane == 0) {
@@ -1030,25 +1130,37 @@ __global__ __launch_bounds__(kBlock) void k_features(const T* __restrict__ pool,
             rows[j] = pool + (((((uint64_t)z * R + j) << G.c) + x) << G.log2g);
         }
         uint32_t nat = 0;
-        for (uint32_t off = lane * CA; off < G.g; off += 64 * CA) {
-            const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
-            uint4 d[R];
+        // two chunk positions per lane in flight, r loads each
+        for (uint32_t off0 = lane * CA; off0 < G.g; off0 += 2 * 64 * CA) {
+            uint4 dd[2][R];
 #pragma unroll
-            for (int j = 0; j < R; j++) d[j] = *reinterpret_cast<const uint4*>(rows[j] + off);
+            for (uint32_t u = 0; u < 2; u++) {
+                const uint32_t off = off0 + u * 64 * CA;
+                if (off < G.g) {
 #pragma unroll
-            for (uint32_t b = 0; b < CA; b++) {
-                const uint32_t actb = at_in_word<T>(word_of(ac, b / N), b % N);
-                uint32_t e = 0, ok = 1;
-#pragma unroll
-                for (int j = 0; j < R; j++) {
-                    const uint32_t at = at_in_word<T>(word_of(d[j], b / N), b % N);
-                    const uint32_t dist = actb >= at ? actb - at : actb + G.twok - at;
-                    ok &= (at != G.twok) & (dist < G.k);
-                    e = dist > e ? dist : e;
+                    for (int j = 0; j < R; j++) dd[u][j] = *reinterpret_cast<const uint4*>(rows[j] + off);
                 }
-                if (ok) {
-                    nat += e < kq;
-                    if (e < 64) atomicAdd(&hist[e], 1u);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 2; u++) {
+                const uint32_t off = off0 + u * 64 * CA;
+                if (off >= G.g) break;
+                const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
+#pragma unroll
+                for (uint32_t b = 0; b < CA; b++) {
+                    const uint32_t actb = at_in_word<T>(word_of(ac, b / N), b % N);
+                    uint32_t e = 0, ok = 1;
+#pragma unroll
+                    for (int j = 0; j < R; j++) {
+                        const uint32_t at = at_in_word<T>(word_of(dd[u][j], b / N), b % N);
+                        const uint32_t dist = actb >= at ? actb - at : actb + G.twok - at;
+                        ok &= (at != G.twok) & (dist < G.k);
+                        e = dist > e ? dist : e;
+                    }
+                    if (ok) {
+                        nat += e < kq;
+                        if (e < 64) atomicAdd(&hist[e], 1u);
+                    }
                 }
             }
         }

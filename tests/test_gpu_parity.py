@@ -235,6 +235,7 @@ def test_close_multi_windows(cuda, oracle_lib, geom):
     (dict(k=150, r=4, c=8, s=8, u=1, log2g=9), 310),    # blocks of 1 AT and a 213-AT last block
     (dict(k=300, r=4, c=8, s=8, u=3, log2g=4), 610),    # the paper's k; g < 2k: one block holds every AT
     (dict(k=200, r=4, c=9, s=8, u=3, log2g=8), 40),     # 8 frames, a larger pool, no wrap
+    (dict(k=20000, r=4, c=8, s=8, u=1, log2g=5), 12),   # 4k > 2^16: the unpacked form of Alg 1
 ])
 def test_wide_ats(cuda, oracle_lib, geom, slices, mode):
     """k > 127 needs 2k+1 > 256 AT values: 16-bit ATs.  The two long runs go
