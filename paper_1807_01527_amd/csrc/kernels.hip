@@ -1093,13 +1093,14 @@ __global__ __launch_bounds__(kBlock) void k_estimate(const T* __restrict__ pool,
 
 
 // ---------------------------------------------------------------- a7: features
-// Occupancy-by-age features of a host (one wave per host): e_i = largest age
-// over the host's r ATs at position i when all are active for the full
-// window k.  feat[d] = #{i : e_i = d}/g (d < min(k, 61)); feat[61] =
-// min(ln(1 + max(plain, 0)), 20)/16 with plain the Eq 4 estimate for the
-// close's k'; feat[62] = k/64; feat[63] = mean over rows of AAT/(g*2^c).
-// NAT(k') = #{i : e_i < k'} is counted in the same pass, so the plain
-// estimate comes along.  The LDS histogram keeps ages below 64.
+// Occupancy-by-age features of a host (one workgroup per host, its 16-byte
+// chunks of positions spread over the four waves): e_i = largest age over the
+// host's r ATs at position i when all are active for the full window k.
+// feat[d] = #{i : e_i = d}/g (d < min(k, 61)); feat[61] = min(ln(1 + max(plain,
+// 0)), 20)/16 with plain the Eq 4 estimate for the close's k'; feat[62] =
+// k/64; feat[63] = mean over rows of AAT/(g*2^c).  NAT(k') = #{i : e_i < k'}
+// is counted in the same pass, so the plain estimate comes along.  The LDS
+// histogram keeps ages below 64.
 template <int R, typename T>
 __global__ __launch_bounds__(kBlock) void k_features(const T* __restrict__ pool, const uint64_t* __restrict__ aat,
                                                      const uint32_t* __restrict__ aips, uint64_t n, Geometry G,
@@ -1107,17 +1108,14 @@ __global__ __launch_bounds__(kBlock) void k_features(const T* __restrict__ pool,
                                                      double* __restrict__ est, uint8_t* __restrict__ flags) {
     extern __shared__ __align__(16) uint8_t smem_feat[];
     T* act_lut = reinterpret_cast<T*>(smem_feat);
-    uint32_t* hist =
-        reinterpret_cast<uint32_t*>(smem_feat + ((G.g * sizeof(T) + 15u) & ~15u)) + (threadIdx.x >> 6) * 64;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(smem_feat + ((G.g * sizeof(T) + 15u) & ~15u));  // 64 bins
+    __shared__ uint32_t nat_w[kBlock / 64];
     fill_act_lut(act_lut, c0q, G);
     constexpr uint32_t CA = kPerChunk<T>, N = kPerWord<T>;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
-    for (uint64_t h = wave; h < n; h += nwaves) {
-        hist[lane] = 0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    for (uint64_t h = blockIdx.x; h < n; h += gridDim.x) {
+        if (threadIdx.x < 64) hist[threadIdx.x] = 0;
+        __syncthreads();
         const uint32_t a = aips[h];
         const uint32_t f = mangle(a, G.A);
         const uint32_t z = f & G.umask;
@@ -1130,69 +1128,61 @@ __global__ __launch_bounds__(kBlock) void k_features(const T* __restrict__ pool,
             rows[j] = pool + (((((uint64_t)z * R + j) << G.c) + x) << G.log2g);
         }
         uint32_t nat = 0;
-        // two chunk positions per lane in flight, r loads each
-        for (uint32_t off0 = lane * CA; off0 < G.g; off0 += 2 * 64 * CA) {
-            uint4 dd[2][R];
+        for (uint32_t off = threadIdx.x * CA; off < G.g; off += kBlock * CA) {
+            uint4 d[R];
 #pragma unroll
-            for (uint32_t u = 0; u < 2; u++) {
-                const uint32_t off = off0 + u * 64 * CA;
-                if (off < G.g) {
+            for (int j = 0; j < R; j++) d[j] = *reinterpret_cast<const uint4*>(rows[j] + off);
+            const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
 #pragma unroll
-                    for (int j = 0; j < R; j++) dd[u][j] = *reinterpret_cast<const uint4*>(rows[j] + off);
+            for (uint32_t b = 0; b < CA; b++) {
+                const uint32_t actb = at_in_word<T>(word_of(ac, b / N), b % N);
+                uint32_t e = 0, ok = 1;
+#pragma unroll
+                for (int j = 0; j < R; j++) {
+                    const uint32_t at = at_in_word<T>(word_of(d[j], b / N), b % N);
+                    const uint32_t dist = actb >= at ? actb - at : actb + G.twok - at;
+                    ok &= (at != G.twok) & (dist < G.k);
+                    e = dist > e ? dist : e;
                 }
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < 2; u++) {
-                const uint32_t off = off0 + u * 64 * CA;
-                if (off >= G.g) break;
-                const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
-#pragma unroll
-                for (uint32_t b = 0; b < CA; b++) {
-                    const uint32_t actb = at_in_word<T>(word_of(ac, b / N), b % N);
-                    uint32_t e = 0, ok = 1;
-#pragma unroll
-                    for (int j = 0; j < R; j++) {
-                        const uint32_t at = at_in_word<T>(word_of(dd[u][j], b / N), b % N);
-                        const uint32_t dist = actb >= at ? actb - at : actb + G.twok - at;
-                        ok &= (at != G.twok) & (dist < G.k);
-                        e = dist > e ? dist : e;
-                    }
-                    if (ok) {
-                        nat += e < kq;
-                        if (e < 64) atomicAdd(&hist[e], 1u);
-                    }
+                if (ok) {
+                    nat += e < kq;
+                    if (e < 64) atomicAdd(&hist[e], 1u);
                 }
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const uint32_t hv = hist[lane];
         for (uint32_t o = 32; o > 0; o >>= 1) nat += __shfl_xor(nat, o, 64);
-        uint8_t fl = 0;
-        double e_plain = 0.0;
-        if (lane == 0) e_plain = eq4(nat, z, aat, G, &fl);
-        e_plain = __shfl(e_plain, 0, 64);
-        const uint32_t nd = G.k < 61 ? G.k : 61;
-        float fv = lane < nd ? (float)((double)hv / (double)G.g) : 0.0f;
-        if (lane == 61) {
-            double lp = log(1.0 + (e_plain > 0 ? e_plain : 0.0));
-            if (!(lp < 20.0)) lp = 20.0;
-            fv = (float)(lp / 16.0);
-        } else if (lane == 62) {
-            fv = (float)((double)G.k / 64.0);
-        } else if (lane == 63) {
-            const double cells = (double)((uint64_t)G.g << G.c);
-            double s = 0.0;
-            for (uint32_t j = 0; j < G.r; j++) s += (double)aat[(uint64_t)z * G.r + j] / cells;
-            fv = (float)(s / (double)G.r);
+        if (lane == 0) nat_w[wv] = nat;
+        __syncthreads();
+        if (wv == 0) {
+            uint32_t nat_all = 0;
+#pragma unroll
+            for (uint32_t w = 0; w < kBlock / 64; w++) nat_all += nat_w[w];
+            const uint32_t hv = hist[lane];
+            uint8_t fl = 0;
+            double e_plain = 0.0;
+            if (lane == 0) e_plain = eq4(nat_all, z, aat, G, &fl);
+            e_plain = __shfl(e_plain, 0, 64);
+            const uint32_t nd = G.k < 61 ? G.k : 61;
+            float fv = lane < nd ? (float)((double)hv / (double)G.g) : 0.0f;
+            if (lane == 61) {
+                double lp = log(1.0 + (e_plain > 0 ? e_plain : 0.0));
+                if (!(lp < 20.0)) lp = 20.0;
+                fv = (float)(lp / 16.0);
+            } else if (lane == 62) {
+                fv = (float)((double)G.k / 64.0);
+            } else if (lane == 63) {
+                const double cells = (double)((uint64_t)G.g << G.c);
+                double s2 = 0.0;
+                for (uint32_t j = 0; j < G.r; j++) s2 += (double)aat[(uint64_t)z * G.r + j] / cells;
+                fv = (float)(s2 / (double)G.r);
+            }
+            feat[h * 64 + lane] = fv;
+            if (lane == 0) {
+                if (est) est[h] = e_plain;
+                if (flags) flags[h] = fl;
+            }
         }
-        feat[h * 64 + lane] = fv;
-        if (lane == 0) {
-            if (est) est[h] = e_plain;
-            if (flags) flags[h] = fl;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        __syncthreads();  // hist and nat_w are reused by the next host
     }
 }
 
@@ -1923,9 +1913,9 @@ hipError_t launch_features(const uint8_t* pool, const uint64_t* aat, const uint3
                            const Geometry& G, uint32_t c0q, uint32_t kq, float* feat, double* est, uint8_t* flags,
                            hipStream_t st) {
     if (n == 0) return hipSuccess;
-    uint64_t blocks = (n + 3) / 4;
+    uint64_t blocks = n;  // one workgroup per host
     if (blocks > 16384) blocks = 16384;
-    const size_t shmem = ((G.g * G.atb + 15u) & ~15u) + (kBlock / 64) * 64 * sizeof(uint32_t);
+    const size_t shmem = ((G.g * G.atb + 15u) & ~15u) + 64 * sizeof(uint32_t);
     return with_rows_at(G, [&](auto rc, auto t) {
         constexpr int R = decltype(rc)::value;
         using T = decltype(t);
