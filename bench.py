@@ -312,7 +312,7 @@ def main():
                     help="also run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus above 1 is not supported"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus above 1 is not supported"}))
         sys.exit(2)
     if args.warmup < 1:
         args.warmup = 1  # the first pass fills the window; measured windows hold all slices
