@@ -34,6 +34,8 @@ struct Geometry {
     double theta;
 };
 
+Geometry derive_geometry(const at_params& p);  // from a handle's parameters (capi.hip)
+
 // Lazy preserve work of one slice opening: the AT ranges of the two blocks
 // whose timestamp becomes 0 and k, and the (one or two, disjoint) spans of
 // 16-byte chunks covering them.

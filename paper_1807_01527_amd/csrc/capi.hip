@@ -100,46 +100,6 @@ int validate(const at_params& p) {
     return AT_OK;
 }
 
-Geometry derive(const at_params& p) {
-    Geometry G{};
-    G.k = p.k;
-    G.twok = 2 * p.k;
-    G.atb = G.twok < 256 ? 1 : 2;  // AT bytes: 2k + 1 values per AT
-    G.r = p.r;
-    G.c = p.c;
-    G.s = p.s;
-    G.u = p.u;
-    G.W = 32 - p.u;
-    G.log2g = p.log2g;
-    G.g = 1u << p.log2g;
-    G.ncol_mask = (1u << p.c) - 1u;
-    G.umask = (1u << p.u) - 1u;
-    uint64_t st = p.seed;
-    const uint64_t x0 = splitmix_next(st), x1 = splitmix_next(st), x2 = splitmix_next(st);
-    const uint64_t A = (1ull << 31) + x0 % (atp::kPrime - (1ull << 31));
-    G.A = (uint32_t)A;
-    G.Ainv = (uint32_t)pow_mod_p(A, atp::kPrime - 2);
-    G.alpha = x1 | 1ull;
-    G.beta = x2;
-    G.blk_a = G.g / G.twok;
-    G.last_blk = G.twok - 1;
-    G.blk_magic = G.blk_a ? (((1ull << 32) + G.blk_a - 1) / G.blk_a) : 0;
-    G.maskW = G.W == 32 ? 0xFFFFFFFFull : ((1ull << G.W) - 1);
-    for (uint32_t j = 0; j < (uint32_t)atp::kMaxRows; j++) {
-        G.sh[j] = j < p.r ? (p.s * j) % G.W : 0;
-        if (j < p.r) {
-            uint64_t t = (uint64_t)G.ncol_mask << G.sh[j];
-            G.win[j] = (uint32_t)((t | (t >> G.W)) & G.maskW);
-        }
-    }
-    // Section 4.2: super ATVs hold at least g - g*exp(-theta/g) active ATs
-    const double thr = (double)G.g - (double)G.g * std::exp(-p.theta / (double)G.g);
-    double Tc = std::ceil(thr);
-    if (Tc < 0) Tc = 0;
-    G.T = (uint32_t)Tc;
-    G.theta = p.theta;
-    return G;
-}
 
 int dev_err(hipError_t e) { return e == hipSuccess ? AT_OK : (e == hipErrorOutOfMemory ? AT_E_NOMEM : AT_E_DEVICE); }
 
@@ -279,6 +239,53 @@ uint64_t tuple_count(const at_ctx* h, const std::vector<uint32_t>& cnt) {
 
 }  // namespace
 
+namespace atp {
+
+// Hash constants and block layout of a handle, from its parameters (Section 3,
+// Section 4.1); at_create and the streaming server both use it.
+Geometry derive_geometry(const at_params& p) {
+    Geometry G{};
+    G.k = p.k;
+    G.twok = 2 * p.k;
+    G.atb = G.twok < 256 ? 1 : 2;  // AT bytes: 2k + 1 values per AT
+    G.r = p.r;
+    G.c = p.c;
+    G.s = p.s;
+    G.u = p.u;
+    G.W = 32 - p.u;
+    G.log2g = p.log2g;
+    G.g = 1u << p.log2g;
+    G.ncol_mask = (1u << p.c) - 1u;
+    G.umask = (1u << p.u) - 1u;
+    uint64_t st = p.seed;
+    const uint64_t x0 = splitmix_next(st), x1 = splitmix_next(st), x2 = splitmix_next(st);
+    const uint64_t A = (1ull << 31) + x0 % (atp::kPrime - (1ull << 31));
+    G.A = (uint32_t)A;
+    G.Ainv = (uint32_t)pow_mod_p(A, atp::kPrime - 2);
+    G.alpha = x1 | 1ull;
+    G.beta = x2;
+    G.blk_a = G.g / G.twok;
+    G.last_blk = G.twok - 1;
+    G.blk_magic = G.blk_a ? (((1ull << 32) + G.blk_a - 1) / G.blk_a) : 0;
+    G.maskW = G.W == 32 ? 0xFFFFFFFFull : ((1ull << G.W) - 1);
+    for (uint32_t j = 0; j < (uint32_t)atp::kMaxRows; j++) {
+        G.sh[j] = j < p.r ? (p.s * j) % G.W : 0;
+        if (j < p.r) {
+            uint64_t t = (uint64_t)G.ncol_mask << G.sh[j];
+            G.win[j] = (uint32_t)((t | (t >> G.W)) & G.maskW);
+        }
+    }
+    // Section 4.2: super ATVs hold at least g - g*exp(-theta/g) active ATs
+    const double thr = (double)G.g - (double)G.g * std::exp(-p.theta / (double)G.g);
+    double Tc = std::ceil(thr);
+    if (Tc < 0) Tc = 0;
+    G.T = (uint32_t)Tc;
+    G.theta = p.theta;
+    return G;
+}
+
+}  // namespace atp
+
 extern "C" {
 
 const char* at_strerror(int rc) {
@@ -304,7 +311,7 @@ int at_create(const at_params* p, void* hip_stream, at_ctx** out) {
     if (!h) return AT_E_NOMEM;
     h->p = *p;
     if (h->p.tuple_budget == 0) h->p.tuple_budget = 1ull << 32;
-    h->G = derive(h->p);
+    h->G = atp::derive_geometry(h->p);
     h->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;

@@ -45,65 +45,6 @@ double now_ms() {
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-uint64_t splitmix(uint64_t& s) {
-    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-uint64_t pow_mod_p(uint64_t b, uint64_t e) {
-    const uint64_t p = atp::kPrime;
-    uint64_t r = 1;
-    b %= p;
-    while (e) {
-        if (e & 1) r = (r * b) % p;
-        b = (b * b) % p;
-        e >>= 1;
-    }
-    return r;
-}
-
-// The same derivation as a single handle's (at_create): constants from the seed.
-Geometry derive_geometry(const at_params& p) {
-    Geometry G{};
-    G.k = p.k;
-    G.twok = 2 * p.k;
-    G.atb = G.twok < 256 ? 1 : 2;  // AT bytes: 2k + 1 values per AT
-    G.r = p.r;
-    G.c = p.c;
-    G.s = p.s;
-    G.u = p.u;
-    G.W = 32 - p.u;
-    G.log2g = p.log2g;
-    G.g = 1u << p.log2g;
-    G.ncol_mask = (1u << p.c) - 1u;
-    G.umask = (1u << p.u) - 1u;
-    uint64_t st = p.seed;
-    const uint64_t x0 = splitmix(st), x1 = splitmix(st), x2 = splitmix(st);
-    const uint64_t A = (1ull << 31) + x0 % (atp::kPrime - (1ull << 31));
-    G.A = (uint32_t)A;
-    G.Ainv = (uint32_t)pow_mod_p(A, atp::kPrime - 2);
-    G.alpha = x1 | 1ull;
-    G.beta = x2;
-    G.blk_a = G.g / G.twok;
-    G.last_blk = G.twok - 1;
-    G.blk_magic = G.blk_a ? (((1ull << 32) + G.blk_a - 1) / G.blk_a) : 0;
-    G.maskW = G.W == 32 ? 0xFFFFFFFFull : ((1ull << G.W) - 1);
-    for (uint32_t j = 0; j < (uint32_t)atp::kMaxRows; j++) {
-        G.sh[j] = j < p.r ? (p.s * j) % G.W : 0;
-        if (j < p.r) {
-            uint64_t t = (uint64_t)G.ncol_mask << G.sh[j];
-            G.win[j] = (uint32_t)((t | (t >> G.W)) & G.maskW);
-        }
-    }
-    const double thr = (double)G.g - (double)G.g * std::exp(-p.theta / (double)G.g);
-    double Tc = std::ceil(thr);
-    G.T = (uint32_t)(Tc < 0 ? 0 : Tc);
-    G.theta = p.theta;
-    return G;
-}
-
 template <typename T>
 int dalloc(T** p, uint64_t count) {
     *p = nullptr;
@@ -412,7 +353,7 @@ int at_serve_create(const at_serve_config* cfg, at_serve** out) {
     at_serve* S = new (std::nothrow) at_serve();
     if (!S) return AT_E_NOMEM;
     S->cfg = *cfg;
-    S->shape = derive_geometry(shp);
+    S->shape = atp::derive_geometry(shp);
     S->n_atv = ((uint64_t)(S->shape.umask + 1) * S->shape.r) << S->shape.c;
     S->per_link_bytes = link_bytes(S);
     S->slot_used.assign(cfg->max_links, -1);
@@ -487,7 +428,7 @@ int at_serve_open_link(at_serve* S, uint32_t k, uint64_t seed, uint64_t tuple_bu
     L->p.theta = S->cfg.theta;
     L->p.seed = seed;
     L->p.tuple_budget = tuple_budget;
-    L->G = derive_geometry(L->p);
+    L->G = atp::derive_geometry(L->p);
     L->bytes = S->per_link_bytes;
     S->links.push_back(L);
     *link_id = L->id;
