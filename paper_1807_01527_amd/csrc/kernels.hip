@@ -412,10 +412,11 @@ __device__ __forceinline__ void pair_targets(uint32_t a, uint32_t b, const Geome
     }
 }
 
-// Pass 1: block b's per-tile store counts -> cnt[b * n_tiles + tile].
+// Pass 1: block b's per-tile store counts -> cnt[b * n_tiles + tile].  A tile
+// holds whole ATVs (g <= the ATs of a tile), so a store's tile is its ATV's:
+// it depends on aip alone and this pass never reads bip.
 template <int R>
-__global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restrict__ aip,
-                                                       const uint32_t* __restrict__ bip, uint64_t n, Geometry G,
+__global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restrict__ aip, uint64_t n, Geometry G,
                                                        uint32_t ts, uint32_t n_tiles, uint32_t* __restrict__ cnt) {
     __shared__ uint32_t hist[kMaxTiles];
     for (uint32_t t = threadIdx.x; t < n_tiles; t += kBlock) hist[t] = 0;
@@ -423,22 +424,28 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restric
     constexpr uint32_t P = kTileRecs / R;
     const uint64_t lo = (uint64_t)blockIdx.x * P;
     const uint64_t hi = lo + P < n ? lo + P : n;
+    const uint32_t atv_shift = ts - G.log2g;  // ATVs per tile = 2^atv_shift
     // four pairs per thread per round, loads issued before use
     for (uint64_t q0 = lo + threadIdx.x; q0 < hi; q0 += 4 * kBlock) {
-        uint32_t a4[4], b4[4];
+        uint32_t a4[4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             const uint64_t q = q0 + (uint64_t)e * kBlock;
             a4[e] = q < hi ? aip[q] : 0u;
-            b4[e] = q < hi ? bip[q] : 0u;
         }
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             if (q0 + (uint64_t)e * kBlock >= hi) break;
-            uint64_t idx[R];
-            pair_targets<R>(a4[e], b4[e], G, idx);
+            const uint32_t f = mangle(a4[e], G.A);
+            const uint32_t z = f & G.umask;
+            const uint64_t L = (uint64_t)(f >> G.u);
+            const uint64_t LL = L | (L << G.W);
+            const uint64_t zr = (uint64_t)z * R;
 #pragma unroll
-            for (int j = 0; j < R; j++) atomicAdd(&hist[(uint32_t)(idx[j] >> ts)], 1u);
+            for (int j = 0; j < R; j++) {
+                const uint64_t atv = ((zr + j) << G.c) + column(LL, G.sh[j], G.ncol_mask);
+                atomicAdd(&hist[(uint32_t)(atv >> atv_shift)], 1u);
+            }
         }
     }
     __syncthreads();
@@ -1821,8 +1828,7 @@ hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_
     const dim3 cols((z.n_tiles + kBlock - 1) / kBlock, z.nchunk);
     hipError_t e = with_rows<uint8_t>(G.r, [&](auto rc, auto) {
         constexpr int RR = decltype(rc)::value;
-        hipLaunchKernelGGL((k_tile_count<RR>), dim3(z.nb), dim3(kBlock), 0, st, aip, bip, n, G, ts, z.n_tiles,
-                           B.cnt);
+        hipLaunchKernelGGL((k_tile_count<RR>), dim3(z.nb), dim3(kBlock), 0, st, aip, n, G, ts, z.n_tiles, B.cnt);
     });
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_chunksum, cols, dim3(kBlock), 0, st, B.cnt, z.nb, z.n_tiles, B.csum);
