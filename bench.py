@@ -396,13 +396,19 @@ def main():
     rel_l = np.abs(e_learn - truth_n) / truth_n if e_learn is not None else None
     per_launch = args.pairs
     avg_ingest_s = float(ingest_ms.mean()) / 1e3
-    alg_bytes = (8 + LINK["r"]) * per_launch
-    achieved = alg_bytes / avg_ingest_s / 1e9
     # at_ingest_slice's automatic choice (the rule stated with at_set_scan_mode)
     tiles = pool.pool_bytes % 65536 == 0 and pool.pool_bytes // 65536 <= 4096
-    if tiles and per_launch * LINK["r"] * 12 >= pool.pool_bytes:
+    tiled = tiles and per_launch * LINK["r"] * 12 >= pool.pool_bytes
+    # algorithmic bytes of one call: 8 B read + r B of AT state written per
+    # pair; a tiled call that opens the slice (the step's only call) also does
+    # the window count of the close: one read of the pool, 4 B per ATV written
+    alg_pairs = (8 + LINK["r"]) * per_launch
+    alg_count = pool.pool_bytes + 4 * pool.n_atv if tiled and per_launch <= (8 << 20) else 0
+    achieved = (alg_pairs + alg_count) / avg_ingest_s / 1e9
+    if tiled:
         scan_kernels = ("k_tile_count + k_tile_chunksum + k_tile_scan + k_tile_rowpre + k_tile_scatter + k_tile_apply "
-                        "(tiled scan: AT stores grouped per 64 KiB tile, applied in LDS)")
+                        "(tiled scan: AT stores grouped per 64 KiB tile, applied in LDS; the opening preserve and the "
+                        "close's window count run in k_tile_apply)")
     elif LINK["u"] >= 3 and pool.pool_bytes >= (32 << 20) and per_launch >= 65536:
         scan_kernels = "k_bin_pairs + k_scan_bins (binned scan: XCD-local frame bins, then the r byte stores)"
     else:
@@ -435,6 +441,7 @@ def main():
                      "traffic": measured_traffic(), "traffic_of": "the scan kernels of one call, rocprofv3 "
                                                                   "FETCH_SIZE x2 + WRITE_SIZE x1 (copy-calibrated)",
                      "bytes_per_pair": 8 + LINK["r"],
+                     "algorithmic_bytes_per_launch": {"pairs": alg_pairs, "window_count": alg_count},
                      "avg_launch_ms": float(ingest_ms.mean()), "pairs_per_launch": per_launch},
     }
     # the two scans of at_ingest_slice on the same slices (one pass each)

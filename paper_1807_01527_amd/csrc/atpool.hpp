@@ -86,9 +86,12 @@ TileSizes tiled_sizes(uint64_t n, uint64_t pool_bytes, const Geometry& G);
 size_t tiled_lds_bytes(uint32_t n_tiles);  // dynamic LDS of the scatter pass
 // preserve: the call opens the slice; Alg 2 on the due blocks runs inside the
 // tile pass (every tile is visited) instead of a separate launch_preserve.
+// w_out (needs preserve): the tile pass also writes every ATV's kq_w-weight
+// after the call's stores, so a close with that window that follows this one
+// call needs no pass over the pool.
 hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
                                uint64_t pool_bytes, const Geometry& G, uint32_t c0, const TileBufs& B, bool preserve,
-                               hipStream_t st);
+                               uint32_t* w_out, uint32_t kq_w, hipStream_t st);
 // Windows summarised by one close: weights for window j land in
 // w[j * n_atv ...], AAT in aat[j * groups ...], super lists likewise.
 constexpr uint32_t kMaxWindows = 8;

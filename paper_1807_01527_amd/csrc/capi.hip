@@ -47,6 +47,8 @@ struct at_ctx {
     uint8_t* pin = nullptr;       // pinned host staging of query inputs and outputs (grown on demand)
     uint64_t pin_cap = 0;
     bool tiled_ok = false;        // the device has the LDS the tiled scan needs
+    bool wfused = false;          // window-0 weights of the open slice already written by its one tiled call
+    uint32_t wfused_kq = 0;
     int scan_mode = 0;            // 0 auto, 1 direct, 2 binned, 3 tiled
     // grow-on-demand device scratch
     uint32_t* cand = nullptr;
@@ -377,6 +379,8 @@ int scan_path(const at_ctx* h, uint64_t n) {
 int ingest_tiled_buffers(at_ctx* h, uint64_t n);
 
 int ingest_tiled(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, uint64_t n, bool preserve) {
+    // a single batch that opens the slice also writes the full window's weights
+    const bool weights = preserve && n <= kBinBatch;
     int rc = ingest_tiled_buffers(h, n);
     if (rc) {
         // the slice is open already: its preserve must not be lost
@@ -387,9 +391,12 @@ int ingest_tiled(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, ui
     for (uint64_t off = 0; off < n; off += kBinBatch) {
         const uint64_t m = std::min<uint64_t>(kBinBatch, n - off);
         if (atp::launch_ingest_tiled(h->pool, aip_dev + off, bip_dev + off, m, h->pool_bytes, h->G, h->c0, h->tb,
-                                     preserve && off == 0, h->stream) != hipSuccess)
+                                     preserve && off == 0, weights ? h->w_all : nullptr, h->p.k,
+                                     h->stream) != hipSuccess)
             return AT_E_DEVICE;
     }
+    h->wfused = weights;
+    h->wfused_kq = h->p.k;
     return AT_OK;
 }
 
@@ -434,6 +441,7 @@ int at_ingest_slice(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev,
     int rc = open_slice(h, fuse);
     if (rc) return rc;
     if (n == 0) return AT_OK;
+    h->wfused = false;  // any stores after the fused count make it stale
     if (path == kTiled) return ingest_tiled(h, aip_dev, bip_dev, n, fuse);
     if (path == kDirect)
         return atp::launch_ingest(h->pool, aip_dev, bip_dev, n, h->G, h->c0, h->stream) == hipSuccess ? AT_OK
@@ -483,7 +491,11 @@ int at_close_slice_multi(at_ctx* h, const uint32_t* kprimes, uint32_t n) {
     }
     int rc = open_slice(h);
     if (rc) return rc;
-    hipError_t e = atp::launch_close(h->pool, h->w_all, h->n_atv, h->G, h->c0, Wn, h->stream);
+    // the slice's one tiled call already counted window k: no pass over the pool
+    const bool counted = n == 1 && h->wfused && kprimes[0] == h->wfused_kq;
+    h->wfused = false;
+    hipError_t e = counted ? hipSuccess
+                           : atp::launch_close(h->pool, h->w_all, h->n_atv, h->G, h->c0, Wn, h->stream);
     if (e == hipSuccess)
         e = atp::launch_summarize(h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->G, h->n_atv, n, h->stream);
     if (e != hipSuccess) return AT_E_DEVICE;

@@ -632,11 +632,16 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
 // call opens the slice (preserve != 0) Alg 2 first runs here on the two due
 // blocks of every ATV of the tile (the AT ranges of S), before any record:
 // the same order as a separate opening pass, without its extra pool traffic.
+// With w_out the pass also ends the slice's window count: every tile is
+// visited (the call opened the slice) and, once its records are in, the k'-
+// weight of each of its ATVs (Alg 1 with window kq_w) goes to w_out, which
+// is what the close would compute if no other call adds to the slice.
 template <typename T>
 __global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict__ pool,
                                                             const uint16_t* __restrict__ rec,
                                                             const uint32_t* __restrict__ base, Geometry G,
-                                                            uint32_t c0, uint32_t preserve, PreserveSpans S) {
+                                                            uint32_t c0, uint32_t preserve, PreserveSpans S,
+                                                            uint32_t* __restrict__ w_out, uint32_t kq_w) {
     extern __shared__ __align__(16) uint8_t smem_apply[];
     const uint32_t t = blockIdx.x;
     const uint32_t lo = base[t], hi = base[t + 1];
@@ -701,6 +706,58 @@ __global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict_
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kTileBytes / 16; i += kApplyBlock) src[i] = lds[i];
+    if (w_out) {
+        constexpr uint32_t CA = kPerChunk<T>, N = kPerWord<T>;
+        __shared__ uint32_t wl[kTileBytes / 16 / 64];  // per ATV, when an ATV spans more than 64 chunks
+        const uint32_t cpa = G.g / CA;                // chunks per ATV (a power of two)
+        const uint32_t seg = cpa < 64 ? cpa : 64;
+        const uint32_t atvs = (kTileBytes / sizeof(T)) >> G.log2g;
+        const uint64_t atv0 = (uint64_t)t * atvs;
+        const uint32_t lane = threadIdx.x & 63u;
+        if (cpa > 64) {
+            for (uint32_t v = threadIdx.x; v < atvs; v += kApplyBlock) wl[v] = 0;
+            __syncthreads();
+        }
+        const bool packed = G.twok <= 32768u;
+        const uint32_t twok2 = both_halves(G.twok), c_at = both_halves(0x8000u - G.twok);
+        const uint32_t c_kq = both_halves(0x8000u - kq_w);
+        for (uint32_t c = threadIdx.x; c < kTileBytes / 16; c += kApplyBlock) {
+            const uint32_t pos = c * CA;                // AT index inside the tile
+            const uint32_t i0 = pos & (G.g - 1u);       // its position in the ATV
+            uint32_t acw[4];
+#pragma unroll
+            for (uint32_t q = 0; q < 4; q++) {
+                uint32_t wv = 0;
+#pragma unroll
+                for (uint32_t b = 0; b < N; b++) wv |= act_of(i0 + q * N + b, c0, G) << (8 * sizeof(T) * b);
+                acw[q] = wv;
+            }
+            const uint4 ac = make_uint4(acw[0], acw[1], acw[2], acw[3]);
+            const uint4 d = lds[c];
+            uint32_t act_n;
+            if (packed) {
+                constexpr uint32_t NH = 8 / sizeof(T);
+                uint32_t ha[NH], hc[NH], ni = 0;
+                chunk_halves<T>(d, ha);
+                chunk_halves<T>(ac, hc);
+#pragma unroll
+                for (uint32_t q = 0; q < NH; q++) ni += inactive2(alg1_halves(ha[q], hc[q], twok2, c_at), c_kq);
+                act_n = CA - ni;
+            } else {
+                act_n = __popc(active_mask_chunk<T>(d, ac, G.twok, kq_w));
+            }
+            for (uint32_t o = seg / 2; o > 0; o >>= 1) act_n += __shfl_xor(act_n, o, 64);
+            if (lane % seg == 0) {
+                const uint32_t v = pos >> G.log2g;
+                if (cpa <= 64) w_out[atv0 + v] = act_n;
+                else atomicAdd(&wl[v], act_n);
+            }
+        }
+        if (cpa > 64) {
+            __syncthreads();
+            for (uint32_t v = threadIdx.x; v < atvs; v += kApplyBlock) w_out[atv0 + v] = wl[v];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- a4: close
@@ -1819,7 +1876,8 @@ size_t tiled_lds_bytes(uint32_t n_tiles) {
 
 hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
                                uint64_t pool_bytes, const Geometry& G, uint32_t c0, const TileBufs& B, bool preserve,
-                               hipStream_t st) {
+                               uint32_t* w_out, uint32_t kq_w, hipStream_t st) {
+    if (w_out && !preserve) return hipErrorInvalidValue;  // the weights need every tile visited
     if (n == 0) return hipSuccess;
     if (!tiled_fits(pool_bytes)) return hipErrorInvalidValue;
     const TileSizes z = tiled_sizes(n, pool_bytes, G);
@@ -1847,7 +1905,7 @@ hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_
         using T = decltype(t);
         const PreserveSpans S = preserve ? preserve_spans(G, c0) : PreserveSpans{};
         hipLaunchKernelGGL(k_tile_apply<T>, dim3(z.n_tiles), dim3(kApplyBlock), kTileBytes, st, pool, B.rec, B.base,
-                           G, c0, (uint32_t)preserve, S);
+                           G, c0, (uint32_t)preserve, S, w_out, kq_w);
     });
 }
 

@@ -267,3 +267,37 @@ def test_tiled_mode_needs_whole_tiles(cuda):
         g.set_scan_mode(3)
     assert e.value.rc == binding.AT_E_INVAL
     g.destroy()
+
+
+@pytest.mark.parametrize("geom", [
+    dict(k=3, r=4, c=8, s=8, u=1, log2g=6),       # 1024 ATVs per 64 KiB tile, 4 chunks per ATV
+    dict(k=5, r=3, c=10, s=10, u=3, log2g=12),    # 256 chunks per ATV
+    dict(k=150, r=4, c=8, s=8, u=1, log2g=9),     # 16-bit ATs
+])
+def test_tiled_single_call_slices(cuda, oracle_lib, geom):
+    """One tiled call per slice: the call opens the slice, runs the opening
+    preserve in its tile pass and writes the full window's weights there, so
+    a close with k' = k reads no pool.  Closes alternate k' = k and other
+    windows (which take the close kernel), and one slice gets a second call
+    (which makes the fused weights stale)."""
+    k = geom["k"]
+    tr = _tiny(seed=31 + k, n_slices=12, pairs_per_slice=20001, hosts=1 << 10, planted=3, lo=300, hi=3000)
+    g, o = make_pair(dict(**geom, theta=128.0, seed=6, tuple_budget=1 << 22), oracle_lib)
+    g.set_scan_mode(3)
+    for t in range(tr.n_slices):
+        a, b = tr.aip[t], tr.bip[t]
+        if t == 5:
+            half = a.size // 2
+            g.ingest(to_dev(a[:half]), to_dev(b[:half]))
+            g.ingest(to_dev(a[half:]), to_dev(b[half:]))
+        else:
+            g.ingest(to_dev(a), to_dev(b))
+        o.ingest(a, b)
+        kp = k if t % 3 != 2 else max(1, k // 2)
+        g.close(kp)
+        o.close(kp)
+        where = f"slice {t} k'={kp}"
+        compare_state(g, o, where)
+        compare_summary(g, o, where)
+        compare_estimates(g, o, np.unique(np.concatenate([tr.planted_hosts, a[:64]])), where)
+    g.destroy()
