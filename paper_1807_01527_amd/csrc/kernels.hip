@@ -550,6 +550,7 @@ template <int R>
 __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* __restrict__ aip,
                                                                 const uint32_t* __restrict__ bip, uint64_t n,
                                                                 Geometry G, uint32_t ts, uint32_t n_tiles,
+                                                                const uint32_t* __restrict__ cnt,
                                                                 const uint32_t* __restrict__ pre,
                                                                 uint16_t* __restrict__ rec) {
     extern __shared__ __align__(16) uint8_t smem_tile[];
@@ -558,8 +559,6 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
     uint32_t* cur = reinterpret_cast<uint32_t*>(st_tile + kTileRecs);  // counts, then slot cursors
     uint32_t* gbase = cur + ((n_tiles + 3u) & ~3u);                       // run start in rec minus LDS start
     __shared__ uint32_t scratch[kScatterBlock / 64 + 1];
-    for (uint32_t t = threadIdx.x; t < n_tiles; t += kScatterBlock) cur[t] = 0;
-    __syncthreads();
     constexpr uint32_t P = kTileRecs / R;
     constexpr uint32_t PPT = (P + kScatterBlock - 1) / kScatterBlock;  // pairs per thread
     const uint64_t lo = (uint64_t)blockIdx.x * P;
@@ -583,19 +582,18 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
         for (int j = 0; j < R; j++) {
             // tile in the high half, in-tile index in the low half (ts <= 16)
             tgt[e][j] = ok ? (uint32_t)((idx[j] >> ts) << 16) | ((uint32_t)idx[j] & lmask) : ~0u;
-            if (ok) atomicAdd(&cur[tgt[e][j] >> 16], 1u);
         }
     }
-    __syncthreads();
-    // LDS run starts: exclusive scan of the counts, kMaxTiles / kScatterBlock
-    // consecutive tiles per thread
+    // LDS run starts: exclusive scan of the block's counts (its row of the
+    // count table), kMaxTiles / kScatterBlock consecutive tiles per thread
     constexpr uint32_t TPT = kMaxTiles / kScatterBlock;
     const uint32_t* prow = pre + (uint64_t)blockIdx.x * n_tiles;
+    const uint32_t* crow = cnt + (uint64_t)blockIdx.x * n_tiles;
     uint32_t c[TPT], sum = 0;
 #pragma unroll
     for (uint32_t e = 0; e < TPT; e++) {
         const uint32_t t = threadIdx.x * TPT + e;
-        c[e] = t < n_tiles ? cur[t] : 0u;
+        c[e] = t < n_tiles ? crow[t] : 0u;
         sum += c[e];
     }
     uint32_t total;
@@ -1898,7 +1896,7 @@ hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)tiled_lds_bytes(kMaxTiles));
         hipLaunchKernelGGL((k_tile_scatter<RR>), dim3(z.nb), dim3(kScatterBlock), tiled_lds_bytes(z.n_tiles), st, aip,
                            bip, n,
-                           G, ts, z.n_tiles, B.pre, B.rec);
+                           G, ts, z.n_tiles, B.cnt, B.pre, B.rec);
     });
     if (e != hipSuccess) return e;
     return with_at(G, [&](auto t) {
