@@ -554,9 +554,8 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
                                                                 const uint32_t* __restrict__ pre,
                                                                 uint16_t* __restrict__ rec) {
     extern __shared__ __align__(16) uint8_t smem_tile[];
-    uint16_t* st_local = reinterpret_cast<uint16_t*>(smem_tile);
-    uint16_t* st_tile = st_local + kTileRecs;
-    uint32_t* cur = reinterpret_cast<uint32_t*>(st_tile + kTileRecs);  // counts, then slot cursors
+    uint32_t* staged = reinterpret_cast<uint32_t*>(smem_tile);  // tile << 16 | in-tile index, grouped by tile
+    uint32_t* cur = staged + kTileRecs;                             // slot cursors
     uint32_t* gbase = cur + ((n_tiles + 3u) & ~3u);                       // run start in rec minus LDS start
     __shared__ uint32_t scratch[kScatterBlock / 64 + 1];
     constexpr uint32_t P = kTileRecs / R;
@@ -614,15 +613,13 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
         for (int j = 0; j < R; j++) {
             const uint32_t v = tgt[e][j];
             if (v == ~0u) continue;
-            const uint32_t slot = atomicAdd(&cur[v >> 16], 1u);
-            st_local[slot] = (uint16_t)(v & 0xFFFFu);
-            st_tile[slot] = (uint16_t)(v >> 16);
+            staged[atomicAdd(&cur[v >> 16], 1u)] = v;
         }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < total; i += kScatterBlock) {
-        const uint32_t t = st_tile[i];
-        rec[gbase[t] + i] = st_local[i];
+        const uint32_t v = staged[i];
+        rec[gbase[v >> 16] + i] = (uint16_t)(v & 0xFFFFu);
     }
 }
 
@@ -1869,7 +1866,7 @@ TileSizes tiled_sizes(uint64_t n, uint64_t pool_bytes, const Geometry& G) {
 }
 
 size_t tiled_lds_bytes(uint32_t n_tiles) {
-    return 2 * kTileRecs * sizeof(uint16_t) + 2 * (((size_t)n_tiles + 3) & ~(size_t)3) * sizeof(uint32_t);
+    return kTileRecs * sizeof(uint32_t) + 2 * (((size_t)n_tiles + 3) & ~(size_t)3) * sizeof(uint32_t);
 }
 
 hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
