@@ -79,6 +79,7 @@ struct TileBufs {
     uint32_t* pre;   // table_cap: per-(block, tile) run starts
     uint32_t* csum;  // chunk_cap * 4096: per-chunk column sums, then their prefixes
     uint32_t* base;  // 4097 region starts
+    uint8_t* act;    // g ATs: the slice's block timestamp per position (for the window count)
     uint64_t rec_cap, table_cap, chunk_cap;
 };
 bool tiled_fits(uint64_t pool_bytes);

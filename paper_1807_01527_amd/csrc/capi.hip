@@ -121,7 +121,7 @@ int dev_alloc(T** p, uint64_t count) {
 void free_all(at_ctx* h) {
     void* bufs[] = {h->pool, h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->counter, h->prefix, h->cand,
                     h->q_aip, h->q_est, h->q_flags, h->q_nat, h->q_feat, h->q_y, h->q_plain, h->bins, h->bin_fill,
-                    h->tb.rec, h->tb.cnt, h->tb.pre, h->tb.csum, h->tb.base};
+                    h->tb.rec, h->tb.cnt, h->tb.pre, h->tb.csum, h->tb.base, h->tb.act};
     if (h->pin) (void)hipHostFree(h->pin);
     h->pin = nullptr;
     h->pin_cap = 0;
@@ -426,6 +426,7 @@ int ingest_tiled_buffers(at_ctx* h, uint64_t n) {
         h->tb.chunk_cap = z.nchunk;
     }
     if (!h->tb.base && (rc = dev_alloc(&h->tb.base, 4097))) return rc;
+    if (!h->tb.act && (rc = dev_alloc(&h->tb.act, (uint64_t)h->G.g * h->G.atb))) return rc;
     return AT_OK;
 }
 

@@ -498,9 +498,14 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 // One block of kScatterBlock threads: per tile, the exclusive prefix of its
 // chunk sums (in place) and its total; then the exclusive prefix of the tile
 // totals -> base[0..n_tiles].  Thread x takes tiles x, x + kScatterBlock, ...
+template <typename T>
 __global__ __launch_bounds__(kScatterBlock) void k_tile_scan(uint32_t* __restrict__ csum, uint32_t nchunk,
-                                                             uint32_t n_tiles, uint32_t* __restrict__ base) {
+                                                             uint32_t n_tiles, uint32_t* __restrict__ base,
+                                                             T* __restrict__ act_table, Geometry G, uint32_t c0) {
     __shared__ uint32_t scratch[kScatterBlock / 64 + 1];
+    // the slice's block timestamp of every AT position, read by the tile pass
+    if (act_table)
+        for (uint32_t i = threadIdx.x; i < G.g; i += kScatterBlock) act_table[i] = (T)act_of(i, c0, G);
     uint32_t carry = 0;
     for (uint32_t t0 = 0; t0 < n_tiles; t0 += kScatterBlock) {
         const uint32_t t = t0 + threadIdx.x;
@@ -636,7 +641,8 @@ __global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict_
                                                             const uint16_t* __restrict__ rec,
                                                             const uint32_t* __restrict__ base, Geometry G,
                                                             uint32_t c0, uint32_t preserve, PreserveSpans S,
-                                                            uint32_t* __restrict__ w_out, uint32_t kq_w) {
+                                                            uint32_t* __restrict__ w_out, uint32_t kq_w,
+                                                            const T* __restrict__ act_table) {
     extern __shared__ __align__(16) uint8_t smem_apply[];
     const uint32_t t = blockIdx.x;
     const uint32_t lo = base[t], hi = base[t + 1];
@@ -719,15 +725,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict_
         for (uint32_t c = threadIdx.x; c < kTileBytes / 16; c += kApplyBlock) {
             const uint32_t pos = c * CA;                // AT index inside the tile
             const uint32_t i0 = pos & (G.g - 1u);       // its position in the ATV
-            uint32_t acw[4];
-#pragma unroll
-            for (uint32_t q = 0; q < 4; q++) {
-                uint32_t wv = 0;
-#pragma unroll
-                for (uint32_t b = 0; b < N; b++) wv |= act_of(i0 + q * N + b, c0, G) << (8 * sizeof(T) * b);
-                acw[q] = wv;
-            }
-            const uint4 ac = make_uint4(acw[0], acw[1], acw[2], acw[3]);
+            const uint4 ac = *reinterpret_cast<const uint4*>(act_table + i0);
             const uint4 d = lds[c];
             uint32_t act_n;
             if (packed) {
@@ -1885,7 +1883,12 @@ hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_
     });
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_chunksum, cols, dim3(kBlock), 0, st, B.cnt, z.nb, z.n_tiles, B.csum);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScatterBlock), 0, st, B.csum, z.nchunk, z.n_tiles, B.base);
+    e = with_at(G, [&](auto t) {
+        using T = decltype(t);
+        hipLaunchKernelGGL(k_tile_scan<T>, dim3(1), dim3(kScatterBlock), 0, st, B.csum, z.nchunk, z.n_tiles, B.base,
+                           w_out ? reinterpret_cast<T*>(B.act) : nullptr, G, c0);
+    });
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_rowpre, cols, dim3(kBlock), 0, st, B.cnt, B.csum, B.base, z.nb, z.n_tiles, B.pre);
     e = with_rows<uint8_t>(G.r, [&](auto rc, auto) {
         constexpr int RR = decltype(rc)::value;
@@ -1900,7 +1903,7 @@ hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_
         using T = decltype(t);
         const PreserveSpans S = preserve ? preserve_spans(G, c0) : PreserveSpans{};
         hipLaunchKernelGGL(k_tile_apply<T>, dim3(z.n_tiles), dim3(kApplyBlock), kTileBytes, st, pool, B.rec, B.base,
-                           G, c0, (uint32_t)preserve, S, w_out, kq_w);
+                           G, c0, (uint32_t)preserve, S, w_out, kq_w, reinterpret_cast<const T*>(B.act));
     });
 }
 
