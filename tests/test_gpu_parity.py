@@ -301,3 +301,34 @@ def test_tiled_single_call_slices(cuda, oracle_lib, geom):
         compare_summary(g, o, where)
         compare_estimates(g, o, np.unique(np.concatenate([tr.planted_hosts, a[:64]])), where)
     g.destroy()
+
+
+def test_calls_larger_than_one_batch(cuda, oracle_lib):
+    """Calls of more than 8Mi pairs are cut into batches by every scan (the
+    tiled call then leaves the window count to the close).  Two slices of
+    9M pairs, each in one call, on a small pool: all three scans give the
+    oracle's pool and summaries."""
+    from paper_1807_01527_amd.binding import AtPool
+    geom = dict(k=4, r=4, c=8, s=8, u=3, log2g=6, theta=256.0, seed=12)
+    rng = np.random.default_rng(12)
+    n = 9_000_001
+    slices = []
+    for _ in range(2):
+        a = (rng.zipf(1.3, n) % (1 << 16)).astype(np.uint32) * np.uint32(2654435761)
+        b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        slices.append((a, b))
+    o = oracle_lib.Oracle(**geom)
+    for a, b in slices:
+        o.ingest(a, b)
+        o.close(4)
+    want_pool, want_w, want_aat = o.pool(), o.weights(), o.aat()
+    for mode in (1, 2, 3):
+        g = AtPool(**geom)
+        g.set_scan_mode(mode)
+        for a, b in slices:
+            g.ingest(to_dev(a), to_dev(b))
+            g.close(4)
+        assert np.array_equal(g.read_pool(), want_pool), f"mode {mode}: pool differs"
+        w, aat = g.read_summary()
+        assert np.array_equal(w, want_w) and np.array_equal(aat, want_aat), f"mode {mode}: summaries differ"
+        g.destroy()
