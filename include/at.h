@@ -108,7 +108,9 @@ int at_ingest_slice(at_ctx *h, const uint32_t *aip_dev, const uint32_t *bip_dev,
  * of the k' latest slices, 1 <= k' <= k: per-ATV k'-weights |ATV|^k' (Alg 1),
  * active ATs per (row, frame) AAT(k', row, frame) and the super ATVs, those
  * whose weight reaches ceil(g - g*exp(-theta/g)) (Section 4.2, 4.3).  Then
- * t advances.  Asynchronous on the handle's stream.
+ * t advances.  Asynchronous on the handle's stream; the per-(row, frame)
+ * super-ATV counts are also stored in pinned host memory, where at_restore
+ * and at_tuple_count wait for them instead of issuing a copy of their own.
  * Errors: AT_E_INVAL (k' outside [1, k]), AT_E_DEVICE.
  */
 int at_close_slice(at_ctx *h, uint32_t kprime);
@@ -277,6 +279,23 @@ int at_estimate_learned(at_ctx *h, at_mlp *m, const uint32_t *aip_host, uint64_t
 /* The same on device arrays, asynchronous (plain_dev may be NULL). */
 int at_estimate_learned_dev(at_ctx *h, at_mlp *m, const uint32_t *aip_dev, uint64_t n, double *est_dev,
                             uint8_t *flags_dev, double *plain_dev);
+/* at_estimate_learned in two halves, so that a caller can queue the next
+ * slice's at_ingest_slice (or any other call) while the estimates are being
+ * computed.  _begin copies the n host addresses into the handle's own
+ * pinned staging and queues the features, the network and the fallback,
+ * which read the addresses from that staging and store their results there
+ * (device-mapped host memory, no copy commands); it returns without
+ * waiting.  The estimates are those of the window summarised by the last
+ * close before _begin, whatever is queued afterwards.  _end waits for them
+ * and writes n entries to est_out, flags_out and, if not NULL, plain_out
+ * (the same values at_estimate_learned gives).  One _begin may be pending
+ * per handle: a second _begin, or at_estimate_learned, before its _end gives
+ * AT_E_STATE, as does _end without a pending _begin.  Other calls may run in
+ * between.  Errors of _begin as at_estimate_learned; _end: AT_E_STATE,
+ * AT_E_INVAL (null est_out or flags_out with n > 0; the pending estimate is
+ * kept), AT_E_DEVICE (the pending estimate is dropped). */
+int at_estimate_learned_begin(at_ctx *h, at_mlp *m, const uint32_t *aip_host, uint64_t n);
+int at_estimate_learned_end(at_ctx *h, double *est_out, uint8_t *flags_out, double *plain_out);
 
 /* ------------------------------------------------------ streaming server
  * Not in the paper: many links served by one device.  Every admitted link's

@@ -68,6 +68,8 @@ SIGNATURES = {
     "at_mlp_train_step": (C.c_int, [_vp, _vp, _vp, C.c_uint64, C.c_float, _f32p]),
     "at_estimate_learned": (C.c_int, [_vp, _vp, _u32p, C.c_uint64, _f64p, _u8p, _f64p]),
     "at_estimate_learned_dev": (C.c_int, [_vp, _vp, _vp, C.c_uint64, _vp, _vp, _vp]),
+    "at_estimate_learned_begin": (C.c_int, [_vp, _vp, _u32p, C.c_uint64]),
+    "at_estimate_learned_end": (C.c_int, [_vp, _f64p, _u8p, _f64p]),
 }
 MLP_NPARAM = 8385
 FEATURES = 64
@@ -188,6 +190,8 @@ class AtPool:
         _check(self.lib.at_pool_info(self.h, C.byref(pb), C.byref(na)), "at_pool_info")
         self.pool_bytes, self.n_atv = int(pb.value), int(na.value)
         self.at_bytes = self.pool_bytes // (self.n_atv * self.g)   # 1, or 2 for k > 127
+        self._pending_n = 0      # hosts of a pending estimate_learned_begin
+        self._restore_out = None  # restore's output arrays, reused while cap stays the same
 
     @staticmethod
     def try_create(**kw) -> int:
@@ -264,9 +268,10 @@ class AtPool:
 
     def restore(self, cap: int = 1 << 22):
         """Returns (rc, sips, est, flags, n_out); arrays are None unless rc == AT_OK."""
-        sip = np.zeros(max(cap, 1), np.uint32)
-        est = np.zeros(max(cap, 1), np.float64)
-        fl = np.zeros(max(cap, 1), np.uint8)
+        size = max(cap, 1)
+        if self._restore_out is None or self._restore_out[0].size != size:
+            self._restore_out = (np.empty(size, np.uint32), np.empty(size, np.float64), np.empty(size, np.uint8))
+        sip, est, fl = self._restore_out
         n = C.c_uint64()
         rc = self.lib.at_restore(self._handle(), _p(sip, C.c_uint32), _p(est, C.c_double), _p(fl, C.c_uint8),
                                  cap, C.byref(n))
@@ -316,6 +321,23 @@ class AtPool:
         _check(self.lib.at_estimate_learned(self._handle(), mlp._handle(), _p(aip, C.c_uint32), aip.size,
                                             _p(est, C.c_double), _p(fl, C.c_uint8), _p(plain, C.c_double)),
                "at_estimate_learned")
+        return est, fl, plain
+
+    def estimate_learned_begin(self, mlp: "Mlp", aip_host: np.ndarray):
+        """Queue the learned estimates of the hosts; estimate_learned_end collects them."""
+        aip = np.ascontiguousarray(aip_host, np.uint32)
+        _check(self.lib.at_estimate_learned_begin(self._handle(), mlp._handle(), _p(aip, C.c_uint32), aip.size),
+               "at_estimate_learned_begin")
+        self._pending_n = aip.size
+
+    def estimate_learned_end(self):
+        """Wait for the estimates queued by estimate_learned_begin: (learned, flags, plain)."""
+        n = self._pending_n
+        est = np.empty(n, np.float64)
+        fl = np.empty(n, np.uint8)
+        plain = np.empty(n, np.float64)
+        _check(self.lib.at_estimate_learned_end(self._handle(), _p(est, C.c_double), _p(fl, C.c_uint8),
+                                                _p(plain, C.c_double)), "at_estimate_learned_end")
         return est, fl, plain
 
     def estimate_learned_dev(self, mlp: "Mlp", aip_dev, est_dev, flags_dev, plain_dev=None):

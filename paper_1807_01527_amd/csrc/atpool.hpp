@@ -102,8 +102,10 @@ struct CloseWindows {
 };
 hipError_t launch_close(const uint8_t* pool, uint32_t* w, uint64_t n_atv, const Geometry& G, uint32_t c0,
                         const CloseWindows& Wn, hipStream_t st);
-hipError_t launch_summarize(const uint32_t* w, uint64_t* aat, uint32_t* sa, uint32_t* sa_cnt, const Geometry& G,
-                            uint64_t n_atv, uint32_t nwin, hipStream_t st);
+// cnt_host (may be null): device-mapped host memory that also receives the
+// super-list counts of every window, so the host reads them without a copy.
+hipError_t launch_summarize(const uint32_t* w, uint64_t* aat, uint32_t* sa, uint32_t* sa_cnt, uint32_t* cnt_host,
+                            const Geometry& G, uint64_t n_atv, uint32_t nwin, hipStream_t st);
 hipError_t launch_restore_join(const uint32_t* sa, const uint32_t* sa_cnt, const uint64_t* pair_prefix,
                                uint64_t n_items, const Geometry& G, uint32_t* cand, uint64_t cap,
                                unsigned long long* counter, hipStream_t st);

@@ -46,6 +46,16 @@ struct at_ctx {
     atp::TileBufs tb{};           // tiled-scan scratch (grown on demand)
     uint8_t* pin = nullptr;       // pinned host staging of query inputs and outputs (grown on demand)
     uint64_t pin_cap = 0;
+    uint32_t* pin_cnt = nullptr;  // pinned copy of the last close's super-ATV counts, every window,
+    uint32_t* pin_cnt_dev = nullptr;  // stored there by the summary kernel through this mapping
+    uint64_t pin_cnt_cap = 0;     // entries
+    hipEvent_t cnt_ready = nullptr;  // recorded after the summary kernel
+    uint8_t* pin_q = nullptr;     // pinned staging of the split learned estimate (its own, so other
+    uint64_t pin_q_cap = 0;       // queries between _begin and _end cannot overwrite it); the kernels
+    uint8_t* pin_q_dev = nullptr; // read the addresses from it and write the results into it directly
+    hipEvent_t q_done = nullptr;  // recorded after the split estimate's copy back
+    bool q_pending = false;
+    uint64_t q_pending_n = 0;
     bool tiled_ok = false;        // the device has the LDS the tiled scan needs
     bool wfused = false;          // window-0 weights of the open slice already written by its one tiled call
     uint32_t wfused_kq = 0;
@@ -125,6 +135,14 @@ void free_all(at_ctx* h) {
     if (h->pin) (void)hipHostFree(h->pin);
     h->pin = nullptr;
     h->pin_cap = 0;
+    if (h->pin_cnt) (void)hipHostFree(h->pin_cnt);
+    h->pin_cnt = h->pin_cnt_dev = nullptr;
+    if (h->pin_q) (void)hipHostFree(h->pin_q);
+    h->pin_q = h->pin_q_dev = nullptr;
+    if (h->cnt_ready) (void)hipEventDestroy(h->cnt_ready);
+    h->cnt_ready = nullptr;
+    if (h->q_done) (void)hipEventDestroy(h->q_done);
+    h->q_done = nullptr;
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -152,8 +170,26 @@ int open_slice(at_ctx* h, bool deferred = false) {
     return AT_OK;
 }
 
+uint64_t up64(uint64_t x) { return (x + 63) & ~63ull; }
+
+// Byte offsets of the results of a split learned estimate of n hosts in its
+// pinned staging, after the addresses.
+struct OutLayout {
+    uint64_t est, plain, flags, total;
+};
+OutLayout out_layout(uint64_t n) {
+    OutLayout O{};
+    O.est = 0;
+    O.plain = up64(8 * n);
+    O.flags = up64(O.plain + 8 * n);
+    O.total = up64(O.flags + n);
+    return O;
+}
+
 int ensure_query(at_ctx* h, uint64_t n) {
     if (n <= h->q_cap) return AT_OK;
+    // a pending split estimate still reads and writes these buffers
+    if (h->q_pending && hipEventSynchronize(h->q_done) != hipSuccess) return AT_E_DEVICE;
     uint64_t cap = std::max<uint64_t>(n, 1024);
     if (h->q_aip) (void)hipFree(h->q_aip);
     if (h->q_est) (void)hipFree(h->q_est);
@@ -205,28 +241,71 @@ int ensure_pinned(at_ctx* h, uint64_t bytes) {
 
 // Byte offsets of the staging regions for n hosts (64-byte aligned).
 struct PinLayout {
-    uint64_t aip, est, plain, nat, flags, total;
+    uint64_t aip, est, nat, flags, total;
 };
 PinLayout pin_layout(uint64_t n) {
-    auto up = [](uint64_t x) { return (x + 63) & ~63ull; };
     PinLayout L{};
     L.aip = 0;
-    L.est = up(L.aip + 4 * n);
-    L.plain = up(L.est + 8 * n);
-    L.nat = up(L.plain + 8 * n);
-    L.flags = up(L.nat + 4 * n);
-    L.total = up(L.flags + n);
+    L.est = up64(L.aip + 4 * n);
+    L.nat = up64(L.est + 8 * n);
+    L.flags = up64(L.nat + 4 * n);
+    L.total = up64(L.flags + n);
     return L;
 }
 
+// The selected window's super-ATV counts, as the last close's summary stored them in mapped host memory.
 int read_counts(at_ctx* h, std::vector<uint32_t>& cnt) {
     cnt.assign(h->ngroups, 0);
-    int rc = ensure_pinned(h, h->ngroups * sizeof(uint32_t));
-    if (rc) return rc;
-    hipError_t e = hipMemcpyAsync(h->pin, h->sa_cnt, h->ngroups * sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e == hipSuccess) std::memcpy(cnt.data(), h->pin, h->ngroups * sizeof(uint32_t));
-    return dev_err(e);
+    const hipError_t e = hipEventSynchronize(h->cnt_ready);
+    if (e != hipSuccess) return dev_err(e);
+    std::memcpy(cnt.data(), h->pin_cnt + (h->sa_cnt - h->sa_cnt_all), h->ngroups * sizeof(uint32_t));
+    return AT_OK;
+}
+
+// Room for the counts of n windows; waits for the last summary's stores into the old buffer first.
+int ensure_pin_cnt(at_ctx* h, uint64_t entries) {
+    if (entries <= h->pin_cnt_cap) return AT_OK;
+    if (h->pin_cnt) {
+        if (hipEventSynchronize(h->cnt_ready) != hipSuccess) return AT_E_DEVICE;
+        (void)hipHostFree(h->pin_cnt);
+    }
+    h->pin_cnt = h->pin_cnt_dev = nullptr;
+    h->pin_cnt_cap = 0;
+    if (hipHostMalloc((void**)&h->pin_cnt, entries * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        h->pin_cnt = nullptr;
+        (void)hipGetLastError();
+        return AT_E_NOMEM;
+    }
+    if (hipHostGetDevicePointer((void**)&h->pin_cnt_dev, h->pin_cnt, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(h->pin_cnt);
+        h->pin_cnt = h->pin_cnt_dev = nullptr;
+        return AT_E_DEVICE;
+    }
+    h->pin_cnt_cap = entries;
+    return AT_OK;
+}
+
+// Staging of the split learned estimate; only grown while none is pending.
+int ensure_pin_q(at_ctx* h, uint64_t bytes) {
+    if (bytes <= h->pin_q_cap) return AT_OK;
+    if (h->pin_q) (void)hipHostFree(h->pin_q);
+    h->pin_q = h->pin_q_dev = nullptr;
+    h->pin_q_cap = 0;
+    const uint64_t cap = std::max<uint64_t>((bytes + 65535) & ~65535ull, 1u << 16);
+    if (hipHostMalloc((void**)&h->pin_q, cap, hipHostMallocDefault) != hipSuccess) {
+        h->pin_q = nullptr;
+        (void)hipGetLastError();
+        return AT_E_NOMEM;
+    }
+    if (hipHostGetDevicePointer((void**)&h->pin_q_dev, h->pin_q, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(h->pin_q);
+        h->pin_q = h->pin_q_dev = nullptr;
+        return AT_E_DEVICE;
+    }
+    h->pin_q_cap = cap;
+    return AT_OK;
 }
 
 uint64_t tuple_count(const at_ctx* h, const std::vector<uint32_t>& cnt) {
@@ -328,6 +407,18 @@ int at_create(const at_params* p, void* hip_stream, at_ctx** out) {
         (rc = dev_alloc(&h->aat_all, W * h->ngroups)) || (rc = dev_alloc(&h->sa_all, W * h->n_atv)) ||
         (rc = dev_alloc(&h->sa_cnt_all, W * h->ngroups)) || (rc = dev_alloc(&h->counter, 1)) ||
         (rc = dev_alloc(&h->prefix, h->nframe + 1))) {
+        free_all(h);
+        delete h;
+        return rc;
+    }
+    if (hipEventCreateWithFlags(&h->cnt_ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->q_done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        free_all(h);
+        delete h;
+        return AT_E_DEVICE;
+    }
+    if ((rc = ensure_pin_cnt(h, h->ngroups))) {
         free_all(h);
         delete h;
         return rc;
@@ -490,7 +581,9 @@ int at_close_slice_multi(at_ctx* h, const uint32_t* kprimes, uint32_t n) {
         if (kprimes[j] < 1 || kprimes[j] > h->p.k) return AT_E_INVAL;
         Wn.kq[j] = kprimes[j];
     }
-    int rc = open_slice(h);
+    int rc = ensure_pin_cnt(h, (uint64_t)n * h->ngroups);
+    if (rc) return rc;
+    rc = open_slice(h);
     if (rc) return rc;
     // the slice's one tiled call already counted window k: no pass over the pool
     const bool counted = n == 1 && h->wfused && kprimes[0] == h->wfused_kq;
@@ -498,7 +591,9 @@ int at_close_slice_multi(at_ctx* h, const uint32_t* kprimes, uint32_t n) {
     hipError_t e = counted ? hipSuccess
                            : atp::launch_close(h->pool, h->w_all, h->n_atv, h->G, h->c0, Wn, h->stream);
     if (e == hipSuccess)
-        e = atp::launch_summarize(h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->G, h->n_atv, n, h->stream);
+        e = atp::launch_summarize(h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->pin_cnt_dev, h->G, h->n_atv, n,
+                                  h->stream);
+    if (e == hipSuccess) e = hipEventRecord(h->cnt_ready, h->stream);
     if (e != hipSuccess) return AT_E_DEVICE;
     h->nwin = n;
     for (uint32_t j = 0; j < n; j++) h->win_kq[j] = kprimes[j];
@@ -917,31 +1012,55 @@ int at_estimate_learned_dev(at_ctx* h, at_mlp* M, const uint32_t* aip_dev, uint6
     return e == hipSuccess ? AT_OK : AT_E_DEVICE;
 }
 
+int at_estimate_learned_begin(at_ctx* h, at_mlp* M, const uint32_t* aip_host, uint64_t n) {
+    if (!h || !M || (n && !aip_host)) return AT_E_INVAL;
+    if (!h->queryable || h->q_pending) return AT_E_STATE;
+    if (n > 0) {
+        const uint64_t off = up64(4 * n);  // results follow the addresses in the staging
+        const OutLayout O = out_layout(n);
+        int rc = ensure_query(h, n);
+        if (!rc) rc = ensure_pin_q(h, off + O.total);
+        if (rc) return rc;
+        // the kernels read the addresses from the staging and store the
+        // results there: no copy commands between them and the host
+        std::memcpy(h->pin_q, aip_host, n * sizeof(uint32_t));
+        uint8_t* res = h->pin_q_dev + off;
+        rc = at_estimate_learned_dev(h, M, reinterpret_cast<const uint32_t*>(h->pin_q_dev), n,
+                                     reinterpret_cast<double*>(res + O.est), res + O.flags,
+                                     reinterpret_cast<double*>(res + O.plain));
+        if (rc) return rc;
+        if (hipEventRecord(h->q_done, h->stream) != hipSuccess) return AT_E_DEVICE;
+    }
+    h->q_pending = true;
+    h->q_pending_n = n;
+    return AT_OK;
+}
+
+int at_estimate_learned_end(at_ctx* h, double* est_out, uint8_t* flags_out, double* plain_out) {
+    if (!h) return AT_E_INVAL;
+    if (!h->q_pending) return AT_E_STATE;
+    const uint64_t n = h->q_pending_n;
+    if (n && (!est_out || !flags_out)) return AT_E_INVAL;
+    h->q_pending = false;
+    if (n == 0) return AT_OK;
+    const hipError_t e = hipEventSynchronize(h->q_done);
+    if (e != hipSuccess) return dev_err(e);
+    const uint8_t* res = h->pin_q + up64(4 * n);
+    const OutLayout O = out_layout(n);
+    std::memcpy(est_out, res + O.est, n * sizeof(double));
+    std::memcpy(flags_out, res + O.flags, n);
+    if (plain_out) std::memcpy(plain_out, res + O.plain, n * sizeof(double));
+    return AT_OK;
+}
+
 int at_estimate_learned(at_ctx* h, at_mlp* M, const uint32_t* aip_host, uint64_t n, double* est_out,
                         uint8_t* flags_out, double* plain_out) {
     if (!h || !M || (n && (!aip_host || !est_out || !flags_out))) return AT_E_INVAL;
-    if (!h->queryable) return AT_E_STATE;
+    if (!h->queryable || h->q_pending) return AT_E_STATE;
     if (n == 0) return AT_OK;
-    int rc = ensure_query(h, n);
-    const PinLayout L = pin_layout(n);
-    if (!rc) rc = ensure_pinned(h, L.total);
+    const int rc = at_estimate_learned_begin(h, M, aip_host, n);
     if (rc) return rc;
-    std::memcpy(h->pin + L.aip, aip_host, n * sizeof(uint32_t));
-    hipError_t e = hipMemcpyAsync(h->q_aip, h->pin + L.aip, n * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream);
-    if (e != hipSuccess) return AT_E_DEVICE;
-    // est and flags of the learned path land in q_est / q_nat (as bytes); plain in q_plain
-    rc = at_estimate_learned_dev(h, M, h->q_aip, n, h->q_est, reinterpret_cast<uint8_t*>(h->q_nat), h->q_plain);
-    if (rc) return rc;
-    e = hipMemcpyAsync(h->pin + L.est, h->q_est, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(h->pin + L.flags, h->q_nat, n, hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess && plain_out)
-        e = hipMemcpyAsync(h->pin + L.plain, h->q_plain, n * sizeof(double), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return dev_err(e);
-    std::memcpy(est_out, h->pin + L.est, n * sizeof(double));
-    std::memcpy(flags_out, h->pin + L.flags, n);
-    if (plain_out) std::memcpy(plain_out, h->pin + L.plain, n * sizeof(double));
-    return AT_OK;
+    return at_estimate_learned_end(h, est_out, flags_out, plain_out);
 }
 
 }  // extern "C"

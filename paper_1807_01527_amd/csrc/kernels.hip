@@ -708,7 +708,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict_
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kTileBytes / 16; i += kApplyBlock) src[i] = lds[i];
     if (w_out) {
-        constexpr uint32_t CA = kPerChunk<T>, N = kPerWord<T>;
+        constexpr uint32_t CA = kPerChunk<T>;
         __shared__ uint32_t wl[kTileBytes / 16 / 64];  // per ATV, when an ATV spans more than 64 chunks
         const uint32_t cpa = G.g / CA;                // chunks per ATV (a power of two)
         const uint32_t seg = cpa < 64 ? cpa : 64;
@@ -832,7 +832,8 @@ __global__ __launch_bounds__(kBlock) void k_close(const T* __restrict__ pool, ui
 // ascending list of super columns (weight >= T) with its length.
 __global__ __launch_bounds__(kBlock) void k_summarize(const uint32_t* __restrict__ w_all, uint64_t* __restrict__ aat_all,
                                                       uint32_t* __restrict__ sa_all, uint32_t* __restrict__ sa_cnt_all,
-                                                      Geometry G, uint64_t n_atv, uint32_t ngroups) {
+                                                      uint32_t* __restrict__ cnt_host, Geometry G, uint64_t n_atv,
+                                                      uint32_t ngroups) {
     __shared__ uint32_t wave_cnt[kBlock / 64];
     __shared__ unsigned long long wave_sum[kBlock / 64];
     const uint32_t grp = blockIdx.x;
@@ -870,6 +871,7 @@ __global__ __launch_bounds__(kBlock) void k_summarize(const uint32_t* __restrict
         for (uint32_t q = 0; q < kBlock / 64; q++) t += wave_sum[q];
         aat[grp] = t;
         sa_cnt[grp] = written;
+        if (cnt_host) cnt_host[(uint64_t)blockIdx.y * ngroups + grp] = written;  // mapped host memory
     }
 }
 
@@ -1921,10 +1923,11 @@ hipError_t launch_close(const uint8_t* pool, uint32_t* w, uint64_t n_atv, const 
     });
 }
 
-hipError_t launch_summarize(const uint32_t* w, uint64_t* aat, uint32_t* sa, uint32_t* sa_cnt, const Geometry& G,
-                            uint64_t n_atv, uint32_t nwin, hipStream_t st) {
+hipError_t launch_summarize(const uint32_t* w, uint64_t* aat, uint32_t* sa, uint32_t* sa_cnt, uint32_t* cnt_host,
+                            const Geometry& G, uint64_t n_atv, uint32_t nwin, hipStream_t st) {
     const uint32_t groups = (G.umask + 1) * G.r;
-    hipLaunchKernelGGL(k_summarize, dim3(groups, nwin), dim3(kBlock), 0, st, w, aat, sa, sa_cnt, G, n_atv, groups);
+    hipLaunchKernelGGL(k_summarize, dim3(groups, nwin), dim3(kBlock), 0, st, w, aat, sa, sa_cnt, cnt_host, G, n_atv,
+                       groups);
     return hipGetLastError();
 }
 

@@ -182,3 +182,59 @@ def test_learned_estimate_and_fallback(torch_cuda, oracle_lib):
         assert np.array_equal((fl & 4) != 0, ~inside)
         assert np.array_equal((fl & 8) != 0, est >= geom["theta"])
         assert np.array_equal(fl & 3, f_plain & 3)
+
+
+def test_split_learned_estimate(torch_cuda, oracle_lib):
+    """at_estimate_learned_begin/_end give what at_estimate_learned gives for
+    the window closed before _begin, while a restore, a query that grows the
+    query scratch, and the next slice's ingest and close run in between; and
+    the pending-state rules hold."""
+    from paper_1807_01527_amd.binding import AT_E_STATE, AtError, Mlp
+    tr = traffic.generate(traffic.config_tiny(seed=8, n_slices=5, pairs_per_slice=30000, hosts=1 << 11))
+    geom = dict(k=3, r=4, c=8, s=8, u=1, log2g=8, theta=200.0, seed=2)
+    g, o = make_pair(geom, oracle_lib)
+    net = Mlp(ref.init_params(3))
+    for t in range(3):
+        g.ingest(to_dev(tr.aip[t]), to_dev(tr.bip[t]))
+        o.ingest(tr.aip[t], tr.bip[t])
+        g.close(3)
+        o.close(3)
+    hosts = np.unique(tr.aip[2][:700])
+    e1, f1, p1 = g.estimate_learned(net, hosts)
+    rc1, sip1, est1, fl1, m1 = g.restore(cap=1 << 16)
+    e_o, _, _ = o.estimate(hosts)
+    np.testing.assert_allclose(p1, e_o, rtol=1e-12, atol=0)
+
+    g.estimate_learned_begin(net, hosts)
+    for call in (lambda: g.estimate_learned_begin(net, hosts), lambda: g.estimate_learned(net, hosts)):
+        with pytest.raises(AtError) as ei:
+            call()
+        assert ei.value.rc == AT_E_STATE
+    rc2, sip2, est2, fl2, m2 = g.restore(cap=1 << 16)
+    assert (rc2, m2) == (rc1, m1)
+    if rc1 == 0:
+        assert np.array_equal(sip2, sip1) and np.array_equal(est2, est1) and np.array_equal(fl2, fl1)
+    big = np.unique(np.concatenate([tr.aip[2], np.arange(1, 5000, dtype=np.uint32)]))
+    assert big.size > 4096    # past the query scratch the 700 hosts sized
+    e_big, _, _ = g.estimate(big)
+    e_big_o, _, _ = o.estimate(big)
+    np.testing.assert_allclose(e_big, e_big_o, rtol=1e-12, atol=0)
+    g.ingest(to_dev(tr.aip[3]), to_dev(tr.bip[3]))
+    g.close(3)
+    e2, f2, p2 = g.estimate_learned_end()
+    assert np.array_equal(e2, e1) and np.array_equal(f2, f1) and np.array_equal(p2, p1)
+    with pytest.raises(AtError) as ei:
+        g.estimate_learned_end()
+    assert ei.value.rc == AT_E_STATE
+
+    # the new window: split and whole calls agree; an empty split call is allowed
+    o.ingest(tr.aip[3], tr.bip[3])
+    o.close(3)
+    e3, f3, p3 = g.estimate_learned(net, hosts)
+    g.estimate_learned_begin(net, hosts)
+    e4, f4, p4 = g.estimate_learned_end()
+    assert np.array_equal(e4, e3) and np.array_equal(f4, f3) and np.array_equal(p4, p3)
+    np.testing.assert_allclose(p3, o.estimate(hosts)[0], rtol=1e-12, atol=0)
+    g.estimate_learned_begin(net, hosts[:0])
+    e5, f5, p5 = g.estimate_learned_end()
+    assert e5.size == f5.size == p5.size == 0
