@@ -41,6 +41,15 @@ __device__ __forceinline__ uint32_t act_of(uint32_t i, uint32_t c0, const Geomet
     return v >= G.twok ? v - G.twok : v;
 }
 
+// act_of when every block holds at least two ATs (blk_a >= 2, so the magic
+// multiplier fits 32 bits): one high multiply, and the wrap as an unsigned
+// minimum (v < 4k: v - 2k wraps above v exactly when v < 2k).
+__device__ __forceinline__ uint32_t act_of_narrow(uint32_t i, uint32_t c0, uint32_t magic, const Geometry& G) {
+    const uint32_t b = min(__umulhi(i, magic), G.last_blk);
+    const uint32_t v = c0 + b;
+    return min(v, v - G.twok);
+}
+
 // Column x_j of LBS: c bits starting at bit sh[j], cyclic modulo W.  LL holds
 // L twice (L | L << W) so one 64-bit shift reads across the wrap.
 __device__ __forceinline__ uint32_t column(uint64_t LL, uint32_t sh, uint32_t mask) {
@@ -628,6 +637,49 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
     }
 }
 
+// Records [lo, hi) of a tile set their ATs in the LDS copy tl to the block
+// timestamp ACT(i): a ragged head and tail one by one, the 8-aligned body
+// eight at a time with 16-byte loads, four in flight per thread.
+template <typename T, typename F>
+__device__ __forceinline__ void apply_records(T* tl, const uint16_t* __restrict__ rec, uint32_t lo, uint32_t hi,
+                                              uint32_t gmask, F act) {
+    const uint32_t a8 = (lo + 7u) & ~7u, b8 = hi & ~7u;
+    if (a8 >= b8) {
+        for (uint32_t q = lo + threadIdx.x; q < hi; q += kApplyBlock) {
+            const uint32_t loc = rec[q];
+            tl[loc] = (T)act(loc & gmask);
+        }
+        return;
+    }
+    if (lo + threadIdx.x < a8) {
+        const uint32_t loc = rec[lo + threadIdx.x];
+        tl[loc] = (T)act(loc & gmask);
+    }
+    if (b8 + threadIdx.x < hi) {
+        const uint32_t loc = rec[b8 + threadIdx.x];
+        tl[loc] = (T)act(loc & gmask);
+    }
+    const uint4* r8 = reinterpret_cast<const uint4*>(rec + a8);
+    const uint32_t n8 = (b8 - a8) / 8;
+    for (uint32_t q0 = threadIdx.x; q0 < n8; q0 += 4 * kApplyBlock) {
+        uint4 v[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; u++) {
+            const uint32_t q = q0 + u * kApplyBlock;
+            v[u] = q < n8 ? r8[q] : make_uint4(~0u, ~0u, ~0u, ~0u);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 4; u++) {
+            if (q0 + u * kApplyBlock >= n8) break;
+#pragma unroll
+            for (uint32_t e = 0; e < 8; e++) {
+                const uint32_t loc = (word_of(v[u], e / 2) >> (16 * (e & 1))) & 0xFFFFu;
+                tl[loc] = (T)act(loc & gmask);
+            }
+        }
+    }
+}
+
 // Pass 3: one workgroup per tile applies the tile's records in LDS.  When the
 // call opens the slice (preserve != 0) Alg 2 first runs here on the two due
 // blocks of every ATV of the tile (the AT ranges of S), before any record:
@@ -667,43 +719,11 @@ __global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict_
         __syncthreads();
     }
     const uint32_t gmask = G.g - 1u;
-    // records [lo, hi): a ragged head and tail one by one, the 8-aligned body
-    // eight at a time with 16-byte loads
-    const uint32_t a8 = (lo + 7u) & ~7u, b8 = hi & ~7u;
-    if (a8 >= b8) {
-        for (uint32_t q = lo + threadIdx.x; q < hi; q += kApplyBlock) {
-            const uint32_t loc = rec[q];
-            tl[loc] = (T)act_of(loc & gmask, c0, G);
-        }
+    if (G.blk_a >= 2) {
+        const uint32_t magic = (uint32_t)G.blk_magic;
+        apply_records<T>(tl, rec, lo, hi, gmask, [&](uint32_t i) { return act_of_narrow(i, c0, magic, G); });
     } else {
-        if (lo + threadIdx.x < a8) {
-            const uint32_t loc = rec[lo + threadIdx.x];
-            tl[loc] = (T)act_of(loc & gmask, c0, G);
-        }
-        if (b8 + threadIdx.x < hi) {
-            const uint32_t loc = rec[b8 + threadIdx.x];
-            tl[loc] = (T)act_of(loc & gmask, c0, G);
-        }
-        const uint4* r8 = reinterpret_cast<const uint4*>(rec + a8);
-        const uint32_t n8 = (b8 - a8) / 8;
-        // four 16-byte loads in flight per thread
-        for (uint32_t q0 = threadIdx.x; q0 < n8; q0 += 4 * kApplyBlock) {
-            uint4 v[4];
-#pragma unroll
-            for (uint32_t u = 0; u < 4; u++) {
-                const uint32_t q = q0 + u * kApplyBlock;
-                v[u] = q < n8 ? r8[q] : make_uint4(~0u, ~0u, ~0u, ~0u);
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < 4; u++) {
-                if (q0 + u * kApplyBlock >= n8) break;
-#pragma unroll
-                for (uint32_t e = 0; e < 8; e++) {
-                    const uint32_t loc = (word_of(v[u], e / 2) >> (16 * (e & 1))) & 0xFFFFu;
-                    tl[loc] = (T)act_of(loc & gmask, c0, G);
-                }
-            }
-        }
+        apply_records<T>(tl, rec, lo, hi, gmask, [&](uint32_t i) { return act_of(i, c0, G); });
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kTileBytes / 16; i += kApplyBlock) src[i] = lds[i];
@@ -1169,13 +1189,16 @@ __global__ __launch_bounds__(kBlock) void k_features(const T* __restrict__ pool,
     T* act_lut = reinterpret_cast<T*>(smem_feat);
     uint32_t* hist = reinterpret_cast<uint32_t*>(smem_feat + ((G.g * sizeof(T) + 15u) & ~15u));  // 64 bins
     __shared__ uint32_t nat_w[kBlock / 64];
+    // the first host's address is loaded while the table fills (it may sit
+    // in host memory)
+    uint32_t a_next = blockIdx.x < n ? aips[blockIdx.x] : 0u;
     fill_act_lut(act_lut, c0q, G);
     constexpr uint32_t CA = kPerChunk<T>, N = kPerWord<T>;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     for (uint64_t h = blockIdx.x; h < n; h += gridDim.x) {
         if (threadIdx.x < 64) hist[threadIdx.x] = 0;
         __syncthreads();
-        const uint32_t a = aips[h];
+        const uint32_t a = a_next;
         const uint32_t f = mangle(a, G.A);
         const uint32_t z = f & G.umask;
         const uint64_t L = (uint64_t)(f >> G.u);
@@ -1186,6 +1209,12 @@ __global__ __launch_bounds__(kBlock) void k_features(const T* __restrict__ pool,
             uint32_t x = column(LL, G.sh[j], G.ncol_mask);
             rows[j] = pool + (((((uint64_t)z * R + j) << G.c) + x) << G.log2g);
         }
+        if (h + gridDim.x < n) a_next = aips[h + gridDim.x];
+        // ages 0..15 are counted in registers, four 16-bit counts per word,
+        // and summed over the wave before they reach the LDS histogram: the
+        // ages of a window pile onto a few bins, and per-AT atomics on them
+        // serialise.  A wave counts at most 64 * g / kBlock <= 8192 per bin.
+        uint64_t h0 = 0, h1 = 0, h2 = 0, h3 = 0;
         uint32_t nat = 0;
         for (uint32_t off = threadIdx.x * CA; off < G.g; off += kBlock * CA) {
             uint4 d[R];
@@ -1205,11 +1234,31 @@ __global__ __launch_bounds__(kBlock) void k_features(const T* __restrict__ pool,
                 }
                 if (ok) {
                     nat += e < kq;
-                    if (e < 64) atomicAdd(&hist[e], 1u);
+                    if (e < 16) {
+                        const uint64_t inc = 1ull << ((e & 3u) * 16u);
+                        const uint32_t q = e >> 2;
+                        h0 += q == 0 ? inc : 0ull;
+                        h1 += q == 1 ? inc : 0ull;
+                        h2 += q == 2 ? inc : 0ull;
+                        h3 += q == 3 ? inc : 0ull;
+                    } else if (e < 64) {
+                        atomicAdd(&hist[e], 1u);
+                    }
                 }
             }
         }
-        for (uint32_t o = 32; o > 0; o >>= 1) nat += __shfl_xor(nat, o, 64);
+        for (uint32_t o = 32; o > 0; o >>= 1) {
+            nat += __shfl_xor(nat, o, 64);
+            h0 += __shfl_xor(h0, o, 64);
+            h1 += __shfl_xor(h1, o, 64);
+            h2 += __shfl_xor(h2, o, 64);
+            h3 += __shfl_xor(h3, o, 64);
+        }
+        if (lane < 16) {
+            const uint64_t hw = lane < 4 ? h0 : lane < 8 ? h1 : lane < 12 ? h2 : h3;
+            const uint32_t c = (uint32_t)(hw >> ((lane & 3u) * 16u)) & 0xFFFFu;
+            if (c) atomicAdd(&hist[lane], c);
+        }
         if (lane == 0) nat_w[wv] = nat;
         __syncthreads();
         if (wv == 0) {
