@@ -399,6 +399,22 @@ __global__ __launch_bounds__(kBlock) void k_scan_bins(const uint64_t* __restrict
 // tile: the tile is read into LDS, every record sets its AT to the value its
 // index implies (its block timestamp), and the tile is written back.  The
 // random stores hit LDS; HBM sees streams.
+// a[j] <- a[(j + rot) mod R] for a lane-varying rot < R, as a barrel of
+// fixed rotations (by 1, 2, 4) so that the array is only ever indexed by
+// constants and stays in registers
+template <int R>
+__device__ __forceinline__ void rotate_rows(uint32_t (&a)[R], uint32_t rot) {
+#pragma unroll
+    for (int b = 1; b < R; b <<= 1) {
+        const bool on = (rot & (uint32_t)b) != 0;
+        uint32_t t[R];
+#pragma unroll
+        for (int j = 0; j < R; j++) t[j] = a[(j + b) % R];
+#pragma unroll
+        for (int j = 0; j < R; j++) a[j] = on ? t[j] : a[j];
+    }
+}
+
 constexpr uint32_t kTileBytes = 1u << 16;
 constexpr uint32_t kTileRecs = 16384;  // records per block in passes 1 and 2
 constexpr uint32_t kMaxTiles = 4096;
@@ -406,18 +422,24 @@ constexpr uint32_t kTileChunk = 64;    // rows (blocks) per chunk of the column 
 constexpr uint32_t kApplyBlock = 1024;
 constexpr uint32_t kScatterBlock = 1024;  // 16 waves: the scatter block holds 96 KiB of LDS
 
+// The tiled scan only runs on pools of at most kMaxTiles * kTileBytes =
+// 2^28 bytes, so ATV and AT indices fit 32 bits there: the index arithmetic
+// of passes 1 and 2 is 32-bit (half the instructions of the 64-bit form).
+static_assert((uint64_t)kMaxTiles * kTileBytes <= (1ull << 32), "tiled AT indices fit 32 bits");
+
+// the r target AT indices of a pair (Alg 3), 32-bit
 template <int R>
-__device__ __forceinline__ void pair_targets(uint32_t a, uint32_t b, const Geometry& G, uint64_t* idx) {
+__device__ __forceinline__ void pair_targets(uint32_t a, uint32_t b, const Geometry& G, uint32_t* idx) {
     const uint32_t f = mangle(a, G.A);
     const uint32_t z = f & G.umask;
     const uint64_t L = (uint64_t)(f >> G.u);
     const uint64_t LL = L | (L << G.W);
     const uint32_t i = (uint32_t)((G.alpha * (uint64_t)b + G.beta) >> (64 - G.log2g));
-    const uint64_t zr = (uint64_t)z * R;
+    const uint32_t zc = (z * (uint32_t)R) << G.c;
 #pragma unroll
     for (int j = 0; j < R; j++) {
         const uint32_t x = column(LL, G.sh[j], G.ncol_mask);
-        idx[j] = ((((zr + j) << G.c) + x) << G.log2g) | i;
+        idx[j] = ((zc + ((uint32_t)j << G.c) + x) << G.log2g) | i;
     }
 }
 
@@ -434,6 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restric
     const uint64_t lo = (uint64_t)blockIdx.x * P;
     const uint64_t hi = lo + P < n ? lo + P : n;
     const uint32_t atv_shift = ts - G.log2g;  // ATVs per tile = 2^atv_shift
+    const uint32_t rot = threadIdx.x % R;
     // four pairs per thread per round, loads issued before use
     for (uint64_t q0 = lo + threadIdx.x; q0 < hi; q0 += 4 * kBlock) {
         uint32_t a4[4];
@@ -449,12 +472,19 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restric
             const uint32_t z = f & G.umask;
             const uint64_t L = (uint64_t)(f >> G.u);
             const uint64_t LL = L | (L << G.W);
-            const uint64_t zr = (uint64_t)z * R;
+            const uint32_t zc = (z * (uint32_t)R) << G.c;
+            uint32_t tile[R];
 #pragma unroll
             for (int j = 0; j < R; j++) {
-                const uint64_t atv = ((zr + j) << G.c) + column(LL, G.sh[j], G.ncol_mask);
-                atomicAdd(&hist[(uint32_t)(atv >> atv_shift)], 1u);
+                const uint32_t atv = zc + ((uint32_t)j << G.c) + column(LL, G.sh[j], G.ncol_mask);
+                tile[j] = atv >> atv_shift;
             }
+            // lane l adds row (j + l) mod R at step j: lanes holding the same
+            // frequent host then hit different counters in one instruction
+            // instead of piling onto one
+            rotate_rows<R>(tile, rot);
+#pragma unroll
+            for (int j = 0; j < R; j++) atomicAdd(&hist[tile[j]], 1u);
         }
     }
     __syncthreads();
@@ -463,16 +493,36 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restric
 }
 
 // Column sums of cnt over each chunk of kTileChunk rows -> csum[chunk][tile].
+// A block takes 64 tiles of one chunk; each of its kColGroups waves sums
+// kTileChunk / kColGroups rows (loads issued together) and the waves' sums
+// meet in LDS.  Rows of 64 tiles are 256-byte coalesced reads.
+constexpr uint32_t kColTiles = 64;
+constexpr uint32_t kColGroups = kBlock / kColTiles;
+constexpr uint32_t kColRows = kTileChunk / kColGroups;
+static_assert(kColGroups * kColRows == kTileChunk, "a chunk splits evenly over the waves");
+
 __global__ __launch_bounds__(kBlock) void k_tile_chunksum(const uint32_t* __restrict__ cnt, uint32_t nb,
                                                           uint32_t n_tiles, uint32_t* __restrict__ csum) {
-    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= n_tiles) return;
+    __shared__ uint32_t part[kColGroups][kColTiles];
+    const uint32_t tl = threadIdx.x % kColTiles, rg = threadIdx.x / kColTiles;
+    const uint32_t t = blockIdx.x * kColTiles + tl;
     const uint32_t c = blockIdx.y;
-    const uint32_t b1 = (c + 1) * kTileChunk < nb ? (c + 1) * kTileChunk : nb;
+    const uint32_t b0 = c * kTileChunk + rg * kColRows;
+    uint32_t v[kColRows];
+#pragma unroll
+    for (uint32_t e = 0; e < kColRows; e++)
+        v[e] = (t < n_tiles && b0 + e < nb) ? cnt[(uint64_t)(b0 + e) * n_tiles + t] : 0u;
     uint32_t s = 0;
-#pragma unroll 8
-    for (uint32_t b = c * kTileChunk; b < b1; b++) s += cnt[(uint64_t)b * n_tiles + t];
-    csum[(uint64_t)c * n_tiles + t] = s;
+#pragma unroll
+    for (uint32_t e = 0; e < kColRows; e++) s += v[e];
+    part[rg][tl] = s;
+    __syncthreads();
+    if (rg == 0 && t < n_tiles) {
+        uint32_t tot = 0;
+#pragma unroll
+        for (uint32_t g = 0; g < kColGroups; g++) tot += part[g][tl];
+        csum[(uint64_t)c * n_tiles + t] = tot;
+    }
 }
 
 // Exclusive scan of one block's values held as v (one per thread, NT
@@ -540,23 +590,45 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scan(uint32_t* __restric
     if (threadIdx.x == 0) base[n_tiles] = carry;
 }
 
-// Start of every (block, tile) run in the record array -> pre[b][tile].
+// Start of every (block, tile) run in the record array -> pre[b][tile].  The
+// same split as the chunk sums: each wave's 16 rows, loads issued together,
+// start after the rows of the waves before it.
 __global__ __launch_bounds__(kBlock) void k_tile_rowpre(const uint32_t* __restrict__ cnt,
                                                         const uint32_t* __restrict__ cpre,
                                                         const uint32_t* __restrict__ base, uint32_t nb,
                                                         uint32_t n_tiles, uint32_t* __restrict__ pre) {
-    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= n_tiles) return;
+    __shared__ uint32_t part[kColGroups][kColTiles];
+    const uint32_t tl = threadIdx.x % kColTiles, rg = threadIdx.x / kColTiles;
+    const uint32_t t = blockIdx.x * kColTiles + tl;
     const uint32_t c = blockIdx.y;
-    const uint32_t b1 = (c + 1) * kTileChunk < nb ? (c + 1) * kTileChunk : nb;
+    const uint32_t b0 = c * kTileChunk + rg * kColRows;
+    const bool col = t < n_tiles;
+    uint32_t v[kColRows];
+#pragma unroll
+    for (uint32_t e = 0; e < kColRows; e++) v[e] = (col && b0 + e < nb) ? cnt[(uint64_t)(b0 + e) * n_tiles + t] : 0u;
+    uint32_t s = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < kColRows; e++) s += v[e];
+    part[rg][tl] = s;
+    __syncthreads();
+    if (!col) return;
     uint32_t run = base[t] + cpre[(uint64_t)c * n_tiles + t];
-#pragma unroll 8
-    for (uint32_t b = c * kTileChunk; b < b1; b++) {
-        const uint64_t o = (uint64_t)b * n_tiles + t;
-        const uint32_t v = cnt[o];
-        pre[o] = run;
-        run += v;
+    for (uint32_t g = 0; g < rg; g++) run += part[g][tl];
+#pragma unroll
+    for (uint32_t e = 0; e < kColRows; e++) {
+        if (b0 + e < nb) pre[(uint64_t)(b0 + e) * n_tiles + t] = run;
+        run += v[e];
     }
+}
+
+// Workgroups are dealt to the 8 XCDs in turn (w -> XCD w mod 8).  This gives
+// XCD x the x-th contiguous share of the logical blocks instead, in order, so
+// that blocks running side by side on one XCD write neighbouring runs of each
+// tile: their partial cache lines meet in that XCD's L2 and leave it whole.
+__device__ __forceinline__ uint32_t xcd_contiguous_block(uint32_t w, uint32_t nb) {
+    constexpr uint32_t kXcds = 8;
+    const uint32_t x = w % kXcds, l = w / kXcds, q = nb / kXcds, rem = nb % kXcds;
+    return x * q + (x < rem ? x : rem) + l;
 }
 
 // Pass 2: the block's records grouped by tile in LDS, then written run by run.
@@ -574,7 +646,8 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
     __shared__ uint32_t scratch[kScatterBlock / 64 + 1];
     constexpr uint32_t P = kTileRecs / R;
     constexpr uint32_t PPT = (P + kScatterBlock - 1) / kScatterBlock;  // pairs per thread
-    const uint64_t lo = (uint64_t)blockIdx.x * P;
+    const uint32_t blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const uint64_t lo = (uint64_t)blk * P;
     const uint64_t hi = lo + P < n ? lo + P : n;
     const uint32_t lmask = (1u << ts) - 1u;
     // hash the block's pairs once; the targets stay in registers
@@ -589,19 +662,19 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
 #pragma unroll
     for (uint32_t e = 0; e < PPT; e++) {
         const bool ok = lo + threadIdx.x + (uint64_t)e * kScatterBlock < hi;
-        uint64_t idx[R];
+        uint32_t idx[R];
         pair_targets<R>(a4[e], b4[e], G, idx);
 #pragma unroll
         for (int j = 0; j < R; j++) {
             // tile in the high half, in-tile index in the low half (ts <= 16)
-            tgt[e][j] = ok ? (uint32_t)((idx[j] >> ts) << 16) | ((uint32_t)idx[j] & lmask) : ~0u;
+            tgt[e][j] = ok ? ((idx[j] >> ts) << 16) | (idx[j] & lmask) : ~0u;
         }
     }
     // LDS run starts: exclusive scan of the block's counts (its row of the
     // count table), kMaxTiles / kScatterBlock consecutive tiles per thread
     constexpr uint32_t TPT = kMaxTiles / kScatterBlock;
-    const uint32_t* prow = pre + (uint64_t)blockIdx.x * n_tiles;
-    const uint32_t* crow = cnt + (uint64_t)blockIdx.x * n_tiles;
+    const uint32_t* prow = pre + (uint64_t)blk * n_tiles;
+    const uint32_t* crow = cnt + (uint64_t)blk * n_tiles;
     uint32_t c[TPT], sum = 0;
 #pragma unroll
     for (uint32_t e = 0; e < TPT; e++) {
@@ -1927,7 +2000,7 @@ hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_
     const TileSizes z = tiled_sizes(n, pool_bytes, G);
     if (z.recs > B.rec_cap || z.table > B.table_cap || z.nchunk > B.chunk_cap) return hipErrorInvalidValue;
     const uint32_t ts = 16u - (G.atb == 2 ? 1u : 0u);  // log2 of the ATs per tile
-    const dim3 cols((z.n_tiles + kBlock - 1) / kBlock, z.nchunk);
+    const dim3 cols((z.n_tiles + kColTiles - 1) / kColTiles, z.nchunk);
     hipError_t e = with_rows<uint8_t>(G.r, [&](auto rc, auto) {
         constexpr int RR = decltype(rc)::value;
         hipLaunchKernelGGL((k_tile_count<RR>), dim3(z.nb), dim3(kBlock), 0, st, aip, n, G, ts, z.n_tiles, B.cnt);
