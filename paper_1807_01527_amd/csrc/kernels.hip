@@ -123,6 +123,25 @@ __device__ __forceinline__ Alg1Halves alg1_halves(uint32_t at2, uint32_t act2, u
 __device__ __forceinline__ uint32_t inactive2(const Alg1Halves& h, uint32_t c_kq) {
     return __popc(((as_u32(as_u16x2(h.dist) + as_u16x2(c_kq))) | h.off) & 0x80008000u);
 }
+// Alg 1 on four byte ATs per 32-bit operation, while 4k <= 128 (k <= 32).
+// With d = ACT + 2k - AT, in [0, 4k) so that no carry or borrow crosses a
+// byte, an AT is active for window k' when AT != 2k and d < k' or
+// 2k <= d < 2k + k' (the distance (ACT - AT) mod 2k is below k').  Bit 7 of
+// every byte carries the comparisons: (d | 0x80) - c keeps bit 7 exactly
+// when d >= c.
+constexpr uint32_t kByteHigh = 0x80808080u, kByteOnes = 0x01010101u;
+struct ByteLanes {
+    uint32_t dh, live, ge2k;
+};
+__device__ __forceinline__ ByteLanes byte_lanes(uint32_t at4, uint32_t act4, uint32_t twok4) {
+    const uint32_t dh = ((act4 + twok4) - at4) | kByteHigh;
+    return {dh, ((at4 ^ twok4) | kByteHigh) - kByteOnes, dh - twok4};
+}
+// active ATs among the four for window k' (kq4 = k' and tkq4 = 2k + k' in every byte)
+__device__ __forceinline__ uint32_t byte_active(const ByteLanes& b, uint32_t kq4, uint32_t tkq4) {
+    return __popc((~(b.dh - kq4) | (b.ge2k & ~(b.dh - tkq4))) & b.live & kByteHigh);
+}
+
 // the 16-bit halves of a 16-byte chunk of ATs (bytes: even and odd bytes of every word apart)
 template <typename T>
 __device__ __forceinline__ void chunk_halves(uint4 v, uint32_t* h /* 8 or 4 */) {
@@ -813,15 +832,22 @@ __global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict_
             __syncthreads();
         }
         const bool packed = G.twok <= 32768u;
+        const bool bytes4 = sizeof(T) == 1 && G.twok <= 64u;
         const uint32_t twok2 = both_halves(G.twok), c_at = both_halves(0x8000u - G.twok);
         const uint32_t c_kq = both_halves(0x8000u - kq_w);
+        const uint32_t twok4 = G.twok * kByteOnes, kq4 = kq_w * kByteOnes, tkq4 = (G.twok + kq_w) * kByteOnes;
         for (uint32_t c = threadIdx.x; c < kTileBytes / 16; c += kApplyBlock) {
             const uint32_t pos = c * CA;                // AT index inside the tile
             const uint32_t i0 = pos & (G.g - 1u);       // its position in the ATV
             const uint4 ac = *reinterpret_cast<const uint4*>(act_table + i0);
             const uint4 d = lds[c];
             uint32_t act_n;
-            if (packed) {
+            if (bytes4) {
+                act_n = 0;
+#pragma unroll
+                for (uint32_t q = 0; q < 4; q++)
+                    act_n += byte_active(byte_lanes(word_of(d, q), word_of(ac, q), twok4), kq4, tkq4);
+            } else if (packed) {
                 constexpr uint32_t NH = 8 / sizeof(T);
                 uint32_t ha[NH], hc[NH], ni = 0;
                 chunk_halves<T>(d, ha);
@@ -863,10 +889,13 @@ __global__ __launch_bounds__(kBlock) void k_close(const T* __restrict__ pool, ui
     const uint32_t apw = 64 / lpa;
     const uint32_t sub = lane / lpa, sl = lane % lpa;
     const uint32_t steps = G.g / (CA * lpa);
-    // the packed form counts inactive ATs; it needs 4k <= 2^16
+    // the packed form counts inactive ATs; it needs 4k <= 2^16.  Byte ATs with
+    // 4k <= 128 count active ATs four per operation instead.
     const bool packed = G.twok <= 32768u;
+    const bool bytes4 = sizeof(T) == 1 && G.twok <= 64u;
     const uint32_t twok2 = both_halves(G.twok), c_at = both_halves(0x8000u - G.twok);
     const uint32_t c_kq0 = both_halves(0x8000u - Wn.kq[0]);
+    const uint32_t twok4 = G.twok * kByteOnes;
     const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
     for (uint64_t base = wave * apw; base < n_atv; base += nwaves * apw) {
@@ -886,7 +915,19 @@ __global__ __launch_bounds__(kBlock) void k_close(const T* __restrict__ pool, ui
                 for (uint32_t u = 0; u < 4; u++) {
                     if (st0 + u >= steps) break;
                     const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + ((st0 + u) * lpa + sl) * CA);
-                    if (packed) {
+                    if (bytes4) {
+#pragma unroll
+                        for (uint32_t q = 0; q < 4; q++) {
+                            const ByteLanes b = byte_lanes(word_of(d[u], q), word_of(ac, q), twok4);
+                            cnt[0] += byte_active(b, Wn.kq[0] * kByteOnes, (G.twok + Wn.kq[0]) * kByteOnes);
+                            if (Wn.n > 1) {
+#pragma unroll
+                                for (uint32_t j = 1; j < kMaxWindows; j++)
+                                    if (j < Wn.n)
+                                        cnt[j] += byte_active(b, Wn.kq[j] * kByteOnes, (G.twok + Wn.kq[j]) * kByteOnes);
+                            }
+                        }
+                    } else if (packed) {
                         constexpr uint32_t NH = 8 / sizeof(T);  // 16-bit halves per chunk
                         uint32_t ha[NH], hc[NH];
                         chunk_halves<T>(d[u], ha);
@@ -914,7 +955,7 @@ __global__ __launch_bounds__(kBlock) void k_close(const T* __restrict__ pool, ui
 #pragma unroll
         for (uint32_t j = 0; j < kMaxWindows; j++) {
             if (j >= Wn.n) break;
-            uint32_t c = packed && atv < n_atv ? steps * CA - cnt[j] : cnt[j];  // the lane's active ATs
+            uint32_t c = packed && !bytes4 && atv < n_atv ? steps * CA - cnt[j] : cnt[j];  // the lane's active ATs
             for (uint32_t o = lpa / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
             if (sl == 0 && atv < n_atv) w[(uint64_t)j * n_atv + atv] = c;
         }
