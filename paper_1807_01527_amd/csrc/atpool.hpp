@@ -156,15 +156,28 @@ struct AdamConst {
 };
 
 hipError_t launch_mlp_forward(const float* X, uint64_t n, const MlpDev& P, float* y, hipStream_t st);
+
+// The learned estimate's fallback rule applied to each network output as it
+// is produced: z = y + 16 f[61]; estimate exp(z) inside [zlo, zhi], else the
+// plain estimate with AT_F_FALLBACK; AT_F_SUPER when the estimate reaches
+// theta; AT_F_SAT and AT_F_NEG kept from the plain flags.
+struct LearnedEpilogue {
+    const double* plain;
+    const uint8_t* pflags;
+    double zlo, zhi, theta;
+    double* est;
+    uint8_t* flags;
+    double* plain_out;  // may be null: a copy of the plain estimates next to est
+};
+// Forward pass of the n feature rows X straight into L's estimates and flags.
+hipError_t launch_mlp_forward_learned(const float* X, uint64_t n, const MlpDev& P, const LearnedEpilogue& L,
+                                      hipStream_t st);
 hipError_t launch_mlp_train_fwd_bwd(const float* X, const float* t, uint64_t n, uint64_t nrows, const MlpDev& P,
                                     const MlpScratch& S, hipStream_t st);
 hipError_t launch_mlp_loss(const float* y, const float* t, uint64_t n, float* out, hipStream_t st);
 hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, const AdamConst& C, const MlpOut& O,
                            hipStream_t st);
 hipError_t launch_mlp_refresh(const float* w, const MlpOut& O, hipStream_t st);
-hipError_t launch_learned_combine(const float* y, const float* feat, const double* plain, const uint8_t* pflags,
-                                  uint64_t n, double zlo, double zhi, double theta, double* est, uint8_t* flags,
-                                  hipStream_t st);
 
 hipError_t launch_ace_age(uint8_t* p, uint64_t bytes, hipStream_t st);
 hipError_t launch_scatter_probe(uint8_t* dst, uint64_t bytes, const uint32_t* a, const uint32_t* b, uint64_t n,

@@ -68,7 +68,6 @@ struct at_ctx {
     uint8_t* q_flags = nullptr;
     uint32_t* q_nat = nullptr;
     float* q_feat = nullptr;      // n x 64 features
-    float* q_y = nullptr;         // network outputs
     double* q_plain = nullptr;
     uint64_t q_cap = 0;
     // slice clock
@@ -130,7 +129,7 @@ int dev_alloc(T** p, uint64_t count) {
 
 void free_all(at_ctx* h) {
     void* bufs[] = {h->pool, h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->counter, h->prefix, h->cand,
-                    h->q_aip, h->q_est, h->q_flags, h->q_nat, h->q_feat, h->q_y, h->q_plain, h->bins, h->bin_fill,
+                    h->q_aip, h->q_est, h->q_flags, h->q_nat, h->q_feat, h->q_plain, h->bins, h->bin_fill,
                     h->tb.rec, h->tb.cnt, h->tb.pre, h->tb.csum, h->tb.base, h->tb.act};
     if (h->pin) (void)hipHostFree(h->pin);
     h->pin = nullptr;
@@ -196,19 +195,17 @@ int ensure_query(at_ctx* h, uint64_t n) {
     if (h->q_flags) (void)hipFree(h->q_flags);
     if (h->q_nat) (void)hipFree(h->q_nat);
     if (h->q_feat) (void)hipFree(h->q_feat);
-    if (h->q_y) (void)hipFree(h->q_y);
     if (h->q_plain) (void)hipFree(h->q_plain);
     h->q_aip = nullptr;
     h->q_est = nullptr;
     h->q_flags = nullptr;
     h->q_nat = nullptr;
     h->q_feat = nullptr;
-    h->q_y = nullptr;
     h->q_plain = nullptr;
     h->q_cap = 0;
     int rc;
     if ((rc = dev_alloc(&h->q_aip, cap)) || (rc = dev_alloc(&h->q_est, cap)) || (rc = dev_alloc(&h->q_flags, cap)) ||
-        (rc = dev_alloc(&h->q_nat, cap)) || (rc = dev_alloc(&h->q_feat, cap * 64)) || (rc = dev_alloc(&h->q_y, cap)) ||
+        (rc = dev_alloc(&h->q_nat, cap)) || (rc = dev_alloc(&h->q_feat, cap * 64)) ||
         (rc = dev_alloc(&h->q_plain, cap)))
         return rc;
     h->q_cap = cap;
@@ -1002,13 +999,15 @@ int at_estimate_learned_dev(at_ctx* h, at_mlp* M, const uint32_t* aip_dev, uint6
     if (n == 0) return AT_OK;
     int rc = ensure_query(h, n);
     if (rc) return rc;
-    double* plain = plain_dev ? plain_dev : h->q_plain;
-    hipError_t e = atp::launch_features(h->pool, h->aat, aip_dev, n, h->G, h->c0_query, h->kq, h->q_feat, plain,
-                                        h->q_flags, h->stream);
-    if (e == hipSuccess) e = atp::launch_mlp_forward(h->q_feat, n, mlp_dev(M), h->q_y, h->stream);
-    if (e == hipSuccess)
-        e = atp::launch_learned_combine(h->q_y, h->q_feat, plain, h->q_flags, n, std::log(16.0) - 0.5,
-                                        std::log(262144.0) + 0.5, h->p.theta, est_dev, flags_dev, h->stream);
+    // the plain estimates stay in device memory for the fallback (the outputs
+    // may be mapped host memory); the network's epilogue copies them out
+    hipError_t e = atp::launch_features(h->pool, h->aat, aip_dev, n, h->G, h->c0_query, h->kq, h->q_feat,
+                                        h->q_plain, h->q_flags, h->stream);
+    if (e == hipSuccess) {
+        const atp::LearnedEpilogue L{h->q_plain, h->q_flags, std::log(16.0) - 0.5, std::log(262144.0) + 0.5,
+                                     h->p.theta, est_dev, flags_dev, plain_dev};
+        e = atp::launch_mlp_forward_learned(h->q_feat, n, mlp_dev(M), L, h->stream);
+    }
     return e == hipSuccess ? AT_OK : AT_E_DEVICE;
 }
 

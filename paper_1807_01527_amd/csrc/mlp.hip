@@ -57,16 +57,38 @@ __device__ __forceinline__ void load4_T(const uint16_t* T, uint64_t ldT, uint32_
     v[3] = (uint16_t)(pk.y >> 16);
 }
 
+// The fallback rule for row i (see LearnedEpilogue), shared by the fused
+// epilogue and k_learned_combine.
+__device__ __forceinline__ void learned_store(const double* __restrict__ plain, const uint8_t* __restrict__ pflags,
+                                              double zlo, double zhi, double theta, uint64_t i, float y, float f61,
+                                              double* __restrict__ est, uint8_t* __restrict__ flags) {
+    const double z = (double)y + 16.0 * (double)f61;
+    uint8_t fl = pflags[i] & (uint8_t)(AT_F_SAT | AT_F_NEG);
+    double e;
+    if (!(z >= zlo && z <= zhi)) {
+        e = plain[i];
+        fl |= AT_F_FALLBACK;
+    } else {
+        e = exp(z);
+    }
+    if (e >= theta) fl |= AT_F_SUPER;
+    est[i] = e;
+    flags[i] = fl;
+}
+
 // Forward pass.  nrows is a multiple of 64, so every wave of a block runs the
 // same number of iterations and block barriers are safe.  TRAIN also stores
 // the bf16 input and hidden activations feature-major for the backward pass.
 // n_dev, when given, holds the row count (written by an earlier kernel of the
-// same graph); n is then only the capacity.
+// same graph); n is then only the capacity.  With L.est set (inference only)
+// each output goes through the learned estimate's fallback rule instead of
+// to y.
 template <bool TRAIN>
 __global__ __launch_bounds__(kBlock) void k_mlp_fwd(const float* __restrict__ X, uint64_t n, uint64_t nrows,
                                                     MlpDev P, float* __restrict__ y, uint16_t* __restrict__ XT,
                                                     uint16_t* __restrict__ H1T, uint16_t* __restrict__ H2T,
-                                                    uint64_t ldT, const uint64_t* __restrict__ n_dev) {
+                                                    uint64_t ldT, const uint64_t* __restrict__ n_dev,
+                                                    LearnedEpilogue L) {
     __shared__ __align__(16) uint16_t hs[kBlock / 64][16][D + 8];
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t m = lane & 15u, q = lane >> 4;
@@ -137,7 +159,19 @@ __global__ __launch_bounds__(kBlock) void k_mlp_fwd(const float* __restrict__ X,
 #pragma unroll
         for (int e = 0; e < 4; e++)
             for (uint32_t o = 1; o < 16; o <<= 1) part[e] += __shfl_xor(part[e], o, 64);
-        if (m == 0) {
+        if (!TRAIN && L.est) {
+            // every lane of a 16-lane group holds its four sums after the
+            // butterfly: lanes m < 4 take one row each, in parallel
+            if (m < 4) {
+                const float pv = m == 0 ? part[0] : m == 1 ? part[1] : m == 2 ? part[2] : part[3];
+                const uint64_t rr = r0 + 4 * q + m;
+                if (rr < n) {
+                    learned_store(L.plain, L.pflags, L.zlo, L.zhi, L.theta, rr, pv + P.b3[0], X[rr * D + 61], L.est,
+                                  L.flags);
+                    if (L.plain_out) L.plain_out[rr] = L.plain[rr];
+                }
+            }
+        } else if (m == 0) {
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const uint64_t rr = r0 + 4 * q + e;
@@ -319,20 +353,8 @@ __global__ void k_learned_combine(const float* __restrict__ y, const float* __re
                                   double zlo, double zhi, double theta, double* __restrict__ est,
                                   uint8_t* __restrict__ flags, const uint64_t* __restrict__ n_dev) {
     if (n_dev) n = *n_dev < n ? *n_dev : n;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const double z = (double)y[i] + 16.0 * (double)feat[i * kMlpDim + 61];
-        uint8_t fl = pflags[i] & (uint8_t)(AT_F_SAT | AT_F_NEG);
-        double e;
-        if (!(z >= zlo && z <= zhi)) {
-            e = plain[i];
-            fl |= AT_F_FALLBACK;
-        } else {
-            e = exp(z);
-        }
-        if (e >= theta) fl |= AT_F_SUPER;
-        est[i] = e;
-        flags[i] = fl;
-    }
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        learned_store(plain, pflags, zlo, zhi, theta, i, y[i], feat[i * kMlpDim + 61], est, flags);
 }
 
 }  // namespace
@@ -343,7 +365,19 @@ hipError_t launch_mlp_forward(const float* X, uint64_t n, const MlpDev& P, float
     uint64_t blocks = nrows / 64;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_mlp_fwd<false>, dim3((uint32_t)blocks), dim3(kBlock), 0, st, X, n, nrows, P, y, nullptr,
-                       nullptr, nullptr, (uint64_t)0, (const uint64_t*)nullptr);
+                       nullptr, nullptr, (uint64_t)0, (const uint64_t*)nullptr, LearnedEpilogue{});
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward_learned(const float* X, uint64_t n, const MlpDev& P, const LearnedEpilogue& L,
+                                      hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (!L.est || !L.flags || !L.plain || !L.pflags) return hipErrorInvalidValue;
+    const uint64_t nrows = (n + 63) / 64 * 64;
+    uint64_t blocks = nrows / 64;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_mlp_fwd<false>, dim3((uint32_t)blocks), dim3(kBlock), 0, st, X, n, nrows, P, (float*)nullptr,
+                       nullptr, nullptr, nullptr, (uint64_t)0, (const uint64_t*)nullptr, L);
     return hipGetLastError();
 }
 
@@ -353,7 +387,7 @@ hipError_t launch_mlp_forward_devn(const float* X, const uint64_t* n_dev, uint64
     uint64_t blocks = nrows / 64;
     if (blocks > 2048) blocks = 2048;
     hipLaunchKernelGGL(k_mlp_fwd<false>, dim3((uint32_t)blocks), dim3(kBlock), 0, st, X, nrows_max, nrows, P, y,
-                       nullptr, nullptr, nullptr, (uint64_t)0, n_dev);
+                       nullptr, nullptr, nullptr, (uint64_t)0, n_dev, LearnedEpilogue{});
     return hipGetLastError();
 }
 
@@ -362,7 +396,7 @@ hipError_t launch_mlp_train_fwd_bwd(const float* X, const float* t, uint64_t n, 
     uint64_t blocks = nrows / 64;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_mlp_fwd<true>, dim3((uint32_t)blocks), dim3(kBlock), 0, st, X, n, nrows, P, S.y, S.XT,
-                       S.H1T, S.H2T, nrows, (const uint64_t*)nullptr);
+                       S.H1T, S.H2T, nrows, (const uint64_t*)nullptr, LearnedEpilogue{});
     hipLaunchKernelGGL(k_mlp_bwd, dim3((uint32_t)blocks), dim3(kBlock), 0, st, S.y, t, n, nrows, 2.0f / (float)n, P,
                        S.H1T, S.H2T, S.dH1T, S.dH2T, S.dy, nrows);
     const uint32_t nchunks = (uint32_t)(nrows / kMlpChunk);
@@ -386,17 +420,6 @@ hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, cons
 
 hipError_t launch_mlp_refresh(const float* w, const MlpOut& O, hipStream_t st) {
     hipLaunchKernelGGL(k_mlp_refresh, dim3((kMlpParams + kBlock - 1) / kBlock), dim3(kBlock), 0, st, w, O);
-    return hipGetLastError();
-}
-
-hipError_t launch_learned_combine(const float* y, const float* feat, const double* plain, const uint8_t* pflags,
-                                  uint64_t n, double zlo, double zhi, double theta, double* est, uint8_t* flags,
-                                  hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    uint64_t blocks = (n + kBlock - 1) / kBlock;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_learned_combine, dim3((uint32_t)blocks), dim3(kBlock), 0, st, y, feat, plain, pflags, n, zlo,
-                       zhi, theta, est, flags, (const uint64_t*)nullptr);
     return hipGetLastError();
 }
 
