@@ -462,6 +462,18 @@ __device__ __forceinline__ void pair_targets(uint32_t a, uint32_t b, const Geome
     }
 }
 
+// Workgroups are dealt to the 8 XCDs in turn (w -> XCD w mod 8).  This gives
+// XCD x the x-th contiguous share of the logical blocks instead, in order, so
+// that blocks running side by side on one XCD write neighbouring runs of each
+// tile (pass 2): their partial cache lines meet in that XCD's L2 and leave it
+// whole.  Pass 1 uses the same mapping, so a block's pairs are read by both
+// passes on one XCD.
+__device__ __forceinline__ uint32_t xcd_contiguous_block(uint32_t w, uint32_t nb) {
+    constexpr uint32_t kXcds = 8;
+    const uint32_t x = w % kXcds, l = w / kXcds, q = nb / kXcds, rem = nb % kXcds;
+    return x * q + (x < rem ? x : rem) + l;
+}
+
 // Pass 1: block b's per-tile store counts -> cnt[b * n_tiles + tile].  A tile
 // holds whole ATVs (g <= the ATs of a tile), so a store's tile is its ATV's:
 // it depends on aip alone and this pass never reads bip.
@@ -472,7 +484,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restric
     for (uint32_t t = threadIdx.x; t < n_tiles; t += kBlock) hist[t] = 0;
     __syncthreads();
     constexpr uint32_t P = kTileRecs / R;
-    const uint64_t lo = (uint64_t)blockIdx.x * P;
+    const uint32_t blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    const uint64_t lo = (uint64_t)blk * P;
     const uint64_t hi = lo + P < n ? lo + P : n;
     const uint32_t atv_shift = ts - G.log2g;  // ATVs per tile = 2^atv_shift
     const uint32_t rot = threadIdx.x % R;
@@ -507,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restric
         }
     }
     __syncthreads();
-    uint32_t* row = cnt + (uint64_t)blockIdx.x * n_tiles;
+    uint32_t* row = cnt + (uint64_t)blk * n_tiles;
     for (uint32_t t = threadIdx.x; t < n_tiles; t += kBlock) row[t] = hist[t];
 }
 
@@ -638,16 +651,6 @@ __global__ __launch_bounds__(kBlock) void k_tile_rowpre(const uint32_t* __restri
         if (b0 + e < nb) pre[(uint64_t)(b0 + e) * n_tiles + t] = run;
         run += v[e];
     }
-}
-
-// Workgroups are dealt to the 8 XCDs in turn (w -> XCD w mod 8).  This gives
-// XCD x the x-th contiguous share of the logical blocks instead, in order, so
-// that blocks running side by side on one XCD write neighbouring runs of each
-// tile: their partial cache lines meet in that XCD's L2 and leave it whole.
-__device__ __forceinline__ uint32_t xcd_contiguous_block(uint32_t w, uint32_t nb) {
-    constexpr uint32_t kXcds = 8;
-    const uint32_t x = w % kXcds, l = w / kXcds, q = nb / kXcds, rem = nb % kXcds;
-    return x * q + (x < rem ? x : rem) + l;
 }
 
 // Pass 2: the block's records grouped by tile in LDS, then written run by run.
