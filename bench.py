@@ -391,9 +391,12 @@ def main():
     torch.cuda.synchronize()
     rec = {"ingest_ms": [], "close_ms": [], "last": None}
     torch.cuda.synchronize()
+    step_ms = []
     t_start = time.perf_counter()
     for s in range(args.steps):
+        s0 = time.perf_counter()
         step(rec)
+        step_ms.append(1e3 * (time.perf_counter() - s0))
         log(f"step {s + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
@@ -439,6 +442,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "slices": S, "pairs_per_slice": args.pairs, "k": K,
                    "pool_ats": pool.pool_bytes, "parallelism": "single GPU"},
+        "step_ms": {"min": min(step_ms), "median": float(np.median(step_ms)), "max": max(step_ms),
+                    "all": [round(x, 3) for x in step_ms]},
         "ingest_mpps": per_launch / avg_ingest_s / 1e6,
         "slice_close_ms": {"p50": float(np.percentile(close_ms, 50)), "p99": float(np.percentile(close_ms, 99)),
                            "includes": "close + restore + plain and learned estimates of the true super points, "

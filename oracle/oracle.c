@@ -57,26 +57,38 @@ static uint64_t powmod(uint64_t b, uint64_t e, uint64_t m)
     return r;
 }
 
-/* ---- Alg 1: is `at` active in the latest k' slices, given its ACT? */
-int oat_check_at(uint32_t k, uint32_t act, uint32_t at, uint32_t kprime)
+/* ---- Section 3: age of an AT.  An AT that is not inactive holds the ACT
+ * of the slice that last set it, and the ACT advances by one per slice modulo
+ * 2k, so the number of slices since then (modulo 2k) is the ACT difference. */
+static uint32_t at_age(uint32_t k, uint32_t act, uint32_t at)
 {
-    if (at == 2 * k) return 0;
-    uint32_t dis = (act + 2 * k - at) % (2 * k);
-    return dis <= kprime - 1;
+    uint32_t m = 2 * k;
+    return act >= at ? act - at : act + m - at;
 }
 
-/* ---- Alg 2: preserveAT at the beginning of a slice, given the block's ACT. */
+/* ---- checkAT (Alg 1, Section 3): active in the latest k' slices means not
+ * inactive (value 2k) and set fewer than k' slices ago. */
+int oat_check_at(uint32_t k, uint32_t act, uint32_t at, uint32_t kprime)
+{
+    if (at >= 2 * k) return 0;
+    return at_age(k, act, at) < kprime;
+}
+
+/* ---- preserveAT (Alg 2, Section 3), applied at the start of a slice to an AT
+ * whose block has just reached ACT `act`.  Only the blocks whose ACT becomes 0
+ * or k are examined, so each AT is examined once every k slices.  At that
+ * moment the AT must not survive if it was set k or more slices ago: a
+ * value equal to the new ACT was written 2k slices back (the clock wrapped),
+ * and any other value lies (act - value) mod 2k slices back.  Such an AT
+ * becomes inactive; every younger one is left alone. */
 uint32_t oat_preserve_at(uint32_t k, uint32_t act, uint32_t at)
 {
-    if (act % k != 0) return at;
-    if (act == 0) {
-        if (at <= k) at = 2 * k;
-    }
-    if (act == k) {
-        if (k <= at && at <= 2 * k - 1) at = 2 * k;
-        if (at == 0) at = 2 * k;
-    }
-    return at;
+    uint32_t inactive = 2 * k;
+    if (at >= inactive) return at;
+    if (act != 0 && act != k) return at;
+    uint32_t since = at_age(k, act, at);
+    if (since == 0) since = 2 * k;
+    return since >= k ? inactive : at;
 }
 
 /* ---- Section 4.1: IP mangling f(a) = A*a mod p and its inverse. */

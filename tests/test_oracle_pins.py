@@ -504,3 +504,159 @@ def test_requery_equals_close_with_that_window(oracle_lib):
         eb, fb, nb = b.estimate(hosts)
         assert np.array_equal(na, nb) and np.array_equal(fa, fb) and np.array_equal(ea, eb)
     assert a.requery(0) == oracle_lib.E_INVAL and a.requery(k + 1) == oracle_lib.E_INVAL
+
+
+# --------------------------------------------------------------------------
+# Eq 3 / Eq 4 under load: the bias term UP (product of the rows' P_j)
+# --------------------------------------------------------------------------
+
+def test_eq3_expected_nat_and_unbiased_estimate_under_load(oracle_lib):
+    """Eq 3: with background load, a position outside the host's BIdx is
+    active in all r of its ATVs with probability UP = prod_j P_j, so
+    E[NAT] = |BIdx| + UP * (g - |BIdx|), and Eq 4 then estimates n without
+    bias.  Two frames with different loads (UP ~ 0.41 and ~ 0.03), hosts of
+    80, 160 and 320 distinct bips, 120 seeds.  |BIdx| is the exact count of
+    distinct BH values of the host's bips; P_j comes from AAT, which the
+    window-replay pin ties to raw pairs.  A sum of the P_j in place of their
+    product, a dropped (1 - UP), UP over fewer rows or another frame's AAT
+    each moves the mean estimate by at least 40%."""
+    from ._scenarios import LOADED, frames_of, loaded_frames  # noqa: F401
+    g = 1 << LOADED["log2g"]
+    ncol = 1 << LOADED["c"]
+    rows = []
+    for seed in range(120):
+        o = oracle_lib.Oracle(**LOADED, seed=seed + 100)
+        aip, bip, targets, tframes, tn, tb = loaded_frames(o, seed)
+        o.ingest(aip, bip)
+        o.close(1)
+        est, fl, nat = o.estimate(targets)
+        P = o.aat().astype(np.float64) / (g * ncol)
+        for q in range(targets.size):
+            z = int(tframes[q])
+            assert frames_of(o, targets[q:q + 1])[0] == z
+            up = float(np.prod(P[z * o.r:(z + 1) * o.r]))
+            bidx = len({o.bh(int(b)) for b in tb[q]})
+            rows.append((z, int(tn[q]), int(nat[q]), bidx, up, float(est[q]), int(fl[q])))
+    rows = np.array(rows, dtype=np.float64)
+    heavy_up = rows[rows[:, 0] == 0, 4].mean()
+    assert 0.3 < heavy_up < 0.55 and rows[rows[:, 0] == 1, 4].mean() < 0.06
+    for z in (0, 1):
+        for n in (80, 160, 320):
+            r = rows[(rows[:, 0] == z) & (rows[:, 1] == n)]
+            dev = r[:, 2] - (r[:, 3] + r[:, 4] * (g - r[:, 3]))
+            assert abs(dev.mean()) < 4 * dev.std() / math.sqrt(len(r)) + 0.5, (z, n, dev.mean())
+            rel = r[:, 5] / n
+            assert np.isfinite(rel).all()
+            assert abs(rel.mean() - 1.0) < 4 * rel.std() / math.sqrt(len(r)) + 0.02, (z, n, rel.mean())
+            assert (r[:, 6] == 0).all()          # no SAT / NEG / SUPER flag at these sizes (theta 1024)
+
+
+def test_eq4_unseen_hosts_estimate_zero_and_flag_negatives(oracle_lib):
+    """A host never seen has n = 0; at heavy load its NAT counts only
+    false-active positions, so Eq 4 is zero on average and negative whenever
+    NAT < g * UP, which then carries AT_F_NEG (reading of the undefined edge)."""
+    from ._scenarios import LOADED, loaded_frames, unseen_hosts
+    g = 1 << LOADED["log2g"]
+    o = oracle_lib.Oracle(**LOADED, seed=7)
+    aip, bip, *_ = loaded_frames(o, 3)
+    o.ingest(aip, bip)
+    o.close(1)
+    hosts = unseen_hosts(o, 3)
+    assert hosts.size == 2000 and not np.isin(hosts, aip).any()
+    est, fl, nat = o.estimate(hosts)
+    up = float(np.prod(o.aat()[:o.r].astype(np.float64) / (g << o.c)))
+    sd = math.sqrt(g * up / (1 - up))
+    assert abs(est.mean()) < 4 * sd / math.sqrt(hosts.size) + 1.0
+    neg = (fl & oracle_lib.F_NEG) != 0
+    assert 0.3 < neg.mean() < 0.7
+    assert np.array_equal(neg, est < 0)
+    assert not (fl & oracle_lib.F_SAT).any()
+
+
+def test_eq4_saturated_host_is_clamped_to_g_minus_one(oracle_lib):
+    """A host whose every AT position is active (NAT = g) makes Eq 4's
+    logarithm infinite; it is estimated as if NAT were g - 1 and flagged
+    AT_F_SAT.  A second host of the same frame with exactly g - 1 active
+    positions must get the same estimate without the flag."""
+    from ._scenarios import CLAMP, clamp_hosts
+    o = oracle_lib.Oracle(**CLAMP, seed=4)
+    aip, bip, h_all, h_most, _ = clamp_hosts(o)
+    o.ingest(aip, bip)
+    o.close(CLAMP["k"])
+    est, fl, nat = o.estimate(np.array([h_all, h_most], np.uint32))
+    g = 1 << CLAMP["log2g"]
+    assert nat.tolist() == [g, g - 1]
+    assert fl[0] & oracle_lib.F_SAT and not fl[1] & oracle_lib.F_SAT
+    assert np.isfinite(est).all() and est[0] == est[1] and est[0] > 0
+
+
+def test_eq4_full_frame_gives_infinity(oracle_lib):
+    """When every AT of every row of the frame is active, P_j = 1 for all rows,
+    UP = 1 and Eq 4's denominator g * (1 - UP) is zero: +inf with AT_F_SAT."""
+    from ._scenarios import FULL, full_frame
+    o = oracle_lib.Oracle(**FULL, seed=2)
+    aip, bip, probe = full_frame()
+    o.ingest(aip, bip)
+    o.close(FULL["k"])
+    g = 1 << FULL["log2g"]
+    assert (o.pool() < 2 * FULL["k"]).all()          # every AT set in this slice
+    assert (o.aat() == g << FULL["c"]).all()
+    est, fl, nat = o.estimate(probe)
+    assert np.isinf(est).all() and (est > 0).all()
+    assert ((fl & oracle_lib.F_SAT) != 0).all() and ((fl & oracle_lib.F_SUPER) != 0).all()
+    assert (nat == g).all()
+
+
+# --------------------------------------------------------------------------
+# Features of the learned correction against exact per-pair timestamps
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k,log2g", [(5, 6), (12, 5), (3, 7)])
+def test_features_age_histogram_matches_exact_timestamps(oracle_lib, k, log2g):
+    """e_i = the largest age over a host's r ATs at position i when all r were
+    set within the last k slices: with 64-bit exact timestamps of every AT
+    (last slice in which some pair touched it) the histogram of e_i over
+    positions must equal feat[d] * g, its prefix sums NAT(k') of Alg 5 for
+    every k' <= k, feat[62] = k/64, feat[63] the mean P_j of the frame and
+    feat[61] the clipped log of the plain estimate."""
+    o = oracle_lib.Oracle(k=k, r=4, c=8, s=8, u=1, log2g=log2g, seed=30 + k)
+    g, ncol = o.g, 1 << o.c
+    ts = np.full(o.pool_size, -(10**9), np.int64)
+    rng = np.random.default_rng(k)
+    hosts = rng.integers(0, 2**32, 8, dtype=np.uint64).astype(np.uint32)
+    # background hosts share the targets' ATVs, so a position's r ATs are set
+    # in different slices and the largest age differs from the others
+    bg = rng.integers(0, 2**32, 3000, dtype=np.uint64).astype(np.uint32)
+    T = 3 * k + 4
+    for t in range(T):
+        n = 0 if t % 5 == 4 else int(rng.integers(20, 4 * g))
+        if n:
+            aip = np.concatenate([hosts[rng.integers(0, hosts.size, n)], bg[rng.integers(0, bg.size, 8 * n)]])
+            bip = rng.integers(0, 2**32, aip.size, dtype=np.uint64).astype(np.uint32)
+            o.ingest(aip, bip)
+            for atv, i in _positions(o, aip, bip):
+                ts[atv * g + i] = t
+        o.close(k)
+    t = T - 1
+    feat = o.features(hosts)
+    est, _, _ = o.estimate(hosts)
+    aat = o.aat().astype(np.float64) / (g * ncol)
+    for q, a in enumerate(hosts.tolist()):
+        z, x = o.rrh(a)
+        rows = [(z * o.r + j) * ncol + int(x[j]) for j in range(o.r)]
+        last = np.stack([ts[rw * g:(rw + 1) * g] for rw in rows])      # r x g last-set slices
+        ages = t - last
+        live = (ages < k).all(axis=0)
+        e = ages.max(axis=0)[live]
+        hist = np.bincount(e, minlength=k)[:k]
+        assert np.array_equal((feat[q, :min(k, 61)] * g).astype(np.int64), hist[:61]), (a, hist)
+        assert (feat[q, min(k, 61):61] == 0).all()
+        assert feat[q, 62] == np.float32(k / 64)
+        assert feat[q, 63] == np.float32(aat[z * o.r:(z + 1) * o.r].sum() / o.r)
+        lp = min(math.log1p(max(float(est[q]), 0.0)), 20.0) / 16
+        assert abs(float(feat[q, 61]) - lp) <= 1e-6 * max(lp, 1e-30) + 1e-7
+    for kp in range(1, k + 1):
+        o.requery(kp)
+        _, _, nat = o.estimate(hosts)
+        pref = np.rint(feat[:, :kp].astype(np.float64) * g).sum(axis=1)
+        assert np.array_equal(pref.astype(np.int64), nat.astype(np.int64)), kp
