@@ -1,15 +1,24 @@
-"""Throughput and slice-close latency of the ATVC hot path on one MI355X.
+"""Throughput, slice-close latency and accuracy of the ATVC hot path on one MI355X.
 
-One step = one pass of the whole path over the realistic-link workload:
-10 slices of 5M (aip, bip) pairs (50M pairs), k = 10, a 2^26-AT pool
-(c=9, s=7, u=3, g=4096).  Per slice: open + scan (at_ingest_slice), close
-(at_close_slice), restore (at_restore) and the estimates of the window's true
-super points (at_estimate).  Inputs are resident in HBM before timing starts.
+Headline (the large configuration): four links served together, each 200M
+(aip, bip) pairs in 60 slices of 3,333,333, k = 60 (7-bit ATs in bytes), a
+2^28-AT pool per link ((c, s, u, g) = (10, 6, 4, 4096), r = 4; 1 GiB of
+pools), aip Zipf 1.1 over 2^24 hosts, uniform 32-bit bips, 661 planted hosts
+log-uniform over [1024, 2^20], seeds 0-3, with the learned correction and the
+streaming server on.  One step = one pass of every link over its 60 slices:
+per slice and link the server scans the pairs (open + lazy preserve + scan),
+closes the slice (window weights, AAT, super lists), runs the restore, the
+plain estimates of the window's true super points and the learned
+correction.  Inputs are resident in HBM before timing starts; the producer
+keeps at most two slices per link in flight.
 
-Prints one JSON line.  `value` is pairs per second over whole steps (Mpps);
-the ingest-only rate, slice-close latency p50/p99, the mean relative error of
-the plain estimator over the true super points, the roofline of the dominant
-kernel (the fused pair scan) and the single-core oracle baseline ride along.
+Prints one JSON line: `value` is pairs per second over whole steps (Mpps),
+with slice-close latency p50/p99/max, the mean relative error of the plain
+and learned estimates over the true super points, the roofline of the
+dominant kernel (the tiled scan launches), per-step wall times and the
+single-core oracle baseline.  The realistic-link configuration, the 16-link
+serving shape, a restore-list workload and the probes ride along as extra
+keys.
 """
 from __future__ import annotations
 
@@ -27,9 +36,14 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 LINK = dict(k=10, r=4, c=9, s=7, u=3, log2g=12, theta=1024.0, seed=0)
-WORKLOAD = ("link: 50M pairs in 10 slices of 5M, aip Zipf 1.2 over 2^22 hosts, bips from 2^26 values, "
-            "30% repeats, 371 planted log-uniform [1024, 2^18]; k=10, 2^26-AT pool (c=9,s=7,u=3,g=4096,r=4), "
-            "theta=1024")
+LINK_WORKLOAD = ("link: 50M pairs in 10 slices of 5M, aip Zipf 1.2 over 2^22 hosts, bips from 2^26 values, "
+                 "30% repeats, 371 planted log-uniform [1024, 2^18]; k=10, 2^26-AT pool (c=9,s=7,u=3,g=4096,r=4), "
+                 "theta=1024")
+LARGE = dict(k=60, r=4, c=10, s=6, u=4, log2g=12, theta=1024.0)
+LARGE_LINKS, LARGE_SLICES, LARGE_PAIRS = 4, 60, 3_333_333
+LARGE_WORKLOAD = ("large: 4 served links, each 200M pairs in 60 slices of 3,333,333, aip Zipf 1.1 over 2^24 hosts, "
+                  "uniform 32-bit bips, 661 planted log-uniform [1024, 2^20], seeds 0-3; k=60, 2^28-AT pool per link "
+                  "(c=10,s=6,u=4,g=4096,r=4; 1 GiB in all), theta=1024, learned correction and streaming server on")
 
 
 def log(msg: str):
@@ -252,12 +266,12 @@ def paper_scale(slices: int, seed: int = 0) -> dict:
     }
 
 
-def measured_traffic():
-    """HBM bytes per scan launch from the committed counter runs, or None when
-    the kernel source has changed since they were taken."""
+def measured_traffic(profile: str):
+    """HBM bytes per launch from a committed counter summary, or None when the
+    kernel source has changed since the counters were taken."""
     import hashlib
     try:
-        with open(os.path.join(ROOT, "profiles", "ingest_link_pmc.json")) as fh:
+        with open(os.path.join(ROOT, "profiles", profile)) as fh:
             rec = json.load(fh)
         with open(os.path.join(ROOT, "paper_1807_01527_amd", "csrc", "kernels.hip"), "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
@@ -268,102 +282,189 @@ def measured_traffic():
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(tr, truth_hosts, budget_s: float = 15.0) -> dict:
-    """The oracle as it stands, single-threaded on a host core, over the
-    slices of the same trace (passing over them again while the window keeps
-    sliding) until about budget_s of work is done."""
-    from oracle import oracle
-    o = oracle.Oracle(**LINK)
-    t0 = time.perf_counter()
-    pairs = 0
-    closes = []
-    n = 0
-    while time.perf_counter() - t0 <= budget_s and n < 4 * tr.n_slices:
-        t = n % tr.n_slices
-        o.ingest(tr.aip[t], tr.bip[t])
-        pairs += tr.aip[t].size
-        c0 = time.perf_counter()
-        o.close(LINK["k"])
-        o.estimate(truth_hosts)
-        closes.append(time.perf_counter() - c0)
-        n += 1
-    el = time.perf_counter() - t0
-    return {"value": pairs / el / 1e6, "unit": "Mpps", "cores": 1, "kind": "oracle",
-            "sample": f"{n} slices of the {tr.n_slices}-slice trace, in order and again ({pairs} pairs): eager "
-                      f"preserve + scan + close + estimate of the {truth_hosts.size} true super points, single thread",
-            "slice_close_ms_mean": 1e3 * float(np.mean(closes)), "seconds": el}
+def pct(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--slices", type=int, default=10)
-    ap.add_argument("--pairs", type=int, default=5_000_000)
-    ap.add_argument("--no-serve", action="store_true", help="skip the streaming-server phase")
-    ap.add_argument("--scatter-sweep", action="store_true",
-                    help="only sweep the random byte-store probe over buffer sizes (1 MiB .. 1 GiB) and exit")
-    ap.add_argument("--paper-scale", type=int, default=0, metavar="SLICES",
-                    help="only run the k=300, 2^32-AT sliding shape over SLICES slices (3600 for 3300 windows) "
-                         "and exit")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain 256 MiB device copy (calibrates the HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus above 1 is not supported"}))
-        sys.exit(2)
-    if args.warmup < 1:
-        args.warmup = 1  # the first pass fills the window; measured windows hold all slices
+# --------------------------------------------------------------- large config
+def large_workload(dev):
+    """Per link (seeds 0-3): device pair streams of the 60 slices and the true
+    super points of the full window (exact distinct counts >= theta)."""
+    from paper_1807_01527_amd import learned
+    from paper_1807_01527_amd import traffic_gpu as tg
+    wl = []
+    for seed in range(LARGE_LINKS):
+        a, b, planted = tg.link_stream(seed, LARGE_SLICES * LARGE_PAIRS, dev, **learned.LARGE_STREAM)
+        hosts, counts = learned.exact_counts(a, b)
+        m = counts >= LARGE["theta"]
+        wl.append(dict(a=a, b=b, planted=planted, truth_h=hosts[m], truth_n=counts[m]))
+    return wl
+
+
+def headline(args, dev, wl, mlp) -> dict:
+    import ctypes as C
+    import gc
+
+    from paper_1807_01527_amd.binding import Server
+    shape = {k: v for k, v in LARGE.items() if k != "k"}
+    K = LARGE["k"]
+    pool_bytes = (1 << (LARGE["c"] + LARGE["u"])) * LARGE["r"] * (1 << LARGE["log2g"])
+    watch_cap = 16384
+    srv = Server(hbm_budget=LARGE_LINKS * (pool_bytes + (64 << 20)), max_links=LARGE_LINKS, cand_cap=2048,
+                 watch_cap=watch_cap, **shape)
+    if mlp is not None:
+        srv.set_mlp(mlp)
+    ids = []
+    for li, w in enumerate(wl):
+        # tuple budget 2^24: at this load every ATV is super, so a restore
+        # answers AT_E_BUDGET with U instead of enumerating column tuples
+        lid, adm = srv.open_link(K, li, tuple_budget=1 << 24)
+        assert adm, "the four pools fit the budget"
+        srv.set_watch(lid, w["truth_h"][:watch_cap])
+        ids.append(lid)
+    P = LARGE_PAIRS
+    ptrs = [[(w["a"][t * P:].data_ptr(), w["b"][t * P:].data_ptr()) for t in range(LARGE_SLICES)] for w in wl]
+    lib, h = srv.lib, srv.h
+    got = {lid: [] for lid in ids}
+
+    def drain():
+        for r in srv.results():
+            got[r["link"]].append(r)
+
+    def run_pass():
+        # per link, slice t is queued (its pairs and its end in one call) once
+        # slice t-2 has its result: at most two slices of a link in flight
+        base = {lid: len(got[lid]) for lid in ids}
+        nxt = [0] * len(ids)
+        while True:
+            moved = False
+            for li, lid in enumerate(ids):
+                t = nxt[li]
+                if t < LARGE_SLICES and t - (len(got[lid]) - base[lid]) < 2:
+                    pa, pb = ptrs[li][t]
+                    rc = lib.at_serve_submit_last(h, lid, C.c_void_p(pa), C.c_void_p(pb), P, K)
+                    assert rc == 0, rc
+                    nxt[li] += 1
+                    moved = True
+            if all(len(got[lid]) - base[lid] >= LARGE_SLICES for lid in ids):
+                return
+            if not moved:
+                drain()
+
+    srv.start()
+    for _ in range(args.warmup):
+        run_pass()
+    warm = {lid: len(got[lid]) for lid in ids}
+    t_calls0 = srv.tiled_stats()
+    gc.collect()
+    gc.disable()
+    step_ms = []
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        s0 = time.perf_counter()
+        run_pass()
+        step_ms.append(1e3 * (time.perf_counter() - s0))
+    elapsed = time.perf_counter() - t_start
+    gc.enable()
+    for s in range(args.steps):
+        log(f"large step {s + 1}/{args.steps}: {step_ms[s]:.2f} ms")
+    srv.stop()
+    drain()
+    t_calls1 = srv.tiled_stats()
+    st = srv.stats()
+    srv.destroy()
+    timed = [r for lid in ids for r in got[lid][warm[lid]:]]
+    lat = [r["latency_ms"] for r in timed]
+    rcs = {}
+    for r in timed:
+        rcs[str(r["restore_rc"])] = rcs.get(str(r["restore_rc"]), 0) + 1
+    # accuracy over the true super points of the full window (last close)
+    rel_p, rel_l, fb, nw = [], [], 0, 0
+    for li, lid in enumerate(ids):
+        last = got[lid][-1]
+        n = wl[li]["truth_n"][:watch_cap].astype(np.float64)
+        rel_p.append(np.abs(last["watch_plain"] - n) / n)
+        rel_l.append(np.abs(last["watch_learned"] - n) / n)
+        fb += int(np.count_nonzero(last["watch_flags"] & 4))
+        nw += n.size
+    truth_total = int(sum(w["truth_h"].size for w in wl))
+    pairs = LARGE_LINKS * LARGE_SLICES * LARGE_PAIRS * args.steps
+    calls = t_calls1["calls"] - t_calls0["calls"]
+    tpairs = t_calls1["pairs"] - t_calls0["pairs"]
+    tms = t_calls1["device_ms"] - t_calls0["device_ms"]
+    return dict(
+        value=pairs / elapsed / 1e6, elapsed=elapsed, pairs=pairs, step_ms=step_ms,
+        slice_close_ms={"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat), "closes": len(lat),
+                        "includes": "from the call that queues a slice's last pairs and its end to its result on "
+                                    "the host: the scan of those pairs, the close, the restore (AT_E_BUDGET at "
+                                    "this load), plain and learned estimates of the window's true super points"},
+        restore_rc_counts=rcs,
+        mean_rel_err={"plain": float(np.mean(np.concatenate(rel_p))),
+                      "learned": float(np.mean(np.concatenate(rel_l))) if mlp is not None else None,
+                      "hosts": nw, "fallbacks": fb, "true_super_points": truth_total,
+                      "over": "true super points of each link's full window (exact distinct count >= 1024), "
+                              "at its last close"},
+        tiled={"launches": calls, "pairs": tpairs, "device_ms": tms, "steps": st["steps"]},
+        pool_bytes=pool_bytes, n_atv=pool_bytes >> LARGE["log2g"])
+
+
+def probe_rate(dev, bytes_: int, a, b, n: int, r: int = 4, reps: int = 5) -> dict:
+    """Uniform random byte stores (r per item) into a buffer of `bytes_`."""
+    import torch
+
+    from paper_1807_01527_amd.binding import probe_scatter
+    stream = torch.cuda.current_stream()
+    buf = torch.empty(bytes_, dtype=torch.uint8, device=dev)
+    for _ in range(2):
+        probe_scatter(buf, a, b, n, r, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        probe_scatter(buf, a, b, n, r, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del buf
+    return {"buffer_bytes": bytes_, "items": n, "r": r, "avg_launch_ms": ms, "mpps": n / ms / 1e3,
+            "stores_per_s": r * n / (ms / 1e3)}
+
+
+# ----------------------------------------------------------- realistic link
+def link_config2(args, dev, learned, Mlp) -> dict:
+    """The realistic-link configuration through the single-link API (one
+    tiled call per slice that opens it, fused window count)."""
+    import gc
 
     import torch
 
-    if args.scatter_sweep:
-        scatter_sweep()
-        return
-    if args.paper_scale:
-        print(json.dumps({"paper_scale": paper_scale(args.paper_scale)}), flush=True)
-        return
-
     from paper_1807_01527_amd import traffic
-    from paper_1807_01527_amd import learned
-    from paper_1807_01527_amd.binding import AtPool, Mlp, probe_ace_age, probe_scatter
-
+    from paper_1807_01527_amd.binding import AtPool, probe_ace_age, probe_scatter
     t0 = time.perf_counter()
     tr = traffic.generate(traffic.config_link(seed=0, n_slices=args.slices, pairs_per_slice=args.pairs))
     truth_h, truth_n = traffic.window_counts(tr.aip, tr.bip, min_count=int(LINK["theta"]))
-    log(f"trace ready in {time.perf_counter() - t0:.1f}s: {tr.cfg.total_pairs} pairs, "
+    log(f"link trace ready in {time.perf_counter() - t0:.1f}s: {tr.cfg.total_pairs} pairs, "
         f"{truth_h.size} true super points")
-
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
     aip_d = [torch.from_numpy(a.view(np.int32)).to(dev) for a in tr.aip]
     bip_d = [torch.from_numpy(b.view(np.int32)).to(dev) for b in tr.bip]
     stream = torch.cuda.current_stream()
     pool = AtPool(**LINK, stream=stream)
     weights = learned.load_weights("link")
     mlp = Mlp(weights) if weights is not None else None
-    S = tr.n_slices
-    K = LINK["k"]
-    cap = 1 << 20
+    S, K, cap = tr.n_slices, LINK["k"], 1 << 20
 
     def step(record):
-        ev = []
-        lat = []
+        ev, lat = [], []
         last = None
 
         def ingest(t):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            pool.ingest(aip_d[t], bip_d[t])    # opens the slice (lazy preserve) and scans its pairs
+            pool.ingest(aip_d[t], bip_d[t])
             e1.record(stream)
             ev.append((e0, e1))
 
-        # Slice t's queries are queued, then slice t+1's pairs behind them, and
-        # only then does the host wait for t's results: the device never idles
-        # while the host copies results out.
         ingest(0)
         for t in range(S):
             c0 = time.perf_counter()
@@ -372,12 +473,12 @@ def main():
                 pool.estimate_learned_begin(mlp, truth_h)
             rc, sip, est, fl, m = pool.restore(cap=cap)
             if mlp is None:
-                e_plain, f_plain = pool.estimate_plain(truth_h)
+                e_plain, _ = pool.estimate_plain(truth_h)
                 e_learn = None
             if t + 1 < S:
                 ingest(t + 1)
             if mlp is not None:
-                e_learn, f_learn, e_plain = pool.estimate_learned_end()
+                e_learn, _, e_plain = pool.estimate_learned_end()
             lat.append(time.perf_counter() - c0)
             last = (rc, m, e_plain, e_learn)
         if record is not None:
@@ -386,23 +487,21 @@ def main():
             record["close_ms"].extend(1e3 * x for x in lat)
             record["last"] = last
 
-    for _ in range(args.warmup):
+    for _ in range(max(1, args.link_warmup)):
         step(None)
     torch.cuda.synchronize()
     rec = {"ingest_ms": [], "close_ms": [], "last": None}
-    torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
     step_ms = []
     t_start = time.perf_counter()
-    for s in range(args.steps):
+    for s in range(args.link_steps):
         s0 = time.perf_counter()
         step(rec)
         step_ms.append(1e3 * (time.perf_counter() - s0))
-        log(f"step {s + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-
-    total_pairs = tr.cfg.total_pairs * args.steps
-    ms_step = 1e3 * elapsed / args.steps
+    gc.enable()
     ingest_ms = np.array(rec["ingest_ms"])
     close_ms = np.array(rec["close_ms"])
     rc, m, e_plain, e_learn = rec["last"]
@@ -410,58 +509,28 @@ def main():
     rel_l = np.abs(e_learn - truth_n) / truth_n if e_learn is not None else None
     per_launch = args.pairs
     avg_ingest_s = float(ingest_ms.mean()) / 1e3
-    # at_ingest_slice's automatic choice (the rule stated with at_set_scan_mode)
-    tiles = pool.pool_bytes % 65536 == 0 and pool.pool_bytes // 65536 <= 4096
-    tiled = tiles and per_launch * LINK["r"] * 12 >= pool.pool_bytes
-    # algorithmic bytes of one call: 8 B read + r B of AT state written per
-    # pair; a tiled call that opens the slice (the step's only call) also does
-    # the window count of the close: one read of the pool, 4 B per ATV written
     alg_pairs = (8 + LINK["r"]) * per_launch
-    alg_count = pool.pool_bytes + 4 * pool.n_atv if tiled and per_launch <= (8 << 20) else 0
+    alg_count = pool.pool_bytes + 4 * pool.n_atv
     achieved = (alg_pairs + alg_count) / avg_ingest_s / 1e9
-    if tiled:
-        scan_kernels = ("k_tile_count + k_tile_chunksum + k_tile_scan + k_tile_rowpre + k_tile_scatter + k_tile_apply "
-                        "(tiled scan: AT stores grouped per 64 KiB tile, applied in LDS; the opening preserve and the "
-                        "close's window count run in k_tile_apply)")
-    elif LINK["u"] >= 3 and pool.pool_bytes >= (32 << 20) and per_launch >= 65536:
-        scan_kernels = "k_bin_pairs + k_scan_bins (binned scan: XCD-local frame bins, then the r byte stores)"
-    else:
-        scan_kernels = "k_ingest (fused pair hash + r byte scatter)"
     out = {
-        "metric": "Mpps ingested + slice-close p99 ms; mean rel. error plain vs learned at θ=1024",
-        "value": total_pairs / elapsed / 1e6,
-        "unit": "Mpps",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u8",
-        "data": "synthetic",
-        "config": {"workload": WORKLOAD, "slices": S, "pairs_per_slice": args.pairs, "k": K,
-                   "pool_ats": pool.pool_bytes, "parallelism": "single GPU"},
-        "step_ms": {"min": min(step_ms), "median": float(np.median(step_ms)), "max": max(step_ms),
-                    "all": [round(x, 3) for x in step_ms]},
+        "workload": LINK_WORKLOAD, "value_mpps": tr.cfg.total_pairs * args.link_steps / elapsed / 1e6,
+        "ms_per_step": 1e3 * elapsed / args.link_steps, "steps": args.link_steps,
+        "step_ms": {"min": min(step_ms), "median": float(np.median(step_ms)), "max": max(step_ms)},
         "ingest_mpps": per_launch / avg_ingest_s / 1e6,
-        "slice_close_ms": {"p50": float(np.percentile(close_ms, 50)), "p99": float(np.percentile(close_ms, 99)),
-                           "includes": "close + restore + plain and learned estimates of the true super points, "
-                                       "host wall clock from the close call to the estimates on the host (the next "
-                                       "slice's ingest is queued meanwhile)"},
-        "restore": {"rc": int(rc), "n_out": int(m), "note": "AT_E_BUDGET (-6) at this load: every ATV is super"},
+        "slice_close_ms": {"p50": pct(close_ms, 50), "p99": pct(close_ms, 99), "max": float(close_ms.max()),
+                           "includes": "close + restore tuple count (AT_E_BUDGET at this load) + plain and learned "
+                                       "estimates of the true super points, host wall clock"},
+        "restore": {"rc": int(rc), "n_out": int(m)},
         "mean_rel_err": {"plain": float(rel.mean()), "learned": float(rel_l.mean()) if rel_l is not None else None,
-                         "hosts": int(truth_h.size),
-                         "over": "true super points of the window (exact distinct count >= 1024)"},
-        "roofline": {"kernel": scan_kernels, "bound": "hbm",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(), "traffic_of": "the scan kernels of one call, rocprofv3 "
-                                                                  "FETCH_SIZE x2 + WRITE_SIZE x1 (copy-calibrated)",
-                     "bytes_per_pair": 8 + LINK["r"],
+                         "hosts": int(truth_h.size)},
+        "roofline": {"kernel": "k_tile_count + k_tile_chunksum + k_tile_scan + k_tile_rowpre + k_tile_scatter + "
+                               "k_tile_apply (one at_ingest_slice call that opens the slice)",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("ingest_link_pmc.json"),
                      "algorithmic_bytes_per_launch": {"pairs": alg_pairs, "window_count": alg_count},
                      "avg_launch_ms": float(ingest_ms.mean()), "pairs_per_launch": per_launch},
     }
-    # the two scans of at_ingest_slice on the same slices (one pass each)
+    # the three scans of at_ingest_slice on the same slices
     modes = {}
     for mode, name in ((1, "direct"), (2, "binned"), (3, "tiled")):
         pool.set_scan_mode(mode)
@@ -480,31 +549,11 @@ def main():
         modes[name] = {"avg_ms": ms, "mpps": per_launch / (ms / 1e3) / 1e6}
     pool.set_scan_mode(0)
     out["scan_modes"] = modes
-    # scatter roofline: the same input stream and r byte stores per pair at
-    # uniformly random positions of a pool-sized buffer
-    probe_buf = torch.empty(pool.pool_bytes, dtype=torch.uint8, device=dev)
-    pr = []
-    for rep in range(2):
-        for t in range(S):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            probe_scatter(probe_buf, aip_d[t], bip_d[t], args.pairs, LINK["r"], stream=stream)
-            e1.record(stream)
-            if rep:
-                pr.append((e0, e1))
-    torch.cuda.synchronize()
-    probe_ms = float(np.mean([a.elapsed_time(b) for a, b in pr]))
-    del probe_buf
-    out["scatter_probe"] = {
-        "what": "uniform random byte stores, r per pair, into a buffer of the pool's size, same input stream",
-        "mpps": per_launch / (probe_ms / 1e3) / 1e6, "avg_launch_ms": probe_ms,
-        "stores_per_s": LINK["r"] * per_launch / (probe_ms / 1e3),
-        "ingest_frac_of_probe": (per_launch / avg_ingest_s) / (per_launch / (probe_ms / 1e3)),
-    }
-    # the paper's comparison of slice maintenance: aging counters (ACE) rewrite
-    # the whole pool at every slice end, asynchronous timestamps preserve two
-    # blocks of every ATV (measured on the opening call of each slice)
+    pr = probe_rate(dev, pool.pool_bytes, aip_d[0], bip_d[0], args.pairs)
+    out["scatter_probe"] = {**pr, "what": "uniform random byte stores, r per pair, into a buffer of the pool's size",
+                            "ingest_frac_of_probe": (per_launch / avg_ingest_s) / (pr["mpps"] * 1e6)}
+    # slice maintenance: the lazy preserve kernel alone (an opening call with
+    # no pairs launches only k_preserve) against one aging pass of ACE counters
     ace_buf = torch.full((pool.pool_bytes,), 7, dtype=torch.uint8, device=dev)
     pres, ages = [], []
     for t in range(S):
@@ -524,8 +573,214 @@ def main():
     am = float(np.mean([a.elapsed_time(b) for a, b in ages]))
     del ace_buf
     out["slice_maintenance"] = {"at_lazy_preserve_ms": pm, "ace_aging_ms": am, "ratio": am / pm,
-                                "note": f"per slice, {pool.pool_bytes >> 20} MiB pool, k={K}: the timestamps touch "
-                                        f"2 of 2k blocks per ATV, the aging counters all of them"}
+                                "note": f"event-timed single launches on a {pool.pool_bytes >> 20} MiB pool, k={K}: "
+                                        "the timestamps touch 2 of 2k blocks per ATV, the aging counters all of "
+                                        "them; kernel-only times are in the rocprofv3 summary"}
+    pool.destroy()
+    if mlp is not None:
+        mlp.destroy()
+    return out, tr, truth_h
+
+
+def restore_lists(dev) -> dict:
+    """Slice-close latency where the restore returns candidate lists: the small
+    configuration's traffic in the (9, 7, 3, 4096) geometry at paper-like load
+    (k = 4, a 2^26-AT pool), closes with restore and the candidates' estimates."""
+    import torch
+
+    from paper_1807_01527_amd import traffic
+    from paper_1807_01527_amd.binding import AtPool
+    tr = traffic.generate(traffic.config_small(seed=0))
+    params = dict(k=4, r=4, c=9, s=7, u=3, log2g=12, theta=1024.0, seed=0)
+    pool = AtPool(**params)
+    aip_d = [torch.from_numpy(a.view(np.int32)).to(dev) for a in tr.aip]
+    bip_d = [torch.from_numpy(b.view(np.int32)).to(dev) for b in tr.bip]
+    lat, m_out, rcs = [], [], {}
+    for rep in range(12):
+        for t in range(tr.n_slices):
+            pool.ingest(aip_d[t], bip_d[t])
+            torch.cuda.synchronize()
+            c0 = time.perf_counter()
+            pool.close(4)
+            rc, sip, est, fl, m = pool.restore(cap=1 << 20)
+            el = 1e3 * (time.perf_counter() - c0)
+            if rep >= 2:
+                lat.append(el)
+                m_out.append(m)
+                rcs[str(rc)] = rcs.get(str(rc), 0) + 1
+    pool.destroy()
+    return {"workload": "small configuration traffic (4 x 250k pairs, 32 planted) in the (9,7,3,4096) geometry, k=4, "
+                        "2^26-AT pool", "closes": len(lat), "restore_rc_counts": rcs,
+            "candidates_mean": float(np.mean(m_out)),
+            "slice_close_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat),
+                               "includes": "close + restore join and sort + estimates of every candidate, host "
+                                           "wall clock, the slice's pairs already scanned"}}
+
+
+def host_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def cpu_baseline_large(wl, budget_s: float = 20.0) -> dict:
+    """The oracle as it stands, single-threaded and pinned to one host core,
+    on the first slices of link 0 of the large configuration: eager preserve,
+    scan, close and the estimates of the window's true super points, until
+    about budget_s of work is done."""
+    from oracle import oracle
+    info = host_info()
+    cpu = sorted(os.sched_getaffinity(0))[0]
+    old = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {cpu})
+    try:
+        w = wl[0]
+        o = oracle.Oracle(**LARGE, seed=0, tuple_budget=1 << 24)
+        hosts = np.ascontiguousarray(w["truth_h"])
+        P = LARGE_PAIRS
+        work, pairs, closes, n = 0.0, 0, [], 0
+        while work <= budget_s and n < LARGE_SLICES:
+            a = w["a"][n * P:(n + 1) * P].cpu().numpy().view(np.uint32)   # host copies: not oracle work
+            b = w["b"][n * P:(n + 1) * P].cpu().numpy().view(np.uint32)
+            s0 = time.perf_counter()
+            o.ingest(a, b)
+            c0 = time.perf_counter()
+            o.close(LARGE["k"])
+            o.tuple_count()
+            o.estimate(hosts)
+            c1 = time.perf_counter()
+            closes.append(c1 - c0)
+            work += c1 - s0
+            pairs += a.size
+            n += 1
+        o.close_handle()
+    finally:
+        os.sched_setaffinity(0, old)
+    return work, pairs, closes, n, info, cpu
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline (large configuration)")
+    ap.add_argument("--slices", type=int, default=10)
+    ap.add_argument("--pairs", type=int, default=5_000_000)
+    ap.add_argument("--link-steps", type=int, default=20)
+    ap.add_argument("--link-warmup", type=int, default=3)
+    ap.add_argument("--scatter-sweep", action="store_true",
+                    help="only sweep the random byte-store probe over buffer sizes (1 MiB .. 1 GiB) and exit")
+    ap.add_argument("--paper-scale", type=int, default=0, metavar="SLICES",
+                    help="only run the k=300, 2^32-AT sliding shape over SLICES slices (3600 for 3300 windows) "
+                         "and exit")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (calibrates the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only (every box here has one); "
+                                   "--gpus above 1 is not supported"}))
+        sys.exit(2)
+    args.warmup = max(1, args.warmup)  # the first pass fills the window: measured windows hold all 60 slices
+
+    import torch
+
+    if args.scatter_sweep:
+        scatter_sweep()
+        return
+    if args.paper_scale:
+        print(json.dumps({"paper_scale": paper_scale(args.paper_scale)}), flush=True)
+        return
+
+    from paper_1807_01527_amd import learned
+    from paper_1807_01527_amd.binding import Mlp
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    wl = large_workload(dev)
+    torch.cuda.synchronize()
+    log(f"large workload ready in {time.perf_counter() - t0:.1f}s: {LARGE_LINKS} x {LARGE_SLICES * LARGE_PAIRS} "
+        f"pairs, {[w['truth_h'].size for w in wl]} true super points")
+    wts = learned.load_weights("large")
+    mlp = Mlp(wts) if wts is not None else None
+    hl = headline(args, dev, wl, mlp)
+    # the dominant kernel: the tiled scan launches of the served links (one per
+    # link and slice; each opens the slice and, its end queued with it, counts
+    # the window's weights)
+    tl = hl["tiled"]
+    launches = max(tl["launches"], 1)
+    avg_ms = tl["device_ms"] / launches
+    ppl = tl["pairs"] / launches
+    alg_pairs = (8 + LARGE["r"]) * ppl
+    alg_count = hl["pool_bytes"] + 4 * hl["n_atv"]
+    achieved = (alg_pairs + alg_count) / (avg_ms / 1e3) / 1e9 if tl["launches"] else 0.0
+    step_ms = hl["step_ms"]
+    out = {
+        "metric": "Mpps ingested + slice-close p99 ms; mean rel. error plain vs learned at θ=1024",
+        "value": hl["value"],
+        "unit": "Mpps",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * hl["elapsed"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": LARGE_WORKLOAD, "links": LARGE_LINKS, "slices": LARGE_SLICES,
+                   "pairs_per_slice": LARGE_PAIRS, "k": LARGE["k"], "pool_ats_per_link": hl["pool_bytes"],
+                   "learned": mlp is not None, "parallelism": "single GPU"},
+        "step_ms": {"min": min(step_ms), "median": float(np.median(step_ms)), "max": max(step_ms),
+                    "all": [round(x, 3) for x in step_ms]},
+        "slice_close_ms": hl["slice_close_ms"],
+        "restore_rc_counts": hl["restore_rc_counts"],
+        "mean_rel_err": hl["mean_rel_err"],
+        "roofline": {"kernel": "tiled scan launch of a served link's slice: k_tile_count + k_tile_chunksum + "
+                               "k_tile_scan + k_tile_rowpre + k_tile_scatter + k_tile_apply (stores grouped per "
+                               "64 KiB tile and applied in LDS; the opening preserve and the window count run in "
+                               "k_tile_apply)",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("ingest_large_pmc.json"),
+                     "traffic_of": "the six kernels of one launch, rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled "
+                                   "by its count for a plain device copy",
+                     "bytes_per_pair": 8 + LARGE["r"],
+                     "algorithmic_bytes_per_launch": {"pairs": alg_pairs, "window_count": alg_count},
+                     "avg_launch_ms": avg_ms, "pairs_per_launch": ppl, "launches_timed": tl["launches"],
+                     "timing": "HIP events around each launch on the server's scan stream"},
+        "tiled_share_of_pairs": tl["pairs"] / hl["pairs"] if hl["pairs"] else None,
+    }
+    # random-store roofline at the headline's total pool size (1 GiB) and at one pool
+    a0 = wl[0]["a"][:LARGE_PAIRS // 4 * 4]
+    b0 = wl[0]["b"][:LARGE_PAIRS // 4 * 4]
+    pr_all = probe_rate(dev, LARGE_LINKS * hl["pool_bytes"], a0, b0, LARGE_PAIRS // 4 * 4)
+    pr_one = probe_rate(dev, hl["pool_bytes"], a0, b0, LARGE_PAIRS // 4 * 4)
+    scan_mpps = ppl / (avg_ms / 1e3) / 1e6 if tl["launches"] else None
+    out["scatter_probe"] = {"what": "uniform random byte stores, 4 per pair of link 0's first slice",
+                            "all_pools_1GiB": pr_all, "one_pool_256MiB": pr_one,
+                            "tiled_scan_mpps": scan_mpps,
+                            "tiled_scan_over_probe_at_1GiB": scan_mpps / pr_all["mpps"] if scan_mpps else None}
+    if not args.no_extras:
+        log("realistic-link configuration ...")
+        link, tr, truth_h = link_config2(args, dev, learned, Mlp)
+        out["link_config"] = link
+        log("streaming-server phase (16 links) ...")
+        smlp = None
+        w_s = learned.load_weights("serve_mix")
+        if w_s is not None:
+            smlp = Mlp(w_s)
+        out["serving_16_links"] = serve_phase(dev, mlp=smlp)
+        log("restore-list latency ...")
+        out["restore_lists"] = restore_lists(dev)
     if args.copy_probe:
         x = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         y = torch.empty_like(x)
@@ -534,20 +789,15 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = {"read": x.numel(), "write": y.numel(), "launches": 3}
         del x, y
-    if not args.no_serve:
-        log("streaming-server phase ...")
-        pool.destroy()
-        del aip_d, bip_d
-        torch.cuda.empty_cache()
-        smlp = None
-        w_small = learned.load_weights("serve")
-        if w_small is not None:
-            smlp = Mlp(w_small)
-        out["serving"] = serve_phase(dev, mlp=smlp)
     if not args.no_cpu_baseline:
-        log("timing the oracle on the host ...")
-        out["cpu_baseline"] = cpu_baseline(tr, truth_h)
-    pool.destroy()
+        log("timing the oracle on one host core ...")
+        el, pairs, closes, n, info, cpu = cpu_baseline_large(wl)
+        out["cpu_baseline"] = {"value": pairs / el / 1e6, "unit": "Mpps", "cores": 1, "kind": "oracle",
+                               "sample": f"the first {n} slices of link 0 of the large configuration ({pairs} "
+                                         f"pairs): eager preserve + scan + close + estimates of its "
+                                         f"{wl[0]['truth_h'].size} true super points, single thread pinned to "
+                                         f"CPU {cpu}",
+                               "slice_close_ms_mean": 1e3 * float(np.mean(closes)), "seconds": el, **info}
     print(json.dumps(out), flush=True)
 
 

@@ -218,6 +218,7 @@ int at_tuple_count(at_ctx *h, uint64_t *U);
  * Batches of up to 8M pairs at a time.  AT_E_INVAL for another mode. */
 int at_set_scan_mode(at_ctx *h, int mode);
 
+
 /* ------------------------------------------------------ learned correction
  * Not in the paper: a small network that corrects the plain estimate from the
  * host's occupancy-by-age profile, with the plain estimate kept as fallback.
@@ -321,7 +322,7 @@ typedef struct {
     uint64_t hbm_budget;   /* bytes of device memory the links may hold       */
     uint32_t max_links;    /* links resident at once, 1..64                    */
     uint32_t cand_cap;     /* restore candidates returned per close, 1..2048   */
-    uint32_t watch_cap;    /* watch hosts per link, 0..4096                    */
+    uint32_t watch_cap;    /* watch hosts per link, 0..16384                   */
     uint32_t r, c, s, u;   /* shared geometry (u <= 8)                         */
     uint32_t log2g;
     double theta;
@@ -364,6 +365,13 @@ int at_serve_submit(at_serve *s, uint32_t link_id, const uint32_t *aip_dev, cons
                     uint64_t n);
 /* Queue the end of the link's current slice with window k' (1 <= k' <= k). */
 int at_serve_end_slice(at_serve *s, uint32_t link_id, uint32_t kprime);
+/* at_serve_submit of the slice's last chunk (n may be 0) and
+ * at_serve_end_slice as one queue operation, so that no step can take the
+ * chunk without its end: a step that scans a whole slice with the tiled scan
+ * then also counts the slice's window weights, and the close reads no pool.
+ * Latency is measured from this call. */
+int at_serve_submit_last(at_serve *s, uint32_t link_id, const uint32_t *aip_dev, const uint32_t *bip_dev,
+                         uint64_t n, uint32_t kprime);
 /* Run one batched step (synchronous); *n_results = slices closed by it. */
 int at_serve_step(at_serve *s, uint32_t *n_results);
 /* Start a native thread that runs steps back to back while any link has
@@ -381,6 +389,14 @@ int at_serve_next_result(at_serve *s, at_serve_result *out, uint32_t *cand, doub
 int at_serve_stats(at_serve *s, uint64_t *out4);
 /* Synchronous copy of an active link's pool to the host. */
 int at_serve_read_pool(at_serve *s, uint32_t link_id, uint8_t *host_out);
+/* Tiled scans run by the server so far: launches (one per link per step,
+ * more when a link's step holds over 8M pairs), the pairs they scanned and
+ * their summed device time in ms (HIP events around each launch on its
+ * stream).  A link's step goes to the tiled scan, instead of the batched
+ * byte-store scan, when its r*n stores times 12 (30 once the resident pools
+ * exceed the 256 MiB last-level cache) reach its pool's bytes and the pool
+ * is whole 64 KiB tiles, at most 4096.  Any pointer may be NULL. */
+int at_serve_tiled_stats(at_serve *s, uint64_t *calls, uint64_t *pairs, double *device_ms);
 
 /* Comparator probe: one aging pass of ACE counters (the sliding-window
  * counters the paper compares asynchronous timestamps against, Section 2.3):

@@ -263,15 +263,27 @@ void oat_destroy(oat *o)
 
 /* Opening slice t: the ACT of every block advances (C0 = t mod 2k) and
  * preserveAT (Alg 2) runs on every AT of the pool. */
+/* ACT of every AT position for the slice whose first block has ACT c0: the
+ * same for every ATV (the blocks are positions within an ATV). */
+static uint32_t *act_table(const oat *o, uint32_t c0)
+{
+    uint32_t *act = (uint32_t *)malloc((size_t)o->g * sizeof(uint32_t));
+    if (act)
+        for (uint32_t i = 0; i < o->g; i++) act[i] = act_of(o, c0, i);
+    return act;
+}
+
 static void open_slice(oat *o)
 {
     uint32_t k = o->p.k;
     o->c0 = (uint32_t)(o->t % (2 * k));
+    uint32_t *act = act_table(o, o->c0);
     for (uint64_t v = 0; v < o->n_atv; v++) {
         uint16_t *atv = o->at + v * o->g;
         for (uint32_t i = 0; i < o->g; i++)
-            atv[i] = (uint16_t)oat_preserve_at(k, act_of(o, o->c0, i), atv[i]);
+            atv[i] = (uint16_t)oat_preserve_at(k, act ? act[i] : act_of(o, o->c0, i), atv[i]);
     }
+    free(act);
     o->open = 1;
     o->queryable = 0;
 }
@@ -303,6 +315,7 @@ int oat_close(oat *o, uint32_t kprime)
     if (kprime < 1 || kprime > o->p.k) return OAT_E_INVAL;
     if (!o->open) open_slice(o);
     memset(o->aat, 0, sizeof(uint64_t) * (size_t)o->nframe * o->p.r);
+    uint32_t *act = act_table(o, o->c0);
     for (uint32_t z = 0; z < o->nframe; z++)
         for (uint32_t j = 0; j < o->p.r; j++)
             for (uint32_t x = 0; x < o->ncol; x++) {
@@ -310,11 +323,12 @@ int oat_close(oat *o, uint32_t kprime)
                 const uint16_t *atv = o->at + v * o->g;
                 uint32_t w = 0;
                 for (uint32_t i = 0; i < o->g; i++)
-                    w += (uint32_t)oat_check_at(o->p.k, act_of(o, o->c0, i), atv[i], kprime);
+                    w += (uint32_t)oat_check_at(o->p.k, act ? act[i] : act_of(o, o->c0, i), atv[i], kprime);
                 o->w[v] = w;
                 o->aat[(uint64_t)z * o->p.r + j] += w;
                 o->super[v] = (w >= o->T);
             }
+    free(act);
     o->c0_query = o->c0;
     o->kq = kprime;
     o->t += 1;

@@ -97,6 +97,7 @@ SIGNATURES.update({
     "at_serve_set_watch": (C.c_int, [_vp, C.c_uint32, _u32p, C.c_uint32]),
     "at_serve_submit": (C.c_int, [_vp, C.c_uint32, _vp, _vp, C.c_uint64]),
     "at_serve_end_slice": (C.c_int, [_vp, C.c_uint32, C.c_uint32]),
+    "at_serve_submit_last": (C.c_int, [_vp, C.c_uint32, _vp, _vp, C.c_uint64, C.c_uint32]),
     "at_serve_step": (C.c_int, [_vp, _u32p]),
     "at_serve_start": (C.c_int, [_vp]),
     "at_serve_stop": (C.c_int, [_vp]),
@@ -104,6 +105,7 @@ SIGNATURES.update({
                                        _f64p, _f64p, _u8p, C.c_uint32]),
     "at_serve_stats": (C.c_int, [_vp, _u64p]),
     "at_serve_read_pool": (C.c_int, [_vp, C.c_uint32, _u8p]),
+    "at_serve_tiled_stats": (C.c_int, [_vp, _u64p, _u64p, _f64p]),
 })
 
 _lib = None
@@ -475,6 +477,11 @@ class Server:
     def end_slice(self, lid: int, kprime: int) -> int:
         return self.lib.at_serve_end_slice(self.h, lid, kprime)
 
+    def submit_last(self, lid: int, aip_dev, bip_dev, kprime: int, n: Optional[int] = None) -> int:
+        n = aip_dev.numel() if n is None else n
+        return self.lib.at_serve_submit_last(self.h, lid, C.c_void_p(_dev_ptr(aip_dev)),
+                                             C.c_void_p(_dev_ptr(bip_dev)), n, kprime)
+
     def step(self) -> int:
         n = C.c_uint32()
         _check(self.lib.at_serve_step(self.h, C.byref(n)), "at_serve_step")
@@ -491,11 +498,10 @@ class Server:
         """Pop every ready result as dicts."""
         out = []
         cc, wc = self.cand_cap, self.watch_cap
-        cand = np.zeros(cc, np.uint32)
-        ce, cl = np.zeros(cc), np.zeros(cc)
-        cf = np.zeros(cc, np.uint8)
-        wp, wl = np.zeros(max(wc, 1)), np.zeros(max(wc, 1))
-        wf = np.zeros(max(wc, 1), np.uint8)
+        if getattr(self, "_rbuf", None) is None:   # staging reused across calls
+            self._rbuf = (np.zeros(cc, np.uint32), np.zeros(cc), np.zeros(cc), np.zeros(cc, np.uint8),
+                          np.zeros(max(wc, 1)), np.zeros(max(wc, 1)), np.zeros(max(wc, 1), np.uint8))
+        cand, ce, cl, cf, wp, wl, wf = self._rbuf
         while True:
             r = ServeResult()
             rc = self.lib.at_serve_next_result(self.h, C.byref(r), _p(cand, C.c_uint32), _p(ce, C.c_double),
@@ -519,3 +525,9 @@ class Server:
         out = np.zeros(self.pool_bytes, np.uint8)
         _check(self.lib.at_serve_read_pool(self.h, lid, _p(out, C.c_uint8)), "at_serve_read_pool")
         return out
+
+    def tiled_stats(self) -> dict:
+        calls, pairs, ms = C.c_uint64(), C.c_uint64(), C.c_double()
+        _check(self.lib.at_serve_tiled_stats(self.h, C.byref(calls), C.byref(pairs), C.byref(ms)),
+               "at_serve_tiled_stats")
+        return dict(calls=int(calls.value), pairs=int(pairs.value), device_ms=float(ms.value))

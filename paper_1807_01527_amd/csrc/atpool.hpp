@@ -215,7 +215,8 @@ struct ChunkDesc {
     uint32_t slot, c0, vec, pad;
 };
 struct CloseDesc {
-    uint32_t slot, c0, kq, pad;
+    uint32_t slot, c0, kq;
+    uint32_t ready;  // the slice's weights for window kq were written by its tiled scan: no pool pass
 };
 
 struct StepDesc {  // one serving step, copied to the device before each replay
@@ -260,6 +261,18 @@ struct ServeBufs {  // device buffers of one server's step graph
     uint32_t cand_cap;
     uint32_t pad;
 };
+
+// Copy up to kGatherMax chunks of pairs into one contiguous pair of arrays
+// (the chunks of one link that a serving step scans with the tiled scan).
+constexpr uint32_t kGatherMax = 16;
+struct GatherList {
+    uint32_t n;
+    const uint32_t* aip[kGatherMax];
+    const uint32_t* bip[kGatherMax];
+    uint64_t cnt[kGatherMax];
+    uint64_t off[kGatherMax];  // destination offset of each chunk
+};
+hipError_t launch_gather_pairs(const GatherList& Lst, uint32_t* aip_out, uint32_t* bip_out, hipStream_t st);
 
 hipError_t launch_serve_ingest_branch(const ServeBufs& B, const Geometry& shape, hipStream_t st);
 hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, uint64_t n_atv, hipStream_t st);

@@ -466,19 +466,14 @@ int scan_path(const at_ctx* h, uint64_t n) {
 
 int ingest_tiled_buffers(at_ctx* h, uint64_t n);
 
-int ingest_tiled(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, uint64_t n, bool preserve) {
+// The tiled launches of a call with the given scratch.
+int ingest_tiled_with(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, uint64_t n, bool preserve,
+                      const atp::TileBufs& tb) {
     // a single batch that opens the slice also writes the full window's weights
     const bool weights = preserve && n <= kBinBatch;
-    int rc = ingest_tiled_buffers(h, n);
-    if (rc) {
-        // the slice is open already: its preserve must not be lost
-        if (preserve && atp::launch_preserve(h->pool, h->n_atv, h->G, h->c0, h->stream) != hipSuccess)
-            return AT_E_DEVICE;
-        return rc;
-    }
     for (uint64_t off = 0; off < n; off += kBinBatch) {
         const uint64_t m = std::min<uint64_t>(kBinBatch, n - off);
-        if (atp::launch_ingest_tiled(h->pool, aip_dev + off, bip_dev + off, m, h->pool_bytes, h->G, h->c0, h->tb,
+        if (atp::launch_ingest_tiled(h->pool, aip_dev + off, bip_dev + off, m, h->pool_bytes, h->G, h->c0, tb,
                                      preserve && off == 0, weights ? h->w_all : nullptr, h->p.k,
                                      h->stream) != hipSuccess)
             return AT_E_DEVICE;
@@ -486,6 +481,17 @@ int ingest_tiled(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, ui
     h->wfused = weights;
     h->wfused_kq = h->p.k;
     return AT_OK;
+}
+
+int ingest_tiled(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, uint64_t n, bool preserve) {
+    int rc = ingest_tiled_buffers(h, n);
+    if (rc) {
+        // the slice is open already: its preserve must not be lost
+        if (preserve && atp::launch_preserve(h->pool, h->n_atv, h->G, h->c0, h->stream) != hipSuccess)
+            return AT_E_DEVICE;
+        return rc;
+    }
+    return ingest_tiled_with(h, aip_dev, bip_dev, n, preserve, h->tb);
 }
 
 int ingest_tiled_buffers(at_ctx* h, uint64_t n) {

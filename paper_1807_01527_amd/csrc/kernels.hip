@@ -1508,7 +1508,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_close(const StepDesc* __restri
         const uint64_t gi = base + sub;
         uint32_t cnt = 0;
         const uint32_t ci = (uint32_t)(gi / n_atv);
-        if (gi < total) {
+        if (gi < total && !d->close[ci].ready) {
             const CloseDesc& cdsc = d->close[ci];
             const LinkSlot& ls = L[cdsc.slot];
             const uint64_t atv = gi - (uint64_t)ci * n_atv;
@@ -1528,7 +1528,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_close(const StepDesc* __restri
             }
         }
         for (uint32_t o = lpa / 2; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-        if (sl == 0 && gi < total) L[d->close[ci].slot].w[gi - (uint64_t)ci * n_atv] = cnt;
+        if (sl == 0 && gi < total && !d->close[ci].ready) L[d->close[ci].slot].w[gi - (uint64_t)ci * n_atv] = cnt;
     }
 }
 
@@ -1813,6 +1813,20 @@ __global__ __launch_bounds__(kBlock) void k_serve_features(const StepDesc* __res
 // Comparator: the aging counters of ACE (Section 2.3) must all be decremented
 // at every slice end -- one read and one write of the whole pool -- where the
 // asynchronous timestamps only touch two blocks of each ATV (k_preserve).
+// blockIdx.y = chunk; the chunk's pairs copied with a grid-stride loop
+__global__ __launch_bounds__(kBlock) void k_gather_pairs(GatherList Lst, uint32_t* __restrict__ aip_out,
+                                                         uint32_t* __restrict__ bip_out) {
+    const uint32_t c = blockIdx.y;
+    if (c >= Lst.n) return;
+    const uint32_t* __restrict__ a = Lst.aip[c];
+    const uint32_t* __restrict__ b = Lst.bip[c];
+    const uint64_t n = Lst.cnt[c], off = Lst.off[c];
+    for (uint64_t q = (uint64_t)blockIdx.x * kBlock + threadIdx.x; q < n; q += (uint64_t)gridDim.x * kBlock) {
+        aip_out[off + q] = a[q];
+        bip_out[off + q] = b[q];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_ace_age(uint8_t* __restrict__ p, uint64_t n16) {
     for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n16; q += (uint64_t)gridDim.x * blockDim.x) {
         uint4 v = reinterpret_cast<uint4*>(p)[q];
@@ -2207,6 +2221,16 @@ hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, 
             return hipErrorInvalidValue;
     }
 #undef AT_SERVE_FEAT
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_pairs(const GatherList& Lst, uint32_t* aip_out, uint32_t* bip_out, hipStream_t st) {
+    if (Lst.n == 0) return hipSuccess;
+    if (Lst.n > kGatherMax) return hipErrorInvalidValue;
+    uint64_t most = 0;
+    for (uint32_t c = 0; c < Lst.n; c++) most = Lst.cnt[c] > most ? Lst.cnt[c] : most;
+    const uint32_t gx = grid_for(most, 2048);
+    hipLaunchKernelGGL(k_gather_pairs, dim3(gx, Lst.n), dim3(kBlock), 0, st, Lst, aip_out, bip_out);
     return hipGetLastError();
 }
 

@@ -13,6 +13,15 @@
 // then copies the results to pinned host memory.  A link whose slice ends is
 // closed in the step after its last chunk was scanned, and its next slice
 // waits for that close, so the two branches never touch the same pool.
+//
+// A link whose queued pairs in a step are many next to its pool takes the
+// tiled scan instead (stores grouped per 64 KiB tile and applied in LDS, the
+// pool streamed once): its chunks are gathered into one array and scanned by
+// launches on a third stream while the graph runs, since the grids of those
+// launches depend on the step's pair count.  Its slice is opened by the tile
+// pass (the preserve runs there), and when the slice's end is already queued
+// behind its chunks the tile pass also writes the window's weights, so the
+// close that follows reads no pool.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -70,6 +79,8 @@ struct Event {
 
 struct Link {
     uint32_t id = 0;
+    bool wready = false;     // weights of the open slice's window wready_kq written by its tiled scan
+    uint32_t wready_kq = 0;
     int state = L_WAITING;
     at_params p{};
     Geometry G{};
@@ -153,6 +164,17 @@ struct at_serve {
     uint64_t steps = 0;
     double last_step_ms = 0.0;
     uint64_t pairs_ingested = 0;
+    // tiled scans: stream, scratch, timing
+    hipStream_t s2 = nullptr;
+    bool tiled_ok = false;
+    uint64_t pool_bytes = 0;
+    atp::TileBufs tb{};
+    uint32_t* stage_a = nullptr;  // gathered chunks of one link
+    uint32_t* stage_b = nullptr;
+    uint64_t stage_cap = 0;
+    std::vector<hipEvent_t> tev;  // start/end event pairs of the step's tiled launches
+    uint64_t tiled_calls = 0, tiled_pairs = 0;
+    double tiled_ms = 0.0;
 };
 
 namespace atp {
@@ -319,10 +341,131 @@ void free_server(at_serve* S) {
     void* h[] = {S->h_desc, S->h_state, S->h_hosts, S->h_est, S->h_estl, S->h_flagsl};
     for (void* p : h)
         if (p) (void)hipHostFree(p);
+    void* t[] = {S->tb.rec, S->tb.cnt, S->tb.pre, S->tb.csum, S->tb.base, S->tb.act, S->stage_a, S->stage_b};
+    for (void* p : t)
+        if (p) (void)hipFree(p);
+    for (hipEvent_t e : S->tev) (void)hipEventDestroy(e);
     if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
     if (S->ev_join) (void)hipEventDestroy(S->ev_join);
+    if (S->s2) (void)hipStreamDestroy(S->s2);
     if (S->s1) (void)hipStreamDestroy(S->s1);
     if (S->s0) (void)hipStreamDestroy(S->s0);
+}
+
+// The tiled scan streams the pool once per call; straight byte stores cost a
+// partial-line write-back each, about 12 bytes' worth while the pools stay in
+// the 256 MiB last-level cache and about 30 once they do not.  So a link's
+// step goes tiled when its r*n stores times that cost reach its pool size.
+constexpr uint64_t kLastLevelCache = 256ull << 20;
+constexpr uint64_t kTileBatch = 8ull << 20;  // pairs per tiled launch
+
+bool take_tiled(const at_serve* S, uint64_t n) {  // caller holds mu
+    if (!S->tiled_ok || n == 0) return false;
+    uint64_t resident = 0;
+    for (int id : S->slot_used)
+        if (id >= 0) resident += S->pool_bytes;
+    const uint64_t per_store = resident > kLastLevelCache ? 30 : 12;
+    return n * S->shape.r * per_store >= S->pool_bytes;
+}
+
+int tiled_buffers(at_serve* S, uint64_t n) {
+    const atp::TileSizes z = atp::tiled_sizes(std::min<uint64_t>(n, kTileBatch), S->pool_bytes, S->shape);
+    int rc;
+    if (z.recs > S->tb.rec_cap) {
+        if (S->tb.rec) (void)hipFree(S->tb.rec);
+        S->tb.rec_cap = 0;
+        if ((rc = dalloc(&S->tb.rec, z.recs))) return rc;
+        S->tb.rec_cap = z.recs;
+    }
+    if (z.table > S->tb.table_cap) {
+        if (S->tb.cnt) (void)hipFree(S->tb.cnt);
+        if (S->tb.pre) (void)hipFree(S->tb.pre);
+        S->tb.cnt = S->tb.pre = nullptr;
+        S->tb.table_cap = 0;
+        if ((rc = dalloc(&S->tb.cnt, z.table)) || (rc = dalloc(&S->tb.pre, z.table))) return rc;
+        S->tb.table_cap = z.table;
+    }
+    if (z.nchunk > S->tb.chunk_cap) {
+        if (S->tb.csum) (void)hipFree(S->tb.csum);
+        S->tb.chunk_cap = 0;
+        if ((rc = dalloc(&S->tb.csum, (uint64_t)z.nchunk * 4096))) return rc;
+        S->tb.chunk_cap = z.nchunk;
+    }
+    if (!S->tb.base && (rc = dalloc(&S->tb.base, 4097))) return rc;
+    if (!S->tb.act && (rc = dalloc(&S->tb.act, (uint64_t)S->shape.g))) return rc;
+    return AT_OK;
+}
+
+int stage_buffers(at_serve* S, uint64_t n) {
+    if (n <= S->stage_cap) return AT_OK;
+    if (S->stage_a) (void)hipFree(S->stage_a);
+    if (S->stage_b) (void)hipFree(S->stage_b);
+    S->stage_a = S->stage_b = nullptr;
+    S->stage_cap = 0;
+    int rc;
+    if ((rc = dalloc(&S->stage_a, n)) || (rc = dalloc(&S->stage_b, n))) return rc;
+    S->stage_cap = n;
+    return AT_OK;
+}
+
+// One link's chunks of a step, scanned by the tiled scan.
+struct TiledJob {
+    Link* L;
+    std::vector<const Event*> chunks;
+    uint64_t n;
+    bool opens;     // the scan opens the slice: the tile pass runs its preserve
+    bool weights;   // the slice's end is queued behind its chunks: the tile pass counts window kq
+    uint32_t kq;
+};
+
+// Launch the tiled jobs on s2 (events around each launch for the timing).
+int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed) {
+    *n_timed = 0;
+    for (TiledJob& J : jobs) {
+        Link* L = J.L;
+        int rc = tiled_buffers(S, J.n);
+        if (!rc && J.chunks.size() > 1) rc = stage_buffers(S, J.n);
+        if (rc) return rc;
+        const uint32_t* a = J.chunks[0]->aip;
+        const uint32_t* b = J.chunks[0]->bip;
+        if (J.chunks.size() > 1) {
+            atp::GatherList G{};
+            uint64_t off = 0;
+            for (size_t c = 0; c < J.chunks.size(); c++) {
+                G.aip[G.n] = J.chunks[c]->aip;
+                G.bip[G.n] = J.chunks[c]->bip;
+                G.cnt[G.n] = J.chunks[c]->n;
+                G.off[G.n] = off;
+                off += J.chunks[c]->n;
+                if (++G.n == atp::kGatherMax || c + 1 == J.chunks.size()) {
+                    if (atp::launch_gather_pairs(G, S->stage_a, S->stage_b, S->s2) != hipSuccess) return AT_E_DEVICE;
+                    G.n = 0;
+                }
+            }
+            a = S->stage_a;
+            b = S->stage_b;
+        }
+        const bool single = J.n <= kTileBatch;
+        for (uint64_t off = 0; off < J.n; off += kTileBatch) {
+            const uint64_t m = std::min<uint64_t>(kTileBatch, J.n - off);
+            const bool first = off == 0;
+            while (S->tev.size() < 2 * (*n_timed + 1)) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return AT_E_DEVICE;
+                S->tev.push_back(e);
+            }
+            if (hipEventRecord(S->tev[2 * *n_timed], S->s2) != hipSuccess) return AT_E_DEVICE;
+            const bool w = J.weights && single && first;
+            if (atp::launch_ingest_tiled(L->pool, a + off, b + off, m, S->pool_bytes, L->G, L->c0, S->tb,
+                                         J.opens && first, w ? L->w : nullptr, J.kq, S->s2) != hipSuccess)
+                return AT_E_DEVICE;
+            if (hipEventRecord(S->tev[2 * *n_timed + 1], S->s2) != hipSuccess) return AT_E_DEVICE;
+            ++*n_timed;
+        }
+        L->wready = J.weights && single;
+        L->wready_kq = J.kq;
+    }
+    return AT_OK;
 }
 
 }  // namespace
@@ -341,7 +484,7 @@ int at_serve_create(const at_serve_config* cfg, at_serve** out) {
     shp.log2g = cfg->log2g;
     shp.theta = cfg->theta;
     if (cfg->max_links < 1 || cfg->max_links > atp::kServeMaxLinks || cfg->cand_cap < 1 || cfg->cand_cap > 2048 ||
-        cfg->u > 8 || cfg->watch_cap > 4096)
+        cfg->u > 8 || cfg->watch_cap > 16384)
         return AT_E_INVAL;
     {  // the geometry rules of at_create
         const uint32_t W = 32 - shp.u;
@@ -356,11 +499,19 @@ int at_serve_create(const at_serve_config* cfg, at_serve** out) {
     S->shape = atp::derive_geometry(shp);
     S->n_atv = ((uint64_t)(S->shape.umask + 1) * S->shape.r) << S->shape.c;
     S->per_link_bytes = link_bytes(S);
+    S->pool_bytes = S->n_atv << S->shape.log2g;
+    {
+        int dev = 0, lds = 0;
+        S->tiled_ok = hipGetDevice(&dev) == hipSuccess &&
+                      hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+                      (size_t)lds >= atp::tiled_lds_bytes(4096) + 1024 && atp::tiled_fits(S->pool_bytes);
+    }
     S->slot_used.assign(cfg->max_links, -1);
     S->max_hosts = (uint64_t)cfg->max_links * (cfg->cand_cap + cfg->watch_cap);
     int rc = AT_OK;
     hipError_t e = hipStreamCreateWithFlags(&S->s0, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s1, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) rc = AT_E_DEVICE;
@@ -397,6 +548,7 @@ int at_serve_destroy(at_serve* S) {
     { std::lock_guard<std::mutex> sg(S->step_mu); }
     (void)hipStreamSynchronize(S->s0);
     (void)hipStreamSynchronize(S->s1);
+    (void)hipStreamSynchronize(S->s2);
     free_server(S);
     delete S;
     return AT_OK;
@@ -531,6 +683,21 @@ int at_serve_end_slice(at_serve* S, uint32_t link_id, uint32_t kprime) {
     return AT_OK;
 }
 
+int at_serve_submit_last(at_serve* S, uint32_t link_id, const uint32_t* aip_dev, const uint32_t* bip_dev,
+                         uint64_t n, uint32_t kprime) {
+    if (!S || (n && (!aip_dev || !bip_dev))) return AT_E_INVAL;
+    const double t = now_ms();
+    std::lock_guard<std::mutex> g(S->mu);
+    if (link_id >= S->links.size()) return AT_E_INVAL;
+    Link* L = S->links[link_id];
+    if (L->state != L_ACTIVE) return AT_E_STATE;
+    if (kprime < 1 || kprime > L->p.k) return AT_E_INVAL;
+    if (n) L->q.push_back(Event{false, aip_dev, bip_dev, n, 0, 0.0});
+    L->q.push_back(Event{true, nullptr, nullptr, 0, kprime, t});
+    S->cv.notify_one();
+    return AT_OK;
+}
+
 int at_serve_step(at_serve* S, uint32_t* n_results) {
     if (!S) return AT_E_INVAL;
     if (n_results) *n_results = 0;
@@ -551,6 +718,7 @@ int at_serve_step(at_serve* S, uint32_t* n_results) {
         uint64_t slice;
     };
     std::vector<CloseRec> closes;
+    std::vector<TiledJob> tiled;
     uint64_t pairs = 0;
     for (Link* L : S->links) {
         if (!L || L->state != L_ACTIVE || L->q.empty()) continue;
@@ -561,8 +729,40 @@ int at_serve_step(at_serve* S, uint32_t* n_results) {
             c.slot = (uint32_t)L->slot;
             c.c0 = L->c0;
             c.kq = first.kprime;
+            c.ready = L->wready && L->wready_kq == first.kprime ? 1u : 0u;
+            L->wready = false;
             closes.push_back(CloseRec{L, first.kprime, first.t_arrival, L->t});
             continue;
+        }
+        {
+            // the step's pairs of this link's current slice, and whether its end follows them
+            uint64_t n = 0;
+            bool end_follows = false;
+            uint32_t kq = 0;
+            for (const Event& ev : L->q) {
+                if (ev.end) {
+                    end_follows = true;
+                    kq = ev.kprime;
+                    break;
+                }
+                if (ev.aip) n += ev.n;
+            }
+            if (take_tiled(S, n)) {
+                TiledJob J{L, {}, n, !L->open, false, kq};
+                if (!L->open) {
+                    L->open = true;
+                    L->c0 = (uint32_t)(L->t % L->G.twok);
+                }
+                J.weights = J.opens && end_follows;
+                for (Event& ev : L->q) {
+                    if (ev.end) break;
+                    if (!ev.aip) continue;
+                    J.chunks.push_back(&ev);
+                }
+                pairs += n;
+                tiled.push_back(std::move(J));
+                continue;
+            }
         }
         // open the slice if needed, then queue its chunks (stopping at its end)
         if (!L->open) {
@@ -595,14 +795,27 @@ int at_serve_step(at_serve* S, uint32_t* n_results) {
 
     const double t0 = now_ms();
     hipError_t e = hipGraphLaunch(S->exec, S->s0);
+    uint32_t n_timed = 0;
+    int trc = e == hipSuccess ? run_tiled(S, tiled, &n_timed) : AT_OK;
     if (e == hipSuccess) e = hipStreamSynchronize(S->s0);
+    hipError_t e2 = hipStreamSynchronize(S->s2);
     const double t1 = now_ms();
-    if (e != hipSuccess) return AT_E_DEVICE;
+    if (e != hipSuccess || e2 != hipSuccess) return AT_E_DEVICE;
+    if (trc) return trc;
+    for (uint32_t q = 0; q < n_timed; q++) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, S->tev[2 * q], S->tev[2 * q + 1]) == hipSuccess) S->tiled_ms += ms;
+    }
+    S->tiled_calls += n_timed;
 
     lk.lock();
     S->steps++;
     S->last_step_ms = t1 - t0;
     S->pairs_ingested += pairs;
+    for (const TiledJob& J : tiled) {
+        S->tiled_pairs += J.n;
+        for (const Event* ev : J.chunks) const_cast<Event*>(ev)->aip = nullptr;  // handed to this step
+    }
     // retire scanned chunks and closed slices
     for (Link* L : S->links) {
         if (!L || L->state != L_ACTIVE) continue;
@@ -743,6 +956,15 @@ int at_serve_stats(at_serve* S, uint64_t* out4) {
     out4[1] = S->pairs_ingested;
     out4[2] = S->used_bytes;
     out4[3] = S->waiting.size();
+    return AT_OK;
+}
+
+int at_serve_tiled_stats(at_serve* S, uint64_t* calls, uint64_t* pairs, double* device_ms) {
+    if (!S) return AT_E_INVAL;
+    std::lock_guard<std::mutex> g(S->mu);
+    if (calls) *calls = S->tiled_calls;
+    if (pairs) *pairs = S->tiled_pairs;
+    if (device_ms) *device_ms = S->tiled_ms;
     return AT_OK;
 }
 

@@ -35,6 +35,121 @@ GEOMS = {
     "serve": dict(k=30, r=4, c=9, s=8, u=1, log2g=12, theta=1024.0),
 }
 KS = {"serve": (5, 10, 30)}
+
+# Traffic-shaped training sets: whole traces of a configuration's own traffic
+# law through its own geometry (one window per trace), sampled over the
+# label range.  "large": the large configuration, 60 slices of 3,333,333
+# pairs, k = 60, a 2^28-AT pool, aip Zipf 1.1 over 2^24 hosts, 661 planted
+# hosts log-uniform over [1024, 2^20].  "serve_mix": the serving links' pools
+# (2^24 ATs) with k from {5, 10, 30}, lognormal slices (median 2M, sigma 1,
+# clipped to [100k, 20M]) of small-configuration content.
+STREAM_GEOMS = {
+    "large": dict(k=60, r=4, c=10, s=6, u=4, log2g=12, theta=1024.0),
+    "serve_mix": dict(k=30, r=4, c=9, s=8, u=1, log2g=12, theta=1024.0),
+}
+LARGE_STREAM = dict(hosts=1 << 24, zipf_s=1.1, planted=661, lo=1024, hi=1 << 20, card_dist="loguniform")
+LARGE_SLICES, LARGE_PAIRS = 60, 3_333_333
+
+
+def stream_trace(name: str, seed: int, dev):
+    """One trace of a traffic-shaped family: (k, per-slice (aip, bip) device
+    views, aip and bip of the whole window as device tensors)."""
+    from . import traffic_gpu as tg
+    if name == "large":
+        n = LARGE_SLICES * LARGE_PAIRS
+        a, b, _ = tg.link_stream(seed, n, dev, **LARGE_STREAM)
+        bounds = [t * LARGE_PAIRS for t in range(LARGE_SLICES + 1)]
+        k = STREAM_GEOMS[name]["k"]
+    else:
+        k = (5, 10, 30)[seed % 3]
+        rng = np.random.default_rng(seed)
+        sizes = np.clip(np.exp(np.log(2e6) + rng.standard_normal(k)), 1e5, 2e7).astype(np.int64)
+        bounds = np.concatenate([[0], np.cumsum(sizes)]).tolist()
+        a, b, _ = tg.link_stream(seed, int(bounds[-1]), dev)
+    slices = [(a[lo:hi], b[lo:hi]) for lo, hi in zip(bounds[:-1], bounds[1:])]
+    return k, slices, a, b
+
+
+def exact_counts(a, b):
+    """Exact distinct bips per aip over the given pairs (device tensors of
+    int32 holding 32-bit words): (hosts uint32, counts int64) on the host."""
+    import torch
+    from .traffic_gpu import _srl
+    keys = torch.unique(((a.to(torch.int64) & 0xFFFFFFFF) << 32) | (b.to(torch.int64) & 0xFFFFFFFF))
+    hosts, counts = torch.unique(_srl(keys, 32), return_counts=True)
+    return hosts.cpu().numpy().astype(np.uint32), counts.cpu().numpy().astype(np.int64)
+
+
+def build_dataset_stream(name: str, n_samples: int, seed: int = 1, log=print, per_trace: int = 40000):
+    """(features, ln n) from whole traces of the family `name`: every host of
+    the window with at least theta distinct bips, and as many hosts with 16 to
+    theta - 1 sampled uniformly, until n_samples are collected.  Trace seeds
+    start at 1000 * seed + 100, away from the evaluation seeds."""
+    import torch
+    geom = STREAM_GEOMS[name]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    X, T = [], []
+    have, tr = 0, 0
+    t0 = time.perf_counter()
+    while have < n_samples:
+        ts = 1000 * seed + 100 + tr
+        k, slices, a, b = stream_trace(name, ts, dev)
+        pool = AtPool(**{**geom, "k": k}, seed=ts)
+        for sa, sb in slices:
+            pool.ingest(sa, sb)
+            pool.close(k)
+        hosts, counts = exact_counts(a, b)
+        big = np.nonzero(counts >= geom["theta"])[0]
+        small = np.nonzero((counts >= 16) & (counts < geom["theta"]))[0]
+        rng = np.random.default_rng(ts)
+        take = min(small.size, max(big.size, per_trace - big.size))
+        sel = np.concatenate([big, rng.choice(small, take, replace=False)])[:per_trace]
+        hd = torch.from_numpy(hosts[sel].view(np.int32)).to(dev)
+        feat = torch.empty((sel.size, 64), dtype=torch.float32, device=dev)
+        pool.features(hd, feat)
+        X.append(feat)
+        T.append(torch.from_numpy(np.log(counts[sel].astype(np.float64)).astype(np.float32)).to(dev))
+        have += sel.size
+        pool.destroy()
+        del a, b, slices
+        tr += 1
+        log(f"  dataset {name}: {tr} traces, {have} samples, {time.perf_counter() - t0:.1f}s")
+    torch.cuda.synchronize()
+    return torch.cat(X)[:n_samples].contiguous(), torch.cat(T)[:n_samples].contiguous()
+
+
+def evaluate_stream(name: str, mlp: Optional[Mlp], seeds=range(2)) -> Dict[str, float]:
+    """Mean relative error of the plain and learned estimates over the true
+    super points (exact count >= theta) of whole traces of the family, at
+    the seeds given (the large configuration's own links are seeds 0-3)."""
+    import torch
+    geom = STREAM_GEOMS[name]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    rel_p, rel_l, fb = [], [], 0
+    for sd in seeds:
+        k, slices, a, b = stream_trace(name, sd, dev)
+        pool = AtPool(**{**geom, "k": k}, seed=sd)
+        for sa, sb in slices:
+            pool.ingest(sa, sb)
+            pool.close(k)
+        hosts, counts = exact_counts(a, b)
+        m = counts >= geom["theta"]
+        h, n = hosts[m], counts[m]
+        if mlp is not None:
+            est_l, fl, plain = pool.estimate_learned(mlp, h)
+            rel_l.append(np.abs(est_l - n) / n)
+            fb += int(np.count_nonzero(fl & 4))
+        else:
+            plain, _ = pool.estimate_plain(h)
+        rel_p.append(np.abs(plain - n) / n)
+        pool.destroy()
+    out = {"plain": float(np.mean(np.concatenate(rel_p))), "hosts": int(sum(x.size for x in rel_p))}
+    if mlp is not None:
+        out["learned"] = float(np.mean(np.concatenate(rel_l)))
+        out["fallbacks"] = fb
+    return out
+
+
 WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
 
 
@@ -179,7 +294,7 @@ def load_weights(name: str) -> Optional[np.ndarray]:
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--geom", choices=sorted(GEOMS), default="small")
+    ap.add_argument("--geom", choices=sorted(GEOMS) + sorted(STREAM_GEOMS), default="small")
     ap.add_argument("--samples", type=int, default=1_000_000)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--seed", type=int, default=1)
@@ -190,7 +305,11 @@ def main(argv=None):
     torch.cuda.set_device(0)
     log = lambda m: print(m, flush=True)  # noqa: E731
     t0 = time.perf_counter()
-    X, T = build_dataset(args.geom, args.samples, seed=args.seed, log=log)
+    stream = args.geom in STREAM_GEOMS
+    if stream:
+        X, T = build_dataset_stream(args.geom, args.samples, seed=args.seed, log=log)
+    else:
+        X, T = build_dataset(args.geom, args.samples, seed=args.seed, log=log)
     log(f"dataset: {X.shape[0]} samples in {time.perf_counter() - t0:.1f}s")
     mlp = Mlp(init_params(args.seed))
     t1 = time.perf_counter()
@@ -200,7 +319,10 @@ def main(argv=None):
     if args.out:
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         np.save(args.out, mlp.get_params())
-    res = evaluate(args.geom, mlp, seeds=range(args.eval_seeds))
+    if stream:
+        res = evaluate_stream(args.geom, mlp, seeds=range(args.eval_seeds))
+    else:
+        res = evaluate(args.geom, mlp, seeds=range(args.eval_seeds))
     log(f"evaluation ({args.geom} traffic, seeds 0..{args.eval_seeds - 1}): {res}")
     return res
 

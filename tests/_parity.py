@@ -118,3 +118,58 @@ def compare_serve_results(got, want, where):
         assert np.array_equal(g["cand_flags"], w["cand_flags"]), tag
         assert np.array_equal(g["watch_flags"], w["watch_flags"]), tag
         assert g["latency_ms"] > 0
+
+
+def oracle_link_run(oracle_mod, params: dict, k: int, seed: int, events, watch: np.ndarray, cand_cap: int,
+                    tuple_budget: int = 0):
+    """The CPU oracle driven like a served link: events are ("chunk", aip, bip)
+    host arrays and ("end", k') slice ends.  Per close: restore outcome
+    (cap = cand_cap), candidates, plain estimates and SAT/NEG flags of the
+    candidates and the watch hosts.  Returns (records, final pool)."""
+    o = oracle_mod.Oracle(k=k, seed=seed, tuple_budget=tuple_budget, **params)
+    out = []
+    for ev in events:
+        if ev[0] == "chunk":
+            o.ingest(ev[1], ev[2])
+            continue
+        o.close(ev[1])
+        rc, cand, m = o.restore(cap=cand_cap)
+        rec = dict(restore_rc=rc, n_out=m, cand=cand if rc == 0 else np.zeros(0, np.uint32))
+        if rc == 0 and cand.size:
+            rec["cand_plain"], rec["cand_flags"], _ = o.estimate(cand)
+        else:
+            rec["cand_plain"], rec["cand_flags"] = np.zeros(0), np.zeros(0, np.uint8)
+        rec["watch_plain"], rec["watch_flags"], _ = o.estimate(np.asarray(watch, np.uint32))
+        out.append(rec)
+    pool = o.pool()
+    o.close_handle()
+    return out, pool
+
+
+def oracle_link_runs(oracle_mod, jobs, workers: int = 8):
+    """oracle_link_run over several links at once (the oracle's calls release
+    the interpreter lock, so threads run the links in parallel)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=max(1, min(workers, len(jobs)))) as ex:
+        futs = [ex.submit(oracle_link_run, oracle_mod, *job) for job in jobs]
+        return [f.result() for f in futs]
+
+
+def compare_serve_with_oracle(got, want, where):
+    """Per closed slice: a served link's results against the oracle's: restore
+    outcome and count, candidate list, plain FP64 estimates to EST_RTOL, and
+    the flags of the plain estimate (AT_F_SAT, AT_F_NEG)."""
+    assert len(got) == len(want), f"{where}: {len(got)} closes served, {len(want)} in the oracle"
+    for s, (g, w) in enumerate(zip(got, want)):
+        tag = f"{where} slice {s}"
+        assert g["restore_rc"] == w["restore_rc"], (tag, g["restore_rc"], w["restore_rc"])
+        assert g["n_out"] == w["n_out"], (tag, g["n_out"], w["n_out"])
+        assert np.array_equal(g["cand"], w["cand"]), tag
+        for key, fkey in (("cand_plain", "cand_flags"), ("watch_plain", "watch_flags")):
+            a, b = np.asarray(g[key]), np.asarray(w[key])
+            assert a.shape == b.shape, (tag, key)
+            assert np.array_equal(np.isfinite(a), np.isfinite(b)), (tag, key)
+            fin = np.isfinite(b)
+            assert np.array_equal(a[~fin], b[~fin]), (tag, key)
+            assert np.all(np.abs(a[fin] - b[fin]) <= EST_RTOL * np.abs(b[fin])), (tag, key)
+            assert np.array_equal(np.asarray(g[fkey]) & 3, np.asarray(w[fkey]) & 3), (tag, fkey)

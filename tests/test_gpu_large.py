@@ -23,8 +23,8 @@ import pytest
 
 from oracle import mlp as ref
 
-from ._parity import (compare_estimates, compare_restore, compare_serve_results, compare_state, compare_summary,
-                      make_pair)
+from ._parity import (compare_estimates, compare_restore, compare_serve_results, compare_serve_with_oracle,
+                      compare_state, compare_summary, make_pair, oracle_link_run)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -149,8 +149,27 @@ def _serve(links, net, params, chunk=65536):
     return ids, results, pools
 
 
-@pytest.mark.timeout(600)
-def test_large_four_links_served_equal_single_link(torch_cuda):
+def _oracle_events(a, b, slices, k):
+    """Host copies of a link's slices as oracle events (a whole slice per
+    chunk: the state does not depend on how a slice is split)."""
+    ah = a.cpu().numpy().view(np.uint32)
+    bh = b.cpu().numpy().view(np.uint32)
+    ev = []
+    for lo, hi in slices:
+        if hi > lo:
+            ev.append(("chunk", ah[lo:hi], bh[lo:hi]))
+        ev.append(("end", k))
+    return ev
+
+
+@pytest.mark.timeout(900)
+def test_large_four_links_served_equal_single_link(torch_cuda, oracle_lib):
+    """Four served links of the large configuration with the learned
+    correction on: every close equals the CPU oracle fed the same pairs
+    (restore outcome, plain estimates of the watch hosts, flags, final pool;
+    the oracles run in threads while the GPU works) and the single-link API."""
+    from concurrent.futures import ThreadPoolExecutor
+
     from paper_1807_01527_amd.binding import Mlp
     net = Mlp(ref.init_params(7).astype(np.float32) * np.float32(0.5))
     links = []
@@ -159,16 +178,26 @@ def test_large_four_links_served_equal_single_link(torch_cuda):
         slices = [(t * LARGE_PAIRS, (t + 1) * LARGE_PAIRS) for t in range(LARGE_SLICES)]
         links.append(dict(k=LARGE["k"], seed=seed, a=a, b=b, slices=slices, watch=planted[:WATCH_CAP]))
     params = {k: v for k, v in LARGE.items() if k != "k"}
+    ex = ThreadPoolExecutor(max_workers=4)
+    futs = [ex.submit(oracle_link_run, oracle_lib, params, ln["k"], ln["seed"],
+                      _oracle_events(ln["a"], ln["b"], ln["slices"], ln["k"]), ln["watch"], CAND_CAP, BUDGET)
+            for ln in links]
     ids, res, pools = _serve(links, net, params)
     for i, (lid, ln) in enumerate(zip(ids, links)):
         want, pool = _single_link(ln["k"], ln["seed"], ln["a"], ln["b"], ln["slices"], net, ln["watch"], params)
         compare_serve_results(res[lid], want, f"large link {i}")
         assert np.array_equal(pools[lid], pool), f"large link {i}: pool differs"
         print(f"large link {i}: {len(want)} slices identical served and alone", flush=True)
+    for i, (lid, f) in enumerate(zip(ids, futs)):
+        want, pool = f.result()
+        compare_serve_with_oracle(res[lid], want, f"large link {i} vs oracle")
+        assert np.array_equal(pools[lid], pool), f"large link {i}: pool differs from the oracle"
+        print(f"large link {i}: {len(want)} slices identical served and in the oracle", flush=True)
+    ex.shutdown()
 
 
-@pytest.mark.timeout(600)
-def test_serving_shape_sixteen_links(torch_cuda):
+@pytest.mark.timeout(900)
+def test_serving_shape_sixteen_links(torch_cuda, oracle_lib):
     from paper_1807_01527_amd import traffic_gpu as tg
     from paper_1807_01527_amd.binding import Mlp
     rng = np.random.default_rng(5)
@@ -182,8 +211,54 @@ def test_serving_shape_sixteen_links(torch_cuda):
         a, b, planted = tg.link_stream(500 + i, int(bounds[-1]), "cuda")
         links.append(dict(k=int([5, 10, 30][i % 3]), seed=500 + i, a=a, b=b,
                           slices=list(zip(bounds[:-1].tolist(), bounds[1:].tolist())), watch=planted[:WATCH_CAP]))
+    from concurrent.futures import ThreadPoolExecutor
+    ex = ThreadPoolExecutor(max_workers=8)
+    futs = [ex.submit(oracle_link_run, oracle_lib, SERVE, ln["k"], ln["seed"],
+                      _oracle_events(ln["a"], ln["b"], ln["slices"], ln["k"]), ln["watch"], CAND_CAP, BUDGET)
+            for ln in links]
     ids, res, pools = _serve(links, net, SERVE)
     for i, (lid, ln) in enumerate(zip(ids, links)):
         want, pool = _single_link(ln["k"], ln["seed"], ln["a"], ln["b"], ln["slices"], net, ln["watch"], SERVE)
         compare_serve_results(res[lid], want, f"serving-shape link {i}")
         assert np.array_equal(pools[lid], pool), f"serving-shape link {i}: pool differs"
+    for i, (lid, f) in enumerate(zip(ids, futs)):
+        want, pool = f.result()
+        compare_serve_with_oracle(res[lid], want, f"serving-shape link {i} vs oracle")
+        assert np.array_equal(pools[lid], pool), f"serving-shape link {i}: pool differs from the oracle"
+    ex.shutdown()
+
+
+PAPER = dict(k=300, r=4, c=14, s=6, u=4, log2g=12, theta=1024.0, seed=0, tuple_budget=1 << 40)
+
+
+@pytest.mark.timeout(900)
+def test_paper_geometry_16bit_vs_oracle(torch_cuda, oracle_lib):
+    """The paper's own sliding shape (Section 5.2 and the geometry of 5.1):
+    k = 300 (10-bit ATs, held in 16-bit words), (c, s, u, g) = (14, 6, 4,
+    4096), r = 4: 2^32 ATs, an 8 GiB pool whose byte offsets pass 2^32.
+    Three one-second slices of the synthetic sliding traffic (100k fresh
+    background pairs sent 10 times each, 1000 planted hosts) against the
+    oracle: weights and AAT after every slice, the whole pool after the last,
+    then the estimates of the planted hosts and a sample, and the restore."""
+    from paper_1807_01527_amd import traffic_gpu as tg
+    shape = tg.SlidingShape(k=PAPER["k"])
+    planted, _ = tg.sliding_planted(shape, 0, "cuda")
+    g, o = make_pair(PAPER, oracle_lib)
+    assert g.pool_bytes == 2 * (1 << 32)
+    last = None
+    for t in range(3):
+        a, b = tg.sliding_slice(shape, 0, t, "cuda")
+        g.ingest(a, b)
+        last = a.cpu().numpy().view(np.uint32)
+        o.ingest(last, b.cpu().numpy().view(np.uint32))
+        g.close(PAPER["k"])
+        o.close(PAPER["k"])
+        compare_state(g, o, f"paper geometry slice {t}", pool=(t == 2))
+        compare_summary(g, o, f"paper geometry slice {t}")
+        print(f"paper geometry slice {t}: {a.numel()} pairs, state identical", flush=True)
+    rng = np.random.default_rng(1)
+    sample = np.unique(np.concatenate([planted, last[rng.integers(0, last.size, 3000)]]))
+    compare_estimates(g, o, sample, "paper geometry")
+    rc, _, m = compare_restore(g, o, cap=1 << 22, where="paper geometry")
+    print(f"paper geometry: restore rc={rc} m={m}", flush=True)
+    g.destroy()

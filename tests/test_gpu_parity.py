@@ -332,3 +332,49 @@ def test_calls_larger_than_one_batch(cuda, oracle_lib):
         w, aat = g.read_summary()
         assert np.array_equal(w, want_w) and np.array_equal(aat, want_aat), f"mode {mode}: summaries differ"
         g.destroy()
+
+
+def test_eq4_edge_branches_match_oracle(cuda, oracle_lib):
+    """Windows built so that Eq 4 takes each of its edge branches on both
+    sides: a heavy frame (UP ~ 0.41) with unseen hosts (negative estimates,
+    AT_F_NEG), a host with every AT position active (NAT = g clamped, AT_F_SAT),
+    and a frame with every AT active (UP = 1: +inf, AT_F_SAT).  Pools,
+    summaries, NAT, flags and estimates must match, and the flags must occur."""
+    from ._scenarios import CLAMP, FULL, LOADED, clamp_hosts, full_frame, loaded_frames, unseen_hosts
+    # heavy frame, unseen hosts and targets
+    g, o = make_pair(dict(**LOADED, seed=7), oracle_lib)
+    aip, bip, targets, *_ = loaded_frames(o, 3)
+    g.ingest(to_dev(aip), to_dev(bip))
+    o.ingest(aip, bip)
+    g.close(1)
+    o.close(1)
+    compare_state(g, o, "loaded frames")
+    compare_summary(g, o, "loaded frames")
+    hosts = np.concatenate([unseen_hosts(o, 3), targets])
+    _, fl, _ = compare_estimates(g, o, hosts, "loaded frames")
+    assert (fl & 2).any() and ((fl & 2) == 0).any()
+    g.destroy()
+    # NAT = g clamped
+    g, o = make_pair(dict(**CLAMP, seed=4), oracle_lib)
+    aip, bip, h_all, h_most, _ = clamp_hosts(o)
+    g.ingest(to_dev(aip), to_dev(bip))
+    o.ingest(aip, bip)
+    g.close(CLAMP["k"])
+    o.close(CLAMP["k"])
+    compare_state(g, o, "clamp")
+    e, fl, nat = compare_estimates(g, o, np.array([h_all, h_most], np.uint32), "clamp")
+    assert nat.tolist() == [1 << CLAMP["log2g"], (1 << CLAMP["log2g"]) - 1]
+    assert fl[0] & 1 and not fl[1] & 1 and e[0] == e[1]
+    g.destroy()
+    # UP = 1
+    g, o = make_pair(dict(**FULL, seed=2), oracle_lib)
+    aip, bip, probe = full_frame()
+    g.ingest(to_dev(aip), to_dev(bip))
+    o.ingest(aip, bip)
+    g.close(FULL["k"])
+    o.close(FULL["k"])
+    compare_state(g, o, "full frame")
+    compare_summary(g, o, "full frame")
+    e, fl, _ = compare_estimates(g, o, probe, "full frame")
+    assert np.isinf(e).all() and ((fl & 1) != 0).all()
+    g.destroy()

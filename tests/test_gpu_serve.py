@@ -11,7 +11,8 @@ import pytest
 from oracle import mlp as ref
 from paper_1807_01527_amd import traffic
 
-from ._parity import compare_serve_results as _compare, to_dev
+from ._parity import compare_serve_results as _compare
+from ._parity import compare_serve_with_oracle, oracle_link_runs, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -133,13 +134,29 @@ def _links(n, rng, n_slices=7):
     return links, keep
 
 
-def test_mix_equals_alone_and_single_link_api(torch_cuda):
+def _oracle_jobs(links):
+    jobs = []
+    for ln in links:
+        ev = [("chunk", e[3], e[4]) if e[0] == "chunk" else e for e in ln["events"]]
+        jobs.append((SHAPE, ln["k"], ln["seed"], ev, ln["watch"], CAND_CAP))
+    return jobs
+
+
+def test_mix_equals_alone_and_single_link_api(torch_cuda, oracle_lib):
     from paper_1807_01527_amd.binding import Mlp
     rng = np.random.default_rng(0)
     links, keep = _links(8, rng)
     net = Mlp(ref.init_params(5).astype(np.float32) * np.float32(0.5))
     ids, res, pools, stats = _serve(links, net, seed=1)
     assert stats["steps"] > 10 and stats["waiting"] == 0
+    # every served link against the CPU oracle fed the same chunks
+    orc = oracle_link_runs(oracle_lib, _oracle_jobs(links))
+    seen = set()
+    for i, (lid, (want, pool)) in enumerate(zip(ids, orc)):
+        compare_serve_with_oracle(res[lid], want, f"link {i} in the mix vs oracle")
+        assert np.array_equal(pools[lid], pool), f"link {i}: pool differs from the oracle"
+        seen |= {r["restore_rc"] for r in want}
+    assert 0 in seen                      # some closes restore candidate lists
     for i, (lid, ln) in enumerate(zip(ids, links)):
         want, pool = _reference(ln["k"], ln["seed"], ln["events"], ln["watch"], net)
         _compare(res[lid], want, f"link {i} in the mix")
@@ -178,3 +195,116 @@ def test_admission_by_budget(torch_cuda):
     srv.close_link(got[1][0])
     assert srv.link_state(got[3][0])[0] == 1 and srv.stats()["waiting"] == 0
     srv.destroy()
+
+
+# Pools of 4 tiles (256 KiB): a link's step goes to the tiled scan once it
+# holds about 5.5k pairs, so the mix below runs both scans.
+TILED_SHAPE = dict(r=4, c=9, s=8, u=1, log2g=6, theta=48.0)
+
+
+def test_tiled_steps_match_oracle(torch_cuda, oracle_lib):
+    """Links whose steps take the tiled scan (chunks gathered, the opening
+    preserve in the tile pass, and with at_serve_submit_last the window count
+    too) and links whose steps take the batched byte stores, interleaved:
+    every close equals the CPU oracle and the single-link API, and the
+    server reports tiled launches."""
+    from paper_1807_01527_amd.binding import AtPool, Mlp, Server
+    rng = np.random.default_rng(11)
+    net = Mlp(ref.init_params(3).astype(np.float32) * np.float32(0.5))
+    links, keep = [], []
+    for i in range(6):
+        k = [3, 5, 8][i % 3]
+        tr = traffic.generate(traffic.config_tiny(seed=200 + i, n_slices=2 * k + 3, pairs_per_slice=24000,
+                                                  hosts=1 << 10, planted=3, lo=200, hi=900))
+        ev = []
+        for t in range(tr.n_slices):
+            n = 0 if rng.random() < 0.1 else int(rng.integers(1000, tr.aip[t].size + 1))
+            a, b = tr.aip[t][:n], tr.bip[t][:n]
+            cuts = np.sort(rng.integers(0, n + 1, int(rng.integers(0, 3)))) if n else []
+            bounds = [0, *list(cuts), n]
+            parts = [(lo, hi) for lo, hi in zip(bounds[:-1], bounds[1:]) if hi > lo]
+            da, db = (to_dev(a), to_dev(b)) if n else (None, None)
+            keep += [da, db]
+            last = bool(rng.random() < 0.6)
+            for j, (lo, hi) in enumerate(parts):
+                if last and j == len(parts) - 1:
+                    ev.append(("last", da[lo:hi], db[lo:hi], a[lo:hi], b[lo:hi], k))
+                else:
+                    ev.append(("chunk", da[lo:hi], db[lo:hi], a[lo:hi], b[lo:hi]))
+            if not (last and parts):
+                ev.append(("end", k))
+        watch = np.unique(np.concatenate([tr.planted_hosts, tr.aip[0][:20]]))[:WATCH_CAP]
+        links.append(dict(k=k, seed=300 + i, events=ev, watch=watch))
+    srv = Server(hbm_budget=1 << 32, max_links=8, cand_cap=CAND_CAP, watch_cap=WATCH_CAP, **TILED_SHAPE)
+    srv.set_mlp(net)
+    ids = []
+    for ln in links:
+        lid, adm = srv.open_link(ln["k"], ln["seed"])
+        assert adm
+        srv.set_watch(lid, ln["watch"])
+        ids.append(lid)
+    cursor = [0] * len(links)
+    results = {lid: [] for lid in ids}
+    n_sub = 0
+    while any(c < len(ln["events"]) for c, ln in zip(cursor, links)):
+        i = int(rng.integers(0, len(links)))
+        if cursor[i] >= len(links[i]["events"]):
+            continue
+        e = links[i]["events"][cursor[i]]
+        cursor[i] += 1
+        if e[0] == "chunk":
+            assert srv.submit(ids[i], e[1], e[2]) == 0
+        elif e[0] == "last":
+            assert srv.submit_last(ids[i], e[1], e[2], e[5]) == 0
+        else:
+            assert srv.end_slice(ids[i], e[1]) == 0
+        n_sub += 1
+        if n_sub % int(rng.integers(2, 9)) == 0:
+            srv.step()
+            for r in srv.results():
+                results[r["link"]].append(r)
+    for _ in range(200):
+        if all(srv.link_state(lid)[2] == 0 for lid in ids):
+            break
+        srv.step()
+        for r in srv.results():
+            results[r["link"]].append(r)
+    for r in srv.results():
+        results[r["link"]].append(r)
+    pools = {lid: srv.read_pool(lid) for lid in ids}
+    ts = srv.tiled_stats()
+    srv.destroy()
+    assert ts["calls"] > 0 and 0 < ts["pairs"] and ts["device_ms"] > 0
+    jobs = []
+    for ln in links:
+        ev = []
+        for e in ln["events"]:
+            if e[0] in ("chunk", "last"):
+                ev.append(("chunk", e[3], e[4]))
+            if e[0] == "last":
+                ev.append(("end", e[5]))
+            if e[0] == "end":
+                ev.append(e)
+        jobs.append((TILED_SHAPE, ln["k"], ln["seed"], ev, ln["watch"], CAND_CAP))
+        ln["flat"] = ev
+    orc = oracle_link_runs(oracle_lib, jobs)
+    for i, (lid, (want, pool)) in enumerate(zip(ids, orc)):
+        compare_serve_with_oracle(results[lid], want, f"tiled mix link {i} vs oracle")
+        assert np.array_equal(pools[lid], pool), f"tiled mix link {i}: pool differs from the oracle"
+    # and against the single-link API on the same device chunks
+    for i, (lid, ln) in enumerate(zip(ids, links)):
+        g = AtPool(k=ln["k"], seed=ln["seed"], **TILED_SHAPE)
+        out = []
+        for e in ln["events"]:
+            if e[0] in ("chunk", "last"):
+                g.ingest(e[1], e[2])
+            if e[0] in ("last", "end"):
+                g.close(e[-1] if e[0] == "last" else e[1])
+                e_l, f_l, e_p = g.estimate_learned(net, ln["watch"])
+                out.append((e_l, f_l))
+        assert len(out) == len(results[lid])
+        for s_, ((e_l, f_l), r) in enumerate(zip(out, results[lid])):
+            assert np.array_equal(r["watch_flags"], f_l), (i, s_)
+            fin = np.isfinite(e_l)
+            assert np.all(np.abs(r["watch_learned"][fin] - e_l[fin]) <= 1e-12 * np.abs(e_l[fin])), (i, s_)
+        g.destroy()

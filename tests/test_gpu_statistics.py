@@ -5,15 +5,16 @@
   not reported, FPR = N+/N and FNR = N-/N.  Reported = restored candidates
   whose estimate reaches theta.  On the realistic-link traffic in the paper's
   geometry (c, s, u, g) = (14, 6, 4, 4096), 2^32 ATs at a row load near the
-  paper's, the method must find nearly all of them; its false reports must
-  be hosts just below theta (the estimator's spread) or a few addresses
-  never seen.
+  paper's: FNR <= 1% with every miss less than 15% above theta; FPR <= 6%,
+  every false report a host within 15% below theta (the estimator's spread)
+  or an address never seen, those at most 5% of N.
 - Small-configuration traffic in the (9, 7, 3, 4096) companion geometry:
   consecutive columns share only c - s = 2 bits, so restore admits many
   phantom addresses (never seen; each of their ATVs is super because of
-  other heavy hosts) with large estimates.  Every true super point must be
-  found and every false report must be such a phantom or a host near the
-  threshold; the phantom count is printed.
+  other heavy hosts) with large estimates.  At most 5% of the true super
+  points may be missed, each less than 15% above theta, and every false
+  report must be such a phantom or a host within 10% of the threshold; the
+  phantom count is printed.
 - Section 5.1's g comparison (the estimate-vs-real figure): with g = 1024,
   hosts above 5000 are estimated poorly, with g = 4096 they are not.  On the
   same traffic and columns, the larger g must give the smaller error for
@@ -97,8 +98,9 @@ def test_fpr_fnr_paper_geometry(torch_cuda, link_trace):
 
 def test_companion_geometry_phantoms(torch_cuda):
     """Small-configuration traffic in the (9, 7, 3, 4096) companion geometry
-    (row load about 0.06): every true super point is found, and every false
-    report is a phantom address that never appeared in the traffic."""
+    (row load about 0.06): at most 5% of the true super points are missed,
+    each just above theta, and every false report is a phantom address that
+    never appeared in the traffic or a host near theta."""
     tr = traffic.generate(traffic.config_small(seed=0))
     h, n = traffic.window_counts(tr.aip, tr.bip, min_count=1)
     geom = dict(k=4, r=4, c=9, s=7, u=3, log2g=12, theta=1024.0, seed=0)
@@ -109,7 +111,10 @@ def test_companion_geometry_phantoms(torch_cuda):
     phantoms = [a for a in false if counts.get(a, 0) == 0]
     print(f"companion geometry: N={N} reported={len(reported)} candidates={m} false={len(false)} "
           f"phantoms={len(phantoms)}")
-    assert len(true_sp - reported) <= 0.05 * N
+    missed = true_sp - reported
+    print(f"companion geometry: missed {sorted(counts[a] for a in missed)}")
+    assert len(missed) <= 0.05 * N
+    assert all(counts[a] < 1.15 * 1024 for a in missed)
     assert all(counts.get(a, 0) == 0 or counts[a] > 0.9 * 1024 for a in false)
     g.destroy()
 

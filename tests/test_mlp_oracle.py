@@ -54,3 +54,36 @@ def test_adam_first_step_closed_form():
     p1, m1, v1 = mlp.adam(p, z, z, g, 1, 1e-3)
     assert np.allclose(p - p1, 1e-3 * np.sign(g), rtol=1e-4, atol=1e-9)
     assert np.allclose(m1, 0.1 * g, rtol=1e-6) and np.allclose(v1, 0.001 * g * g, rtol=1e-5)
+
+
+def _fp32_shuffled_forward(p, X, seed):
+    """The bf16 rounding points of the device with FP32 sums taken in a
+    shuffled order (one product at a time), as another accumulation order."""
+    W1, b1, W2, b2, w3, b3 = mlp.unpack(np.asarray(p, np.float64))
+    f32 = np.float32
+    rng = np.random.default_rng(seed)
+    Xb, W1b, W2b, w3b = mlp.bf16(X), mlp.bf16(W1), mlp.bf16(W2), mlp.bf16(w3)
+
+    def dot(A, B):  # A[n,64] @ B[64,m] in float32, shuffled order
+        z = np.zeros((A.shape[0], B.shape[1]), f32)
+        for k in rng.permutation(A.shape[1]):
+            z = (z + A[:, k:k + 1] * B[k:k + 1, :]).astype(f32)
+        return z
+
+    h1 = mlp.bf16(np.maximum(dot(Xb, W1b.T) + b1.astype(f32), 0))
+    h2 = mlp.bf16(np.maximum(dot(h1, W2b.T) + b2.astype(f32), 0))
+    return dot(h2, w3b[:, None])[:, 0] + f32(b3)
+
+
+def test_forward_bound_covers_another_summation_order():
+    """The per-row bound the GPU forward test uses holds for FP32 sums in
+    other orders, and is far below the output scale."""
+    from .test_gpu_mlp import _forward_bound, _rand_problem
+    for seed in range(3):
+        p, X, _ = _rand_problem(seed, 1500)
+        y_r, _ = mlp.forward_bf16(p, X)
+        y_s = _fp32_shuffled_forward(p, X, seed)
+        d = np.abs(y_s.astype(np.float64) - y_r)
+        b = _forward_bound(p, X)
+        assert (d <= b).all()
+        assert np.median(b) < 1e-2 and b.max() < 0.1
