@@ -198,8 +198,11 @@ def test_admission_by_budget(torch_cuda):
 
 
 # Pools of 4 tiles (256 KiB): a link's step goes to the tiled scan once it
-# holds about 5.5k pairs, so the mix below runs both scans.
+# holds about 5.5k pairs, so the mix below runs both scans.  At this load
+# most windows hold millions of candidate tuples; a budget of 2^22 tuples
+# keeps the oracle's Alg 4 to seconds (both sides then answer AT_E_BUDGET).
 TILED_SHAPE = dict(r=4, c=9, s=8, u=1, log2g=6, theta=48.0)
+TILED_BUDGET = 1 << 22
 
 
 def test_tiled_steps_match_oracle(torch_cuda, oracle_lib):
@@ -239,7 +242,7 @@ def test_tiled_steps_match_oracle(torch_cuda, oracle_lib):
     srv.set_mlp(net)
     ids = []
     for ln in links:
-        lid, adm = srv.open_link(ln["k"], ln["seed"])
+        lid, adm = srv.open_link(ln["k"], ln["seed"], tuple_budget=TILED_BUDGET)
         assert adm
         srv.set_watch(lid, ln["watch"])
         ids.append(lid)
@@ -285,7 +288,7 @@ def test_tiled_steps_match_oracle(torch_cuda, oracle_lib):
                 ev.append(("end", e[5]))
             if e[0] == "end":
                 ev.append(e)
-        jobs.append((TILED_SHAPE, ln["k"], ln["seed"], ev, ln["watch"], CAND_CAP))
+        jobs.append((TILED_SHAPE, ln["k"], ln["seed"], ev, ln["watch"], CAND_CAP, TILED_BUDGET))
         ln["flat"] = ev
     orc = oracle_link_runs(oracle_lib, jobs)
     for i, (lid, (want, pool)) in enumerate(zip(ids, orc)):
