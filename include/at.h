@@ -219,6 +219,25 @@ int at_tuple_count(at_ctx *h, uint64_t *U);
 int at_set_scan_mode(at_ctx *h, int mode);
 
 
+/*
+ * at_ingest_slice_noalloc -- at_ingest_slice for callers that cannot
+ * allocate device memory: code under HIP stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, ordering and result as
+ * at_ingest_slice (every scan gives the same pool); it calls no allocator.
+ * When the scan mode picks the tiled scan, the call's records and tables live
+ * in a fixed device array of AT_NOALLOC_SCRATCH_BYTES that the library keeps
+ * on every GPU it runs on until the process ends; where at_ingest_slice would
+ * bin, the direct scan (no scratch) runs.  n above AT_NOALLOC_MAX_PAIRS gives
+ * AT_E_INVAL with nothing done: split larger slices over several calls.  All
+ * calls on one GPU share that array and nothing in it needs clearing; calls
+ * that overlap in time on one GPU (other handles' streams included) race.
+ * Errors: as at_ingest_slice; AT_E_DEVICE if the array's address could not be
+ * had when the handle was created.
+ */
+#define AT_NOALLOC_MAX_PAIRS (1ull << 20)
+#define AT_NOALLOC_SCRATCH_BYTES (33ull << 20)
+int at_ingest_slice_noalloc(at_ctx *h, const uint32_t *aip_dev, const uint32_t *bip_dev, uint64_t n);
+
 /* ------------------------------------------------------ learned correction
  * Not in the paper: a small network that corrects the plain estimate from the
  * host's occupancy-by-age profile, with the plain estimate kept as fallback.

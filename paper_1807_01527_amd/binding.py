@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libatpool.so")
 
 AT_OK, AT_E_INVAL, AT_E_STATE, AT_E_NOMEM, AT_E_OVERFLOW, AT_E_DEVICE, AT_E_BUDGET = 0, -1, -2, -3, -4, -5, -6
 AT_F_SAT, AT_F_NEG, AT_F_FALLBACK, AT_F_SUPER = 1, 2, 4, 8
+NOALLOC_MAX_PAIRS = 1 << 20           # AT_NOALLOC_MAX_PAIRS
 
 
 class AtError(RuntimeError):
@@ -39,6 +40,7 @@ _u8p, _u32p, _u64p, _f64p, _f32p = (C.POINTER(C.c_uint8), C.POINTER(C.c_uint32),
 SIGNATURES = {
     "at_create": (C.c_int, [C.POINTER(Params), _vp, C.POINTER(_vp)]),
     "at_ingest_slice": (C.c_int, [_vp, _vp, _vp, C.c_uint64]),
+    "at_ingest_slice_noalloc": (C.c_int, [_vp, _vp, _vp, C.c_uint64]),
     "at_close_slice": (C.c_int, [_vp, C.c_uint32]),
     "at_close_slice_multi": (C.c_int, [_vp, _u32p, C.c_uint32]),
     "at_select_window": (C.c_int, [_vp, C.c_uint32]),
@@ -231,6 +233,16 @@ class AtPool:
             raise ValueError("n exceeds the device arrays")
         _check(self.lib.at_ingest_slice(self._handle(), C.c_void_p(_dev_ptr(aip_dev)),
                                         C.c_void_p(_dev_ptr(bip_dev)), n), "at_ingest_slice")
+
+    def ingest_noalloc(self, aip_dev, bip_dev, n: Optional[int] = None) -> int:
+        """at_ingest_slice_noalloc; returns its code (AT_E_INVAL above
+        NOALLOC_MAX_PAIRS) instead of raising."""
+        if n is None:
+            n = aip_dev.numel()
+        if aip_dev.numel() < n or bip_dev.numel() < n:
+            raise ValueError("n exceeds the device arrays")
+        return self.lib.at_ingest_slice_noalloc(self._handle(), C.c_void_p(_dev_ptr(aip_dev)),
+                                                C.c_void_p(_dev_ptr(bip_dev)), n)
 
     def ingest_raw(self, aip_ptr: int, bip_ptr: int, n: int) -> int:
         return self.lib.at_ingest_slice(self._handle(), C.c_void_p(aip_ptr), C.c_void_p(bip_ptr), n)

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -60,6 +61,7 @@ struct at_ctx {
     bool wfused = false;          // window-0 weights of the open slice already written by its one tiled call
     uint32_t wfused_kq = 0;
     int scan_mode = 0;            // 0 auto, 1 direct, 2 binned, 3 tiled
+    uint8_t* scratch_dev = nullptr;  // this device's address of the no-alloc scratch array (or null)
     // grow-on-demand device scratch
     uint32_t* cand = nullptr;
     uint64_t cand_cap = 0;
@@ -155,6 +157,60 @@ bool device_accessible(const void* ptr) {
     }
     return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged ||
            attr.type == hipMemoryTypeUnified || (attr.type == hipMemoryTypeHost && attr.devicePointer != nullptr);
+}
+
+}  // namespace
+
+// Scratch of at_ingest_slice_noalloc: the tiled scan's records and tables of
+// one call, for callers that cannot allocate.  Every GPU the library runs on
+// holds its own copy until the process ends.  In host code the array's name
+// is only a stand-in: kernels get the device address that
+// hipGetSymbolAddress returns with that device current, kept per device.
+static __device__ __align__(256) uint8_t scratch[AT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+uint8_t* scratch_addr[kMaxDevices] = {};
+
+// Set-up, once per device (the caller has made `device` current): the
+// array's address on that device, or null if it cannot be had.
+uint8_t* scratch_on(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (!scratch_addr[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        scratch_addr[device] = static_cast<uint8_t*>(ptr);
+    }
+    return scratch_addr[device];
+}
+
+uint64_t up256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// The tiled scan's buffers for a call of z's size carved from the scratch
+// array at base; returns the bytes used.
+uint64_t carve_tiles(uint8_t* base, const atp::TileSizes& z, const Geometry& G, atp::TileBufs* tb) {
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        uint8_t* p = base ? base + off : nullptr;
+        off += up256(bytes);
+        return p;
+    };
+    tb->rec = reinterpret_cast<uint16_t*>(take(z.recs * 2));
+    tb->cnt = reinterpret_cast<uint32_t*>(take(z.table * 4));
+    tb->pre = reinterpret_cast<uint32_t*>(take(z.table * 4));
+    tb->csum = reinterpret_cast<uint32_t*>(take((uint64_t)z.nchunk * 4096 * 4));
+    tb->base = reinterpret_cast<uint32_t*>(take(4097 * 4));
+    tb->act = take((uint64_t)G.g * G.atb);
+    tb->rec_cap = z.recs;
+    tb->table_cap = z.table;
+    tb->chunk_cap = z.nchunk;
+    return off;
 }
 
 // Opening slice t: C0 = t mod 2k and Alg 2 on the due blocks.  With
@@ -395,6 +451,7 @@ int at_create(const at_params* p, void* hip_stream, at_ctx** out) {
         delete h;
         return AT_E_DEVICE;
     }
+    h->scratch_dev = scratch_on(h->device);  // null: at_ingest_slice_noalloc answers AT_E_DEVICE
     h->nframe = 1u << p->u;
     h->ngroups = h->nframe * p->r;
     h->n_atv = (uint64_t)h->ngroups << p->c;
@@ -557,6 +614,31 @@ int at_ingest_slice(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev,
             return AT_E_DEVICE;
     }
     return AT_OK;
+}
+
+int at_ingest_slice_noalloc(at_ctx* h, const uint32_t* aip_dev, const uint32_t* bip_dev, uint64_t n) {
+    if (!h || n > AT_NOALLOC_MAX_PAIRS) return AT_E_INVAL;
+    if (n > 0) {
+        if (!aip_dev || !bip_dev) return AT_E_INVAL;
+        if (!device_accessible(aip_dev) || !device_accessible(bip_dev)) return AT_E_INVAL;
+    }
+    int path = n ? scan_path(h, n) : 0;
+    if (path == kBinned) path = kDirect;  // the binned scan's bins are not in the scratch array
+    atp::TileBufs tb{};
+    if (path == kTiled) {
+        // checked before the slice opens: a tiled call that opens it owns its preserve
+        if (!h->scratch_dev) return AT_E_DEVICE;
+        const atp::TileSizes z = atp::tiled_sizes(n, h->pool_bytes, h->G);
+        if (carve_tiles(h->scratch_dev, z, h->G, &tb) > AT_NOALLOC_SCRATCH_BYTES) return AT_E_INVAL;
+    }
+    const bool fuse = !h->open && path == kTiled;
+    int rc = open_slice(h, fuse);
+    if (rc) return rc;
+    if (n == 0) return AT_OK;
+    h->wfused = false;
+    if (path == kTiled) return ingest_tiled_with(h, aip_dev, bip_dev, n, fuse, tb);
+    return atp::launch_ingest(h->pool, aip_dev, bip_dev, n, h->G, h->c0, h->stream) == hipSuccess ? AT_OK
+                                                                                                 : AT_E_DEVICE;
 }
 
 int at_set_scan_mode(at_ctx* h, int mode) {
