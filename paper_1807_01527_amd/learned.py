@@ -10,6 +10,7 @@ This module only orchestrates.  Labels are the exact distinct counts of the
 synthetic traces.
 
     python -m paper_1807_01527_amd.learned --geom small --samples 1000000 --out weights/small.npy
+    python -m paper_1807_01527_amd.learned --geom large --samples 500000 --eval-seeds 4 --out weights/large.npy
 """
 from __future__ import annotations
 
@@ -102,7 +103,7 @@ def build_dataset_stream(name: str, n_samples: int, seed: int = 1, log=print, pe
         big = np.nonzero(counts >= geom["theta"])[0]
         small = np.nonzero((counts >= 16) & (counts < geom["theta"]))[0]
         rng = np.random.default_rng(ts)
-        take = min(small.size, max(big.size, per_trace - big.size))
+        take = min(small.size, big.size)
         sel = np.concatenate([big, rng.choice(small, take, replace=False)])[:per_trace]
         hd = torch.from_numpy(hosts[sel].view(np.int32)).to(dev)
         feat = torch.empty((sel.size, 64), dtype=torch.float32, device=dev)

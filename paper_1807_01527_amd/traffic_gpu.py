@@ -102,12 +102,15 @@ _CDF = {}
 
 
 def _zipf_cdf(hosts: int, s: float, device) -> torch.Tensor:
+    """Zipf(s) CDF over ranks 1..hosts.  The prefix sums run on the host in
+    rank order: a device scan may associate its float additions differently
+    from run to run, and a last-bit change moves the rank a uniform draw maps
+    to, so a trace would no longer be the same in every process."""
     key = (hosts, s, str(device))
     if key not in _CDF:
-        w = torch.arange(1, hosts + 1, dtype=torch.float64, device=device).pow(-s)
-        c = torch.cumsum(w, 0)
+        c = np.cumsum(np.arange(1, hosts + 1, dtype=np.float64) ** -s)
         _CDF.clear()
-        _CDF[key] = c / c[-1]
+        _CDF[key] = torch.from_numpy(c / c[-1]).to(device)
     return _CDF[key]
 
 
