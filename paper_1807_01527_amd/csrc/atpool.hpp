@@ -77,7 +77,7 @@ struct TileBufs {
     uint16_t* rec;   // rec_cap records
     uint32_t* cnt;   // table_cap: per-block tile counts
     uint32_t* pre;   // table_cap: per-(block, tile) run starts
-    uint32_t* csum;  // chunk_cap * 4096: per-chunk column sums, then their prefixes
+    uint32_t* csum;  // chunk_cap * 4096: per-chunk column sums, then the tile totals (nchunk + 1 rows)
     uint32_t* base;  // 4097 region starts
     uint8_t* act;    // g ATs: the slice's block timestamp per position (for the window count)
     uint64_t rec_cap, table_cap, chunk_cap;
@@ -219,9 +219,20 @@ struct CloseDesc {
     uint32_t ready;  // the slice's weights for window kq were written by its tiled scan: no pool pass
 };
 
+struct ServeState;
+struct ServeExport {  // device addresses of the mapped host copies of a step's results
+    ServeState* state;
+    uint32_t* hosts;
+    double* est;
+    double* est_l;
+    uint8_t* flags;
+    uint64_t max_hosts;
+};
+
 struct StepDesc {  // one serving step, copied to the device before each replay
     uint32_t n_open, n_chunks, n_close, pad;
     uint64_t n_units;
+    ServeExport xp;  // where the step's results go
     uint64_t open_prefix[kServeMaxLinks + 1];
     OpenDesc open[kServeMaxLinks];
     CloseDesc close[kServeMaxLinks];
@@ -257,6 +268,7 @@ struct ServeBufs {  // device buffers of one server's step graph
     float* y;          // network output
     double* est_l;     // learned estimates
     uint8_t* flags_l;  // returned flags
+    uint8_t* act;      // kServeMaxLinks x g: block timestamp of every AT position, per close
     uint64_t max_hosts;
     uint32_t cand_cap;
     uint32_t pad;
@@ -276,6 +288,9 @@ hipError_t launch_gather_pairs(const GatherList& Lst, uint32_t* aip_out, uint32_
 
 hipError_t launch_serve_ingest_branch(const ServeBufs& B, const Geometry& shape, hipStream_t st);
 hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, uint64_t n_atv, hipStream_t st);
+// State block and the used host rows to the descriptor's export set (flags:
+// learned when `learned`, else plain).
+hipError_t launch_serve_export(const ServeBufs& B, bool learned, hipStream_t st);
 hipError_t launch_mlp_forward_devn(const float* X, const uint64_t* n_dev, uint64_t nrows_max, const MlpDev& P, float* y,
                                    hipStream_t st);
 hipError_t launch_learned_combine_devn(const float* y, const float* feat, const double* plain, const uint8_t* pflags,

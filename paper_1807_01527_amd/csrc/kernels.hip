@@ -479,9 +479,21 @@ __device__ __forceinline__ uint32_t xcd_contiguous_block(uint32_t w, uint32_t nb
 // it depends on aip alone and this pass never reads bip.
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restrict__ aip, uint64_t n, Geometry G,
-                                                       uint32_t ts, uint32_t n_tiles, uint32_t* __restrict__ cnt) {
+                                                       uint32_t ts, uint32_t n_tiles, uint32_t* __restrict__ cnt,
+                                                       uint32_t* __restrict__ tot, void* __restrict__ act_table,
+                                                       uint32_t c0) {
     __shared__ uint32_t hist[kMaxTiles];
     for (uint32_t t = threadIdx.x; t < n_tiles; t += kBlock) hist[t] = 0;
+    {   // tile totals start at zero (the column pass adds into them); the
+        // slice's block timestamp of every AT position, for the tile pass
+        const uint32_t tid = blockIdx.x * kBlock + threadIdx.x, nthr = gridDim.x * kBlock;
+        for (uint32_t t = tid; t < n_tiles; t += nthr) tot[t] = 0;
+        if (act_table)
+            for (uint32_t i = tid; i < G.g; i += nthr) {
+                if (G.atb == 2) static_cast<uint16_t*>(act_table)[i] = (uint16_t)act_of(i, c0, G);
+                else static_cast<uint8_t*>(act_table)[i] = (uint8_t)act_of(i, c0, G);
+            }
+    }
     __syncthreads();
     constexpr uint32_t P = kTileRecs / R;
     const uint32_t blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
@@ -524,10 +536,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restric
     for (uint32_t t = threadIdx.x; t < n_tiles; t += kBlock) row[t] = hist[t];
 }
 
-// Column sums of cnt over each chunk of kTileChunk rows -> csum[chunk][tile].
-// A block takes 64 tiles of one chunk; each of its kColGroups waves sums
-// kTileChunk / kColGroups rows (loads issued together) and the waves' sums
-// meet in LDS.  Rows of 64 tiles are 256-byte coalesced reads.
+// Column sums of cnt over each chunk of kTileChunk rows -> csum[chunk][tile],
+// and their totals over the chunks -> csum[nchunk][tile].  A block takes 64
+// tiles of one chunk; each of its kColGroups waves sums kTileChunk /
+// kColGroups rows (loads issued together) and the waves' sums meet in LDS.
+// Rows of 64 tiles are 256-byte coalesced reads.
 constexpr uint32_t kColTiles = 64;
 constexpr uint32_t kColGroups = kBlock / kColTiles;
 constexpr uint32_t kColRows = kTileChunk / kColGroups;
@@ -554,6 +567,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_chunksum(const uint32_t* __rest
 #pragma unroll
         for (uint32_t g = 0; g < kColGroups; g++) tot += part[g][tl];
         csum[(uint64_t)c * n_tiles + t] = tot;
+        // the row after the last chunk holds the tile totals
+        atomicAdd(&csum[(uint64_t)gridDim.y * n_tiles + t], tot);
     }
 }
 
@@ -586,65 +601,64 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
     return r;
 }
 
-// One block of kScatterBlock threads: per tile, the exclusive prefix of its
-// chunk sums (in place) and its total; then the exclusive prefix of the tile
-// totals -> base[0..n_tiles].  Thread x takes tiles x, x + kScatterBlock, ...
-template <typename T>
-__global__ __launch_bounds__(kScatterBlock) void k_tile_scan(uint32_t* __restrict__ csum, uint32_t nchunk,
-                                                             uint32_t n_tiles, uint32_t* __restrict__ base,
-                                                             T* __restrict__ act_table, Geometry G, uint32_t c0) {
-    __shared__ uint32_t scratch[kScatterBlock / 64 + 1];
-    // the slice's block timestamp of every AT position, read by the tile pass
-    if (act_table)
-        for (uint32_t i = threadIdx.x; i < G.g; i += kScatterBlock) act_table[i] = (T)act_of(i, c0, G);
-    uint32_t carry = 0;
-    for (uint32_t t0 = 0; t0 < n_tiles; t0 += kScatterBlock) {
-        const uint32_t t = t0 + threadIdx.x;
-        uint32_t run = 0;
-        if (t < n_tiles)
-            for (uint32_t c0 = 0; c0 < nchunk; c0 += 8) {
-                uint32_t v[8];
-#pragma unroll
-                for (uint32_t u = 0; u < 8; u++)
-                    v[u] = c0 + u < nchunk ? csum[(uint64_t)(c0 + u) * n_tiles + t] : 0u;
-#pragma unroll
-                for (uint32_t u = 0; u < 8; u++)
-                    if (c0 + u < nchunk) {
-                        csum[(uint64_t)(c0 + u) * n_tiles + t] = run;
-                        run += v[u];
-                    }
-            }
-        uint32_t sum;
-        const uint32_t p = block_exclusive_scan<kScatterBlock>(run, scratch, &sum);
-        if (t < n_tiles) base[t] = carry + p;
-        carry += sum;
-    }
-    if (threadIdx.x == 0) base[n_tiles] = carry;
-}
-
-// Start of every (block, tile) run in the record array -> pre[b][tile].  The
-// same split as the chunk sums: each wave's 16 rows, loads issued together,
-// start after the rows of the waves before it.
+// Start of every (block, tile) run in the record array -> pre[b][tile], and
+// of every tile's records -> base[tile] (base[n_tiles] = all records).  A
+// tile's records start after those of every earlier tile (the totals of the
+// tiles before the block's 64, summed by the whole block, then a prefix over
+// the 64); a chunk's runs start after the earlier chunks' (their column sums).
+// Within the chunk the same split as the chunk sums: each wave's 16 rows,
+// loads issued together, start after the rows of the waves before it.
 __global__ __launch_bounds__(kBlock) void k_tile_rowpre(const uint32_t* __restrict__ cnt,
-                                                        const uint32_t* __restrict__ cpre,
-                                                        const uint32_t* __restrict__ base, uint32_t nb,
-                                                        uint32_t n_tiles, uint32_t* __restrict__ pre) {
+                                                        const uint32_t* __restrict__ csum, uint32_t nb,
+                                                        uint32_t n_tiles, uint32_t* __restrict__ pre,
+                                                        uint32_t* __restrict__ base) {
     __shared__ uint32_t part[kColGroups][kColTiles];
+    __shared__ uint32_t cp[kColGroups][kColTiles];
+    __shared__ uint32_t red[kBlock / 64];
+    __shared__ uint32_t tbase[kColTiles];
     const uint32_t tl = threadIdx.x % kColTiles, rg = threadIdx.x / kColTiles;
-    const uint32_t t = blockIdx.x * kColTiles + tl;
-    const uint32_t c = blockIdx.y;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t t0 = blockIdx.x * kColTiles, t = t0 + tl;
+    const uint32_t c = blockIdx.y, nchunk = gridDim.y;
+    const uint32_t* tot = csum + (uint64_t)nchunk * n_tiles;
     const uint32_t b0 = c * kTileChunk + rg * kColRows;
     const bool col = t < n_tiles;
     uint32_t v[kColRows];
 #pragma unroll
     for (uint32_t e = 0; e < kColRows; e++) v[e] = (col && b0 + e < nb) ? cnt[(uint64_t)(b0 + e) * n_tiles + t] : 0u;
+    // records of the tiles before this block's
+    uint32_t before = 0;
+    for (uint32_t q = threadIdx.x; q < t0; q += kBlock) before += tot[q];
+    for (uint32_t o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
+    if (lane == 0) red[wv] = before;
+    // this chunk's runs start after the earlier chunks' (split over the waves)
+    uint32_t cs = 0;
+    for (uint32_t q = rg; q < c; q += kColGroups) cs += col ? csum[(uint64_t)q * n_tiles + t] : 0u;
+    cp[rg][tl] = cs;
     uint32_t s = 0;
 #pragma unroll
     for (uint32_t e = 0; e < kColRows; e++) s += v[e];
     part[rg][tl] = s;
     __syncthreads();
+    if (wv == 0) {
+        uint32_t b = 0;
+        for (uint32_t w = 0; w < kBlock / 64; w++) b += red[w];
+        const uint32_t tt = col ? tot[t] : 0u;
+        uint32_t x = tt;  // inclusive prefix of the 64 tiles' totals
+        for (uint32_t o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        tbase[lane] = b + x - tt;
+        if (c == 0 && col) {
+            base[t] = b + x - tt;
+            if (t == n_tiles - 1) base[n_tiles] = b + x;
+        }
+    }
+    __syncthreads();
     if (!col) return;
-    uint32_t run = base[t] + cpre[(uint64_t)c * n_tiles + t];
+    uint32_t run = tbase[tl];
+    for (uint32_t g = 0; g < kColGroups; g++) run += cp[g][tl];
     for (uint32_t g = 0; g < rg; g++) run += part[g][tl];
 #pragma unroll
     for (uint32_t e = 0; e < kColRows; e++) {
@@ -1492,9 +1506,20 @@ __global__ __launch_bounds__(kBlock) void k_serve_ingest(const StepDesc* __restr
 // k'-weights of every ATV of every closing link; block timestamps are
 // computed per byte (links differ in k and C0).
 __global__ __launch_bounds__(kBlock) void k_serve_close(const StepDesc* __restrict__ d, const LinkSlot* __restrict__ L,
-                                                        uint64_t n_atv, uint32_t log2g) {
+                                                        uint64_t n_atv, uint32_t log2g, uint8_t* __restrict__ act) {
     const uint32_t ncl = d->n_close;
     if (ncl == 0) return;
+    {   // the block timestamp of every AT position, per close (read by the feature pass)
+        const uint32_t g = 1u << log2g;
+        const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x, nthr = (uint64_t)gridDim.x * kBlock;
+        for (uint64_t q = tid; q < (uint64_t)ncl * g; q += nthr) {
+            const uint32_t ci = (uint32_t)(q >> log2g), i = (uint32_t)(q & (g - 1u));
+            act[q] = (uint8_t)act_of(i, d->close[ci].c0, L[d->close[ci].slot].G);
+        }
+    }
+    bool all_ready = true;  // every slice's weights already counted by its tiled scan: nothing to read
+    for (uint32_t ci = 0; ci < ncl; ci++) all_ready &= d->close[ci].ready != 0;
+    if (all_ready) return;
     const uint32_t g = 1u << log2g;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t lpa = g / 16 < 64 ? g / 16 : 64;
@@ -1574,37 +1599,53 @@ __global__ __launch_bounds__(kBlock) void k_serve_summarize(const StepDesc* __re
     }
 }
 
-// One thread per closing link: restore items per frame, U and the budget
-// rule; then the items prefix over links (single block, thread 0).
+// One wave per closing link, a lane per frame: restore items per frame (their
+// prefix), U (a saturating sum) and the budget rule; then the items prefix
+// over links (thread 0).
+__device__ __forceinline__ uint64_t sat_add(uint64_t a, uint64_t b) { return UINT64_MAX - a < b ? UINT64_MAX : a + b; }
+
 __global__ void k_serve_restore_prep(const StepDesc* __restrict__ d, const LinkSlot* __restrict__ L,
                                      ServeState* __restrict__ S) {
     const uint32_t ncl = d->n_close;
-    for (uint32_t ci = threadIdx.x; ci < ncl; ci += blockDim.x) {
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    for (uint32_t ci = wv; ci < ncl; ci += nwv) {
         const LinkSlot& ls = L[d->close[ci].slot];
         const Geometry& G = ls.G;
         const uint32_t nframe = G.umask + 1;
         uint64_t U = 0, items = 0;
-        ls.frame_prefix[0] = 0;
-        for (uint32_t z = 0; z < nframe; z++) {
-            uint64_t prod = 1;
-            bool empty = false;
-            for (uint32_t j = 0; j < G.r; j++) {
-                const uint64_t cj = ls.sa_cnt[(uint64_t)z * G.r + j];
-                empty |= cj == 0;
-                prod = (prod == 0 || cj == 0) ? 0 : (prod > UINT64_MAX / cj ? UINT64_MAX : prod * cj);
+        if (lane == 0) ls.frame_prefix[0] = 0;
+        for (uint32_t z0 = 0; z0 < nframe; z0 += 64) {
+            const uint32_t z = z0 + lane;
+            uint64_t prod = 0, it = 0;
+            if (z < nframe) {
+                prod = 1;
+                bool empty = false;
+                for (uint32_t j = 0; j < G.r; j++) {
+                    const uint64_t cj = ls.sa_cnt[(uint64_t)z * G.r + j];
+                    empty |= cj == 0;
+                    prod = (prod == 0 || cj == 0) ? 0 : (prod > UINT64_MAX / cj ? UINT64_MAX : prod * cj);
+                }
+                it = empty ? 0 : ls.sa_cnt[(uint64_t)z * G.r];
+                if (!empty && G.r >= 2) it *= ls.sa_cnt[(uint64_t)z * G.r + 1];
             }
-            U = (UINT64_MAX - U < prod) ? UINT64_MAX : U + prod;
-            uint64_t it = empty ? 0 : ls.sa_cnt[(uint64_t)z * G.r];
-            if (!empty && G.r >= 2) it *= ls.sa_cnt[(uint64_t)z * G.r + 1];
-            items += it;
-            ls.frame_prefix[z + 1] = items;
+            uint64_t x = it;  // inclusive prefix of the items over the lanes
+            for (uint32_t o = 1; o < 64; o <<= 1) {
+                const uint64_t y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            if (z < nframe) ls.frame_prefix[z + 1] = items + x;
+            items += __shfl(x, 63, 64);
+            for (uint32_t o = 32; o > 0; o >>= 1) prod = sat_add(prod, __shfl_xor(prod, o, 64));
+            U = sat_add(U, prod);
         }
-        CloseOut& o = S->out[ci];
-        o.U = U;
-        o.rc = U > ls.tuple_budget ? AT_E_BUDGET : AT_OK;
-        o.items = o.rc == AT_OK ? items : 0;
-        o.cnt = 0;
-        o.m = 0;
+        if (lane == 0) {
+            CloseOut& o = S->out[ci];
+            o.U = U;
+            o.rc = U > ls.tuple_budget ? AT_E_BUDGET : AT_OK;
+            o.items = o.rc == AT_OK ? items : 0;
+            o.cnt = 0;
+            o.m = 0;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1729,7 +1770,9 @@ template <int R>
 __global__ __launch_bounds__(kBlock) void k_serve_features(const StepDesc* __restrict__ d,
                                                            const LinkSlot* __restrict__ L,
                                                            const ServeState* __restrict__ S,
-                                                           const uint32_t* __restrict__ hosts, float* __restrict__ feat,
+                                                           const uint32_t* __restrict__ hosts,
+                                                           const uint8_t* __restrict__ act_all,
+                                                           float* __restrict__ feat,
                                                            double* __restrict__ est, uint8_t* __restrict__ pflags) {
     __shared__ uint32_t hist_all[kBlock / 64][128];
     uint32_t* hist = hist_all[threadIdx.x >> 6];
@@ -1757,23 +1800,34 @@ __global__ __launch_bounds__(kBlock) void k_serve_features(const StepDesc* __res
 #pragma unroll
         for (int j = 0; j < R; j++)
             rows[j] = ls.pool + (((((uint64_t)z * R + j) << G.c) + column(LL, G.sh[j], G.ncol_mask)) << G.log2g);
+        // Two positions per packed 16-bit operation: per row the distance
+        // (ACT - AT) mod 2k, with bit 15 set for an inactive AT, and its
+        // maximum over the rows; the position counts (at age e) when e < k,
+        // i.e. every row is active for the full window.
+        const uint8_t* actp = act_all + ((uint64_t)ci << G.log2g);
+        const uint32_t twok2 = both_halves(G.twok), c_at = both_halves(0x8000u - G.twok);
         for (uint32_t off = lane * 16; off < G.g; off += 64 * 16) {
             uint4 dv[R];
 #pragma unroll
             for (int j = 0; j < R; j++) dv[j] = *reinterpret_cast<const uint4*>(rows[j] + off);
+            const uint4 av = *reinterpret_cast<const uint4*>(actp + off);
 #pragma unroll
-            for (int b = 0; b < 16; b++) {
-                const uint32_t sh = 8 * (b & 3);
-                const uint32_t actb = act_of(off + b, cdsc.c0, G);
-                uint32_t e = 0, ok = 1;
+            for (uint32_t q = 0; q < 4; q++) {
+                const uint32_t aw = word_of(av, q);
+                const uint32_t act_e = aw & 0x00FF00FFu, act_o = (aw >> 8) & 0x00FF00FFu;
+                u16x2 e_e = {0, 0}, e_o = {0, 0};
 #pragma unroll
                 for (int j = 0; j < R; j++) {
-                    const uint32_t at = ((b < 4 ? dv[j].x : b < 8 ? dv[j].y : b < 12 ? dv[j].z : dv[j].w) >> sh) & 0xFFu;
-                    const uint32_t dist = actb >= at ? actb - at : actb + G.twok - at;
-                    ok &= (at != G.twok) & (dist < G.k);
-                    e = dist > e ? dist : e;
+                    const uint32_t w = word_of(dv[j], q);
+                    const Alg1Halves he = alg1_halves(w & 0x00FF00FFu, act_e, twok2, c_at);
+                    const Alg1Halves ho = alg1_halves((w >> 8) & 0x00FF00FFu, act_o, twok2, c_at);
+                    e_e = __builtin_elementwise_max(e_e, as_u16x2(he.dist | he.off));
+                    e_o = __builtin_elementwise_max(e_o, as_u16x2(ho.dist | ho.off));
                 }
-                if (ok) atomicAdd(&hist[e], 1u);
+                if (e_e.x < G.k) atomicAdd(&hist[e_e.x], 1u);
+                if (e_o.x < G.k) atomicAdd(&hist[e_o.x], 1u);
+                if (e_e.y < G.k) atomicAdd(&hist[e_e.y], 1u);
+                if (e_o.y < G.k) atomicAdd(&hist[e_o.y], 1u);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1807,6 +1861,32 @@ __global__ __launch_bounds__(kBlock) void k_serve_features(const StepDesc* __res
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// The step's results to mapped host memory: the state block, then per host
+// of the list its address, plain estimate, learned estimate (when a network
+// is set) and flags.  Only the n_hosts rows in use cross the bus.
+__global__ __launch_bounds__(kBlock) void k_serve_export(const StepDesc* __restrict__ d,
+                                                         const ServeState* __restrict__ S,
+                                                         const uint32_t* __restrict__ hosts,
+                                                         const double* __restrict__ est,
+                                                         const double* __restrict__ est_l,
+                                                         const uint8_t* __restrict__ flags) {
+    const ServeExport X = d->xp;
+    const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t nthr = (uint64_t)gridDim.x * kBlock;
+    constexpr uint32_t kWords = sizeof(ServeState) / 8;
+    static_assert(sizeof(ServeState) % 8 == 0, "the state block copies as 8-byte words");
+    const uint64_t* sw = reinterpret_cast<const uint64_t*>(S);
+    uint64_t* dw = reinterpret_cast<uint64_t*>(X.state);
+    for (uint64_t q = tid; q < kWords; q += nthr) dw[q] = sw[q];
+    const uint64_t n = S->n_hosts < X.max_hosts ? S->n_hosts : X.max_hosts;
+    for (uint64_t h = tid; h < n; h += nthr) {
+        X.hosts[h] = hosts[h];
+        X.est[h] = est[h];
+        if (est_l) X.est_l[h] = est_l[h];
+        X.flags[h] = flags[h];
     }
 }
 
@@ -2056,22 +2136,18 @@ hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_
     if (n == 0) return hipSuccess;
     if (!tiled_fits(pool_bytes)) return hipErrorInvalidValue;
     const TileSizes z = tiled_sizes(n, pool_bytes, G);
-    if (z.recs > B.rec_cap || z.table > B.table_cap || z.nchunk > B.chunk_cap) return hipErrorInvalidValue;
+    if (z.recs > B.rec_cap || z.table > B.table_cap || z.nchunk + 1 > B.chunk_cap) return hipErrorInvalidValue;
     const uint32_t ts = 16u - (G.atb == 2 ? 1u : 0u);  // log2 of the ATs per tile
     const dim3 cols((z.n_tiles + kColTiles - 1) / kColTiles, z.nchunk);
+    uint32_t* tot = B.csum + (uint64_t)z.nchunk * z.n_tiles;  // the row after the chunk sums
     hipError_t e = with_rows<uint8_t>(G.r, [&](auto rc, auto) {
         constexpr int RR = decltype(rc)::value;
-        hipLaunchKernelGGL((k_tile_count<RR>), dim3(z.nb), dim3(kBlock), 0, st, aip, n, G, ts, z.n_tiles, B.cnt);
+        hipLaunchKernelGGL((k_tile_count<RR>), dim3(z.nb), dim3(kBlock), 0, st, aip, n, G, ts, z.n_tiles, B.cnt, tot,
+                           w_out ? static_cast<void*>(B.act) : nullptr, c0);
     });
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_chunksum, cols, dim3(kBlock), 0, st, B.cnt, z.nb, z.n_tiles, B.csum);
-    e = with_at(G, [&](auto t) {
-        using T = decltype(t);
-        hipLaunchKernelGGL(k_tile_scan<T>, dim3(1), dim3(kScatterBlock), 0, st, B.csum, z.nchunk, z.n_tiles, B.base,
-                           w_out ? reinterpret_cast<T*>(B.act) : nullptr, G, c0);
-    });
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile_rowpre, cols, dim3(kBlock), 0, st, B.cnt, B.csum, B.base, z.nb, z.n_tiles, B.pre);
+    hipLaunchKernelGGL(k_tile_rowpre, cols, dim3(kBlock), 0, st, B.cnt, B.csum, z.nb, z.n_tiles, B.pre, B.base);
     e = with_rows<uint8_t>(G.r, [&](auto rc, auto) {
         constexpr int RR = decltype(rc)::value;
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile_scatter<RR>),
@@ -2195,10 +2271,11 @@ hipError_t launch_serve_ingest_branch(const ServeBufs& B, const Geometry& shape,
 
 hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, uint64_t n_atv, hipStream_t st) {
     const uint32_t ngroups = (shape.umask + 1) * shape.r;
-    hipLaunchKernelGGL(k_serve_close, dim3(kServeGrid), dim3(kBlock), 0, st, B.desc, B.slots, n_atv, shape.log2g);
+    hipLaunchKernelGGL(k_serve_close, dim3(kServeGrid), dim3(kBlock), 0, st, B.desc, B.slots, n_atv, shape.log2g,
+                       B.act);
     hipLaunchKernelGGL(k_serve_summarize, dim3(kServeMaxLinks * ngroups), dim3(kBlock), 0, st, B.desc, B.slots,
                        ngroups);
-    hipLaunchKernelGGL(k_serve_restore_prep, dim3(1), dim3(64), 0, st, B.desc, B.slots, B.state);
+    hipLaunchKernelGGL(k_serve_restore_prep, dim3(1), dim3(1024), 0, st, B.desc, B.slots, B.state);
     hipLaunchKernelGGL(k_serve_restore_join, dim3(kServeGrid), dim3(kBlock), 0, st, B.desc, B.slots, B.state,
                        B.cand_cap);
     hipLaunchKernelGGL(k_serve_host_offsets, dim3(1), dim3(64), 0, st, B.desc, B.slots, B.state, B.cand_cap);
@@ -2206,7 +2283,7 @@ hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, 
 #define AT_SERVE_FEAT(RR)                                                                                     \
     case RR:                                                                                                  \
         hipLaunchKernelGGL((k_serve_features<RR>), dim3(kServeGrid), dim3(kBlock), 0, st, B.desc, B.slots, B.state, \
-                           B.hosts, B.feat, B.est, B.pflags);                                                 \
+                           B.hosts, B.act, B.feat, B.est, B.pflags);                                          \
         break;
     switch (shape.r) {
         AT_SERVE_FEAT(1)
@@ -2221,6 +2298,12 @@ hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, 
             return hipErrorInvalidValue;
     }
 #undef AT_SERVE_FEAT
+    return hipGetLastError();
+}
+
+hipError_t launch_serve_export(const ServeBufs& B, bool learned, hipStream_t st) {
+    hipLaunchKernelGGL(k_serve_export, dim3(64), dim3(kBlock), 0, st, B.desc, B.state, B.hosts, B.est,
+                       learned ? B.est_l : nullptr, learned ? B.flags_l : B.pflags);
     return hipGetLastError();
 }
 

@@ -10,9 +10,10 @@
 //   close:  batched close, super lists, restore (budget rule, join, sort),
 //           features + plain estimates of candidates and watch hosts, and
 //           the learned correction;
-// then copies the results to pinned host memory.  A link whose slice ends is
-// closed in the step after its last chunk was scanned, and its next slice
-// waits for that close, so the two branches never touch the same pool.
+// then writes the used rows of the results straight into mapped pinned host
+// memory.  A link whose slice ends is closed in the step after its last
+// chunk was scanned, and its next slice waits for that close, so the two
+// branches never touch the same pool.
 //
 // A link whose queued pairs in a step are many next to its pool takes the
 // tiled scan instead (stores grouped per 64 KiB tile and applied in LDS, the
@@ -21,9 +22,12 @@
 // launches depend on the step's pair count.  Its slice is opened by the tile
 // pass (the preserve runs there), and when the slice's end is already queued
 // behind its chunks the tile pass also writes the window's weights, so the
-// close that follows reads no pool.
+// close that follows reads no pool.  When the link's previous slice closes
+// in the same step, those launches wait on the third stream until the graph
+// has finished with the pool, so a slice takes one step instead of two.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -100,6 +104,8 @@ struct Link {
     uint64_t t = 0;          // slices closed
     bool open = false;
     uint32_t c0 = 0;
+    bool next_open = false;  // slice t+1 was opened by a scan queued behind this step's close of slice t
+    uint32_t next_c0 = 0;
     std::deque<Event> q;
     uint64_t consumed = 0;   // events consumed (chunks + ends)
 };
@@ -139,14 +145,22 @@ struct at_serve {
     float* d_y = nullptr;
     double* d_estl = nullptr;
     uint8_t* d_flagsl = nullptr;
+    uint8_t* d_act = nullptr;     // per close: block timestamp of every AT position
     uint64_t max_hosts = 0;
-    // pinned host
+    // pinned host: the step descriptor, and two sets of mapped result arrays
+    // (the export kernel writes step s's results into set s mod 2, so the
+    // native thread reads one step's results while the next one runs)
     StepDesc* h_desc = nullptr;
-    ServeState* h_state = nullptr;
-    uint32_t* h_hosts = nullptr;
-    double* h_est = nullptr;
-    double* h_estl = nullptr;
-    uint8_t* h_flagsl = nullptr;
+    struct ResultSet {
+        ServeState* state = nullptr;
+        uint32_t* hosts = nullptr;
+        double* est = nullptr;
+        double* estl = nullptr;
+        uint8_t* flags = nullptr;
+        atp::ServeExport xp{};  // their device addresses
+    } rs[2];
+    int cur_set = 0;
+    hipEvent_t ev_graph = nullptr; // recorded after each graph launch: the pool is free for scans
     // graph
     at_mlp* mlp = nullptr;
     const void* mlp_key = nullptr;
@@ -161,6 +175,16 @@ struct at_serve {
     int worker_rc = AT_OK;
     // results
     std::deque<Result> results;
+    // closes of the last step whose results are not yet published (in set pend_set)
+    struct PendingClose {
+        uint32_t link, kq;
+        double t_arrival;
+        uint64_t slice;
+    };
+    std::vector<PendingClose> pending;
+    int pend_set = 0;
+    bool pend_mlp = false;
+    double pend_step_ms = 0.0;
     uint64_t steps = 0;
     double last_step_ms = 0.0;
     uint64_t pairs_ingested = 0;
@@ -270,6 +294,7 @@ int capture_graph(at_serve* S) {
     B.y = S->d_y;
     B.est_l = S->d_estl;
     B.flags_l = S->d_flagsl;
+    B.act = S->d_act;
     B.max_hosts = S->max_hosts;
     B.cand_cap = S->cfg.cand_cap;
     atp::MlpDev P{};
@@ -295,16 +320,7 @@ int capture_graph(at_serve* S) {
         ec = atp::launch_learned_combine_devn(S->d_y, S->d_feat, S->d_est, S->d_pflags, &S->d_state->n_hosts,
                                               S->max_hosts, std::log(16.0) - 0.5, std::log(262144.0) + 0.5,
                                               S->cfg.theta, S->d_estl, S->d_flagsl, S->s1);
-    if (ec == hipSuccess)
-        ec = hipMemcpyAsync(S->h_state, S->d_state, sizeof(ServeState), hipMemcpyDeviceToHost, S->s1);
-    if (ec == hipSuccess)
-        ec = hipMemcpyAsync(S->h_hosts, S->d_hosts, S->max_hosts * 4, hipMemcpyDeviceToHost, S->s1);
-    if (ec == hipSuccess) ec = hipMemcpyAsync(S->h_est, S->d_est, S->max_hosts * 8, hipMemcpyDeviceToHost, S->s1);
-    if (ec == hipSuccess && have_mlp)
-        ec = hipMemcpyAsync(S->h_estl, S->d_estl, S->max_hosts * 8, hipMemcpyDeviceToHost, S->s1);
-    if (ec == hipSuccess)
-        ec = hipMemcpyAsync(S->h_flagsl, have_mlp ? S->d_flagsl : S->d_pflags, S->max_hosts, hipMemcpyDeviceToHost,
-                            S->s1);
+    if (ec == hipSuccess) ec = atp::launch_serve_export(B, have_mlp, S->s1);
     if (ec == hipSuccess) ec = hipEventRecord(S->ev_join, S->s1);
     // branch 0: open + scan
     if (ec == hipSuccess) ec = atp::launch_serve_ingest_branch(B, S->shape, S->s0);
@@ -335,16 +351,18 @@ void free_server(at_serve* S) {
         }
     }
     void* d[] = {S->d_desc, S->d_slots, S->d_state, S->d_hosts, S->d_feat, S->d_est, S->d_pflags, S->d_y, S->d_estl,
-                 S->d_flagsl};
+                 S->d_flagsl, S->d_act};
     for (void* p : d)
         if (p) (void)hipFree(p);
-    void* h[] = {S->h_desc, S->h_state, S->h_hosts, S->h_est, S->h_estl, S->h_flagsl};
+    void* h[] = {S->h_desc,        S->rs[0].state, S->rs[0].hosts, S->rs[0].est, S->rs[0].estl, S->rs[0].flags,
+                 S->rs[1].state,   S->rs[1].hosts, S->rs[1].est,   S->rs[1].estl, S->rs[1].flags};
     for (void* p : h)
         if (p) (void)hipHostFree(p);
     void* t[] = {S->tb.rec, S->tb.cnt, S->tb.pre, S->tb.csum, S->tb.base, S->tb.act, S->stage_a, S->stage_b};
     for (void* p : t)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : S->tev) (void)hipEventDestroy(e);
+    if (S->ev_graph) (void)hipEventDestroy(S->ev_graph);
     if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
     if (S->ev_join) (void)hipEventDestroy(S->ev_join);
     if (S->s2) (void)hipStreamDestroy(S->s2);
@@ -385,11 +403,11 @@ int tiled_buffers(at_serve* S, uint64_t n) {
         if ((rc = dalloc(&S->tb.cnt, z.table)) || (rc = dalloc(&S->tb.pre, z.table))) return rc;
         S->tb.table_cap = z.table;
     }
-    if (z.nchunk > S->tb.chunk_cap) {
+    if (z.nchunk + 1 > S->tb.chunk_cap) {
         if (S->tb.csum) (void)hipFree(S->tb.csum);
         S->tb.chunk_cap = 0;
-        if ((rc = dalloc(&S->tb.csum, (uint64_t)z.nchunk * 4096))) return rc;
-        S->tb.chunk_cap = z.nchunk;
+        if ((rc = dalloc(&S->tb.csum, (uint64_t)(z.nchunk + 1) * 4096))) return rc;
+        S->tb.chunk_cap = z.nchunk + 1;
     }
     if (!S->tb.base && (rc = dalloc(&S->tb.base, 4097))) return rc;
     if (!S->tb.act && (rc = dalloc(&S->tb.act, (uint64_t)S->shape.g))) return rc;
@@ -416,13 +434,23 @@ struct TiledJob {
     bool opens;     // the scan opens the slice: the tile pass runs its preserve
     bool weights;   // the slice's end is queued behind its chunks: the tile pass counts window kq
     uint32_t kq;
+    uint32_t c0;    // block clock of the scanned slice
+    bool after_graph;  // the link's previous slice closes in this step's graph: wait for it
 };
 
-// Launch the tiled jobs on s2 (events around each launch for the timing).
+// Launch the tiled jobs on s2 (events around each launch for the timing):
+// first those of links the graph leaves alone, then, once the graph is done
+// with their pools, those of links whose previous slice it closes.
 int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed) {
     *n_timed = 0;
+    std::stable_partition(jobs.begin(), jobs.end(), [](const TiledJob& J) { return !J.after_graph; });
+    bool waited = false;
     for (TiledJob& J : jobs) {
         Link* L = J.L;
+        if (J.after_graph && !waited) {
+            if (hipStreamWaitEvent(S->s2, S->ev_graph, 0) != hipSuccess) return AT_E_DEVICE;
+            waited = true;
+        }
         int rc = tiled_buffers(S, J.n);
         if (!rc && J.chunks.size() > 1) rc = stage_buffers(S, J.n);
         if (rc) return rc;
@@ -456,7 +484,7 @@ int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed) {
             }
             if (hipEventRecord(S->tev[2 * *n_timed], S->s2) != hipSuccess) return AT_E_DEVICE;
             const bool w = J.weights && single && first;
-            if (atp::launch_ingest_tiled(L->pool, a + off, b + off, m, S->pool_bytes, L->G, L->c0, S->tb,
+            if (atp::launch_ingest_tiled(L->pool, a + off, b + off, m, S->pool_bytes, L->G, J.c0, S->tb,
                                          J.opens && first, w ? L->w : nullptr, J.kq, S->s2) != hipSuccess)
                 return AT_E_DEVICE;
             if (hipEventRecord(S->tev[2 * *n_timed + 1], S->s2) != hipSuccess) return AT_E_DEVICE;
@@ -514,21 +542,34 @@ int at_serve_create(const at_serve_config* cfg, at_serve** out) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_graph, hipEventDisableTiming);
     if (e != hipSuccess) rc = AT_E_DEVICE;
     if (!rc && ((rc = dalloc(&S->d_desc, 1)) || (rc = dalloc(&S->d_slots, atp::kServeMaxLinks)) ||
                 (rc = dalloc(&S->d_state, 1)) || (rc = dalloc(&S->d_hosts, S->max_hosts)) ||
                 (rc = dalloc(&S->d_feat, S->max_hosts * 64)) || (rc = dalloc(&S->d_est, S->max_hosts)) ||
                 (rc = dalloc(&S->d_pflags, S->max_hosts)) || (rc = dalloc(&S->d_y, S->max_hosts)) ||
-                (rc = dalloc(&S->d_estl, S->max_hosts)) || (rc = dalloc(&S->d_flagsl, S->max_hosts)))) {
+                (rc = dalloc(&S->d_estl, S->max_hosts)) || (rc = dalloc(&S->d_flagsl, S->max_hosts)) ||
+                (rc = dalloc(&S->d_act, (uint64_t)atp::kServeMaxLinks * S->shape.g)))) {
     }
     if (!rc) {
-        if (hipHostMalloc((void**)&S->h_desc, sizeof(StepDesc), 0) != hipSuccess ||
-            hipHostMalloc((void**)&S->h_state, sizeof(ServeState), 0) != hipSuccess ||
-            hipHostMalloc((void**)&S->h_hosts, S->max_hosts * 4, 0) != hipSuccess ||
-            hipHostMalloc((void**)&S->h_est, S->max_hosts * 8, 0) != hipSuccess ||
-            hipHostMalloc((void**)&S->h_estl, S->max_hosts * 8, 0) != hipSuccess ||
-            hipHostMalloc((void**)&S->h_flagsl, S->max_hosts, 0) != hipSuccess)
-            rc = AT_E_NOMEM;
+        if (hipHostMalloc((void**)&S->h_desc, sizeof(StepDesc), 0) != hipSuccess) rc = AT_E_NOMEM;
+        const unsigned mf = hipHostMallocMapped;
+        for (int q = 0; q < 2 && !rc; q++) {
+            at_serve::ResultSet& R = S->rs[q];
+            if (hipHostMalloc((void**)&R.state, sizeof(ServeState), mf) != hipSuccess ||
+                hipHostMalloc((void**)&R.hosts, S->max_hosts * 4, mf) != hipSuccess ||
+                hipHostMalloc((void**)&R.est, S->max_hosts * 8, mf) != hipSuccess ||
+                hipHostMalloc((void**)&R.estl, S->max_hosts * 8, mf) != hipSuccess ||
+                hipHostMalloc((void**)&R.flags, S->max_hosts, mf) != hipSuccess)
+                rc = AT_E_NOMEM;
+            R.xp.max_hosts = S->max_hosts;
+            if (!rc && (hipHostGetDevicePointer((void**)&R.xp.state, R.state, 0) != hipSuccess ||
+                        hipHostGetDevicePointer((void**)&R.xp.hosts, R.hosts, 0) != hipSuccess ||
+                        hipHostGetDevicePointer((void**)&R.xp.est, R.est, 0) != hipSuccess ||
+                        hipHostGetDevicePointer((void**)&R.xp.est_l, R.estl, 0) != hipSuccess ||
+                        hipHostGetDevicePointer((void**)&R.xp.flags, R.flags, 0) != hipSuccess))
+                rc = AT_E_DEVICE;
+        }
     }
     if (rc) {
         free_server(S);
@@ -698,8 +739,56 @@ int at_serve_submit_last(at_serve* S, uint32_t link_id, const uint32_t* aip_dev,
     return AT_OK;
 }
 
-int at_serve_step(at_serve* S, uint32_t* n_results) {
-    if (!S) return AT_E_INVAL;
+}  // extern "C"
+
+namespace {
+
+// The pending closes' results (from mapped set pend_set) into the result
+// queue; returns how many.  Caller holds mu.
+uint32_t publish_pending(at_serve* S) {
+    const at_serve::ResultSet& X = S->rs[S->pend_set];
+    const double now = now_ms();
+    uint32_t produced = 0;
+    for (uint32_t ci = 0; ci < S->pending.size(); ci++) {
+        const at_serve::PendingClose& pc = S->pending[ci];
+        const atp::CloseOut& o = X.state->out[ci];
+        Result R{};
+        R.r.link = pc.link;
+        R.r.kprime = pc.kq;
+        R.r.slice = pc.slice;
+        R.r.restore_rc = o.rc;
+        R.r.n_out = o.rc == AT_E_BUDGET ? o.U : o.m;
+        R.r.n_cand = o.n_cand;
+        R.r.n_watch = o.n_hosts - o.n_cand;
+        R.r.latency_ms = now - pc.t_arrival;
+        R.r.step_ms = S->pend_step_ms;
+        const uint64_t h0 = o.host_off, nc = o.n_cand, nw = (uint64_t)o.n_hosts - nc;
+        R.cand.assign(X.hosts + h0, X.hosts + h0 + nc);
+        R.cand_est.assign(X.est + h0, X.est + h0 + nc);
+        R.watch_plain.assign(X.est + h0 + nc, X.est + h0 + nc + nw);
+        const uint8_t fb = S->pend_mlp ? 0 : (uint8_t)AT_F_FALLBACK;
+        R.cand_flags.resize(nc);
+        R.watch_flags.resize(nw);
+        for (uint64_t q = 0; q < nc; q++) R.cand_flags[q] = X.flags[h0 + q] | fb;
+        for (uint64_t q = 0; q < nw; q++) R.watch_flags[q] = X.flags[h0 + nc + q] | fb;
+        if (S->pend_mlp) {
+            R.cand_learned.assign(X.estl + h0, X.estl + h0 + nc);
+            R.watch_learned.assign(X.estl + h0 + nc, X.estl + h0 + nc + nw);
+        } else {
+            R.cand_learned = R.cand_est;
+            R.watch_learned = R.watch_plain;
+        }
+        S->results.push_back(std::move(R));
+        produced++;
+    }
+    S->pending.clear();
+    return produced;
+}
+
+// One step.  The previous step's results are published once this step's
+// work is on the GPU (so reading them overlaps it); with `flush` this step's
+// own results are published before returning.
+int serve_step(at_serve* S, uint32_t* n_results, bool flush) {
     if (n_results) *n_results = 0;
     std::lock_guard<std::mutex> sg(S->step_mu);
     std::unique_lock<std::mutex> lk(S->mu);
@@ -711,6 +800,8 @@ int at_serve_step(at_serve* S, uint32_t* n_results) {
     D.n_open = D.n_chunks = D.n_close = 0;
     D.n_units = 0;
     D.open_prefix[0] = 0;
+    const int set = S->cur_set;  // this step's results go to mapped set `set`
+    D.xp = S->rs[set].xp;
     struct CloseRec {
         Link* L;
         uint32_t kq;
@@ -732,6 +823,28 @@ int at_serve_step(at_serve* S, uint32_t* n_results) {
             c.ready = L->wready && L->wready_kq == first.kprime ? 1u : 0u;
             L->wready = false;
             closes.push_back(CloseRec{L, first.kprime, first.t_arrival, L->t});
+            // the next slice's pairs queued behind this end, if the tiled scan takes
+            // them, are scanned after the graph has finished with the pool
+            uint64_t n = 0;
+            bool end_follows = false;
+            uint32_t kq = 0;
+            for (auto it = std::next(L->q.begin()); it != L->q.end(); ++it) {
+                if (it->end) {
+                    end_follows = true;
+                    kq = it->kprime;
+                    break;
+                }
+                if (it->aip) n += it->n;
+            }
+            if (take_tiled(S, n)) {
+                L->next_open = true;
+                L->next_c0 = (uint32_t)((L->t + 1) % L->G.twok);
+                TiledJob J{L, {}, n, true, end_follows, kq, L->next_c0, true};
+                for (auto it = std::next(L->q.begin()); it != L->q.end() && !it->end; ++it)
+                    if (it->aip) J.chunks.push_back(&*it);
+                pairs += n;
+                tiled.push_back(std::move(J));
+            }
             continue;
         }
         {
@@ -748,11 +861,12 @@ int at_serve_step(at_serve* S, uint32_t* n_results) {
                 if (ev.aip) n += ev.n;
             }
             if (take_tiled(S, n)) {
-                TiledJob J{L, {}, n, !L->open, false, kq};
+                TiledJob J{L, {}, n, !L->open, false, kq, 0, false};
                 if (!L->open) {
                     L->open = true;
                     L->c0 = (uint32_t)(L->t % L->G.twok);
                 }
+                J.c0 = L->c0;
                 J.weights = J.opens && end_follows;
                 for (Event& ev : L->q) {
                     if (ev.end) break;
@@ -795,8 +909,14 @@ int at_serve_step(at_serve* S, uint32_t* n_results) {
 
     const double t0 = now_ms();
     hipError_t e = hipGraphLaunch(S->exec, S->s0);
+    if (e == hipSuccess) e = hipEventRecord(S->ev_graph, S->s0);
     uint32_t n_timed = 0;
     int trc = e == hipSuccess ? run_tiled(S, tiled, &n_timed) : AT_OK;
+    uint32_t produced = 0;
+    {  // the previous step's results (the other mapped set) while this one runs
+        std::lock_guard<std::mutex> g(S->mu);
+        produced += publish_pending(S);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(S->s0);
     hipError_t e2 = hipStreamSynchronize(S->s2);
     const double t1 = now_ms();
@@ -816,7 +936,7 @@ int at_serve_step(at_serve* S, uint32_t* n_results) {
         S->tiled_pairs += J.n;
         for (const Event* ev : J.chunks) const_cast<Event*>(ev)->aip = nullptr;  // handed to this step
     }
-    // retire scanned chunks and closed slices
+    // retire scanned chunks (those ahead of a closed slice's end, below)
     for (Link* L : S->links) {
         if (!L || L->state != L_ACTIVE) continue;
         while (!L->q.empty() && !L->q.front().end && L->q.front().aip == nullptr) {
@@ -824,47 +944,41 @@ int at_serve_step(at_serve* S, uint32_t* n_results) {
             L->consumed++;
         }
     }
-    uint32_t produced = 0;
+    // this step's closes: their results are in set `set`, published by the next
+    // step (or below with flush)
+    S->pending.clear();
+    for (const CloseRec& cr : closes)
+        S->pending.push_back(at_serve::PendingClose{cr.L->id, cr.kq, cr.t_arrival, cr.slice});
+    S->pend_set = set;
+    S->pend_mlp = S->mlp_key != nullptr;
+    S->pend_step_ms = t1 - t0;
+    S->cur_set = set ^ 1;
     for (uint32_t ci = 0; ci < closes.size(); ci++) {
         const CloseRec& cr = closes[ci];
-        const atp::CloseOut& o = S->h_state->out[ci];
-        Result R{};
-        R.r.link = cr.L->id;
-        R.r.kprime = cr.kq;
-        R.r.slice = cr.slice;
-        R.r.restore_rc = o.rc;
-        R.r.n_out = o.rc == AT_E_BUDGET ? o.U : o.m;
-        R.r.n_cand = o.n_cand;
-        R.r.n_watch = o.n_hosts - o.n_cand;
-        R.r.latency_ms = t1 - cr.t_arrival;
-        R.r.step_ms = t1 - t0;
-        const bool have_mlp = S->mlp_key != nullptr;
-        for (uint32_t q = 0; q < o.n_hosts; q++) {
-            const uint64_t h = (uint64_t)o.host_off + q;
-            const double plain = S->h_est[h];
-            const double learned = have_mlp ? S->h_estl[h] : plain;
-            const uint8_t fl = S->h_flagsl[h] | (have_mlp ? 0 : (uint8_t)AT_F_FALLBACK);
-            if (q < o.n_cand) {
-                R.cand.push_back(S->h_hosts[h]);
-                R.cand_est.push_back(plain);
-                R.cand_learned.push_back(learned);
-                R.cand_flags.push_back(fl);
-            } else {
-                R.watch_plain.push_back(plain);
-                R.watch_learned.push_back(learned);
-                R.watch_flags.push_back(fl);
-            }
-        }
-        S->results.push_back(std::move(R));
         Link* L = cr.L;
         L->q.pop_front();  // the end event
         L->consumed++;
         L->t += 1;
-        L->open = false;
-        produced++;
+        L->open = L->next_open;  // the next slice may have been opened by a scan of this step
+        L->c0 = L->next_open ? L->next_c0 : L->c0;
+        L->next_open = false;
+        while (!L->q.empty() && !L->q.front().end && L->q.front().aip == nullptr) {
+            L->q.pop_front();  // the next slice's chunks that scan took
+            L->consumed++;
+        }
     }
+    if (flush) produced += publish_pending(S);
     if (n_results) *n_results = produced;
     return AT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int at_serve_step(at_serve* S, uint32_t* n_results) {
+    if (!S) return AT_E_INVAL;
+    return serve_step(S, n_results, true);
 }
 
 }  // extern "C"
@@ -882,11 +996,12 @@ void worker_loop(at_serve* S) {
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(S->mu);
+            if (!has_work(S)) publish_pending(S);  // no step to overlap them with
             S->cv.wait(lk, [&] { return S->stop || has_work(S); });
             if (S->stop && !has_work(S)) return;
         }
         uint32_t n = 0;
-        int rc = at_serve_step(S, &n);
+        int rc = serve_step(S, &n, false);
         if (rc != AT_OK) {
             std::lock_guard<std::mutex> lk(S->mu);
             S->worker_rc = rc;
