@@ -730,8 +730,12 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
         st += c[e];
     }
     __syncthreads();
+    // lane l takes its rows in the order (j + l) mod R, as in pass 1: lanes
+    // holding one frequent host then move different tiles' cursors together
+    const uint32_t rot = threadIdx.x % R;
 #pragma unroll
     for (uint32_t e = 0; e < PPT; e++) {
+        rotate_rows<R>(tgt[e], rot);
 #pragma unroll
         for (int j = 0; j < R; j++) {
             const uint32_t v = tgt[e][j];
@@ -743,49 +747,6 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
     for (uint32_t i = threadIdx.x; i < total; i += kScatterBlock) {
         const uint32_t v = staged[i];
         rec[gbase[v >> 16] + i] = (uint16_t)(v & 0xFFFFu);
-    }
-}
-
-// Records [lo, hi) of a tile set their ATs in the LDS copy tl to the block
-// timestamp ACT(i): a ragged head and tail one by one, the 8-aligned body
-// eight at a time with 16-byte loads, four in flight per thread.
-template <typename T, typename F>
-__device__ __forceinline__ void apply_records(T* tl, const uint16_t* __restrict__ rec, uint32_t lo, uint32_t hi,
-                                              uint32_t gmask, F act) {
-    const uint32_t a8 = (lo + 7u) & ~7u, b8 = hi & ~7u;
-    if (a8 >= b8) {
-        for (uint32_t q = lo + threadIdx.x; q < hi; q += kApplyBlock) {
-            const uint32_t loc = rec[q];
-            tl[loc] = (T)act(loc & gmask);
-        }
-        return;
-    }
-    if (lo + threadIdx.x < a8) {
-        const uint32_t loc = rec[lo + threadIdx.x];
-        tl[loc] = (T)act(loc & gmask);
-    }
-    if (b8 + threadIdx.x < hi) {
-        const uint32_t loc = rec[b8 + threadIdx.x];
-        tl[loc] = (T)act(loc & gmask);
-    }
-    const uint4* r8 = reinterpret_cast<const uint4*>(rec + a8);
-    const uint32_t n8 = (b8 - a8) / 8;
-    for (uint32_t q0 = threadIdx.x; q0 < n8; q0 += 4 * kApplyBlock) {
-        uint4 v[4];
-#pragma unroll
-        for (uint32_t u = 0; u < 4; u++) {
-            const uint32_t q = q0 + u * kApplyBlock;
-            v[u] = q < n8 ? r8[q] : make_uint4(~0u, ~0u, ~0u, ~0u);
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < 4; u++) {
-            if (q0 + u * kApplyBlock >= n8) break;
-#pragma unroll
-            for (uint32_t e = 0; e < 8; e++) {
-                const uint32_t loc = (word_of(v[u], e / 2) >> (16 * (e & 1))) & 0xFFFFu;
-                tl[loc] = (T)act(loc & gmask);
-            }
-        }
     }
 }
 
@@ -810,13 +771,47 @@ __global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict_
     if (lo == hi && !preserve) return;  // nothing lands here: the tile stays as it is
     uint4* lds = reinterpret_cast<uint4*>(smem_apply);
     uint4* src = reinterpret_cast<uint4*>(pool + (uint64_t)t * kTileBytes);
-    for (uint32_t i = threadIdx.x; i < kTileBytes / 16; i += kApplyBlock) lds[i] = src[i];
+    // Everything the workgroup reads is requested before the first wait: the
+    // tile (read and written once per call, so streamed past the caches), the
+    // first records (a ragged head and tail record and one 16-byte chunk of
+    // the aligned body per thread) and, for the window count, the block
+    // timestamps of the thread's chunks.
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    constexpr uint32_t kPerThread = kTileBytes / 16 / kApplyBlock;
+    static_assert(kPerThread * 16 * kApplyBlock == kTileBytes, "a tile is whole 16-byte chunks per thread");
+    constexpr uint32_t CA = kPerChunk<T>;
+    const uint32_t tid = threadIdx.x;
+    u32x4* lds4 = reinterpret_cast<u32x4*>(smem_apply);
+    u32x4* src4 = reinterpret_cast<u32x4*>(src);
+    u32x4 v[kPerThread];
+#pragma unroll
+    for (uint32_t u = 0; u < kPerThread; u++) v[u] = __builtin_nontemporal_load(src4 + tid + u * kApplyBlock);
+    const uint32_t a8 = (lo + 7u) & ~7u, b8 = hi & ~7u;
+    const uint32_t n8 = a8 < b8 ? (b8 - a8) / 8 : 0;
+    const uint4* rb = reinterpret_cast<const uint4*>(rec + a8);
+    uint32_t r_head = ~0u, r_tail = ~0u;
+    uint4 r_body = make_uint4(0, 0, 0, 0);
+    if (n8) {
+        if (lo + tid < a8) r_head = rec[lo + tid];
+        if (b8 + tid < hi) r_tail = rec[b8 + tid];
+        if (tid < n8) r_body = rb[tid];
+    } else if (lo + tid < hi) {
+        r_head = rec[lo + tid];  // a run shorter than 16 records: one each
+    }
+    uint4 acv[kPerThread];
+    if (w_out) {
+#pragma unroll
+        for (uint32_t u = 0; u < kPerThread; u++)
+            acv[u] = *reinterpret_cast<const uint4*>(act_table + (((tid + u * kApplyBlock) * CA) & (G.g - 1u)));
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kPerThread; u++) lds4[tid + u * kApplyBlock] = v[u];
     __syncthreads();
     T* tl = reinterpret_cast<T*>(smem_apply);
     if (preserve) {
         const uint32_t n0 = S.r0hi - S.r0lo, n1 = S.r1hi - S.r1lo, per = n0 + n1;
         const uint32_t atvs = (kTileBytes / sizeof(T)) >> G.log2g;
-        for (uint32_t q = threadIdx.x; q < atvs * per; q += kApplyBlock) {
+        for (uint32_t q = tid; q < atvs * per; q += kApplyBlock) {
             const uint32_t v = q / per, e = q - v * per;
             const uint32_t pos = e < n0 ? S.r0lo + e : S.r1lo + (e - n0);
             T* a = tl + (v << G.log2g) + pos;
@@ -828,16 +823,47 @@ __global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict_
         __syncthreads();
     }
     const uint32_t gmask = G.g - 1u;
+    auto apply = [&](auto act) {
+        if (r_head != ~0u) tl[r_head] = (T)act(r_head & gmask);
+        if (r_tail != ~0u) tl[r_tail] = (T)act(r_tail & gmask);
+        if (tid < n8) {
+#pragma unroll
+            for (uint32_t e = 0; e < 8; e++) {
+                const uint32_t loc = (word_of(r_body, e / 2) >> (16 * (e & 1))) & 0xFFFFu;
+                tl[loc] = (T)act(loc & gmask);
+            }
+        }
+        // the rest of a long run, four chunks in flight per thread
+        for (uint32_t q0 = tid + kApplyBlock; q0 < n8; q0 += 4 * kApplyBlock) {
+            uint4 w[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) {
+                const uint32_t q = q0 + u * kApplyBlock;
+                w[u] = q < n8 ? rb[q] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) {
+                if (q0 + u * kApplyBlock >= n8) break;
+#pragma unroll
+                for (uint32_t e = 0; e < 8; e++) {
+                    const uint32_t loc = (word_of(w[u], e / 2) >> (16 * (e & 1))) & 0xFFFFu;
+                    tl[loc] = (T)act(loc & gmask);
+                }
+            }
+        }
+    };
     if (G.blk_a >= 2) {
         const uint32_t magic = (uint32_t)G.blk_magic;
-        apply_records<T>(tl, rec, lo, hi, gmask, [&](uint32_t i) { return act_of_narrow(i, c0, magic, G); });
+        apply([&](uint32_t i) { return act_of_narrow(i, c0, magic, G); });
     } else {
-        apply_records<T>(tl, rec, lo, hi, gmask, [&](uint32_t i) { return act_of(i, c0, G); });
+        apply([&](uint32_t i) { return act_of(i, c0, G); });
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < kTileBytes / 16; i += kApplyBlock) src[i] = lds[i];
+#pragma unroll
+    for (uint32_t u = 0; u < kPerThread; u++) v[u] = lds4[tid + u * kApplyBlock];
+#pragma unroll
+    for (uint32_t u = 0; u < kPerThread; u++) __builtin_nontemporal_store(v[u], src4 + tid + u * kApplyBlock);
     if (w_out) {
-        constexpr uint32_t CA = kPerChunk<T>;
         __shared__ uint32_t wl[kTileBytes / 16 / 64];  // per ATV, when an ATV spans more than 64 chunks
         const uint32_t cpa = G.g / CA;                // chunks per ATV (a power of two)
         const uint32_t seg = cpa < 64 ? cpa : 64;
@@ -853,10 +879,11 @@ __global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict_
         const uint32_t twok2 = both_halves(G.twok), c_at = both_halves(0x8000u - G.twok);
         const uint32_t c_kq = both_halves(0x8000u - kq_w);
         const uint32_t twok4 = G.twok * kByteOnes, kq4 = kq_w * kByteOnes, tkq4 = (G.twok + kq_w) * kByteOnes;
-        for (uint32_t c = threadIdx.x; c < kTileBytes / 16; c += kApplyBlock) {
+#pragma unroll
+        for (uint32_t u = 0; u < kPerThread; u++) {
+            const uint32_t c = tid + u * kApplyBlock;
             const uint32_t pos = c * CA;                // AT index inside the tile
-            const uint32_t i0 = pos & (G.g - 1u);       // its position in the ATV
-            const uint4 ac = *reinterpret_cast<const uint4*>(act_table + i0);
+            const uint4 ac = acv[u];                    // block timestamps of positions pos mod g ..
             const uint4 d = lds[c];
             uint32_t act_n;
             if (bytes4) {
