@@ -439,7 +439,7 @@ constexpr uint32_t kTileRecs = 16384;  // records per block in passes 1 and 2
 constexpr uint32_t kMaxTiles = 4096;
 constexpr uint32_t kTileChunk = 64;    // rows (blocks) per chunk of the column scans
 constexpr uint32_t kApplyBlock = 1024;
-constexpr uint32_t kScatterBlock = 1024;  // 16 waves: the scatter block holds 96 KiB of LDS
+constexpr uint32_t kScatterBlock = 1024;  // 16 waves; the scatter block holds 80 KiB of LDS, two per CU
 
 // The tiled scan only runs on pools of at most kMaxTiles * kTileBytes =
 // 2^28 bytes, so ATV and AT indices fit 32 bits there: the index arithmetic
@@ -675,11 +675,13 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
                                                                 const uint32_t* __restrict__ cnt,
                                                                 const uint32_t* __restrict__ pre,
                                                                 uint16_t* __restrict__ rec) {
+    // 80 KiB of LDS, so that two blocks share a CU: the staged records, then
+    // one word per tile (its slot cursor, later its run's offset in rec);
+    // the block scan's scratch sits where the records go, before they do
     extern __shared__ __align__(16) uint8_t smem_tile[];
     uint32_t* staged = reinterpret_cast<uint32_t*>(smem_tile);  // tile << 16 | in-tile index, grouped by tile
-    uint32_t* cur = staged + kTileRecs;                             // slot cursors
-    uint32_t* gbase = cur + ((n_tiles + 3u) & ~3u);                       // run start in rec minus LDS start
-    __shared__ uint32_t scratch[kScatterBlock / 64 + 1];
+    uint32_t* cur = staged + kTileRecs;                         // slot cursors, then rec offset minus LDS start
+    uint32_t* scratch = staged;
     constexpr uint32_t P = kTileRecs / R;
     constexpr uint32_t PPT = (P + kScatterBlock - 1) / kScatterBlock;  // pairs per thread
     const uint32_t blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
@@ -720,13 +722,12 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
     }
     uint32_t total;
     uint32_t st = block_exclusive_scan<kScatterBlock>(sum, scratch, &total);
+    uint32_t st0[TPT];
 #pragma unroll
     for (uint32_t e = 0; e < TPT; e++) {
         const uint32_t t = threadIdx.x * TPT + e;
-        if (t < n_tiles) {
-            cur[t] = st;
-            gbase[t] = prow[t] - st;  // modulo 2^32; exact once a slot is added
-        }
+        st0[e] = st;
+        if (t < n_tiles) cur[t] = st;
         st += c[e];
     }
     __syncthreads();
@@ -744,9 +745,16 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
         }
     }
     __syncthreads();
+    // the cursors become each run's offset in rec minus its LDS start
+#pragma unroll
+    for (uint32_t e = 0; e < TPT; e++) {
+        const uint32_t t = threadIdx.x * TPT + e;
+        if (t < n_tiles) cur[t] = prow[t] - st0[e];  // modulo 2^32; exact once a slot is added
+    }
+    __syncthreads();
     for (uint32_t i = threadIdx.x; i < total; i += kScatterBlock) {
         const uint32_t v = staged[i];
-        rec[gbase[v >> 16] + i] = (uint16_t)(v & 0xFFFFu);
+        rec[cur[v >> 16] + i] = (uint16_t)(v & 0xFFFFu);
     }
 }
 
@@ -1801,8 +1809,13 @@ __global__ __launch_bounds__(kBlock) void k_serve_features(const StepDesc* __res
                                                            const uint8_t* __restrict__ act_all,
                                                            float* __restrict__ feat,
                                                            double* __restrict__ est, uint8_t* __restrict__ pflags) {
-    __shared__ uint32_t hist_all[kBlock / 64][128];
-    uint32_t* hist = hist_all[threadIdx.x >> 6];
+    // per wave kHistCopies histograms of 128 ages (stride kHistStride, odd, so
+    // that copies fall in different banks); lane l adds into copy l mod
+    // kHistCopies, so lanes of equal age rarely hit one address
+    constexpr uint32_t kHistCopies = 8, kHistStride = 129;
+    __shared__ uint32_t hist_all[kBlock / 64][kHistCopies * kHistStride];
+    uint32_t* hist_w = hist_all[threadIdx.x >> 6];
+    uint32_t* hist = hist_w + (threadIdx.x & (kHistCopies - 1u)) * kHistStride;
     const uint32_t ncl = d->n_close;
     if (ncl == 0) return;
     const uint64_t nh = S->n_hosts;
@@ -1815,8 +1828,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_features(const StepDesc* __res
         const CloseDesc& cdsc = d->close[ci];
         const LinkSlot& ls = L[cdsc.slot];
         const Geometry& G = ls.G;
-        hist[lane] = 0;
-        hist[lane + 64] = 0;
+        for (uint32_t q = lane; q < kHistCopies * kHistStride; q += 64) hist_w[q] = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         const uint32_t f = mangle(hosts[h], G.A);
@@ -1859,9 +1871,14 @@ __global__ __launch_bounds__(kBlock) void k_serve_features(const StepDesc* __res
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        const uint32_t hv = hist[lane];
+        uint32_t hv = 0, hv2 = 0;  // ages lane and lane + 64 over the copies
+#pragma unroll
+        for (uint32_t cpy = 0; cpy < kHistCopies; cpy++) {
+            hv += hist_w[cpy * kHistStride + lane];
+            hv2 += hist_w[cpy * kHistStride + lane + 64];
+        }
         const uint32_t kq = cdsc.kq;
-        uint32_t nat = (lane < kq ? hv : 0u) + (lane + 64 < kq ? hist[lane + 64] : 0u);
+        uint32_t nat = (lane < kq ? hv : 0u) + (lane + 64 < kq ? hv2 : 0u);
         for (uint32_t o = 32; o > 0; o >>= 1) nat += __shfl_xor(nat, o, 64);
         uint8_t fl = 0;
         double e_plain = 0.0;
@@ -2153,7 +2170,7 @@ TileSizes tiled_sizes(uint64_t n, uint64_t pool_bytes, const Geometry& G) {
 }
 
 size_t tiled_lds_bytes(uint32_t n_tiles) {
-    return kTileRecs * sizeof(uint32_t) + 2 * (((size_t)n_tiles + 3) & ~(size_t)3) * sizeof(uint32_t);
+    return kTileRecs * sizeof(uint32_t) + (((size_t)n_tiles + 3) & ~(size_t)3) * sizeof(uint32_t);
 }
 
 hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
