@@ -266,8 +266,6 @@ struct ServeBufs {  // device buffers of one server's step graph
     double* est;       // plain estimates
     uint8_t* pflags;   // plain flags
     float* y;          // network output
-    double* est_l;     // learned estimates
-    uint8_t* flags_l;  // returned flags
     uint8_t* act;      // kServeMaxLinks x g: block timestamp of every AT position, per close
     uint64_t max_hosts;
     uint32_t cand_cap;
@@ -288,13 +286,12 @@ hipError_t launch_gather_pairs(const GatherList& Lst, uint32_t* aip_out, uint32_
 
 hipError_t launch_serve_ingest_branch(const ServeBufs& B, const Geometry& shape, hipStream_t st);
 hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, uint64_t n_atv, hipStream_t st);
-// State block and the used host rows to the descriptor's export set (flags:
-// learned when `learned`, else plain).
-hipError_t launch_serve_export(const ServeBufs& B, bool learned, hipStream_t st);
+// State block and the used host rows, with the plain estimates and flags, to
+// the descriptor's export set (a step without a network).
+hipError_t launch_serve_export(const ServeBufs& B, hipStream_t st);
+// The same after the network's forward pass, the learned estimates computed on
+// the way (its fallback rule for z outside [zlo, zhi]).
+hipError_t launch_serve_export_learned(const ServeBufs& B, double zlo, double zhi, double theta, hipStream_t st);
 hipError_t launch_mlp_forward_devn(const float* X, const uint64_t* n_dev, uint64_t nrows_max, const MlpDev& P, float* y,
                                    hipStream_t st);
-hipError_t launch_learned_combine_devn(const float* y, const float* feat, const double* plain, const uint8_t* pflags,
-                                       const uint64_t* n_dev, uint64_t n_max, double zlo, double zhi, double theta,
-                                       double* est, uint8_t* flags, hipStream_t st);
-
 }  // namespace atp

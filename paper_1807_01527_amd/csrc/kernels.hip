@@ -1753,37 +1753,43 @@ __global__ __launch_bounds__(kBlock) void k_serve_restore_join(const StepDesc* _
     }
 }
 
-// Candidate counts, the cap rule and each close's slice of the host list.
-__global__ void k_serve_host_offsets(const StepDesc* __restrict__ d, const LinkSlot* __restrict__ L,
-                                     ServeState* __restrict__ S, uint32_t cap) {
-    if (threadIdx.x != 0) return;
-    uint64_t off = 0;
-    for (uint32_t ci = 0; ci < d->n_close; ci++) {
-        CloseOut& o = S->out[ci];
-        o.m = o.cnt;
-        uint32_t nc = 0;
-        if (o.rc == AT_OK) {
-            if (o.m > cap) o.rc = AT_E_OVERFLOW;
-            else nc = (uint32_t)o.m;
-        }
-        o.n_cand = nc;
-        o.host_off = (uint32_t)off;
-        o.n_hosts = nc + L[d->close[ci].slot].n_watch;
-        off += o.n_hosts;
-    }
-    S->n_hosts = off;
-}
-
-// One workgroup per close: sort its candidates in LDS (cap <= kTile) and
-// write them, then its watch hosts, to the host list.
+// One workgroup per close: the candidate count, the cap rule and the close's
+// slice of the host list (every workgroup derives the offsets of the closes
+// before it from the restore's counts; workgroup 0 also records them), then
+// its candidates sorted in LDS (cap <= kTile) and its watch hosts.
 __global__ __launch_bounds__(kBlock) void k_serve_sort(const StepDesc* __restrict__ d, const LinkSlot* __restrict__ L,
-                                                       const ServeState* __restrict__ S, uint32_t* __restrict__ hosts) {
+                                                       ServeState* __restrict__ S, uint32_t* __restrict__ hosts,
+                                                       uint32_t cap) {
     __shared__ uint32_t s[kTile];
     const uint32_t ci = blockIdx.x;
-    if (ci >= d->n_close) return;
-    const CloseOut& o = S->out[ci];
+    const uint32_t ncl = d->n_close;
+    if (ci >= ncl) return;
+    // n_cand of a close: its count m when the restore ran (AT_OK) and m <= cap,
+    // else 0.  Workgroup 0 may turn AT_OK into AT_E_OVERFLOW meanwhile, which
+    // happens exactly when m > cap: both readings give 0.
+    auto n_cand = [&](uint32_t c) -> uint32_t {
+        const CloseOut& o = S->out[c];
+        return (o.rc == AT_OK && o.cnt <= cap) ? (uint32_t)o.cnt : 0u;
+    };
+    uint64_t off = 0;
+    for (uint32_t c = 0; c < ci; c++) off += n_cand(c) + L[d->close[c].slot].n_watch;
+    const uint32_t n = n_cand(ci);
     const LinkSlot& ls = L[d->close[ci].slot];
-    const uint32_t n = o.n_cand;
+    __syncthreads();  // every thread has read the counts before workgroup 0 writes them
+    if (ci == 0 && threadIdx.x == 0) {
+        uint64_t o2 = 0;
+        for (uint32_t c = 0; c < ncl; c++) {
+            CloseOut& o = S->out[c];
+            const uint32_t nc = n_cand(c);
+            o.m = o.cnt;
+            if (o.rc == AT_OK && o.m > cap) o.rc = AT_E_OVERFLOW;
+            o.n_cand = nc;
+            o.host_off = (uint32_t)o2;
+            o.n_hosts = nc + L[d->close[c].slot].n_watch;
+            o2 += o.n_hosts;
+        }
+        S->n_hosts = o2;
+    }
     uint32_t np2 = 1;
     while (np2 < n) np2 <<= 1;
     for (uint32_t q = threadIdx.x; q < np2; q += blockDim.x) s[q] = q < n ? ls.cand[q] : 0xFFFFFFFFu;
@@ -1796,8 +1802,8 @@ __global__ __launch_bounds__(kBlock) void k_serve_sort(const StepDesc* __restric
             }
             __syncthreads();
         }
-    for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) hosts[o.host_off + q] = s[q];
-    for (uint32_t q = threadIdx.x; q < ls.n_watch; q += blockDim.x) hosts[o.host_off + n + q] = ls.watch[q];
+    for (uint32_t q = threadIdx.x; q < n; q += blockDim.x) hosts[off + q] = s[q];
+    for (uint32_t q = threadIdx.x; q < ls.n_watch; q += blockDim.x) hosts[off + n + q] = ls.watch[q];
 }
 
 // Features and plain estimates of the host list (one wave per host).
@@ -1908,14 +1914,13 @@ __global__ __launch_bounds__(kBlock) void k_serve_features(const StepDesc* __res
     }
 }
 
-// The step's results to mapped host memory: the state block, then per host
-// of the list its address, plain estimate, learned estimate (when a network
-// is set) and flags.  Only the n_hosts rows in use cross the bus.
+// The step's results to mapped host memory (a step without a network): the
+// state block, then per host of the list its address, plain estimate and
+// flags.  Only the n_hosts rows in use cross the bus.
 __global__ __launch_bounds__(kBlock) void k_serve_export(const StepDesc* __restrict__ d,
                                                          const ServeState* __restrict__ S,
                                                          const uint32_t* __restrict__ hosts,
                                                          const double* __restrict__ est,
-                                                         const double* __restrict__ est_l,
                                                          const uint8_t* __restrict__ flags) {
     const ServeExport X = d->xp;
     const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1929,7 +1934,6 @@ __global__ __launch_bounds__(kBlock) void k_serve_export(const StepDesc* __restr
     for (uint64_t h = tid; h < n; h += nthr) {
         X.hosts[h] = hosts[h];
         X.est[h] = est[h];
-        if (est_l) X.est_l[h] = est_l[h];
         X.flags[h] = flags[h];
     }
 }
@@ -2322,8 +2326,8 @@ hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, 
     hipLaunchKernelGGL(k_serve_restore_prep, dim3(1), dim3(1024), 0, st, B.desc, B.slots, B.state);
     hipLaunchKernelGGL(k_serve_restore_join, dim3(kServeGrid), dim3(kBlock), 0, st, B.desc, B.slots, B.state,
                        B.cand_cap);
-    hipLaunchKernelGGL(k_serve_host_offsets, dim3(1), dim3(64), 0, st, B.desc, B.slots, B.state, B.cand_cap);
-    hipLaunchKernelGGL(k_serve_sort, dim3(kServeMaxLinks), dim3(kBlock), 0, st, B.desc, B.slots, B.state, B.hosts);
+    hipLaunchKernelGGL(k_serve_sort, dim3(kServeMaxLinks), dim3(kBlock), 0, st, B.desc, B.slots, B.state, B.hosts,
+                       B.cand_cap);
 #define AT_SERVE_FEAT(RR)                                                                                     \
     case RR:                                                                                                  \
         hipLaunchKernelGGL((k_serve_features<RR>), dim3(kServeGrid), dim3(kBlock), 0, st, B.desc, B.slots, B.state, \
@@ -2345,9 +2349,8 @@ hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, 
     return hipGetLastError();
 }
 
-hipError_t launch_serve_export(const ServeBufs& B, bool learned, hipStream_t st) {
-    hipLaunchKernelGGL(k_serve_export, dim3(64), dim3(kBlock), 0, st, B.desc, B.state, B.hosts, B.est,
-                       learned ? B.est_l : nullptr, learned ? B.flags_l : B.pflags);
+hipError_t launch_serve_export(const ServeBufs& B, hipStream_t st) {
+    hipLaunchKernelGGL(k_serve_export, dim3(64), dim3(kBlock), 0, st, B.desc, B.state, B.hosts, B.est, B.pflags);
     return hipGetLastError();
 }
 

@@ -58,7 +58,7 @@ __device__ __forceinline__ void load4_T(const uint16_t* T, uint64_t ldT, uint32_
 }
 
 // The fallback rule for row i (see LearnedEpilogue), shared by the fused
-// epilogue and k_learned_combine.
+// epilogue and the serving export.
 __device__ __forceinline__ void learned_store(const double* __restrict__ plain, const uint8_t* __restrict__ pflags,
                                               double zlo, double zhi, double theta, uint64_t i, float y, float f61,
                                               double* __restrict__ est, uint8_t* __restrict__ flags) {
@@ -348,16 +348,37 @@ __global__ void k_mlp_refresh(const float* __restrict__ w, MlpOut O) {
 // ln n.  exp(z) is returned when z is finite and inside [zlo, zhi] (the
 // trained range of ln n), else the plain estimate with AT_F_FALLBACK.
 // AT_F_SUPER is recomputed for the returned estimate.
-__global__ void k_learned_combine(const float* __restrict__ y, const float* __restrict__ feat,
-                                  const double* __restrict__ plain, const uint8_t* __restrict__ pflags, uint64_t n,
-                                  double zlo, double zhi, double theta, double* __restrict__ est,
-                                  uint8_t* __restrict__ flags, const uint64_t* __restrict__ n_dev) {
-    if (n_dev) n = *n_dev < n ? *n_dev : n;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        learned_store(plain, pflags, zlo, zhi, theta, i, y[i], feat[i * kMlpDim + 61], est, flags);
+// A serving step's results to the mapped host copy its descriptor names, with
+// the learned estimates computed on the way: the state block, then per host of
+// the list its address, plain estimate, learned estimate (the fallback rule
+// above) and flags.
+__global__ void k_serve_export_learned(const StepDesc* __restrict__ d, const ServeState* __restrict__ S,
+                                       const uint32_t* __restrict__ hosts, const float* __restrict__ y,
+                                       const float* __restrict__ feat, const double* __restrict__ plain,
+                                       const uint8_t* __restrict__ pflags, double zlo, double zhi, double theta) {
+    const ServeExport X = d->xp;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nthr = (uint64_t)gridDim.x * blockDim.x;
+    constexpr uint32_t kWords = sizeof(ServeState) / 8;
+    static_assert(sizeof(ServeState) % 8 == 0, "the state block copies as 8-byte words");
+    const uint64_t* sw = reinterpret_cast<const uint64_t*>(S);
+    uint64_t* dw = reinterpret_cast<uint64_t*>(X.state);
+    for (uint64_t q = tid; q < kWords; q += nthr) dw[q] = sw[q];
+    const uint64_t n = S->n_hosts < X.max_hosts ? S->n_hosts : X.max_hosts;
+    for (uint64_t h = tid; h < n; h += nthr) {
+        X.hosts[h] = hosts[h];
+        X.est[h] = plain[h];
+        learned_store(plain, pflags, zlo, zhi, theta, h, y[h], feat[h * kMlpDim + 61], X.est_l, X.flags);
+    }
 }
 
 }  // namespace
+
+hipError_t launch_serve_export_learned(const ServeBufs& B, double zlo, double zhi, double theta, hipStream_t st) {
+    hipLaunchKernelGGL(k_serve_export_learned, dim3(64), dim3(kBlock), 0, st, B.desc, B.state, B.hosts, B.y, B.feat,
+                       B.est, B.pflags, zlo, zhi, theta);
+    return hipGetLastError();
+}
 
 hipError_t launch_mlp_forward(const float* X, uint64_t n, const MlpDev& P, float* y, hipStream_t st) {
     if (n == 0) return hipSuccess;
@@ -420,17 +441,6 @@ hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, cons
 
 hipError_t launch_mlp_refresh(const float* w, const MlpOut& O, hipStream_t st) {
     hipLaunchKernelGGL(k_mlp_refresh, dim3((kMlpParams + kBlock - 1) / kBlock), dim3(kBlock), 0, st, w, O);
-    return hipGetLastError();
-}
-
-hipError_t launch_learned_combine_devn(const float* y, const float* feat, const double* plain, const uint8_t* pflags,
-                                       const uint64_t* n_dev, uint64_t n_max, double zlo, double zhi, double theta,
-                                       double* est, uint8_t* flags, hipStream_t st) {
-    uint64_t blocks = (n_max + kBlock - 1) / kBlock;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_learned_combine, dim3((uint32_t)blocks), dim3(kBlock), 0, st, y, feat, plain, pflags, n_max,
-                       zlo, zhi, theta, est, flags, n_dev);
     return hipGetLastError();
 }
 

@@ -143,8 +143,6 @@ struct at_serve {
     double* d_est = nullptr;
     uint8_t* d_pflags = nullptr;
     float* d_y = nullptr;
-    double* d_estl = nullptr;
-    uint8_t* d_flagsl = nullptr;
     uint8_t* d_act = nullptr;     // per close: block timestamp of every AT position
     uint64_t max_hosts = 0;
     // pinned host: the step descriptor, and two sets of mapped result arrays
@@ -292,8 +290,6 @@ int capture_graph(at_serve* S) {
     B.est = S->d_est;
     B.pflags = S->d_pflags;
     B.y = S->d_y;
-    B.est_l = S->d_estl;
-    B.flags_l = S->d_flagsl;
     B.act = S->d_act;
     B.max_hosts = S->max_hosts;
     B.cand_cap = S->cfg.cand_cap;
@@ -316,11 +312,10 @@ int capture_graph(at_serve* S) {
     if (ec == hipSuccess) ec = atp::launch_serve_close_branch(B, S->shape, S->n_atv, S->s1);
     if (ec == hipSuccess && have_mlp)
         ec = atp::launch_mlp_forward_devn(S->d_feat, &S->d_state->n_hosts, S->max_hosts, P, S->d_y, S->s1);
-    if (ec == hipSuccess && have_mlp)
-        ec = atp::launch_learned_combine_devn(S->d_y, S->d_feat, S->d_est, S->d_pflags, &S->d_state->n_hosts,
-                                              S->max_hosts, std::log(16.0) - 0.5, std::log(262144.0) + 0.5,
-                                              S->cfg.theta, S->d_estl, S->d_flagsl, S->s1);
-    if (ec == hipSuccess) ec = atp::launch_serve_export(B, have_mlp, S->s1);
+    if (ec == hipSuccess)
+        ec = have_mlp ? atp::launch_serve_export_learned(B, std::log(16.0) - 0.5, std::log(262144.0) + 0.5,
+                                                         S->cfg.theta, S->s1)
+                      : atp::launch_serve_export(B, S->s1);
     if (ec == hipSuccess) ec = hipEventRecord(S->ev_join, S->s1);
     // branch 0: open + scan
     if (ec == hipSuccess) ec = atp::launch_serve_ingest_branch(B, S->shape, S->s0);
@@ -350,8 +345,7 @@ void free_server(at_serve* S) {
             delete L;
         }
     }
-    void* d[] = {S->d_desc, S->d_slots, S->d_state, S->d_hosts, S->d_feat, S->d_est, S->d_pflags, S->d_y, S->d_estl,
-                 S->d_flagsl, S->d_act};
+    void* d[] = {S->d_desc, S->d_slots, S->d_state, S->d_hosts, S->d_feat, S->d_est, S->d_pflags, S->d_y, S->d_act};
     for (void* p : d)
         if (p) (void)hipFree(p);
     void* h[] = {S->h_desc,        S->rs[0].state, S->rs[0].hosts, S->rs[0].est, S->rs[0].estl, S->rs[0].flags,
@@ -441,14 +435,18 @@ struct TiledJob {
 // Launch the tiled jobs on s2 (events around each launch for the timing):
 // first those of links the graph leaves alone, then, once the graph is done
 // with their pools, those of links whose previous slice it closes.
+// When every job waits for the graph they go on the graph's own stream
+// behind it (no cross-stream wait).
 int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed) {
     *n_timed = 0;
     std::stable_partition(jobs.begin(), jobs.end(), [](const TiledJob& J) { return !J.after_graph; });
-    bool waited = false;
+    const bool behind_graph = std::all_of(jobs.begin(), jobs.end(), [](const TiledJob& J) { return J.after_graph; });
+    hipStream_t st = behind_graph ? S->s0 : S->s2;
+    bool waited = behind_graph;
     for (TiledJob& J : jobs) {
         Link* L = J.L;
         if (J.after_graph && !waited) {
-            if (hipStreamWaitEvent(S->s2, S->ev_graph, 0) != hipSuccess) return AT_E_DEVICE;
+            if (hipStreamWaitEvent(st, S->ev_graph, 0) != hipSuccess) return AT_E_DEVICE;
             waited = true;
         }
         int rc = tiled_buffers(S, J.n);
@@ -466,7 +464,7 @@ int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed) {
                 G.off[G.n] = off;
                 off += J.chunks[c]->n;
                 if (++G.n == atp::kGatherMax || c + 1 == J.chunks.size()) {
-                    if (atp::launch_gather_pairs(G, S->stage_a, S->stage_b, S->s2) != hipSuccess) return AT_E_DEVICE;
+                    if (atp::launch_gather_pairs(G, S->stage_a, S->stage_b, st) != hipSuccess) return AT_E_DEVICE;
                     G.n = 0;
                 }
             }
@@ -482,12 +480,12 @@ int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed) {
                 if (hipEventCreate(&e) != hipSuccess) return AT_E_DEVICE;
                 S->tev.push_back(e);
             }
-            if (hipEventRecord(S->tev[2 * *n_timed], S->s2) != hipSuccess) return AT_E_DEVICE;
+            if (hipEventRecord(S->tev[2 * *n_timed], st) != hipSuccess) return AT_E_DEVICE;
             const bool w = J.weights && single && first;
             if (atp::launch_ingest_tiled(L->pool, a + off, b + off, m, S->pool_bytes, L->G, J.c0, S->tb,
-                                         J.opens && first, w ? L->w : nullptr, J.kq, S->s2) != hipSuccess)
+                                         J.opens && first, w ? L->w : nullptr, J.kq, st) != hipSuccess)
                 return AT_E_DEVICE;
-            if (hipEventRecord(S->tev[2 * *n_timed + 1], S->s2) != hipSuccess) return AT_E_DEVICE;
+            if (hipEventRecord(S->tev[2 * *n_timed + 1], st) != hipSuccess) return AT_E_DEVICE;
             ++*n_timed;
         }
         L->wready = J.weights && single;
@@ -548,7 +546,6 @@ int at_serve_create(const at_serve_config* cfg, at_serve** out) {
                 (rc = dalloc(&S->d_state, 1)) || (rc = dalloc(&S->d_hosts, S->max_hosts)) ||
                 (rc = dalloc(&S->d_feat, S->max_hosts * 64)) || (rc = dalloc(&S->d_est, S->max_hosts)) ||
                 (rc = dalloc(&S->d_pflags, S->max_hosts)) || (rc = dalloc(&S->d_y, S->max_hosts)) ||
-                (rc = dalloc(&S->d_estl, S->max_hosts)) || (rc = dalloc(&S->d_flagsl, S->max_hosts)) ||
                 (rc = dalloc(&S->d_act, (uint64_t)atp::kServeMaxLinks * S->shape.g)))) {
     }
     if (!rc) {
