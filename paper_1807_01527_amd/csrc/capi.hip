@@ -204,12 +204,12 @@ uint64_t carve_tiles(uint8_t* base, const atp::TileSizes& z, const Geometry& G, 
     tb->rec = reinterpret_cast<uint16_t*>(take(z.recs * 2));
     tb->cnt = reinterpret_cast<uint32_t*>(take(z.table * 4));
     tb->pre = reinterpret_cast<uint32_t*>(take(z.table * 4));
-    tb->csum = reinterpret_cast<uint32_t*>(take((uint64_t)(z.nchunk + 1) * 4096 * 4));
+    tb->csum = reinterpret_cast<uint32_t*>(take((uint64_t)(z.nchunk + 2) * 4096 * 4));
     tb->base = reinterpret_cast<uint32_t*>(take(4097 * 4));
     tb->act = take((uint64_t)G.g * G.atb);
     tb->rec_cap = z.recs;
     tb->table_cap = z.table;
-    tb->chunk_cap = z.nchunk + 1;
+    tb->chunk_cap = z.nchunk + 2;
     return off;
 }
 
@@ -569,12 +569,12 @@ int ingest_tiled_buffers(at_ctx* h, uint64_t n) {
         if ((rc = dev_alloc(&h->tb.cnt, z.table)) || (rc = dev_alloc(&h->tb.pre, z.table))) return rc;
         h->tb.table_cap = z.table;
     }
-    if (z.nchunk + 1 > h->tb.chunk_cap) {
+    if (z.nchunk + 2 > h->tb.chunk_cap) {
         if (h->tb.csum) (void)hipFree(h->tb.csum);
         h->tb.csum = nullptr;
         h->tb.chunk_cap = 0;
-        if ((rc = dev_alloc(&h->tb.csum, (uint64_t)(z.nchunk + 1) * 4096))) return rc;
-        h->tb.chunk_cap = z.nchunk + 1;
+        if ((rc = dev_alloc(&h->tb.csum, (uint64_t)(z.nchunk + 2) * 4096))) return rc;
+        h->tb.chunk_cap = z.nchunk + 2;
     }
     if (!h->tb.base && (rc = dev_alloc(&h->tb.base, 4097))) return rc;
     if (!h->tb.act && (rc = dev_alloc(&h->tb.act, (uint64_t)h->G.g * h->G.atb))) return rc;

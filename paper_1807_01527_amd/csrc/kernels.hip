@@ -438,6 +438,8 @@ constexpr uint32_t kTileBytes = 1u << 16;
 constexpr uint32_t kTileRecs = 16384;  // records per block in passes 1 and 2
 constexpr uint32_t kMaxTiles = 4096;
 constexpr uint32_t kTileChunk = 64;    // rows (blocks) per chunk of the column scans
+constexpr uint32_t kCountBlock = 1024;  // pass 1: four pairs per thread
+constexpr uint32_t kColTiles = 64;      // tiles per block of the column passes (one wave wide)
 constexpr uint32_t kApplyBlock = 1024;
 constexpr uint32_t kScatterBlock = 1024;  // 16 waves; the scatter block holds 80 KiB of LDS, two per CU
 
@@ -478,16 +480,17 @@ __device__ __forceinline__ uint32_t xcd_contiguous_block(uint32_t w, uint32_t nb
 // holds whole ATVs (g <= the ATs of a tile), so a store's tile is its ATV's:
 // it depends on aip alone and this pass never reads bip.
 template <int R>
-__global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restrict__ aip, uint64_t n, Geometry G,
+__global__ __launch_bounds__(kCountBlock) void k_tile_count(const uint32_t* __restrict__ aip, uint64_t n, Geometry G,
                                                        uint32_t ts, uint32_t n_tiles, uint32_t* __restrict__ cnt,
                                                        uint32_t* __restrict__ tot, void* __restrict__ act_table,
                                                        uint32_t c0) {
     __shared__ uint32_t hist[kMaxTiles];
-    for (uint32_t t = threadIdx.x; t < n_tiles; t += kBlock) hist[t] = 0;
-    {   // tile totals start at zero (the column pass adds into them); the
-        // slice's block timestamp of every AT position, for the tile pass
-        const uint32_t tid = blockIdx.x * kBlock + threadIdx.x, nthr = gridDim.x * kBlock;
-        for (uint32_t t = tid; t < n_tiles; t += nthr) tot[t] = 0;
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += kCountBlock) hist[t] = 0;
+    {   // tile totals and the totals of every 64 tiles start at zero (the
+        // column pass adds into them); the slice's block timestamp of every
+        // AT position, for the tile pass
+        const uint32_t tid = blockIdx.x * kCountBlock + threadIdx.x, nthr = gridDim.x * kCountBlock;
+        for (uint32_t t = tid; t < n_tiles + kMaxTiles / kColTiles; t += nthr) tot[t] = 0;
         if (act_table)
             for (uint32_t i = tid; i < G.g; i += nthr) {
                 if (G.atb == 2) static_cast<uint16_t*>(act_table)[i] = (uint16_t)act_of(i, c0, G);
@@ -502,16 +505,16 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restric
     const uint32_t atv_shift = ts - G.log2g;  // ATVs per tile = 2^atv_shift
     const uint32_t rot = threadIdx.x % R;
     // four pairs per thread per round, loads issued before use
-    for (uint64_t q0 = lo + threadIdx.x; q0 < hi; q0 += 4 * kBlock) {
+    for (uint64_t q0 = lo + threadIdx.x; q0 < hi; q0 += 4 * kCountBlock) {
         uint32_t a4[4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const uint64_t q = q0 + (uint64_t)e * kBlock;
+            const uint64_t q = q0 + (uint64_t)e * kCountBlock;
             a4[e] = q < hi ? aip[q] : 0u;
         }
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            if (q0 + (uint64_t)e * kBlock >= hi) break;
+            if (q0 + (uint64_t)e * kCountBlock >= hi) break;
             const uint32_t f = mangle(a4[e], G.A);
             const uint32_t z = f & G.umask;
             const uint64_t L = (uint64_t)(f >> G.u);
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restric
     }
     __syncthreads();
     uint32_t* row = cnt + (uint64_t)blk * n_tiles;
-    for (uint32_t t = threadIdx.x; t < n_tiles; t += kBlock) row[t] = hist[t];
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += kCountBlock) row[t] = hist[t];
 }
 
 // Column sums of cnt over each chunk of kTileChunk rows -> csum[chunk][tile],
@@ -541,7 +544,6 @@ __global__ __launch_bounds__(kBlock) void k_tile_count(const uint32_t* __restric
 // tiles of one chunk; each of its kColGroups waves sums kTileChunk /
 // kColGroups rows (loads issued together) and the waves' sums meet in LDS.
 // Rows of 64 tiles are 256-byte coalesced reads.
-constexpr uint32_t kColTiles = 64;
 constexpr uint32_t kColGroups = kBlock / kColTiles;
 constexpr uint32_t kColRows = kTileChunk / kColGroups;
 static_assert(kColGroups * kColRows == kTileChunk, "a chunk splits evenly over the waves");
@@ -562,13 +564,20 @@ __global__ __launch_bounds__(kBlock) void k_tile_chunksum(const uint32_t* __rest
     for (uint32_t e = 0; e < kColRows; e++) s += v[e];
     part[rg][tl] = s;
     __syncthreads();
-    if (rg == 0 && t < n_tiles) {
+    if (rg == 0) {  // the first wave: one lane per tile of the block
+        // the row after the last chunk holds the tile totals, then the
+        // totals of every kColTiles tiles (this block's share in one add)
+        uint32_t* totals = csum + (uint64_t)gridDim.y * n_tiles;
         uint32_t tot = 0;
+        if (t < n_tiles) {
 #pragma unroll
-        for (uint32_t g = 0; g < kColGroups; g++) tot += part[g][tl];
-        csum[(uint64_t)c * n_tiles + t] = tot;
-        // the row after the last chunk holds the tile totals
-        atomicAdd(&csum[(uint64_t)gridDim.y * n_tiles + t], tot);
+            for (uint32_t g = 0; g < kColGroups; g++) tot += part[g][tl];
+            csum[(uint64_t)c * n_tiles + t] = tot;
+            atomicAdd(&totals[t], tot);
+        }
+        uint32_t gsum = tot;
+        for (uint32_t o = 32; o > 0; o >>= 1) gsum += __shfl_xor(gsum, o, 64);
+        if (tl == 0) atomicAdd(&totals[n_tiles + blockIdx.x], gsum);
     }
 }
 
@@ -626,9 +635,10 @@ __global__ __launch_bounds__(kBlock) void k_tile_rowpre(const uint32_t* __restri
     uint32_t v[kColRows];
 #pragma unroll
     for (uint32_t e = 0; e < kColRows; e++) v[e] = (col && b0 + e < nb) ? cnt[(uint64_t)(b0 + e) * n_tiles + t] : 0u;
-    // records of the tiles before this block's
+    // records of the tiles before this block's: the totals of the earlier
+    // groups of kColTiles tiles
     uint32_t before = 0;
-    for (uint32_t q = threadIdx.x; q < t0; q += kBlock) before += tot[q];
+    for (uint32_t q = threadIdx.x; q < blockIdx.x; q += kBlock) before += tot[n_tiles + q];
     for (uint32_t o = 32; o > 0; o >>= 1) before += __shfl_xor(before, o, 64);
     if (lane == 0) red[wv] = before;
     // this chunk's runs start after the earlier chunks' (split over the waves)
@@ -2184,13 +2194,13 @@ hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_
     if (n == 0) return hipSuccess;
     if (!tiled_fits(pool_bytes)) return hipErrorInvalidValue;
     const TileSizes z = tiled_sizes(n, pool_bytes, G);
-    if (z.recs > B.rec_cap || z.table > B.table_cap || z.nchunk + 1 > B.chunk_cap) return hipErrorInvalidValue;
+    if (z.recs > B.rec_cap || z.table > B.table_cap || z.nchunk + 2 > B.chunk_cap) return hipErrorInvalidValue;
     const uint32_t ts = 16u - (G.atb == 2 ? 1u : 0u);  // log2 of the ATs per tile
     const dim3 cols((z.n_tiles + kColTiles - 1) / kColTiles, z.nchunk);
     uint32_t* tot = B.csum + (uint64_t)z.nchunk * z.n_tiles;  // the row after the chunk sums
     hipError_t e = with_rows<uint8_t>(G.r, [&](auto rc, auto) {
         constexpr int RR = decltype(rc)::value;
-        hipLaunchKernelGGL((k_tile_count<RR>), dim3(z.nb), dim3(kBlock), 0, st, aip, n, G, ts, z.n_tiles, B.cnt, tot,
+        hipLaunchKernelGGL((k_tile_count<RR>), dim3(z.nb), dim3(kCountBlock), 0, st, aip, n, G, ts, z.n_tiles, B.cnt, tot,
                            w_out ? static_cast<void*>(B.act) : nullptr, c0);
     });
     if (e != hipSuccess) return e;

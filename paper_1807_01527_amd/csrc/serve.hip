@@ -397,11 +397,11 @@ int tiled_buffers(at_serve* S, uint64_t n) {
         if ((rc = dalloc(&S->tb.cnt, z.table)) || (rc = dalloc(&S->tb.pre, z.table))) return rc;
         S->tb.table_cap = z.table;
     }
-    if (z.nchunk + 1 > S->tb.chunk_cap) {
+    if (z.nchunk + 2 > S->tb.chunk_cap) {
         if (S->tb.csum) (void)hipFree(S->tb.csum);
         S->tb.chunk_cap = 0;
-        if ((rc = dalloc(&S->tb.csum, (uint64_t)(z.nchunk + 1) * 4096))) return rc;
-        S->tb.chunk_cap = z.nchunk + 1;
+        if ((rc = dalloc(&S->tb.csum, (uint64_t)(z.nchunk + 2) * 4096))) return rc;
+        S->tb.chunk_cap = z.nchunk + 2;
     }
     if (!S->tb.base && (rc = dalloc(&S->tb.base, 4097))) return rc;
     if (!S->tb.act && (rc = dalloc(&S->tb.act, (uint64_t)S->shape.g))) return rc;
