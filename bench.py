@@ -569,6 +569,39 @@ def link_config2(args, dev, learned, Mlp) -> dict:
         modes[name] = {"avg_ms": ms, "mpps": per_launch / (ms / 1e3) / 1e6}
     pool.set_scan_mode(0)
     out["scan_modes"] = modes
+    # every window k' <= k from one read: the age-histogram close, then each
+    # window re-summarised from the histograms alone; beside it the close of
+    # 8 windows counted in one read
+    hc, rq, mc = [], [], []
+    wins8 = [K - j * (K - 1) // 7 for j in range(8)]
+    for t in range(S):
+        pool.ingest(aip_d[t], bip_d[t])
+        e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+        e0.record(stream)
+        pool.close_hist(K)
+        e1.record(stream)
+        hc.append((e0, e1))
+        for kp in range(1, K + 1):
+            e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+            e2.record(stream)
+            pool.requery(kp)
+            e3.record(stream)
+            rq.append((e2, e3))
+    for t in range(S):
+        pool.ingest(aip_d[t], bip_d[t])
+        e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+        e0.record(stream)
+        pool.close_multi(wins8)
+        e1.record(stream)
+        mc.append((e0, e1))
+    torch.cuda.synchronize()
+    out["every_window"] = {
+        "hist_close_ms": float(np.mean([a.elapsed_time(b) for a, b in hc])),
+        "requery_ms": float(np.mean([a.elapsed_time(b) for a, b in rq])),
+        "close_8_windows_ms": float(np.mean([a.elapsed_time(b) for a, b in mc])),
+        "note": f"event-timed on the {pool.pool_bytes >> 20} MiB pool, k={K}: at_close_slice_hist (one read of the "
+                f"pool, every ATV's {K}-bin age histogram, window k summarised), then at_requery_window for each "
+                f"k' in 1..{K} (histograms only); beside it at_close_slice_multi of windows {wins8}"}
     pr = probe_rate(dev, pool.pool_bytes, aip_d[0], bip_d[0], args.pairs)
     out["scatter_probe"] = {**pr, "what": "uniform random byte stores, r per pair, into a buffer of the pool's size",
                             "ingest_frac_of_probe": (per_launch / avg_ingest_s) / (pr["mpps"] * 1e6)}

@@ -129,6 +129,36 @@ int at_close_slice_multi(at_ctx *h, const uint32_t *kprimes, uint32_t n);
 int at_select_window(at_ctx *h, uint32_t kprime);
 
 /*
+ * at_close_slice_hist -- at_close_slice(h, kprime) that, in the same single
+ * read of the pool, also builds every ATV's age histogram (Section 3: an AT
+ * set in the latest k' slices is active for every window k' <= k, and the
+ * ATs' timestamps stay valid for all of them).  Bin a < k of an ATV counts
+ * its ATs that are not inactive and were set a slices ago (timestamp
+ * distance a modulo 2k), so |ATV|^k' is the sum of its first k' bins for
+ * every k' <= k.  The histograms live in device memory, n_atv x k 16-bit
+ * counts (allocated on first use, freed by at_destroy), and stay valid until
+ * the next slice opens or another close runs.  Summaries, estimates and
+ * restores then follow window kprime.
+ * Errors: AT_E_INVAL (k' outside [1, k], or k > AT_HIST_MAX_K), AT_E_NOMEM,
+ * AT_E_DEVICE.
+ */
+#define AT_HIST_MAX_K 1024
+int at_close_slice_hist(at_ctx *h, uint32_t kprime);
+
+/* Re-summarise the window held since the last at_close_slice_hist for any
+ * k' in [1, k] from the histograms alone (no read of the pool): k'-weights,
+ * AAT(k', row, frame) and super lists (Section 4.2, 4.3).  Estimates and
+ * restores then use window k'.  AT_E_STATE unless the last close was
+ * at_close_slice_hist and no slice has opened since; AT_E_INVAL for k'
+ * outside [1, k]. */
+int at_requery_window(at_ctx *h, uint32_t kprime);
+
+/* Copy the last at_close_slice_hist's histograms (n_atv x k uint16, ATV-major
+ * in ATV index order) to host memory; blocks until copied.  AT_E_STATE as for
+ * at_requery_window. */
+int at_read_age_hist(at_ctx *h, uint16_t *host_out);
+
+/*
  * at_estimate -- cardinality of each of n hosts over the window summarised by
  * the last close (Alg 5 and Eq 4, Section 4.3): NAT = ATs active in all r of
  * the host's ATVs, UP = product over rows of AAT/(g*2^c) in the host's frame,

@@ -363,6 +363,28 @@ int oat_requery(oat *o, uint32_t kprime)
 }
 
 /* Alg 5: NAT(aip) = number of positions i active in all r ATVs of aip. */
+/* Age histogram of every ATV of the window ending at the last closed slice
+ * (Section 3): out[v*k + a] = number of ATs of ATV v, in ATV index order,
+ * that are not inactive and whose age -- the ACT distance since the slice
+ * that set them -- is a, for a < k.  Such an AT is active for window k'
+ * exactly when a < k', so every k'-weight is a prefix sum. */
+int oat_age_hist(const oat *o, uint32_t *out)
+{
+    if (!o || !out) return OAT_E_INVAL;
+    if (!o->queryable) return OAT_E_STATE;
+    uint32_t k = o->p.k;
+    memset(out, 0, sizeof(uint32_t) * (size_t)o->n_atv * k);
+    for (uint64_t v = 0; v < o->n_atv; v++) {
+        const uint16_t *atv = o->at + v * o->g;
+        for (uint32_t i = 0; i < o->g; i++) {
+            if (atv[i] >= 2 * k) continue;
+            uint32_t a = at_age(k, act_of(o, o->c0_query, i), atv[i]);
+            if (a < k) out[v * k + a] += 1;
+        }
+    }
+    return OAT_OK;
+}
+
 static uint32_t nat_of(const oat *o, uint32_t z, const uint32_t *x)
 {
     uint32_t nat = 0;

@@ -78,6 +78,8 @@ uint32_t oat_block_of(const oat *o, uint32_t i);
 int oat_ingest(oat *o, const uint32_t *aip, const uint32_t *bip, uint64_t n);
 int oat_close(oat *o, uint32_t kprime);
 int oat_requery(oat *o, uint32_t kprime);
+/* Per-ATV age histograms of the closed window, n_atv x k counts. */
+int oat_age_hist(const oat *o, uint32_t *out);
 int oat_estimate(const oat *o, const uint32_t *aip, uint64_t n, double *est,
                  uint8_t *flags, uint32_t *nat);
 int oat_restore(const oat *o, uint32_t *out, uint64_t cap, uint64_t *n_out);

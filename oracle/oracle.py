@@ -54,6 +54,7 @@ def lib():
             "oat_ingest": (C.c_int, [vp, u32p, u32p, C.c_uint64]),
             "oat_close": (C.c_int, [vp, C.c_uint32]),
             "oat_requery": (C.c_int, [vp, C.c_uint32]),
+            "oat_age_hist": (C.c_int, [vp, u32p]),
             "oat_estimate": (C.c_int, [vp, u32p, C.c_uint64, f64p, u8p, u32p]),
             "oat_restore": (C.c_int, [vp, u32p, C.c_uint64, u64p]),
             "oat_tuple_count": (C.c_int, [vp, u64p]),
@@ -187,6 +188,14 @@ class Oracle:
     def requery(self, kprime: int) -> int:
         """Summarise the closed window again for another k' (clock unchanged)."""
         return lib().oat_requery(self.h, kprime)
+
+    def age_hist(self) -> np.ndarray:
+        """Per-ATV age histograms of the closed window: (n_atv, k) counts."""
+        out = np.zeros((self.n_atv, self.k), np.uint32)
+        rc = lib().oat_age_hist(self.h, _p(out, C.c_uint32))
+        if rc:
+            raise RuntimeError(f"oat_age_hist rc={rc}")
+        return out
 
     def estimate(self, aip: np.ndarray):
         aip = np.ascontiguousarray(aip, np.uint32)

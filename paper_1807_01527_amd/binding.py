@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libatpool.so")
 AT_OK, AT_E_INVAL, AT_E_STATE, AT_E_NOMEM, AT_E_OVERFLOW, AT_E_DEVICE, AT_E_BUDGET = 0, -1, -2, -3, -4, -5, -6
 AT_F_SAT, AT_F_NEG, AT_F_FALLBACK, AT_F_SUPER = 1, 2, 4, 8
 NOALLOC_MAX_PAIRS = 1 << 20           # AT_NOALLOC_MAX_PAIRS
+AT_HIST_MAX_K = 1024                 # AT_HIST_MAX_K
 
 
 class AtError(RuntimeError):
@@ -44,6 +45,9 @@ SIGNATURES = {
     "at_close_slice": (C.c_int, [_vp, C.c_uint32]),
     "at_close_slice_multi": (C.c_int, [_vp, _u32p, C.c_uint32]),
     "at_select_window": (C.c_int, [_vp, C.c_uint32]),
+    "at_close_slice_hist": (C.c_int, [_vp, C.c_uint32]),
+    "at_requery_window": (C.c_int, [_vp, C.c_uint32]),
+    "at_read_age_hist": (C.c_int, [_vp, _vp]),
     "at_estimate": (C.c_int, [_vp, _u32p, C.c_uint64, _f64p, _u8p]),
     "at_restore": (C.c_int, [_vp, _u32p, _f64p, _u8p, C.c_uint64, _u64p]),
     "at_destroy": (C.c_int, [_vp]),
@@ -256,6 +260,18 @@ class AtPool:
 
     def select_window(self, kprime: int):
         _check(self.lib.at_select_window(self._handle(), kprime), "at_select_window")
+
+    def close_hist(self, kprime: Optional[int] = None):
+        _check(self.lib.at_close_slice_hist(self._handle(), self.k if kprime is None else kprime),
+               "at_close_slice_hist")
+
+    def requery(self, kprime: int):
+        _check(self.lib.at_requery_window(self._handle(), kprime), "at_requery_window")
+
+    def read_age_hist(self) -> np.ndarray:
+        out = np.zeros((self.n_atv, self.k), np.uint16)
+        _check(self.lib.at_read_age_hist(self._handle(), out.ctypes.data_as(C.c_void_p)), "at_read_age_hist")
+        return out
 
     def estimate(self, aip_host: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
         aip = np.ascontiguousarray(aip_host, np.uint32)

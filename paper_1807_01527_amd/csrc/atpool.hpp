@@ -102,6 +102,14 @@ struct CloseWindows {
 };
 hipError_t launch_close(const uint8_t* pool, uint32_t* w, uint64_t n_atv, const Geometry& G, uint32_t c0,
                         const CloseWindows& Wn, hipStream_t st);
+// Age-histogram close: hist[atv * k + a] (a < k) counts the ATVs' ATs of age
+// a, w[atv] receives the kq-weight.  k <= kHistMaxK (LDS bins per wave).
+constexpr uint32_t kHistMaxK = 1024;
+hipError_t launch_close_hist(const uint8_t* pool, uint16_t* hist, uint32_t* w, uint64_t n_atv, const Geometry& G,
+                             uint32_t c0, uint32_t kq, hipStream_t st);
+// w[atv] = sum of the first kq bins of the ATV's histogram row of K bins
+hipError_t launch_hist_weights(const uint16_t* hist, uint32_t K, uint64_t n_atv, uint32_t kq, uint32_t* w,
+                               hipStream_t st);
 // cnt_host (may be null): device-mapped host memory that also receives the
 // super-list counts of every window, so the host reads them without a copy.
 hipError_t launch_summarize(const uint32_t* w, uint64_t* aat, uint32_t* sa, uint32_t* sa_cnt, uint32_t* cnt_host,

@@ -33,6 +33,8 @@ struct at_ctx {
     uint32_t* sa_cnt_all = nullptr;
     uint32_t nwin = 0;
     uint32_t win_kq[atp::kMaxWindows] = {};
+    uint16_t* hist = nullptr;     // per-ATV age histograms of the last close (k bins each), if it built them
+    bool hist_valid = false;
     // ... and the one queries use
     uint32_t* w = nullptr;        // per ATV weight
     uint64_t* aat = nullptr;      // per (frame,row)
@@ -132,7 +134,7 @@ int dev_alloc(T** p, uint64_t count) {
 void free_all(at_ctx* h) {
     void* bufs[] = {h->pool, h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->counter, h->prefix, h->cand,
                     h->q_aip, h->q_est, h->q_flags, h->q_nat, h->q_feat, h->q_plain, h->bins, h->bin_fill,
-                    h->tb.rec, h->tb.cnt, h->tb.pre, h->tb.csum, h->tb.base, h->tb.act};
+                    h->tb.rec, h->tb.cnt, h->tb.pre, h->tb.csum, h->tb.base, h->tb.act, h->hist};
     if (h->pin) (void)hipHostFree(h->pin);
     h->pin = nullptr;
     h->pin_cap = 0;
@@ -673,6 +675,7 @@ int at_close_slice_multi(at_ctx* h, const uint32_t* kprimes, uint32_t n) {
     // the slice's one tiled call already counted window k: no pass over the pool
     const bool counted = n == 1 && h->wfused && kprimes[0] == h->wfused_kq;
     h->wfused = false;
+    h->hist_valid = false;
     hipError_t e = counted ? hipSuccess
                            : atp::launch_close(h->pool, h->w_all, h->n_atv, h->G, h->c0, Wn, h->stream);
     if (e == hipSuccess)
@@ -693,6 +696,57 @@ int at_close_slice_multi(at_ctx* h, const uint32_t* kprimes, uint32_t n) {
 int at_close_slice(at_ctx* h, uint32_t kprime) {
     if (!h) return AT_E_INVAL;
     return at_close_slice_multi(h, &kprime, 1);
+}
+
+int at_close_slice_hist(at_ctx* h, uint32_t kprime) {
+    static_assert(atp::kHistMaxK == AT_HIST_MAX_K, "one histogram limit");
+    if (!h || kprime < 1 || kprime > h->p.k || h->p.k > AT_HIST_MAX_K) return AT_E_INVAL;
+    int rc = ensure_pin_cnt(h, h->ngroups);
+    if (rc) return rc;
+    if (!h->hist && (rc = dev_alloc(&h->hist, h->n_atv * h->p.k))) return rc;
+    rc = open_slice(h);
+    if (rc) return rc;
+    h->wfused = false;
+    h->hist_valid = false;
+    hipError_t e = atp::launch_close_hist(h->pool, h->hist, h->w_all, h->n_atv, h->G, h->c0, kprime, h->stream);
+    if (e == hipSuccess)
+        e = atp::launch_summarize(h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->pin_cnt_dev, h->G, h->n_atv, 1,
+                                  h->stream);
+    if (e == hipSuccess) e = hipEventRecord(h->cnt_ready, h->stream);
+    if (e != hipSuccess) return AT_E_DEVICE;
+    h->nwin = 1;
+    h->win_kq[0] = kprime;
+    h->c0_query = h->c0;
+    use_window(h, 0);
+    h->t += 1;
+    h->open = false;
+    h->queryable = true;
+    h->hist_valid = true;
+    return AT_OK;
+}
+
+int at_requery_window(at_ctx* h, uint32_t kprime) {
+    if (!h || kprime < 1 || kprime > h->p.k) return AT_E_INVAL;
+    if (!h->queryable || !h->hist_valid) return AT_E_STATE;
+    hipError_t e = atp::launch_hist_weights(h->hist, h->p.k, h->n_atv, kprime, h->w_all, h->stream);
+    if (e == hipSuccess)
+        e = atp::launch_summarize(h->w_all, h->aat_all, h->sa_all, h->sa_cnt_all, h->pin_cnt_dev, h->G, h->n_atv, 1,
+                                  h->stream);
+    if (e == hipSuccess) e = hipEventRecord(h->cnt_ready, h->stream);
+    if (e != hipSuccess) return AT_E_DEVICE;
+    h->nwin = 1;
+    h->win_kq[0] = kprime;
+    use_window(h, 0);
+    return AT_OK;
+}
+
+int at_read_age_hist(at_ctx* h, uint16_t* host_out) {
+    if (!h || !host_out) return AT_E_INVAL;
+    if (!h->queryable || !h->hist_valid) return AT_E_STATE;
+    hipError_t e = hipMemcpyAsync(host_out, h->hist, h->n_atv * h->p.k * sizeof(uint16_t), hipMemcpyDeviceToHost,
+                                  h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return dev_err(e);
 }
 
 int at_select_window(at_ctx* h, uint32_t kprime) {

@@ -1024,6 +1024,74 @@ __global__ __launch_bounds__(kBlock) void k_close(const T* __restrict__ pool, ui
     }
 }
 
+// Age histogram of every ATV in one read of the pool (Section 3: an AT holds
+// the timestamp of the slice that last set it, so its age is the timestamp
+// distance, and it counts in window k' exactly when that age is below k').
+// hist[atv * k + a] = #{ATs of the ATV not inactive with age a}, a < k, so
+// the k'-weight of every window k' <= k is a prefix sum of the ATV's row and
+// no later window needs the pool again.  One wave per ATV, each with its own
+// k bins in LDS; the wave also writes the kq-weight of the close's window.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_close_hist(const T* __restrict__ pool, uint16_t* __restrict__ hist,
+                                                       uint32_t* __restrict__ w, uint64_t n_atv, Geometry G,
+                                                       uint32_t c0, uint32_t kq) {
+    extern __shared__ __align__(16) uint8_t smem_hist[];
+    T* act_lut = reinterpret_cast<T*>(smem_hist);
+    const uint32_t K = G.k;
+    const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    uint32_t* bins = reinterpret_cast<uint32_t*>(smem_hist + ((G.g * sizeof(T) + 15u) & ~15u)) + wv * K;
+    for (uint32_t a = lane; a < K; a += 64) bins[a] = 0;
+    fill_act_lut(act_lut, c0, G);  // ends with a barrier
+    constexpr uint32_t CA = kPerChunk<T>, N = kPerWord<T>;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + wv;
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
+    for (uint64_t atv = wave; atv < n_atv; atv += nwaves) {
+        const T* p = pool + (atv << G.log2g);
+        for (uint32_t off = lane * CA; off < G.g; off += 64 * CA) {
+            const uint4 d = *reinterpret_cast<const uint4*>(p + off);
+            const uint4 ac = *reinterpret_cast<const uint4*>(act_lut + off);
+#pragma unroll
+            for (uint32_t b = 0; b < CA; b++) {
+                const uint32_t at = at_in_word<T>(word_of(d, b / N), b % N);
+                const uint32_t act = at_in_word<T>(word_of(ac, b / N), b % N);
+                const uint32_t age = act >= at ? act - at : act + G.twok - at;
+                if (at != G.twok && age < K) atomicAdd(&bins[age], 1u);
+            }
+        }
+        // the wave's own LDS operations complete in order: its bins are whole
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        uint32_t wk = 0;
+        uint16_t* row = hist + atv * K;
+        for (uint32_t a = lane; a < K; a += 64) {
+            const uint32_t v = bins[a];
+            row[a] = (uint16_t)v;  // v <= g <= 2^15
+            wk += a < kq ? v : 0u;
+            bins[a] = 0;
+        }
+        for (uint32_t o = 32; o > 0; o >>= 1) wk += __shfl_xor(wk, o, 64);
+        if (lane == 0) w[atv] = wk;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// k'-weights of every ATV from the age histograms: the sum of the first k'
+// bins of its row (one wave per ATV, coalesced reads of the row).
+__global__ __launch_bounds__(kBlock) void k_hist_weights(const uint16_t* __restrict__ hist, uint32_t K,
+                                                         uint64_t n_atv, uint32_t kq, uint32_t* __restrict__ w) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
+    for (uint64_t atv = wave; atv < n_atv; atv += nwaves) {
+        const uint16_t* row = hist + atv * K;
+        uint32_t s = 0;
+        for (uint32_t a = lane; a < kq; a += 64) s += row[a];
+        for (uint32_t o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) w[atv] = s;
+    }
+}
+
 // One workgroup per (frame, row): AAT = sum of the row's weights, and the
 // ascending list of super columns (weight >= T) with its length.
 __global__ __launch_bounds__(kBlock) void k_summarize(const uint32_t* __restrict__ w_all, uint64_t* __restrict__ aat_all,
@@ -2235,6 +2303,30 @@ hipError_t launch_close(const uint8_t* pool, uint32_t* w, uint64_t n_atv, const 
         hipLaunchKernelGGL(k_close<T>, dim3((uint32_t)blocks), dim3(kBlock), G.g * sizeof(T), st,
                            reinterpret_cast<const T*>(pool), w, n_atv, G, c0, Wn);
     });
+}
+
+hipError_t launch_close_hist(const uint8_t* pool, uint16_t* hist, uint32_t* w, uint64_t n_atv, const Geometry& G,
+                             uint32_t c0, uint32_t kq, hipStream_t st) {
+    if (G.k > kHistMaxK) return hipErrorInvalidValue;
+    uint64_t blocks = (n_atv + kBlock / 64 - 1) / (kBlock / 64);
+    if (blocks > 2048) blocks = 2048;  // every block fills a g-AT timestamp table first
+    const uint32_t lds = ((G.g * G.atb + 15u) & ~15u) + (kBlock / 64) * G.k * 4u;
+    return with_at(G, [&](auto t) {
+        using T = decltype(t);
+        if (lds > 65536u)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_close_hist<T>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_close_hist<T>, dim3((uint32_t)blocks), dim3(kBlock), lds, st,
+                           reinterpret_cast<const T*>(pool), hist, w, n_atv, G, c0, kq);
+    });
+}
+
+hipError_t launch_hist_weights(const uint16_t* hist, uint32_t K, uint64_t n_atv, uint32_t kq, uint32_t* w,
+                               hipStream_t st) {
+    uint64_t blocks = (n_atv + kBlock / 64 - 1) / (kBlock / 64);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_hist_weights, dim3((uint32_t)blocks), dim3(kBlock), 0, st, hist, K, n_atv, kq, w);
+    return hipGetLastError();
 }
 
 hipError_t launch_summarize(const uint32_t* w, uint64_t* aat, uint32_t* sa, uint32_t* sa_cnt, uint32_t* cnt_host,

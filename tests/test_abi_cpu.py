@@ -52,3 +52,14 @@ def test_create_rejects_invalid_geometry(bad):
     h = C.c_void_p()
     assert lib.at_create(C.byref(p), None, C.byref(h)) == binding.AT_E_INVAL
     assert not h.value
+
+
+def test_binding_constants_match_header():
+    """Limits the binding checks against are the header's own #defines."""
+    import re
+    with open(os.path.join(ROOT, "include", "at.h")) as f:
+        text = f.read()
+    defs = dict(re.findall(r"#define\s+(AT_[A-Z_]+)\s+\(?([0-9a-z<>ul ]+?)\)?\s*$", text, re.M))
+    assert eval(defs["AT_HIST_MAX_K"]) == binding.AT_HIST_MAX_K
+    assert eval(defs["AT_NOALLOC_MAX_PAIRS"].replace("ull", "")) == binding.NOALLOC_MAX_PAIRS
+    assert eval(defs["AT_MAX_WINDOWS"]) == 8

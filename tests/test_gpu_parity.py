@@ -230,6 +230,84 @@ def test_close_multi_windows(cuda, oracle_lib, geom):
     g.destroy()
 
 
+@pytest.mark.parametrize("geom", [
+    dict(k=6, r=4, c=8, s=8, u=1, log2g=7),
+    dict(k=60, r=4, c=9, s=7, u=3, log2g=10),     # the large configuration's k
+    dict(k=13, r=4, c=8, s=8, u=1, log2g=4),      # g < 2k: empty blocks
+    dict(k=300, r=4, c=8, s=8, u=1, log2g=9),     # 16-bit ATs, the paper's k
+])
+def test_close_hist_every_window(cuda, oracle_lib, geom):
+    """at_close_slice_hist reads the pool once and keeps every ATV's age
+    histogram: it equals the oracle's, and every window k' <= k summarised
+    from it alone (at_requery_window) equals the oracle re-summarised for
+    that k' -- weights, AAT, estimates and the restore list."""
+    from paper_1807_01527_amd import binding
+    from paper_1807_01527_amd.binding import AtError
+    k = geom["k"]
+    n_slices = min(k, 40) + 4
+    per_slice = 9001 if k <= 13 else 2500
+    tr = _tiny(seed=31 + k, n_slices=n_slices, pairs_per_slice=per_slice, hosts=1 << 10, planted=4, lo=300,
+               hi=2000)
+    g, o = make_pair(dict(**geom, theta=256.0, seed=6, tuple_budget=1 << 22), oracle_lib)
+    # before any histogram close there is nothing to requery
+    g.ingest(to_dev(tr.aip[0]), to_dev(tr.bip[0]))
+    o.ingest(tr.aip[0], tr.bip[0])
+    g.close(k)
+    o.close(k)
+    with pytest.raises(AtError) as e:
+        g.requery(1)
+    assert e.value.rc == binding.AT_E_STATE
+    checks = {3, n_slices - 1}
+    for t in range(1, n_slices):
+        g.ingest(to_dev(tr.aip[t]), to_dev(tr.bip[t]))
+        o.ingest(tr.aip[t], tr.bip[t])
+        kq = 1 + (t * 7) % k
+        g.close_hist(kq)
+        o.close(kq)
+        compare_state(g, o, f"slice {t}")
+        compare_summary(g, o, f"slice {t}")
+        if t not in checks:
+            continue
+        assert np.array_equal(g.read_age_hist().astype(np.uint32), o.age_hist()), f"slice {t}"
+        hosts = np.unique(np.concatenate([tr.planted_hosts, tr.aip[t][:64]]))
+        wins = range(1, k + 1) if k <= 60 else sorted({1, 2, 3, k // 3, k // 2, k - 1, k})
+        for kp in wins:
+            g.requery(kp)
+            assert o.requery(kp) == 0
+            where = f"slice {t} window {kp}"
+            compare_state(g, o, where, pool=False)
+            compare_summary(g, o, where)
+            if kp in (1, k // 2, k) or kp % 17 == 0:
+                compare_estimates(g, o, hosts, where)
+                compare_restore(g, o, where=where)
+    for bad in (0, k + 1):
+        with pytest.raises(AtError) as e:
+            g.requery(bad)
+        assert e.value.rc == binding.AT_E_INVAL
+    # a new slice makes the histograms stale
+    g.ingest(to_dev(tr.aip[0][:10]), to_dev(tr.bip[0][:10]))
+    for call in (lambda: g.requery(1), g.read_age_hist):
+        with pytest.raises(AtError) as e:
+            call()
+        assert e.value.rc == binding.AT_E_STATE
+    g.destroy()
+
+
+def test_close_hist_rejects_long_windows(cuda, oracle_lib):
+    """The histogram close keeps k bins per wave in LDS: k above
+    AT_HIST_MAX_K is refused before any work, and the handle stays usable."""
+    from paper_1807_01527_amd import binding
+    from paper_1807_01527_amd.binding import AtError
+    g, o = make_pair(dict(k=binding.AT_HIST_MAX_K + 1, r=4, c=8, s=8, u=1, log2g=5, seed=2), oracle_lib)
+    with pytest.raises(AtError) as e:
+        g.close_hist()
+    assert e.value.rc == binding.AT_E_INVAL
+    g.close()
+    o.close()
+    compare_state(g, o, "after the refused close")
+    g.destroy()
+
+
 @pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("geom,slices", [
     (dict(k=150, r=4, c=8, s=8, u=1, log2g=9), 310),    # blocks of 1 AT and a 213-AT last block

@@ -660,3 +660,47 @@ def test_features_age_histogram_matches_exact_timestamps(oracle_lib, k, log2g):
         _, _, nat = o.estimate(hosts)
         pref = np.rint(feat[:, :kp].astype(np.float64) * g).sum(axis=1)
         assert np.array_equal(pref.astype(np.int64), nat.astype(np.int64)), kp
+
+
+# --------------------------------------------------------------------------
+# Per-ATV age histograms (one read of the pool serves every window k' <= k)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k,log2g", [(5, 6), (12, 5), (40, 4)])
+def test_atv_age_histograms_match_exact_timestamps(oracle_lib, k, log2g):
+    """Bin a of an ATV's histogram counts its ATs last set exactly a slices
+    before the close (a < k): checked against exact 64-bit timestamps of
+    every AT, at a close inside the first 2k slices and at the last.  Its
+    prefix sums are the k'-weights and AAT that oat_requery computes with
+    Alg 1 for every k' <= k (g = 16 < 2k in the last case, where some blocks
+    are empty)."""
+    o = oracle_lib.Oracle(k=k, r=4, c=8, s=8, u=1, log2g=log2g, seed=50 + k)
+    g, ncol = o.g, 1 << o.c
+    ts = np.full(o.pool_size, -(10**9), np.int64)
+    rng = np.random.default_rng(100 + k)
+    hosts = rng.integers(0, 2**32, 300, dtype=np.uint64).astype(np.uint32)
+    T = 2 * k + 7
+    checks = {k + 2, T - 1}
+    for t in range(T):
+        n = 0 if t % 5 == 4 else int(rng.integers(10, 2 * g))
+        if n:
+            aip = hosts[rng.integers(0, hosts.size, n)]
+            bip = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+            o.ingest(aip, bip)
+            for atv, i in _positions(o, aip, bip):
+                ts[atv * g + i] = t
+        o.close(k)
+        if t not in checks:
+            continue
+        ages = (t - ts).reshape(o.n_atv, g)
+        exact = np.stack([(ages == a).sum(axis=1) for a in range(k)], axis=1)
+        h = o.age_hist()
+        assert h.shape == (o.n_atv, k)
+        assert np.array_equal(h, exact), t
+        assert h.sum() > 0
+        for kp in range(1, k + 1):
+            assert o.requery(kp) == 0
+            w = o.weights()
+            assert np.array_equal(w, exact[:, :kp].sum(axis=1)), (t, kp)
+            assert np.array_equal(o.aat(), w.reshape(-1, ncol).sum(axis=1).astype(np.uint64)), (t, kp)
+        assert o.requery(k) == 0
