@@ -599,6 +599,98 @@ int oat_features(const oat *o, const uint32_t *aip, uint64_t n, float *feat)
     return OAT_OK;
 }
 
+/* ---- ACE, the aging-counter estimator the paper compares against
+ * (Section 2.3).  Every AT position of the same cube holds a timeout counter
+ * of ceil(log2(k+1)) bits instead.  A pair sets the counters it reaches to
+ * the largest value c = 2^bits - 1; every slice after the first starts by
+ * decreasing every counter that is not zero.  At the close of slice t a
+ * counter set in slice s holds c - (t - s) (until it reaches 0), so it is
+ * active for window k' when it is at least c - k' + 1. */
+struct oat_ace {
+    oat *hash;          /* the same cube and hash functions; its ATs unused */
+    uint32_t bits, cmax;
+    uint16_t *cnt;      /* one counter per AT position, ATV-major */
+    uint32_t *w;
+    uint64_t t;
+    int open;
+};
+
+int oat_ace_create(const oat_params *p, oat_ace **out)
+{
+    if (!out) return OAT_E_INVAL;
+    *out = NULL;
+    oat_ace *a = (oat_ace *)calloc(1, sizeof(oat_ace));
+    if (!a) return OAT_E_NOMEM;
+    int rc = oat_create(p, &a->hash);
+    if (rc) {
+        free(a);
+        return rc;
+    }
+    a->bits = 1;
+    while ((1u << a->bits) < p->k + 1) a->bits++;
+    a->cmax = (1u << a->bits) - 1;
+    a->cnt = (uint16_t *)calloc(a->hash->pool_size, sizeof(uint16_t));
+    a->w = (uint32_t *)calloc(a->hash->n_atv, sizeof(uint32_t));
+    if (!a->cnt || !a->w) {
+        oat_ace_destroy(a);
+        return OAT_E_NOMEM;
+    }
+    *out = a;
+    return OAT_OK;
+}
+
+void oat_ace_destroy(oat_ace *a)
+{
+    if (!a) return;
+    oat_destroy(a->hash);
+    free(a->cnt);
+    free(a->w);
+    free(a);
+}
+
+static void ace_open(oat_ace *a)
+{
+    if (a->t > 0)
+        for (uint64_t q = 0; q < a->hash->pool_size; q++)
+            if (a->cnt[q] != 0) a->cnt[q] -= 1;
+    a->open = 1;
+}
+
+int oat_ace_ingest(oat_ace *a, const uint32_t *aip, const uint32_t *bip, uint64_t n)
+{
+    if (!a) return OAT_E_INVAL;
+    if (!a->open) ace_open(a);
+    const oat *o = a->hash;
+    uint32_t x[64], z;
+    for (uint64_t q = 0; q < n; q++) {
+        oat_rrh(o, aip[q], &z, x);
+        uint32_t i = oat_bh(o, bip[q]);
+        for (uint32_t j = 0; j < o->p.r; j++)
+            a->cnt[atv_index(o, z, j, x[j]) * o->g + i] = (uint16_t)a->cmax;
+    }
+    return OAT_OK;
+}
+
+int oat_ace_close(oat_ace *a, uint32_t kprime)
+{
+    if (!a) return OAT_E_INVAL;
+    const oat *o = a->hash;
+    if (kprime < 1 || kprime > o->p.k) return OAT_E_INVAL;
+    if (!a->open) ace_open(a);
+    for (uint64_t v = 0; v < o->n_atv; v++) {
+        uint32_t w = 0;
+        for (uint32_t i = 0; i < o->g; i++) w += a->cnt[v * o->g + i] >= a->cmax - kprime + 1;
+        a->w[v] = w;
+    }
+    a->t += 1;
+    a->open = 0;
+    return OAT_OK;
+}
+
+uint32_t oat_ace_bits(const oat_ace *a) { return a->bits; }
+const uint16_t *oat_ace_counters(const oat_ace *a) { return a->cnt; }
+const uint32_t *oat_ace_weights(const oat_ace *a) { return a->w; }
+
 uint64_t oat_pool_size(const oat *o) { return o->pool_size; }
 const uint16_t *oat_pool(const oat *o) { return o->at; }
 uint64_t oat_n_atv(const oat *o) { return o->n_atv; }

@@ -86,6 +86,19 @@ int oat_restore(const oat *o, uint32_t *out, uint64_t cap, uint64_t *n_out);
 int oat_tuple_count(const oat *o, uint64_t *U);
 int oat_features(const oat *o, const uint32_t *aip, uint64_t n, float *feat /* n x 64 */);
 
+/* ACE, the aging-counter comparator (Section 2.3): ceil(log2(k+1))-bit timeout
+ * counters on the same cube and hashes; set to their largest value c when a
+ * pair reaches them, decreased by one (down to 0) at every slice after the
+ * first, active for window k' when at least c - k' + 1. */
+typedef struct oat_ace oat_ace;
+int oat_ace_create(const oat_params *p, oat_ace **out);
+void oat_ace_destroy(oat_ace *a);
+int oat_ace_ingest(oat_ace *a, const uint32_t *aip, const uint32_t *bip, uint64_t n);
+int oat_ace_close(oat_ace *a, uint32_t kprime);
+uint32_t oat_ace_bits(const oat_ace *a);
+const uint16_t *oat_ace_counters(const oat_ace *a);  /* one per AT position */
+const uint32_t *oat_ace_weights(const oat_ace *a);   /* per ATV, last close */
+
 /* Introspection. */
 uint64_t oat_pool_size(const oat *o);
 const uint16_t *oat_pool(const oat *o);          /* AT values, one word each */

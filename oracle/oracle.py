@@ -55,6 +55,13 @@ def lib():
             "oat_close": (C.c_int, [vp, C.c_uint32]),
             "oat_requery": (C.c_int, [vp, C.c_uint32]),
             "oat_age_hist": (C.c_int, [vp, u32p]),
+            "oat_ace_create": (C.c_int, [C.POINTER(_Params), C.POINTER(vp)]),
+            "oat_ace_destroy": (None, [vp]),
+            "oat_ace_ingest": (C.c_int, [vp, u32p, u32p, C.c_uint64]),
+            "oat_ace_close": (C.c_int, [vp, C.c_uint32]),
+            "oat_ace_bits": (C.c_uint32, [vp]),
+            "oat_ace_counters": (vp, [vp]),
+            "oat_ace_weights": (vp, [vp]),
             "oat_estimate": (C.c_int, [vp, u32p, C.c_uint64, f64p, u8p, u32p]),
             "oat_restore": (C.c_int, [vp, u32p, C.c_uint64, u64p]),
             "oat_tuple_count": (C.c_int, [vp, u64p]),
@@ -271,3 +278,48 @@ class Oracle:
         n = lib().oat_pin_restore_bruteforce(self.h, _p(sup, C.c_uint8), self.r, self.c, self.s,
                                              self.u, _p(out, C.c_uint32), cap)
         return int(n), np.sort(out[: min(n, cap)])
+
+
+class AceOracle:
+    """ACE, the aging-counter comparator (Section 2.3), on the cube and hashes
+    of an Oracle with the same parameters: ceil(log2(k+1))-bit counters set to
+    their largest value, decreased at every slice after the first."""
+
+    def __init__(self, k: int, r: int, c: int, s: int, u: int, log2g: int, theta: float = 1024.0,
+                 seed: int = 0, tuple_budget: int = 0):
+        p = _Params(k, r, c, s, u, log2g, theta, seed, tuple_budget)
+        h = C.c_void_p()
+        rc = lib().oat_ace_create(C.byref(p), C.byref(h))
+        if rc != OK:
+            raise ValueError(f"oat_ace_create rejected the parameters (rc={rc})")
+        self.h = h
+        self.k, self.r, self.c, self.u = k, r, c, u
+        self.g = 1 << log2g
+        self.n_atv = (1 << (c + u)) * r
+        self.bits = int(lib().oat_ace_bits(h))
+        self.cmax = (1 << self.bits) - 1
+
+    def ingest(self, aip: np.ndarray, bip: np.ndarray) -> int:
+        aip = np.ascontiguousarray(aip, np.uint32)
+        bip = np.ascontiguousarray(bip, np.uint32)
+        return lib().oat_ace_ingest(self.h, _p(aip, C.c_uint32), _p(bip, C.c_uint32), aip.size)
+
+    def close(self, kprime: Optional[int] = None) -> int:
+        return lib().oat_ace_close(self.h, self.k if kprime is None else kprime)
+
+    def counters(self) -> np.ndarray:
+        ptr = lib().oat_ace_counters(self.h)
+        n = self.n_atv * self.g
+        return np.ctypeslib.as_array(C.cast(ptr, C.POINTER(C.c_uint16)), (n,)).copy()
+
+    def weights(self) -> np.ndarray:
+        ptr = lib().oat_ace_weights(self.h)
+        return np.ctypeslib.as_array(C.cast(ptr, C.POINTER(C.c_uint32)), (self.n_atv,)).copy()
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().oat_ace_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass

@@ -449,39 +449,50 @@ def test_generator_shapes():
     assert [d[a] for a in tr.planted_hosts.tolist()] == tr.planted_card.tolist()
 
 
-@pytest.mark.parametrize("k", [3, 5, 10])
-def test_ace_comparator_same_windows_k_times_more_updates(oracle_lib, k):
-    """The aging counters the paper compares against (ACE, Section 2.3: set to
-    c = k when visited, decremented at every slice end, active for k' while
-    above k - k') mark exactly the same ATs active as the asynchronous
-    timestamps, but every counter is rewritten at every slice, while the
-    timestamps' preserve touches two blocks of 2k per ATV: k times fewer."""
-    o = oracle_lib.Oracle(k=k, r=4, c=8, s=8, u=1, log2g=6, seed=k)
+@pytest.mark.parametrize("k", [3, 5, 10, 60])
+def test_ace_oracle_matches_exact_timestamps_and_the_timestamps_windows(oracle_lib, k):
+    """The aging counters the paper compares against (ACE, Section 2.3), in the
+    oracle: ceil(log2(k+1))-bit counters, set to c = 2^bits - 1 when visited,
+    decreased at every slice after the first.  After every close each counter
+    equals max(c - age, 0) from exact 64-bit timestamps (0 if never set); the
+    k'-weights ACE reports (at least c - k' + 1) equal the asynchronous
+    timestamps' for the k' of that close, one k' per slice in turn; and ACE
+    rewrites every live counter at every slice while the timestamps' preserve
+    examines two blocks of 2k per ATV: about k times fewer."""
+    geom = dict(k=k, r=4, c=8, s=8, u=1, log2g=6, seed=k)
+    o = oracle_lib.Oracle(**geom)
+    a = oracle_lib.AceOracle(**geom)
+    assert a.bits == math.ceil(math.log2(k + 1)) and a.cmax == (1 << a.bits) - 1
     g = o.g
-    ace = np.zeros(o.pool_size, np.int64)
+    ts = np.full(o.pool_size, -(10**9), np.int64)
     rng = np.random.default_rng(k)
     hosts = rng.integers(0, 2**32, 5, dtype=np.uint64).astype(np.uint32)
     blocks = np.array([o.block_of(i) for i in range(g)])
-    touched = []
-    for t in range(4 * k + 3):
-        if t > 0:
-            ace = np.maximum(ace - 1, 0)          # ACE: every counter ages at the slice end
-        aip = hosts[rng.integers(0, hosts.size, 30)]
-        bip = rng.integers(0, 2**32, 30, dtype=np.uint64).astype(np.uint32)
+    touched, aged = [], []
+    prev = np.zeros(o.pool_size, np.int64)
+    for t in range(2 * k + 7):
+        n = 0 if t % 7 == 6 else 30
+        aip = hosts[rng.integers(0, hosts.size, n)]
+        bip = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
         o.ingest(aip, bip)
+        assert a.ingest(aip, bip) == 0
         for atv, i in _positions(o, aip, bip):
-            ace[atv * g + i] = k
-        o.close(k)
-        pool = o.pool()
-        act = (t % (2 * k) + blocks) % (2 * k)
+            ts[atv * g + i] = t
+        kp = 1 + t % k
+        o.close(kp)
+        assert a.close(kp) == 0
+        cnt = a.counters().astype(np.int64)
+        expect = np.where(ts >= 0, np.maximum(a.cmax - (t - ts), 0), 0)
+        assert np.array_equal(cnt, expect), t
+        assert np.array_equal(a.weights(), o.weights()), (t, kp)
+        if t > 0:
+            aged.append(int(np.count_nonzero(prev)))
+        prev = cnt
         c0 = t % (2 * k)
         due = {(2 * k - c0) % (2 * k), (3 * k - c0) % (2 * k)}
         touched.append(int(np.isin(blocks, list(due)).sum()) * o.n_atv)
-        for kp in range(1, k + 1):
-            at_active = np.array([oracle_lib.check_at(k, int(act[idx % g]), int(pool[idx]), kp)
-                                  for idx in range(0, o.pool_size, 7)])
-            assert np.array_equal(at_active, ace[::7] > k - kp)
     assert abs(np.mean(touched) / o.pool_size - 1.0 / k) < 0.5 / k
+    assert np.mean(aged) > 0
 
 
 def test_requery_equals_close_with_that_window(oracle_lib):
