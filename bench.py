@@ -459,7 +459,7 @@ def link_config2(args, dev, learned, Mlp) -> dict:
     import torch
 
     from paper_1807_01527_amd import traffic
-    from paper_1807_01527_amd.binding import AtPool, probe_ace_age, probe_scatter
+    from paper_1807_01527_amd.binding import AtPool, probe_scatter
     t0 = time.perf_counter()
     tr = traffic.generate(traffic.config_link(seed=0, n_slices=args.slices, pairs_per_slice=args.pairs))
     truth_h, truth_n = traffic.window_counts(tr.aip, tr.bip, min_count=int(LINK["theta"]))
@@ -605,34 +605,95 @@ def link_config2(args, dev, learned, Mlp) -> dict:
     pr = probe_rate(dev, pool.pool_bytes, aip_d[0], bip_d[0], args.pairs)
     out["scatter_probe"] = {**pr, "what": "uniform random byte stores, r per pair, into a buffer of the pool's size",
                             "ingest_frac_of_probe": (per_launch / avg_ingest_s) / (pr["mpps"] * 1e6)}
-    # slice maintenance: the lazy preserve kernel alone (an opening call with
-    # no pairs launches only k_preserve) against one aging pass of ACE counters
-    ace_buf = torch.full((pool.pool_bytes,), 7, dtype=torch.uint8, device=dev)
-    pres, ages = [], []
-    for t in range(S):
-        e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
-        e0.record(stream)
-        pool.ingest(aip_d[t][:0], bip_d[t][:0], n=0)
-        e1.record(stream)
-        e2.record(stream)
-        probe_ace_age(ace_buf, stream=stream)
-        e3.record(stream)
-        pool.ingest(aip_d[t], bip_d[t])
-        pool.close(K)
-        pres.append((e0, e1))
-        ages.append((e2, e3))
-    torch.cuda.synchronize()
-    pm = float(np.mean([a.elapsed_time(b) for a, b in pres]))
-    am = float(np.mean([a.elapsed_time(b) for a, b in ages]))
-    del ace_buf
-    out["slice_maintenance"] = {"at_lazy_preserve_ms": pm, "ace_aging_ms": am, "ratio": am / pm,
-                                "note": f"event-timed single launches on a {pool.pool_bytes >> 20} MiB pool, k={K}: "
-                                        "the timestamps touch 2 of 2k blocks per ATV, the aging counters all of "
-                                        "them; kernel-only times are in the rocprofv3 summary"}
+    out["slice_maintenance"] = maintenance(LINK, aip_d, bip_d, pool, args.pairs)
     pool.destroy()
     if mlp is not None:
         mlp.destroy()
     return out, tr, truth_h
+
+
+def maintenance(params: dict, aip_d, bip_d, pool=None, pairs: int = 0, reps: int = 2) -> dict:
+    """The paper's central claim on one geometry: ACE counters at their own
+    width (every counter aged at every slice) against the asynchronous
+    timestamps packed at theirs (one bit more; the lazy preserve examines 2 of
+    2k blocks per ATV) and in bytes (the library's pool).  The slices go
+    through all three `reps` times; every maintenance and scan step is timed
+    with events on its own, over the passes after the first."""
+    import torch
+
+    from paper_1807_01527_amd.binding import AtCmp, AtPool
+    stream = torch.cuda.current_stream()
+    own = pool is None
+    if own:
+        pool = AtPool(**params, stream=stream)
+    K, S = params["k"], len(aip_d)
+    cmp_ace = AtCmp("ace", **params, stream=stream)
+    cmp_at = AtCmp("at", **params, stream=stream)
+    ev = {n: [] for n in ("ace_age", "ace_set", "at_pack_preserve", "at_pack_set", "at_byte_preserve",
+                          "at_byte_scan")}
+
+    def timed(name, fn):
+        e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        ev[name].append((e0, e1))
+
+    for rep in range(reps):
+        for t in range(S):
+            timed("ace_age", cmp_ace.open_slice)
+            timed("ace_set", lambda: cmp_ace.ingest(aip_d[t], bip_d[t]))
+            cmp_ace.close(K)
+            timed("at_pack_preserve", cmp_at.open_slice)
+            timed("at_pack_set", lambda: cmp_at.ingest(aip_d[t], bip_d[t]))
+            cmp_at.close(K)
+            timed("at_byte_preserve", lambda: pool.ingest(aip_d[t][:0], bip_d[t][:0], n=0))
+            timed("at_byte_scan", lambda: pool.ingest(aip_d[t], bip_d[t]))
+            pool.close(K)
+    torch.cuda.synchronize()
+    ms = {n: float(np.mean([a.elapsed_time(b) for a, b in v[S:]])) for n, v in ev.items()}
+    same = bool(np.array_equal(cmp_ace.read_weights(), cmp_at.read_weights()))
+    out = {
+        "k": K, "ats": pool.n_atv * pool.g, "pairs_per_slice": pairs or int(aip_d[0].numel()),
+        "ace": {"bits": cmp_ace.bits, "bytes": 4 * cmp_ace.n_words, "age_ms": ms["ace_age"],
+                "set_ms": ms["ace_set"]},
+        "at_packed": {"bits": cmp_at.bits, "bytes": 4 * cmp_at.n_words, "preserve_ms": ms["at_pack_preserve"],
+                      "set_ms": ms["at_pack_set"]},
+        "at_bytes": {"bits": 8 * pool.at_bytes, "bytes": pool.pool_bytes, "preserve_ms": ms["at_byte_preserve"],
+                     "scan_ms": ms["at_byte_scan"]},
+        "maintenance_ratio_packed": ms["ace_age"] / ms["at_pack_preserve"],
+        "maintenance_ratio_bytes": ms["ace_age"] / ms["at_byte_preserve"],
+        "same_weights": same,
+        "note": f"event-timed single launches (launch gaps included; kernel times are in the rocprofv3 summary), "
+                f"{S} slices after a first pass over them: ACE ages every counter at every slice, the timestamps "
+                "preserve 2 of 2k blocks per ATV; the packed stores are 32-bit atomics (ACE one OR, a timestamp "
+                "an AND and an OR), the byte pool scans through at_ingest_slice"}
+    cmp_ace.destroy()
+    cmp_at.destroy()
+    if own:
+        pool.destroy()
+    return out
+
+
+def maintenance_both(args, dev) -> dict:
+    """maintenance() on the link geometry (its 10 slices of 5M pairs) and on
+    the large one (link 0's 60 slices of 3.33M pairs)."""
+    import torch
+
+    from paper_1807_01527_amd import traffic
+    from paper_1807_01527_amd import traffic_gpu as tg
+    from paper_1807_01527_amd import learned
+    tr = traffic.generate(traffic.config_link(seed=0, n_slices=args.slices, pairs_per_slice=args.pairs))
+    a = [torch.from_numpy(x.view(np.int32)).to(dev) for x in tr.aip]
+    b = [torch.from_numpy(x.view(np.int32)).to(dev) for x in tr.bip]
+    out = {"link": maintenance(LINK, a, b)}
+    del a, b
+    la, lb, _ = tg.link_stream(0, LARGE_SLICES * LARGE_PAIRS, dev, **learned.LARGE_STREAM)
+    P = LARGE_PAIRS
+    a = [la[t * P:(t + 1) * P] for t in range(LARGE_SLICES)]
+    b = [lb[t * P:(t + 1) * P] for t in range(LARGE_SLICES)]
+    out["large"] = maintenance(dict(LARGE, seed=0), a, b)
+    return out
 
 
 def restore_lists(dev) -> dict:
@@ -736,6 +797,8 @@ def main():
     ap.add_argument("--paper-scale", type=int, default=0, metavar="SLICES",
                     help="only run the k=300, 2^32-AT sliding shape over SLICES slices (3600 for 3300 windows) "
                          "and exit")
+    ap.add_argument("--maintenance", action="store_true",
+                    help="only the ACE / packed-timestamp / byte-timestamp comparison on the link and large geometries")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -759,6 +822,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.maintenance:
+        print(json.dumps({"slice_maintenance": maintenance_both(args, dev)}), flush=True)
+        return
     t0 = time.perf_counter()
     wl = large_workload(dev)
     torch.cuda.synchronize()

@@ -447,13 +447,46 @@ int at_serve_read_pool(at_serve *s, uint32_t link_id, uint8_t *host_out);
  * is whole 64 KiB tiles, at most 4096.  Any pointer may be NULL. */
 int at_serve_tiled_stats(at_serve *s, uint64_t *calls, uint64_t *pairs, double *device_ms);
 
-/* Comparator probe: one aging pass of ACE counters (the sliding-window
- * counters the paper compares asynchronous timestamps against, Section 2.3):
- * every nonzero byte of counters_dev (device, `bytes` a multiple of 16,
- * 16-byte aligned) is decremented by one, as ACE requires at every slice end.
- * Timed against the lazy preserve of at_ingest_slice on a pool of the same
- * size it measures the k-fold saving the paper claims.  Asynchronous. */
-int at_probe_ace_age(uint8_t *counters_dev, uint64_t bytes, void *hip_stream);
+/*
+ * The aging-counter comparator (Section 2.3 against Section 3).  ACE keeps a
+ * timeout counter of ceil(log2(k+1)) bits at every AT position: a pair sets
+ * the counters it reaches to their largest value c = 2^bits - 1, and every
+ * slice after the first starts by decreasing every nonzero counter, so each
+ * slice rewrites the whole pool.  A counter set s slices before a close holds
+ * c - s and counts in window k' when it is at least c - k' + 1.  The
+ * asynchronous timestamps need one bit more (2k+1 values) and their lazy
+ * preserve (Alg 2) examines two of the 2k blocks of every ATV per slice.
+ * Both are kept here at their own width, packed: F = floor(32 / bits) fields
+ * per 32-bit word, position i of ATV v in word v * wv + i / F (wv =
+ * ceil(g / F) words per ATV) at bits [(i % F) * bits, (i % F + 1) * bits),
+ * unused fields and bits zero (timestamp fields start at 2k, inactive).
+ * Sub-word fields take their stores as 32-bit atomics (ACE one OR, a
+ * timestamp an AND and an OR).  The cube, hashes and block layout are those
+ * of an at_ctx made with the same parameters, so the k'-weights of the two
+ * kinds equal at_close_slice's.  Calls are asynchronous on hip_stream except
+ * at_cmp_read.
+ */
+typedef struct at_cmp at_cmp;
+enum { AT_CMP_ACE = 1, AT_CMP_AT = 2 };
+/* kind AT_CMP_ACE or AT_CMP_AT.  AT_E_INVAL (parameters as at_create), AT_E_NOMEM. */
+int at_cmp_create(const at_params *p, int kind, void *hip_stream, at_cmp **out);
+int at_cmp_destroy(at_cmp *c);
+/* out4 = {bits per field, fields per word F, words per ATV, words in all}. */
+int at_cmp_info(const at_cmp *c, uint64_t *out4);
+/* The slice's maintenance only (opening it if it is not): ACE ages every
+ * counter (not before the first slice); the timestamps preserve their two
+ * due blocks.  Later calls in the same slice do nothing. */
+int at_cmp_open_slice(at_cmp *c);
+/* Alg 3 on the packed pool: n pairs, aip_dev/bip_dev device arrays of n
+ * uint32 (opens the slice first if needed). */
+int at_cmp_ingest(at_cmp *c, const uint32_t *aip_dev, const uint32_t *bip_dev, uint64_t n);
+/* End of the slice: per-ATV k'-weights, 1 <= k' <= k (AT_E_INVAL otherwise). */
+int at_cmp_close(at_cmp *c, uint32_t kprime);
+/* Copy the packed words (words_host: "words in all" uint32) and/or the last
+ * close's weights (weights_host: one uint32 per ATV; AT_E_STATE before any
+ * close, or once a slice has opened since) to host memory; blocks.  Either
+ * pointer may be NULL. */
+int at_cmp_read(at_cmp *c, uint32_t *words_host, uint32_t *weights_host);
 
 /* Measurement probe, not part of the method: n items (n a multiple of 4,
  * a_dev/b_dev 16-byte aligned device arrays of n uint32, read like the pair

@@ -62,7 +62,13 @@ SIGNATURES = {
     "at_tuple_count": (C.c_int, [_vp, _u64p]),
     "at_set_scan_mode": (C.c_int, [_vp, C.c_int]),
     "at_probe_scatter": (C.c_int, [_vp, C.c_uint64, _vp, _vp, C.c_uint64, C.c_uint32, _vp]),
-    "at_probe_ace_age": (C.c_int, [_vp, C.c_uint64, _vp]),
+    "at_cmp_create": (C.c_int, [C.POINTER(Params), C.c_int, _vp, C.POINTER(_vp)]),
+    "at_cmp_destroy": (C.c_int, [_vp]),
+    "at_cmp_info": (C.c_int, [_vp, _u64p]),
+    "at_cmp_open_slice": (C.c_int, [_vp]),
+    "at_cmp_ingest": (C.c_int, [_vp, _vp, _vp, C.c_uint64]),
+    "at_cmp_close": (C.c_int, [_vp, C.c_uint32]),
+    "at_cmp_read": (C.c_int, [_vp, _u32p, _u32p]),
     "at_features": (C.c_int, [_vp, _vp, C.c_uint64, _vp, _vp, _vp]),
     "at_mlp_create": (C.c_int, [_vp, C.POINTER(_vp)]),
     "at_mlp_destroy": (C.c_int, [_vp]),
@@ -166,15 +172,6 @@ def probe_scatter(dst_dev, a_dev, b_dev, n: int, r: int, stream=None):
     _check(load().at_probe_scatter(C.c_void_p(_dev_ptr(dst_dev)), dst_dev.numel() * dst_dev.element_size(),
                                    C.c_void_p(_dev_ptr(a_dev)), C.c_void_p(_dev_ptr(b_dev)), n, r,
                                    C.c_void_p(stream.cuda_stream)), "at_probe_scatter")
-
-
-def probe_ace_age(counters_dev, stream=None):
-    """One ACE aging pass over a device byte buffer (see at_probe_ace_age)."""
-    import torch
-    if stream is None:
-        stream = torch.cuda.current_stream()
-    _check(load().at_probe_ace_age(C.c_void_p(_dev_ptr(counters_dev)), counters_dev.numel(),
-                                   C.c_void_p(stream.cuda_stream)), "at_probe_ace_age")
 
 
 class AtPool:
@@ -559,3 +556,68 @@ class Server:
         _check(self.lib.at_serve_tiled_stats(self.h, C.byref(calls), C.byref(pairs), C.byref(ms)),
                "at_serve_tiled_stats")
         return dict(calls=int(calls.value), pairs=int(pairs.value), device_ms=float(ms.value))
+
+
+class AtCmp:
+    """A packed comparator pool (at_cmp_*): ACE counters (kind "ace") or the
+    asynchronous timestamps (kind "at"), each at its own width."""
+
+    KINDS = {"ace": 1, "at": 2}
+
+    def __init__(self, kind: str, k: int, r: int, c: int, s: int, u: int, log2g: int, theta: float = 1024.0,
+                 seed: int = 0, stream=None):
+        import torch
+        self.lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        p = Params(k, r, c, s, u, log2g, theta, seed, 0)
+        h = C.c_void_p()
+        _check(self.lib.at_cmp_create(C.byref(p), self.KINDS[kind], C.c_void_p(stream.cuda_stream), C.byref(h)),
+               "at_cmp_create")
+        self.h = h
+        self.kind, self.k, self.g = kind, k, 1 << log2g
+        self.n_atv = (1 << (c + u)) * r
+        info = np.zeros(4, np.uint64)
+        _check(self.lib.at_cmp_info(self.h, _p(info, C.c_uint64)), "at_cmp_info")
+        self.bits, self.F, self.wv, self.n_words = (int(x) for x in info)
+
+    def open_slice(self):
+        _check(self.lib.at_cmp_open_slice(self.h), "at_cmp_open_slice")
+
+    def ingest(self, aip_dev, bip_dev, n: Optional[int] = None):
+        n = aip_dev.numel() if n is None else n
+        _check(self.lib.at_cmp_ingest(self.h, C.c_void_p(_dev_ptr(aip_dev)), C.c_void_p(_dev_ptr(bip_dev)), n),
+               "at_cmp_ingest")
+
+    def close(self, kprime: Optional[int] = None):
+        _check(self.lib.at_cmp_close(self.h, self.k if kprime is None else kprime), "at_cmp_close")
+
+    def read_words(self) -> np.ndarray:
+        out = np.zeros(self.n_words, np.uint32)
+        _check(self.lib.at_cmp_read(self.h, _p(out, C.c_uint32), None), "at_cmp_read")
+        return out
+
+    def read_weights(self) -> np.ndarray:
+        out = np.zeros(self.n_atv, np.uint32)
+        _check(self.lib.at_cmp_read(self.h, None, _p(out, C.c_uint32)), "at_cmp_read")
+        return out
+
+    def unpack(self, words: np.ndarray) -> np.ndarray:
+        """Field values per AT position (n_atv * g), from the packed layout
+        at.h documents."""
+        w = words.reshape(self.n_atv, self.wv).astype(np.uint64)
+        mask = (1 << self.bits) - 1
+        f = np.stack([(w >> np.uint64(e * self.bits)) & np.uint64(mask) for e in range(self.F)], axis=2)
+        return f.reshape(self.n_atv, self.wv * self.F)[:, :self.g].reshape(-1).astype(np.uint32)
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            self.lib.at_cmp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libatpool.so")
-SOURCES = ["kernels.hip", "mlp.hip", "capi.hip", "serve.hip"]
+SOURCES = ["kernels.hip", "mlp.hip", "capi.hip", "serve.hip", "compare.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

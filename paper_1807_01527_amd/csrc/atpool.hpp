@@ -35,6 +35,7 @@ struct Geometry {
 };
 
 Geometry derive_geometry(const at_params& p);  // from a handle's parameters (capi.hip)
+int validate_params(const at_params& p);        // AT_OK or AT_E_INVAL, as at_create
 
 // Lazy preserve work of one slice opening: the AT ranges of the two blocks
 // whose timestamp becomes 0 and k, and the (one or two, disjoint) spans of
@@ -102,6 +103,28 @@ struct CloseWindows {
 };
 hipError_t launch_close(const uint8_t* pool, uint32_t* w, uint64_t n_atv, const Geometry& G, uint32_t c0,
                         const CloseWindows& Wn, hipStream_t st);
+// Packed comparator pools (f3): `bits`-bit fields, F = 32 / bits per word,
+// ATV v's position i in word v * wv + i / F at bit (i % F) * bits.
+struct CmpLayout {
+    uint32_t bits, F, fmagic;  // fmagic = ceil(2^32 / F): i / F == umulhi(i, fmagic) for i < 2^16
+    uint32_t wv;               // words per ATV
+    uint64_t n_atv;
+};
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+// ACE aging: every nonzero field of n words decreases by one
+hipError_t launch_cmp_age(uint32_t* words, uint64_t n, uint32_t bits, uint32_t lsb, hipStream_t st);
+// a pair's r positions: ACE (ace = true) sets the field to all ones, the
+// packed timestamps set it to the ACT of the position's block
+hipError_t launch_cmp_set(uint32_t* words, const uint32_t* aip, const uint32_t* bip, uint64_t n, const Geometry& G,
+                          const CmpLayout& Lw, bool ace, uint32_t c0, hipStream_t st);
+// lazy preserve (Alg 2) of the packed timestamps on the AT ranges of the two
+// due blocks, one thread per word of the (merged) word spans
+hipError_t launch_cmp_preserve(uint32_t* words, const Geometry& G, const CmpLayout& Lw, uint32_t c0,
+                               const PreserveSpans& S, uint32_t s0lo, uint32_t s0n, uint32_t s1lo, uint32_t s1n,
+                               hipStream_t st);
+// per-ATV k'-weights of a packed pool
+hipError_t launch_cmp_close(const uint32_t* words, const Geometry& G, const CmpLayout& Lw, bool ace, uint32_t c0,
+                            uint32_t kq, uint32_t* w, hipStream_t st);
 // Age-histogram close: hist[atv * k + a] (a < k) counts the ATVs' ATs of age
 // a, w[atv] receives the kq-weight.  k <= kHistMaxK (LDS bins per wave).
 constexpr uint32_t kHistMaxK = 1024;
@@ -187,7 +210,6 @@ hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, cons
                            hipStream_t st);
 hipError_t launch_mlp_refresh(const float* w, const MlpOut& O, hipStream_t st);
 
-hipError_t launch_ace_age(uint8_t* p, uint64_t bytes, hipStream_t st);
 hipError_t launch_scatter_probe(uint8_t* dst, uint64_t bytes, const uint32_t* a, const uint32_t* b, uint64_t n,
                                 uint32_t r, hipStream_t st);
 

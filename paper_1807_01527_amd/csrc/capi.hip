@@ -377,6 +377,8 @@ uint64_t tuple_count(const at_ctx* h, const std::vector<uint32_t>& cnt) {
 
 namespace atp {
 
+int validate_params(const at_params& p) { return validate(p); }
+
 // Hash constants and block layout of a handle, from its parameters (Section 3,
 // Section 4.1); at_create and the streaming server both use it.
 Geometry derive_geometry(const at_params& p) {
@@ -931,13 +933,6 @@ int at_constants(const at_ctx* h, uint64_t* out8) {
     out8[6] = h->G.W;
     out8[7] = h->G.blk_a;
     return AT_OK;
-}
-
-int at_probe_ace_age(uint8_t* counters_dev, uint64_t bytes, void* hip_stream) {
-    if (!counters_dev || bytes == 0 || (bytes % 16) || (reinterpret_cast<uintptr_t>(counters_dev) & 15u))
-        return AT_E_INVAL;
-    if (!device_accessible(counters_dev)) return AT_E_INVAL;
-    return atp::launch_ace_age(counters_dev, bytes, (hipStream_t)hip_stream) == hipSuccess ? AT_OK : AT_E_DEVICE;
 }
 
 int at_probe_scatter(uint8_t* dst_dev, uint64_t bytes, const uint32_t* a_dev, const uint32_t* b_dev, uint64_t n,

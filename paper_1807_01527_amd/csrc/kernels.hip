@@ -2033,21 +2033,126 @@ __global__ __launch_bounds__(kBlock) void k_gather_pairs(GatherList Lst, uint32_
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_ace_age(uint8_t* __restrict__ p, uint64_t n16) {
-    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n16; q += (uint64_t)gridDim.x * blockDim.x) {
-        uint4 v = reinterpret_cast<uint4*>(p)[q];
-        uint32_t w[4] = {v.x, v.y, v.z, v.w};
+// ---------------------------------------------------------------- f3: comparator
+// ACE (Section 2.3) and the asynchronous timestamps side by side, each at its
+// own width in packed fields: ceil(log2(k+1)) bits per ACE counter, one more
+// per timestamp.  Sub-word fields have no byte of their own, so a pair's
+// stores are atomic read-modify-writes of 32-bit words.  ACE sets a field to
+// its largest value (all ones) with one OR.  A timestamp takes an AND that
+// clears the bits its value lacks and an OR that sets those it has; every
+// setter of a field within a slice writes the same value, so any interleaving
+// of the two leaves that value, and fields of other positions are untouched.
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
+    for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (uint64_t)gridDim.x * blockDim.x)
+        p[q] = v;
+}
+
+// ACE aging: a field that is not zero loses one.  Bit 0 of a field of
+// x | x >> 1 | ... | x >> (bits - 1) is set exactly when the field is not
+// zero (the shifts stay inside the field for that bit), and subtracting 1 from
+// a nonzero field never borrows from the next.  Four words per thread.
+__global__ __launch_bounds__(kBlock) void k_cmp_age(uint32_t* __restrict__ w, uint64_t n4, uint32_t bits, uint32_t lsb) {
+    for (uint64_t q = (uint64_t)blockIdx.x * kBlock + threadIdx.x; q < n4; q += (uint64_t)gridDim.x * kBlock) {
+        uint4 v = reinterpret_cast<uint4*>(w)[q];
+        uint32_t x[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            uint32_t x = w[e], out = 0;
-#pragma unroll
-            for (int b = 0; b < 4; b++) {
-                uint32_t c = (x >> (8 * b)) & 0xFFu;
-                out |= (c ? c - 1 : 0u) << (8 * b);
-            }
-            w[e] = out;
+            uint32_t f = x[e];
+            for (uint32_t b = 1; b < bits; b++) f |= x[e] >> b;
+            x[e] -= f & lsb;
         }
-        reinterpret_cast<uint4*>(p)[q] = make_uint4(w[0], w[1], w[2], w[3]);
+        reinterpret_cast<uint4*>(w)[q] = make_uint4(x[0], x[1], x[2], x[3]);
+    }
+}
+
+// Alg 3 on a packed pool: the r positions of each pair.
+__global__ __launch_bounds__(kBlock) void k_cmp_set(uint32_t* __restrict__ words, const uint32_t* __restrict__ aip,
+                                                    const uint32_t* __restrict__ bip, uint64_t n, Geometry G,
+                                                    CmpLayout Lw, uint32_t ace, uint32_t c0) {
+    const uint32_t fmask = (1u << Lw.bits) - 1u;
+    for (uint64_t q = (uint64_t)blockIdx.x * kBlock + threadIdx.x; q < n; q += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t f = mangle(aip[q], G.A);
+        const uint32_t z = f & G.umask;
+        const uint64_t L = (uint64_t)(f >> G.u);
+        const uint64_t LL = L | (L << G.W);
+        const uint32_t i = (uint32_t)((G.alpha * (uint64_t)bip[q] + G.beta) >> (64 - G.log2g));
+        const uint32_t wq = __umulhi(i, Lw.fmagic);
+        const uint32_t sh = (i - wq * Lw.F) * Lw.bits;
+        const uint32_t v = ace ? fmask : act_of(i, c0, G);
+        for (uint32_t j = 0; j < G.r; j++) {
+            const uint64_t atv = ((uint64_t)(z * G.r + j) << G.c) + column(LL, G.sh[j], G.ncol_mask);
+            uint32_t* wp = words + atv * Lw.wv + wq;
+            if (!ace) atomicAnd(wp, ~(fmask << sh) | (v << sh));
+            atomicOr(wp, v << sh);
+        }
+    }
+}
+
+// Alg 2 on the packed timestamps of the two due blocks (their ACT becomes 0
+// or k): one thread per word of the word spans of an ATV, a block holding as
+// many ATVs as fit its 256 threads; only fields whose position lies in a due
+// block change, and no two threads share a word.
+__global__ __launch_bounds__(kBlock) void k_cmp_preserve(uint32_t* __restrict__ words, Geometry G, CmpLayout Lw,
+                                                         uint32_t c0, PreserveSpans S, uint32_t s0lo, uint32_t s0n,
+                                                         uint32_t s1lo, uint32_t s1n) {
+    const uint32_t fmask = (1u << Lw.bits) - 1u;
+    const uint32_t per = s0n + s1n;
+    const bool wide = per >= kBlock;
+    const uint32_t A = wide ? 1u : kBlock / per;  // ATVs per block
+    const uint32_t a = wide ? 0u : threadIdx.x / per;
+    const uint32_t e0 = wide ? threadIdx.x : threadIdx.x - a * per, estep = wide ? kBlock : per;
+    if (a >= A) return;
+    for (uint64_t atv = (uint64_t)blockIdx.x * A + a; atv < Lw.n_atv; atv += (uint64_t)gridDim.x * A) {
+        for (uint32_t e = e0; e < per; e += estep) {
+            const uint32_t wi = e < s0n ? s0lo + e : s1lo + (e - s0n);
+            uint32_t* wp = words + atv * Lw.wv + wi;
+            const uint32_t x = *wp;
+            uint32_t y = x;
+            for (uint32_t fl = 0; fl < Lw.F; fl++) {
+                const uint32_t pos = wi * Lw.F + fl;
+                const bool due = (pos >= S.r0lo && pos < S.r0hi) || (pos >= S.r1lo && pos < S.r1hi);
+                const uint32_t sh = fl * Lw.bits;
+                const uint32_t at = (x >> sh) & fmask;
+                if (!due || at >= G.twok) continue;
+                const uint32_t act = act_of(pos, c0, G);
+                uint32_t since = act >= at ? act - at : act + G.twok - at;
+                if (since == 0) since = G.twok;  // equal to the new ACT: set 2k slices ago
+                if (since >= G.k) y = (y & ~(fmask << sh)) | (G.twok << sh);
+            }
+            if (y != x) *wp = y;
+        }
+    }
+}
+
+// k'-weight of every ATV of a packed pool (one wave per ATV): ACE fields of at
+// least cmax - k' + 1, timestamps not inactive and less than k' slices old.
+__global__ __launch_bounds__(kBlock) void k_cmp_close(const uint32_t* __restrict__ words, Geometry G, CmpLayout Lw,
+                                                      uint32_t ace, uint32_t c0, uint32_t kq,
+                                                      uint32_t* __restrict__ w) {
+    const uint32_t fmask = (1u << Lw.bits) - 1u;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
+    for (uint64_t atv = wave; atv < Lw.n_atv; atv += nwaves) {
+        uint32_t cnt = 0;
+        for (uint32_t wi = lane; wi < Lw.wv; wi += 64) {
+            const uint32_t x = words[atv * Lw.wv + wi];
+            for (uint32_t fl = 0; fl < Lw.F; fl++) {
+                const uint32_t pos = wi * Lw.F + fl;
+                if (pos >= G.g) break;
+                const uint32_t v = (x >> (fl * Lw.bits)) & fmask;
+                if (ace) {
+                    cnt += v + kq > fmask;  // v >= cmax - k' + 1
+                } else {
+                    const uint32_t act = act_of(pos, c0, G);
+                    const uint32_t d = act >= v ? act - v : act + G.twok - v;
+                    cnt += (v != G.twok) & (d < kq);
+                }
+            }
+        }
+        for (uint32_t o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if (lane == 0) w[atv] = cnt;
     }
 }
 
@@ -2466,9 +2571,45 @@ hipError_t launch_gather_pairs(const GatherList& Lst, uint32_t* aip_out, uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_ace_age(uint8_t* p, uint64_t bytes, hipStream_t st) {
-    if (bytes == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ace_age, dim3(grid_for(bytes / 16, 1u << 16)), dim3(kBlock), 0, st, p, bytes / 16);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 1u << 16)), dim3(kBlock), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_cmp_age(uint32_t* words, uint64_t n, uint32_t bits, uint32_t lsb, hipStream_t st) {
+    if (n == 0 || n % 4) return n ? hipErrorInvalidValue : hipSuccess;
+    hipLaunchKernelGGL(k_cmp_age, dim3(grid_for(n / 4, 1u << 16)), dim3(kBlock), 0, st, words, n / 4, bits, lsb);
+    return hipGetLastError();
+}
+
+hipError_t launch_cmp_set(uint32_t* words, const uint32_t* aip, const uint32_t* bip, uint64_t n, const Geometry& G,
+                          const CmpLayout& Lw, bool ace, uint32_t c0, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cmp_set, dim3(grid_for(n, 1u << 16)), dim3(kBlock), 0, st, words, aip, bip, n, G, Lw,
+                       (uint32_t)ace, c0);
+    return hipGetLastError();
+}
+
+hipError_t launch_cmp_preserve(uint32_t* words, const Geometry& G, const CmpLayout& Lw, uint32_t c0,
+                               const PreserveSpans& S, uint32_t s0lo, uint32_t s0n, uint32_t s1lo, uint32_t s1n,
+                               hipStream_t st) {
+    const uint32_t per = s0n + s1n;
+    if (per == 0) return hipSuccess;
+    const uint32_t A = per >= kBlock ? 1u : kBlock / per;
+    uint64_t blocks = (Lw.n_atv + A - 1) / A;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_cmp_preserve, dim3((uint32_t)blocks), dim3(kBlock), 0, st, words, G, Lw, c0, S, s0lo, s0n,
+                       s1lo, s1n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cmp_close(const uint32_t* words, const Geometry& G, const CmpLayout& Lw, bool ace, uint32_t c0,
+                            uint32_t kq, uint32_t* w, hipStream_t st) {
+    uint64_t blocks = (Lw.n_atv + kBlock / 64 - 1) / (kBlock / 64);
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_cmp_close, dim3((uint32_t)blocks), dim3(kBlock), 0, st, words, G, Lw, (uint32_t)ace, c0, kq,
+                       w);
     return hipGetLastError();
 }
 

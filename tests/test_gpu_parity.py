@@ -169,16 +169,62 @@ def test_scan_modes(cuda, oracle_lib, geom, mode):
     run_trace(g, o, tr.aip, tr.bip, batches=5, seed=2, query_hosts=tr.planted_hosts, restore=False)
 
 
-def test_ace_age_probe(cuda):
-    """The comparator's aging pass decrements every nonzero counter by one."""
-    import torch
-    from paper_1807_01527_amd.binding import probe_ace_age
-    rng = np.random.default_rng(3)
-    v = rng.integers(0, 256, 1 << 20).astype(np.uint8)
-    d = torch.from_numpy(v.copy()).cuda()
-    probe_ace_age(d)
-    torch.cuda.synchronize()
-    assert np.array_equal(d.cpu().numpy(), np.maximum(v.astype(np.int64) - 1, 0).astype(np.uint8))
+@pytest.mark.parametrize("geom", [
+    dict(k=3, r=4, c=8, s=8, u=1, log2g=6),      # ACE 2 bits (16 per word), timestamps 3 bits (10 per word)
+    dict(k=10, r=4, c=8, s=8, u=1, log2g=7),     # 4 and 5 bits
+    dict(k=60, r=4, c=9, s=7, u=3, log2g=4),     # 6 and 7 bits; g = 16 < 2k, a ragged last word per ATV
+    dict(k=100, r=4, c=8, s=8, u=1, log2g=8),    # 7 and 8 bits
+    dict(k=300, r=4, c=8, s=8, u=1, log2g=9),    # 9 and 10 bits, the paper's k
+])
+def test_comparator_pools_match_oracle(cuda, oracle_lib, geom):
+    """ACE counters and the asynchronous timestamps, each packed at its own
+    width, set and aged on the same slices: the ACE fields equal the oracle's
+    ACE counters, the timestamp fields equal the oracle's ATs, and the
+    k'-weights of both equal the oracle's (the same ATs active)."""
+    import math
+
+    from paper_1807_01527_amd.binding import AtCmp
+    k = geom["k"]
+    n_slices = 2 * k + 5 if k <= 60 else k + 15
+    tr = _tiny(seed=41 + k, n_slices=n_slices, pairs_per_slice=2001, hosts=1 << 9, planted=3, lo=100, hi=700)
+    ace = AtCmp("ace", **geom, seed=7)
+    pat = AtCmp("at", **geom, seed=7)
+    o = oracle_lib.Oracle(**geom, seed=7)
+    a = oracle_lib.AceOracle(**geom, seed=7)
+    assert ace.bits == a.bits == math.ceil(math.log2(k + 1))
+    assert pat.bits == ace.bits + 1 == math.ceil(math.log2(2 * k + 1))
+    assert ace.F == 32 // ace.bits and pat.wv == -(-o.g // pat.F)
+    rng = np.random.default_rng(k)
+    for t in range(n_slices):
+        aip, bip = tr.aip[t], tr.bip[t]
+        if t % 9 == 4:
+            aip, bip = aip[:0], bip[:0]
+        if t % 4 == 1:
+            ace.open_slice()
+            pat.open_slice()
+        cut = int(rng.integers(0, aip.size + 1))
+        for lo, hi in ((0, cut), (cut, aip.size)):
+            if hi > lo:
+                ace.ingest(to_dev(aip[lo:hi]), to_dev(bip[lo:hi]))
+                pat.ingest(to_dev(aip[lo:hi]), to_dev(bip[lo:hi]))
+        o.ingest(aip, bip)
+        a.ingest(aip, bip)
+        kq = 1 + (t * 5) % k
+        ace.close(kq)
+        pat.close(kq)
+        o.close(kq)
+        a.close(kq)
+        if k > 60 and t % 10 and t != n_slices - 1:
+            continue
+        where = f"slice {t} window {kq}"
+        assert np.array_equal(ace.unpack(ace.read_words()), a.counters()), where
+        assert np.array_equal(pat.unpack(pat.read_words()), o.pool()), where
+        w = o.weights()
+        assert np.array_equal(a.weights(), w), where
+        assert np.array_equal(ace.read_weights(), w), where
+        assert np.array_equal(pat.read_weights(), w), where
+    ace.destroy()
+    pat.destroy()
 
 
 @pytest.mark.parametrize("geom", [
