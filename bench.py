@@ -406,6 +406,7 @@ def headline(args, dev, wl, mlp) -> dict:
     truth_total = int(sum(w["truth_h"].size for w in wl))
     pairs = LARGE_LINKS * LARGE_SLICES * LARGE_PAIRS * args.steps
     calls = t_calls1["calls"] - t_calls0["calls"]
+    tjobs = t_calls1["jobs"] - t_calls0["jobs"]
     tpairs = t_calls1["pairs"] - t_calls0["pairs"]
     tms = t_calls1["device_ms"] - t_calls0["device_ms"]
     return dict(
@@ -424,7 +425,7 @@ def headline(args, dev, wl, mlp) -> dict:
                       "hosts": nw, "fallbacks": fb, "true_super_points": truth_total,
                       "over": "true super points of each link's full window (exact distinct count >= 1024), "
                               "at its last close"},
-        tiled={"launches": calls, "pairs": tpairs, "device_ms": tms, "steps": st["steps"]},
+        tiled={"launches": calls, "jobs": tjobs, "pairs": tpairs, "device_ms": tms, "steps": st["steps"]},
         pool_bytes=pool_bytes, n_atv=pool_bytes >> LARGE["log2g"])
 
 
@@ -833,15 +834,16 @@ def main():
     wts = learned.load_weights("large")
     mlp = Mlp(wts) if wts is not None else None
     hl = headline(args, dev, wl, mlp)
-    # the dominant kernel: the tiled scan launches of the served links (one per
-    # link and slice; each opens the slice and, its end queued with it, counts
-    # the window's weights)
+    # the dominant kernel: the tiled scan launches of the served links (the
+    # links of a step share one launch; each link's scan opens its slice and,
+    # the slice's end queued with it, counts the window's weights)
     tl = hl["tiled"]
     launches = max(tl["launches"], 1)
     avg_ms = tl["device_ms"] / launches
     ppl = tl["pairs"] / launches
+    jpl = tl["jobs"] / launches
     alg_pairs = (8 + LARGE["r"]) * ppl
-    alg_count = hl["pool_bytes"] + 4 * hl["n_atv"]
+    alg_count = jpl * (hl["pool_bytes"] + 4 * hl["n_atv"])
     achieved = (alg_pairs + alg_count) / (avg_ms / 1e3) / 1e9 if tl["launches"] else 0.0
     step_ms = hl["step_ms"]
     out = {
@@ -866,16 +868,18 @@ def main():
         "slice_close_ms_paced": hl["slice_close_ms_paced"],
         "restore_rc_counts": hl["restore_rc_counts"],
         "mean_rel_err": hl["mean_rel_err"],
-        "roofline": {"kernel": "tiled scan launch of a served link's slice: k_tile_count + k_tile_chunksum + "
-                               "k_tile_rowpre + k_tile_scatter + k_tile_apply (stores grouped per 64 KiB tile and "
-                               "applied in LDS; the opening preserve and the window count run in k_tile_apply)",
+        "roofline": {"kernel": "tiled scan launch of a step's served links (one grid row per link in every "
+                               "pass): k_tile_count + k_tile_chunksum + k_tile_rowpre + k_tile_scatter + "
+                               "k_tile_apply (stores grouped per 64 KiB tile and applied in LDS; the opening "
+                               "preserve and the window count run in k_tile_apply)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("ingest_large_pmc.json"),
                      "traffic_of": "the six kernels of one launch, rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled "
                                    "by its count for a plain device copy",
                      "bytes_per_pair": 8 + LARGE["r"],
                      "algorithmic_bytes_per_launch": {"pairs": alg_pairs, "window_count": alg_count},
-                     "avg_launch_ms": avg_ms, "pairs_per_launch": ppl, "launches_timed": tl["launches"],
+                     "avg_launch_ms": avg_ms, "pairs_per_launch": ppl, "links_per_launch": jpl,
+                     "launches_timed": tl["launches"],
                      "timing": "HIP events around each launch on the server's scan stream"},
         "tiled_share_of_pairs": tl["pairs"] / hl["pairs"] if hl["pairs"] else None,
     }

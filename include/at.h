@@ -438,14 +438,16 @@ int at_serve_next_result(at_serve *s, at_serve_result *out, uint32_t *cand, doub
 int at_serve_stats(at_serve *s, uint64_t *out4);
 /* Synchronous copy of an active link's pool to the host. */
 int at_serve_read_pool(at_serve *s, uint32_t link_id, uint8_t *host_out);
-/* Tiled scans run by the server so far: launches (one per link per step,
- * more when a link's step holds over 8M pairs), the pairs they scanned and
- * their summed device time in ms (HIP events around each launch on its
- * stream).  A link's step goes to the tiled scan, instead of the batched
- * byte-store scan, when its r*n stores times 12 (30 once the resident pools
- * exceed the 256 MiB last-level cache) reach its pool's bytes and the pool
- * is whole 64 KiB tiles, at most 4096.  Any pointer may be NULL. */
-int at_serve_tiled_stats(at_serve *s, uint64_t *calls, uint64_t *pairs, double *device_ms);
+/* Tiled scans run by the server so far: launches, the link scans they
+ * covered (a step's tiled links share launches, up to 8 per launch, each a
+ * grid row of every pass; a link's step of over 8M pairs takes launches of
+ * its own), the pairs they scanned and their summed device time in ms (HIP
+ * events around each launch on its stream).  A link's step goes to the tiled
+ * scan, instead of the batched byte-store scan, when its r*n stores times 12
+ * (30 once the resident pools exceed the 256 MiB last-level cache) reach its
+ * pool's bytes and the pool is whole 64 KiB tiles, at most 4096.  Any
+ * pointer may be NULL. */
+int at_serve_tiled_stats(at_serve *s, uint64_t *calls, uint64_t *pairs, double *device_ms, uint64_t *jobs);
 
 /*
  * The aging-counter comparator (Section 2.3 against Section 3).  ACE keeps a

@@ -94,6 +94,24 @@ size_t tiled_lds_bytes(uint32_t n_tiles);  // dynamic LDS of the scatter pass
 hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
                                uint64_t pool_bytes, const Geometry& G, uint32_t c0, const TileBufs& B, bool preserve,
                                uint32_t* w_out, uint32_t kq_w, hipStream_t st);
+// Several tiled scans in one launch of each pass (a grid dimension per job):
+// up to kTileJobsMax jobs that share r and the AT width, each one a call of
+// launch_ingest_tiled with its own pool, pairs (n > 0) and scratch.
+constexpr uint32_t kTileJobsMax = 8;
+struct TileJobSpec {
+    uint8_t* pool;
+    uint64_t pool_bytes;
+    const uint32_t* aip;
+    const uint32_t* bip;
+    uint64_t n;
+    Geometry G;
+    uint32_t c0;
+    bool preserve;
+    uint32_t* w_out;
+    uint32_t kq_w;
+    TileBufs B;
+};
+hipError_t launch_ingest_tiled_batch(const TileJobSpec* jobs, uint32_t n_jobs, hipStream_t st);
 // Windows summarised by one close: weights for window j land in
 // w[j * n_atv ...], AAT in aat[j * groups ...], super lists likewise.
 constexpr uint32_t kMaxWindows = 8;

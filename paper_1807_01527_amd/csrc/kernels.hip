@@ -5,6 +5,7 @@
 // streaming server's kernels use byte ATs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <type_traits>
 
@@ -443,6 +444,32 @@ constexpr uint32_t kColTiles = 64;      // tiles per block of the column passes 
 constexpr uint32_t kApplyBlock = 1024;
 constexpr uint32_t kScatterBlock = 1024;  // 16 waves; the scatter block holds 80 KiB of LDS, two per CU
 
+// One job of a tiled launch (a pool, its pairs and its scratch); a launch of
+// each pass covers up to kTileJobsMax jobs, the job given by one grid
+// dimension, so that the passes of several pools fill the chip together.
+struct TileJob {
+    uint8_t* pool;
+    const uint32_t* aip;
+    const uint32_t* bip;
+    uint16_t* rec;
+    uint32_t* cnt;
+    uint32_t* pre;
+    uint32_t* csum;
+    uint32_t* base;
+    void* act;
+    uint32_t* w_out;
+    uint64_t n;
+    Geometry G;
+    PreserveSpans S;
+    uint32_t c0, preserve, kq_w, n_tiles, nb, nchunk;
+};
+struct TileBatch {
+    TileJob j[kTileJobsMax];
+};
+
+// log2 of the ATs per 64 KiB tile
+__device__ __forceinline__ uint32_t tile_shift(const Geometry& G) { return 16u - (G.atb == 2 ? 1u : 0u); }
+
 // The tiled scan only runs on pools of at most kMaxTiles * kTileBytes =
 // 2^28 bytes, so ATV and AT indices fit 32 bits there: the index arithmetic
 // of passes 1 and 2 is 32-bit (half the instructions of the 64-bit form).
@@ -480,10 +507,15 @@ __device__ __forceinline__ uint32_t xcd_contiguous_block(uint32_t w, uint32_t nb
 // holds whole ATVs (g <= the ATs of a tile), so a store's tile is its ATV's:
 // it depends on aip alone and this pass never reads bip.
 template <int R>
-__global__ __launch_bounds__(kCountBlock) void k_tile_count(const uint32_t* __restrict__ aip, uint64_t n, Geometry G,
-                                                       uint32_t ts, uint32_t n_tiles, uint32_t* __restrict__ cnt,
-                                                       uint32_t* __restrict__ tot, void* __restrict__ act_table,
-                                                       uint32_t c0) {
+__global__ __launch_bounds__(kCountBlock) void k_tile_count(TileBatch J) {
+    const TileJob& TJ = J.j[blockIdx.y];
+    const Geometry& G = TJ.G;
+    const uint32_t* __restrict__ aip = TJ.aip;
+    const uint64_t n = TJ.n;
+    const uint32_t ts = tile_shift(G), n_tiles = TJ.n_tiles, c0 = TJ.c0;
+    uint32_t* __restrict__ cnt = TJ.cnt;
+    uint32_t* __restrict__ tot = TJ.csum + (uint64_t)TJ.nchunk * n_tiles;  // the row after the chunk sums
+    void* __restrict__ act_table = TJ.w_out ? TJ.act : nullptr;
     __shared__ uint32_t hist[kMaxTiles];
     for (uint32_t t = threadIdx.x; t < n_tiles; t += kCountBlock) hist[t] = 0;
     {   // tile totals and the totals of every 64 tiles start at zero (the
@@ -500,6 +532,7 @@ __global__ __launch_bounds__(kCountBlock) void k_tile_count(const uint32_t* __re
     __syncthreads();
     constexpr uint32_t P = kTileRecs / R;
     const uint32_t blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    if (blk >= TJ.nb) return;  // the grid covers the batch's largest job
     const uint64_t lo = (uint64_t)blk * P;
     const uint64_t hi = lo + P < n ? lo + P : n;
     const uint32_t atv_shift = ts - G.log2g;  // ATVs per tile = 2^atv_shift
@@ -548,8 +581,12 @@ constexpr uint32_t kColGroups = kBlock / kColTiles;
 constexpr uint32_t kColRows = kTileChunk / kColGroups;
 static_assert(kColGroups * kColRows == kTileChunk, "a chunk splits evenly over the waves");
 
-__global__ __launch_bounds__(kBlock) void k_tile_chunksum(const uint32_t* __restrict__ cnt, uint32_t nb,
-                                                          uint32_t n_tiles, uint32_t* __restrict__ csum) {
+__global__ __launch_bounds__(kBlock) void k_tile_chunksum(TileBatch J) {
+    const TileJob& TJ = J.j[blockIdx.z];
+    const uint32_t* __restrict__ cnt = TJ.cnt;
+    const uint32_t nb = TJ.nb, n_tiles = TJ.n_tiles, nchunk = TJ.nchunk;
+    uint32_t* __restrict__ csum = TJ.csum;
+    if (blockIdx.y >= nchunk || blockIdx.x * kColTiles >= n_tiles) return;
     __shared__ uint32_t part[kColGroups][kColTiles];
     const uint32_t tl = threadIdx.x % kColTiles, rg = threadIdx.x / kColTiles;
     const uint32_t t = blockIdx.x * kColTiles + tl;
@@ -567,7 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_chunksum(const uint32_t* __rest
     if (rg == 0) {  // the first wave: one lane per tile of the block
         // the row after the last chunk holds the tile totals, then the
         // totals of every kColTiles tiles (this block's share in one add)
-        uint32_t* totals = csum + (uint64_t)gridDim.y * n_tiles;
+        uint32_t* totals = csum + (uint64_t)nchunk * n_tiles;
         uint32_t tot = 0;
         if (t < n_tiles) {
 #pragma unroll
@@ -617,10 +654,14 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 // the 64); a chunk's runs start after the earlier chunks' (their column sums).
 // Within the chunk the same split as the chunk sums: each wave's 16 rows,
 // loads issued together, start after the rows of the waves before it.
-__global__ __launch_bounds__(kBlock) void k_tile_rowpre(const uint32_t* __restrict__ cnt,
-                                                        const uint32_t* __restrict__ csum, uint32_t nb,
-                                                        uint32_t n_tiles, uint32_t* __restrict__ pre,
-                                                        uint32_t* __restrict__ base) {
+__global__ __launch_bounds__(kBlock) void k_tile_rowpre(TileBatch J) {
+    const TileJob& TJ = J.j[blockIdx.z];
+    const uint32_t* __restrict__ cnt = TJ.cnt;
+    const uint32_t* __restrict__ csum = TJ.csum;
+    const uint32_t nb = TJ.nb, n_tiles = TJ.n_tiles, nchunk = TJ.nchunk;
+    uint32_t* __restrict__ pre = TJ.pre;
+    uint32_t* __restrict__ base = TJ.base;
+    if (blockIdx.y >= nchunk || blockIdx.x * kColTiles >= n_tiles) return;
     __shared__ uint32_t part[kColGroups][kColTiles];
     __shared__ uint32_t cp[kColGroups][kColTiles];
     __shared__ uint32_t red[kBlock / 64];
@@ -628,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_rowpre(const uint32_t* __restri
     const uint32_t tl = threadIdx.x % kColTiles, rg = threadIdx.x / kColTiles;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t t0 = blockIdx.x * kColTiles, t = t0 + tl;
-    const uint32_t c = blockIdx.y, nchunk = gridDim.y;
+    const uint32_t c = blockIdx.y;
     const uint32_t* tot = csum + (uint64_t)nchunk * n_tiles;
     const uint32_t b0 = c * kTileChunk + rg * kColRows;
     const bool col = t < n_tiles;
@@ -679,12 +720,16 @@ __global__ __launch_bounds__(kBlock) void k_tile_rowpre(const uint32_t* __restri
 
 // Pass 2: the block's records grouped by tile in LDS, then written run by run.
 template <int R>
-__global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* __restrict__ aip,
-                                                                const uint32_t* __restrict__ bip, uint64_t n,
-                                                                Geometry G, uint32_t ts, uint32_t n_tiles,
-                                                                const uint32_t* __restrict__ cnt,
-                                                                const uint32_t* __restrict__ pre,
-                                                                uint16_t* __restrict__ rec) {
+__global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(TileBatch J) {
+    const TileJob& TJ = J.j[blockIdx.y];
+    const Geometry& G = TJ.G;
+    const uint32_t* __restrict__ aip = TJ.aip;
+    const uint32_t* __restrict__ bip = TJ.bip;
+    const uint64_t n = TJ.n;
+    const uint32_t ts = tile_shift(G), n_tiles = TJ.n_tiles;
+    const uint32_t* __restrict__ cnt = TJ.cnt;
+    const uint32_t* __restrict__ pre = TJ.pre;
+    uint16_t* __restrict__ rec = TJ.rec;
     // 80 KiB of LDS, so that two blocks share a CU: the staged records, then
     // one word per tile (its slot cursor, later its run's offset in rec);
     // the block scan's scratch sits where the records go, before they do
@@ -695,6 +740,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
     constexpr uint32_t P = kTileRecs / R;
     constexpr uint32_t PPT = (P + kScatterBlock - 1) / kScatterBlock;  // pairs per thread
     const uint32_t blk = xcd_contiguous_block(blockIdx.x, gridDim.x);
+    if (blk >= TJ.nb) return;  // the grid covers the batch's largest job
     const uint64_t lo = (uint64_t)blk * P;
     const uint64_t hi = lo + P < n ? lo + P : n;
     const uint32_t lmask = (1u << ts) - 1u;
@@ -777,12 +823,17 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(const uint32_t* 
 // weight of each of its ATVs (Alg 1 with window kq_w) goes to w_out, which
 // is what the close would compute if no other call adds to the slice.
 template <typename T>
-__global__ __launch_bounds__(kApplyBlock) void k_tile_apply(uint8_t* __restrict__ pool,
-                                                            const uint16_t* __restrict__ rec,
-                                                            const uint32_t* __restrict__ base, Geometry G,
-                                                            uint32_t c0, uint32_t preserve, PreserveSpans S,
-                                                            uint32_t* __restrict__ w_out, uint32_t kq_w,
-                                                            const T* __restrict__ act_table) {
+__global__ __launch_bounds__(kApplyBlock) void k_tile_apply(TileBatch J) {
+    const TileJob& TJ = J.j[blockIdx.y];
+    if (blockIdx.x >= TJ.n_tiles) return;  // the grid covers the batch's largest pool
+    const Geometry& G = TJ.G;
+    uint8_t* __restrict__ pool = TJ.pool;
+    const uint16_t* __restrict__ rec = TJ.rec;
+    const uint32_t* __restrict__ base = TJ.base;
+    const uint32_t c0 = TJ.c0, preserve = TJ.preserve, kq_w = TJ.kq_w;
+    const PreserveSpans& S = TJ.S;
+    uint32_t* __restrict__ w_out = TJ.w_out;
+    const T* __restrict__ act_table = static_cast<const T*>(TJ.act);
     extern __shared__ __align__(16) uint8_t smem_apply[];
     const uint32_t t = blockIdx.x;
     const uint32_t lo = base[t], hi = base[t + 1];
@@ -2360,40 +2411,75 @@ size_t tiled_lds_bytes(uint32_t n_tiles) {
     return kTileRecs * sizeof(uint32_t) + (((size_t)n_tiles + 3) & ~(size_t)3) * sizeof(uint32_t);
 }
 
-hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
-                               uint64_t pool_bytes, const Geometry& G, uint32_t c0, const TileBufs& B, bool preserve,
-                               uint32_t* w_out, uint32_t kq_w, hipStream_t st) {
-    if (w_out && !preserve) return hipErrorInvalidValue;  // the weights need every tile visited
-    if (n == 0) return hipSuccess;
-    if (!tiled_fits(pool_bytes)) return hipErrorInvalidValue;
-    const TileSizes z = tiled_sizes(n, pool_bytes, G);
-    if (z.recs > B.rec_cap || z.table > B.table_cap || z.nchunk + 2 > B.chunk_cap) return hipErrorInvalidValue;
-    const uint32_t ts = 16u - (G.atb == 2 ? 1u : 0u);  // log2 of the ATs per tile
-    const dim3 cols((z.n_tiles + kColTiles - 1) / kColTiles, z.nchunk);
-    uint32_t* tot = B.csum + (uint64_t)z.nchunk * z.n_tiles;  // the row after the chunk sums
-    hipError_t e = with_rows<uint8_t>(G.r, [&](auto rc, auto) {
+hipError_t launch_ingest_tiled_batch(const TileJobSpec* js, uint32_t nj, hipStream_t st) {
+    if (nj == 0 || nj > kTileJobsMax) return hipErrorInvalidValue;
+    TileBatch Bt{};
+    uint32_t max_nb = 0, max_tiles = 0, max_chunk = 0;
+    for (uint32_t q = 0; q < nj; q++) {
+        const TileJobSpec& J = js[q];
+        // one instance of each pass serves the batch: rows and AT width agree
+        if (J.G.r != js[0].G.r || J.G.atb != js[0].G.atb) return hipErrorInvalidValue;
+        if (J.w_out && !J.preserve) return hipErrorInvalidValue;  // the weights need every tile visited
+        if (J.n == 0 || !tiled_fits(J.pool_bytes)) return hipErrorInvalidValue;
+        const TileSizes z = tiled_sizes(J.n, J.pool_bytes, J.G);
+        if (z.recs > J.B.rec_cap || z.table > J.B.table_cap || z.nchunk + 2 > J.B.chunk_cap)
+            return hipErrorInvalidValue;
+        TileJob& T = Bt.j[q];
+        T.pool = J.pool;
+        T.aip = J.aip;
+        T.bip = J.bip;
+        T.rec = J.B.rec;
+        T.cnt = J.B.cnt;
+        T.pre = J.B.pre;
+        T.csum = J.B.csum;
+        T.base = J.B.base;
+        T.act = J.B.act;
+        T.w_out = J.w_out;
+        T.n = J.n;
+        T.G = J.G;
+        T.S = J.preserve ? preserve_spans(J.G, J.c0) : PreserveSpans{};
+        T.c0 = J.c0;
+        T.preserve = J.preserve ? 1u : 0u;
+        T.kq_w = J.kq_w;
+        T.n_tiles = z.n_tiles;
+        T.nb = z.nb;
+        T.nchunk = z.nchunk;
+        max_nb = std::max(max_nb, z.nb);
+        max_tiles = std::max(max_tiles, z.n_tiles);
+        max_chunk = std::max(max_chunk, z.nchunk);
+    }
+    // Passes 1 and 2 map blocks to XCDs by blockIdx.x alone: with several jobs
+    // the row of blocks of each is a whole number of XCD rounds.
+    const uint32_t gx = nj == 1 ? max_nb : (max_nb + 7u) & ~7u;
+    const dim3 cols((max_tiles + kColTiles - 1) / kColTiles, max_chunk, nj);
+    const Geometry& G0 = js[0].G;
+    hipError_t e = with_rows<uint8_t>(G0.r, [&](auto rc, auto) {
         constexpr int RR = decltype(rc)::value;
-        hipLaunchKernelGGL((k_tile_count<RR>), dim3(z.nb), dim3(kCountBlock), 0, st, aip, n, G, ts, z.n_tiles, B.cnt, tot,
-                           w_out ? static_cast<void*>(B.act) : nullptr, c0);
+        hipLaunchKernelGGL((k_tile_count<RR>), dim3(gx, nj), dim3(kCountBlock), 0, st, Bt);
     });
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile_chunksum, cols, dim3(kBlock), 0, st, B.cnt, z.nb, z.n_tiles, B.csum);
-    hipLaunchKernelGGL(k_tile_rowpre, cols, dim3(kBlock), 0, st, B.cnt, B.csum, z.nb, z.n_tiles, B.pre, B.base);
-    e = with_rows<uint8_t>(G.r, [&](auto rc, auto) {
+    hipLaunchKernelGGL(k_tile_chunksum, cols, dim3(kBlock), 0, st, Bt);
+    hipLaunchKernelGGL(k_tile_rowpre, cols, dim3(kBlock), 0, st, Bt);
+    e = with_rows<uint8_t>(G0.r, [&](auto rc, auto) {
         constexpr int RR = decltype(rc)::value;
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile_scatter<RR>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)tiled_lds_bytes(kMaxTiles));
-        hipLaunchKernelGGL((k_tile_scatter<RR>), dim3(z.nb), dim3(kScatterBlock), tiled_lds_bytes(z.n_tiles), st, aip,
-                           bip, n,
-                           G, ts, z.n_tiles, B.cnt, B.pre, B.rec);
+        hipLaunchKernelGGL((k_tile_scatter<RR>), dim3(gx, nj), dim3(kScatterBlock), tiled_lds_bytes(max_tiles), st,
+                           Bt);
     });
     if (e != hipSuccess) return e;
-    return with_at(G, [&](auto t) {
+    return with_at(G0, [&](auto t) {
         using T = decltype(t);
-        const PreserveSpans S = preserve ? preserve_spans(G, c0) : PreserveSpans{};
-        hipLaunchKernelGGL(k_tile_apply<T>, dim3(z.n_tiles), dim3(kApplyBlock), kTileBytes, st, pool, B.rec, B.base,
-                           G, c0, (uint32_t)preserve, S, w_out, kq_w, reinterpret_cast<const T*>(B.act));
+        hipLaunchKernelGGL(k_tile_apply<T>, dim3(max_tiles, nj), dim3(kApplyBlock), kTileBytes, st, Bt);
     });
+}
+
+hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,
+                               uint64_t pool_bytes, const Geometry& G, uint32_t c0, const TileBufs& B, bool preserve,
+                               uint32_t* w_out, uint32_t kq_w, hipStream_t st) {
+    if (n == 0) return w_out && !preserve ? hipErrorInvalidValue : hipSuccess;
+    const TileJobSpec J{pool, pool_bytes, aip, bip, n, G, c0, preserve, w_out, kq_w, B};
+    return launch_ingest_tiled_batch(&J, 1, st);
 }
 
 hipError_t launch_close(const uint8_t* pool, uint32_t* w, uint64_t n_atv, const Geometry& G, uint32_t c0,

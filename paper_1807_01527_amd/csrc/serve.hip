@@ -190,12 +190,12 @@ struct at_serve {
     hipStream_t s2 = nullptr;
     bool tiled_ok = false;
     uint64_t pool_bytes = 0;
-    atp::TileBufs tb{};
-    uint32_t* stage_a = nullptr;  // gathered chunks of one link
-    uint32_t* stage_b = nullptr;
-    uint64_t stage_cap = 0;
+    atp::TileBufs tb[atp::kTileJobsMax] = {};     // scratch of each job of a batched launch
+    uint32_t* stage_a[atp::kTileJobsMax] = {};      // gathered chunks of a job's link
+    uint32_t* stage_b[atp::kTileJobsMax] = {};
+    uint64_t stage_cap[atp::kTileJobsMax] = {};
     std::vector<hipEvent_t> tev;  // start/end event pairs of the step's tiled launches
-    uint64_t tiled_calls = 0, tiled_pairs = 0;
+    uint64_t tiled_calls = 0, tiled_jobs = 0, tiled_pairs = 0;
     double tiled_ms = 0.0;
 };
 
@@ -352,9 +352,12 @@ void free_server(at_serve* S) {
                  S->rs[1].state,   S->rs[1].hosts, S->rs[1].est,   S->rs[1].estl, S->rs[1].flags};
     for (void* p : h)
         if (p) (void)hipHostFree(p);
-    void* t[] = {S->tb.rec, S->tb.cnt, S->tb.pre, S->tb.csum, S->tb.base, S->tb.act, S->stage_a, S->stage_b};
-    for (void* p : t)
-        if (p) (void)hipFree(p);
+    for (uint32_t q = 0; q < atp::kTileJobsMax; q++) {
+        const atp::TileBufs& B = S->tb[q];
+        void* t[] = {B.rec, B.cnt, B.pre, B.csum, B.base, B.act, S->stage_a[q], S->stage_b[q]};
+        for (void* p : t)
+            if (p) (void)hipFree(p);
+    }
     for (hipEvent_t e : S->tev) (void)hipEventDestroy(e);
     if (S->ev_graph) (void)hipEventDestroy(S->ev_graph);
     if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
@@ -380,43 +383,44 @@ bool take_tiled(const at_serve* S, uint64_t n) {  // caller holds mu
     return n * S->shape.r * per_store >= S->pool_bytes;
 }
 
-int tiled_buffers(at_serve* S, uint64_t n) {
+int tiled_buffers(at_serve* S, uint32_t slot, uint64_t n) {
     const atp::TileSizes z = atp::tiled_sizes(std::min<uint64_t>(n, kTileBatch), S->pool_bytes, S->shape);
+    atp::TileBufs& B = S->tb[slot];
     int rc;
-    if (z.recs > S->tb.rec_cap) {
-        if (S->tb.rec) (void)hipFree(S->tb.rec);
-        S->tb.rec_cap = 0;
-        if ((rc = dalloc(&S->tb.rec, z.recs))) return rc;
-        S->tb.rec_cap = z.recs;
+    if (z.recs > B.rec_cap) {
+        if (B.rec) (void)hipFree(B.rec);
+        B.rec_cap = 0;
+        if ((rc = dalloc(&B.rec, z.recs))) return rc;
+        B.rec_cap = z.recs;
     }
-    if (z.table > S->tb.table_cap) {
-        if (S->tb.cnt) (void)hipFree(S->tb.cnt);
-        if (S->tb.pre) (void)hipFree(S->tb.pre);
-        S->tb.cnt = S->tb.pre = nullptr;
-        S->tb.table_cap = 0;
-        if ((rc = dalloc(&S->tb.cnt, z.table)) || (rc = dalloc(&S->tb.pre, z.table))) return rc;
-        S->tb.table_cap = z.table;
+    if (z.table > B.table_cap) {
+        if (B.cnt) (void)hipFree(B.cnt);
+        if (B.pre) (void)hipFree(B.pre);
+        B.cnt = B.pre = nullptr;
+        B.table_cap = 0;
+        if ((rc = dalloc(&B.cnt, z.table)) || (rc = dalloc(&B.pre, z.table))) return rc;
+        B.table_cap = z.table;
     }
-    if (z.nchunk + 2 > S->tb.chunk_cap) {
-        if (S->tb.csum) (void)hipFree(S->tb.csum);
-        S->tb.chunk_cap = 0;
-        if ((rc = dalloc(&S->tb.csum, (uint64_t)(z.nchunk + 2) * 4096))) return rc;
-        S->tb.chunk_cap = z.nchunk + 2;
+    if (z.nchunk + 2 > B.chunk_cap) {
+        if (B.csum) (void)hipFree(B.csum);
+        B.chunk_cap = 0;
+        if ((rc = dalloc(&B.csum, (uint64_t)(z.nchunk + 2) * 4096))) return rc;
+        B.chunk_cap = z.nchunk + 2;
     }
-    if (!S->tb.base && (rc = dalloc(&S->tb.base, 4097))) return rc;
-    if (!S->tb.act && (rc = dalloc(&S->tb.act, (uint64_t)S->shape.g))) return rc;
+    if (!B.base && (rc = dalloc(&B.base, 4097))) return rc;
+    if (!B.act && (rc = dalloc(&B.act, (uint64_t)S->shape.g))) return rc;
     return AT_OK;
 }
 
-int stage_buffers(at_serve* S, uint64_t n) {
-    if (n <= S->stage_cap) return AT_OK;
-    if (S->stage_a) (void)hipFree(S->stage_a);
-    if (S->stage_b) (void)hipFree(S->stage_b);
-    S->stage_a = S->stage_b = nullptr;
-    S->stage_cap = 0;
+int stage_buffers(at_serve* S, uint32_t slot, uint64_t n) {
+    if (n <= S->stage_cap[slot]) return AT_OK;
+    if (S->stage_a[slot]) (void)hipFree(S->stage_a[slot]);
+    if (S->stage_b[slot]) (void)hipFree(S->stage_b[slot]);
+    S->stage_a[slot] = S->stage_b[slot] = nullptr;
+    S->stage_cap[slot] = 0;
     int rc;
-    if ((rc = dalloc(&S->stage_a, n)) || (rc = dalloc(&S->stage_b, n))) return rc;
-    S->stage_cap = n;
+    if ((rc = dalloc(&S->stage_a[slot], n)) || (rc = dalloc(&S->stage_b[slot], n))) return rc;
+    S->stage_cap[slot] = n;
     return AT_OK;
 }
 
@@ -432,25 +436,57 @@ struct TiledJob {
     bool after_graph;  // the link's previous slice closes in this step's graph: wait for it
 };
 
-// Launch the tiled jobs on s2 (events around each launch for the timing):
-// first those of links the graph leaves alone, then, once the graph is done
-// with their pools, those of links whose previous slice it closes.
-// When every job waits for the graph they go on the graph's own stream
-// behind it (no cross-stream wait).
-int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed) {
+// One tiled launch of the given jobs between a pair of timing events.
+int launch_timed(at_serve* S, const atp::TileJobSpec* js, uint32_t nj, hipStream_t st, uint32_t* n_timed) {
+    while (S->tev.size() < 2 * (*n_timed + 1)) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return AT_E_DEVICE;
+        S->tev.push_back(e);
+    }
+    if (hipEventRecord(S->tev[2 * *n_timed], st) != hipSuccess) return AT_E_DEVICE;
+    if (atp::launch_ingest_tiled_batch(js, nj, st) != hipSuccess) return AT_E_DEVICE;
+    if (hipEventRecord(S->tev[2 * *n_timed + 1], st) != hipSuccess) return AT_E_DEVICE;
+    ++*n_timed;
+    return AT_OK;
+}
+
+// Launch the tiled jobs (events around each launch for the timing): first
+// those of links the graph leaves alone, on s2, then, once the graph is done
+// with their pools, those of links whose previous slice it closes.  When
+// every job waits for the graph they go on the graph's own stream behind it
+// (no cross-stream wait).  Jobs of one group share launches, up to
+// kTileJobsMax per launch, each with its own scratch slot; a job of more than
+// kTileBatch pairs takes launches of its own, one per kTileBatch pairs.
+int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed, uint32_t* n_jobs) {
     *n_timed = 0;
+    *n_jobs = 0;
     std::stable_partition(jobs.begin(), jobs.end(), [](const TiledJob& J) { return !J.after_graph; });
     const bool behind_graph = std::all_of(jobs.begin(), jobs.end(), [](const TiledJob& J) { return J.after_graph; });
     hipStream_t st = behind_graph ? S->s0 : S->s2;
     bool waited = behind_graph;
+    atp::TileJobSpec batch[atp::kTileJobsMax];
+    uint32_t nb = 0;
+    auto flush = [&]() -> int {
+        if (nb == 0) return AT_OK;
+        const int rc = launch_timed(S, batch, nb, st, n_timed);
+        *n_jobs += nb;
+        nb = 0;
+        return rc;
+    };
     for (TiledJob& J : jobs) {
         Link* L = J.L;
+        int rc;
         if (J.after_graph && !waited) {
+            if ((rc = flush())) return rc;
             if (hipStreamWaitEvent(st, S->ev_graph, 0) != hipSuccess) return AT_E_DEVICE;
             waited = true;
         }
-        int rc = tiled_buffers(S, J.n);
-        if (!rc && J.chunks.size() > 1) rc = stage_buffers(S, J.n);
+        const bool single = J.n <= kTileBatch;
+        if (!single || nb == atp::kTileJobsMax)
+            if ((rc = flush())) return rc;
+        const uint32_t slot = nb;
+        rc = tiled_buffers(S, slot, J.n);
+        if (!rc && J.chunks.size() > 1) rc = stage_buffers(S, slot, J.n);
         if (rc) return rc;
         const uint32_t* a = J.chunks[0]->aip;
         const uint32_t* b = J.chunks[0]->bip;
@@ -464,34 +500,26 @@ int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed) {
                 G.off[G.n] = off;
                 off += J.chunks[c]->n;
                 if (++G.n == atp::kGatherMax || c + 1 == J.chunks.size()) {
-                    if (atp::launch_gather_pairs(G, S->stage_a, S->stage_b, st) != hipSuccess) return AT_E_DEVICE;
+                    if (atp::launch_gather_pairs(G, S->stage_a[slot], S->stage_b[slot], st) != hipSuccess)
+                        return AT_E_DEVICE;
                     G.n = 0;
                 }
             }
-            a = S->stage_a;
-            b = S->stage_b;
+            a = S->stage_a[slot];
+            b = S->stage_b[slot];
         }
-        const bool single = J.n <= kTileBatch;
         for (uint64_t off = 0; off < J.n; off += kTileBatch) {
             const uint64_t m = std::min<uint64_t>(kTileBatch, J.n - off);
             const bool first = off == 0;
-            while (S->tev.size() < 2 * (*n_timed + 1)) {
-                hipEvent_t e;
-                if (hipEventCreate(&e) != hipSuccess) return AT_E_DEVICE;
-                S->tev.push_back(e);
-            }
-            if (hipEventRecord(S->tev[2 * *n_timed], st) != hipSuccess) return AT_E_DEVICE;
-            const bool w = J.weights && single && first;
-            if (atp::launch_ingest_tiled(L->pool, a + off, b + off, m, S->pool_bytes, L->G, J.c0, S->tb,
-                                         J.opens && first, w ? L->w : nullptr, J.kq, st) != hipSuccess)
-                return AT_E_DEVICE;
-            if (hipEventRecord(S->tev[2 * *n_timed + 1], st) != hipSuccess) return AT_E_DEVICE;
-            ++*n_timed;
+            const bool w = J.weights && single;
+            batch[nb++] = atp::TileJobSpec{L->pool, S->pool_bytes, a + off, b + off, m, L->G, J.c0, J.opens && first,
+                                           w ? L->w : nullptr, J.kq, S->tb[slot]};
+            if (!single && (rc = flush())) return rc;
         }
         L->wready = J.weights && single;
         L->wready_kq = J.kq;
     }
-    return AT_OK;
+    return flush();
 }
 
 }  // namespace
@@ -907,8 +935,8 @@ int serve_step(at_serve* S, uint32_t* n_results, bool flush) {
     const double t0 = now_ms();
     hipError_t e = hipGraphLaunch(S->exec, S->s0);
     if (e == hipSuccess) e = hipEventRecord(S->ev_graph, S->s0);
-    uint32_t n_timed = 0;
-    int trc = e == hipSuccess ? run_tiled(S, tiled, &n_timed) : AT_OK;
+    uint32_t n_timed = 0, n_jobs = 0;
+    int trc = e == hipSuccess ? run_tiled(S, tiled, &n_timed, &n_jobs) : AT_OK;
     uint32_t produced = 0;
     {  // the previous step's results (the other mapped set) while this one runs
         std::lock_guard<std::mutex> g(S->mu);
@@ -924,6 +952,7 @@ int serve_step(at_serve* S, uint32_t* n_results, bool flush) {
         if (hipEventElapsedTime(&ms, S->tev[2 * q], S->tev[2 * q + 1]) == hipSuccess) S->tiled_ms += ms;
     }
     S->tiled_calls += n_timed;
+    S->tiled_jobs += n_jobs;
 
     lk.lock();
     S->steps++;
@@ -1071,10 +1100,11 @@ int at_serve_stats(at_serve* S, uint64_t* out4) {
     return AT_OK;
 }
 
-int at_serve_tiled_stats(at_serve* S, uint64_t* calls, uint64_t* pairs, double* device_ms) {
+int at_serve_tiled_stats(at_serve* S, uint64_t* calls, uint64_t* pairs, double* device_ms, uint64_t* jobs) {
     if (!S) return AT_E_INVAL;
     std::lock_guard<std::mutex> g(S->mu);
     if (calls) *calls = S->tiled_calls;
+    if (jobs) *jobs = S->tiled_jobs;
     if (pairs) *pairs = S->tiled_pairs;
     if (device_ms) *device_ms = S->tiled_ms;
     return AT_OK;
