@@ -802,6 +802,8 @@ def main():
                     help="only the ACE / packed-timestamp / byte-timestamp comparison on the link and large geometries")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates the HBM byte counters)")
+    ap.add_argument("--copy-probe-only", action="store_true",
+                    help="only the 256 MiB device copy, three times (the counters' calibration run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only (every box here has one); "
@@ -811,6 +813,14 @@ def main():
 
     import torch
 
+    if args.copy_probe_only:
+        x = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": {"read": x.numel(), "write": y.numel(), "launches": 3}}), flush=True)
+        return
     if args.scatter_sweep:
         scatter_sweep()
         return
