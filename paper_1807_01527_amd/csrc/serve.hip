@@ -83,8 +83,6 @@ struct Event {
 
 struct Link {
     uint32_t id = 0;
-    bool wready = false;     // weights of the open slice's window wready_kq written by its tiled scan
-    uint32_t wready_kq = 0;
     int state = L_WAITING;
     at_params p{};
     Geometry G{};
@@ -104,8 +102,6 @@ struct Link {
     uint64_t t = 0;          // slices closed
     bool open = false;
     uint32_t c0 = 0;
-    bool next_open = false;  // slice t+1 was opened by a scan queued behind this step's close of slice t
-    uint32_t next_c0 = 0;
     std::deque<Event> q;
     uint64_t consumed = 0;   // events consumed (chunks + ends)
 };
@@ -120,6 +116,29 @@ struct Result {
 };
 
 }  // namespace
+
+// One link's chunks of a step, scanned by the tiled scan.
+struct TiledChunk {
+    const uint32_t* aip;
+    const uint32_t* bip;
+    uint64_t n;
+};
+struct TiledJob {
+    Link* L;
+    std::vector<TiledChunk> chunks;  // copied: the queue's records may be retired before the launch
+    uint64_t n;
+    bool opens;     // the scan opens the slice: the tile pass runs its preserve
+    bool weights;   // the slice's end is queued behind its chunks: the tile pass counts window kq
+    uint32_t kq;
+    uint32_t c0;    // block clock of the scanned slice
+};
+
+struct CloseRec {
+    Link* L;
+    uint32_t kq;
+    double t_arrival;
+    uint64_t slice;
+};
 
 struct at_serve {
     at_serve_config cfg{};
@@ -158,7 +177,6 @@ struct at_serve {
         atp::ServeExport xp{};  // their device addresses
     } rs[2];
     int cur_set = 0;
-    hipEvent_t ev_graph = nullptr; // recorded after each graph launch: the pool is free for scans
     // graph
     at_mlp* mlp = nullptr;
     const void* mlp_key = nullptr;
@@ -180,6 +198,19 @@ struct at_serve {
         uint64_t slice;
     };
     std::vector<PendingClose> pending;
+    // a step planned ahead: its tiled scans already queued behind the last
+    // step's graph, its closes for the next step's graph
+    struct Ahead {
+        bool valid = false;
+        std::vector<TiledJob> tiled;
+        std::vector<CloseDesc> cds;
+        std::vector<CloseRec> closes;
+        uint64_t pairs = 0;
+        int tset = 0;
+        uint32_t n_timed = 0, n_jobs = 0;
+    } ahead;
+    int tset = 0;                  // timing-event set of the next step's tiled launches
+    hipEvent_t ev_done = nullptr;  // recorded after a step's graph: its results are complete
     int pend_set = 0;
     bool pend_mlp = false;
     double pend_step_ms = 0.0;
@@ -187,14 +218,13 @@ struct at_serve {
     double last_step_ms = 0.0;
     uint64_t pairs_ingested = 0;
     // tiled scans: stream, scratch, timing
-    hipStream_t s2 = nullptr;
     bool tiled_ok = false;
     uint64_t pool_bytes = 0;
     atp::TileBufs tb[atp::kTileJobsMax] = {};     // scratch of each job of a batched launch
     uint32_t* stage_a[atp::kTileJobsMax] = {};      // gathered chunks of a job's link
     uint32_t* stage_b[atp::kTileJobsMax] = {};
     uint64_t stage_cap[atp::kTileJobsMax] = {};
-    std::vector<hipEvent_t> tev;  // start/end event pairs of the step's tiled launches
+    std::vector<hipEvent_t> tev[2];  // start/end event pairs of a step's tiled launches (two steps in flight)
     uint64_t tiled_calls = 0, tiled_jobs = 0, tiled_pairs = 0;
     double tiled_ms = 0.0;
 };
@@ -308,7 +338,8 @@ int capture_graph(at_serve* S) {
     hipError_t ec = hipMemcpyAsync(S->d_desc, S->h_desc, sizeof(StepDesc), hipMemcpyHostToDevice, S->s0);
     if (ec == hipSuccess) ec = hipEventRecord(S->ev_fork, S->s0);
     if (ec == hipSuccess) ec = hipStreamWaitEvent(S->s1, S->ev_fork, 0);
-    // branch 1: close of slices whose chunks were all scanned in earlier steps
+    // branch 1: close of slices whose chunks are all scanned (in earlier steps, or
+    // by this step's tiled launches, queued ahead of the graph)
     if (ec == hipSuccess) ec = atp::launch_serve_close_branch(B, S->shape, S->n_atv, S->s1);
     if (ec == hipSuccess && have_mlp)
         ec = atp::launch_mlp_forward_devn(S->d_feat, &S->d_state->n_hosts, S->max_hosts, P, S->d_y, S->s1);
@@ -358,11 +389,11 @@ void free_server(at_serve* S) {
         for (void* p : t)
             if (p) (void)hipFree(p);
     }
-    for (hipEvent_t e : S->tev) (void)hipEventDestroy(e);
-    if (S->ev_graph) (void)hipEventDestroy(S->ev_graph);
+    for (const std::vector<hipEvent_t>& v : S->tev)
+        for (hipEvent_t e : v) (void)hipEventDestroy(e);
     if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
+    if (S->ev_done) (void)hipEventDestroy(S->ev_done);
     if (S->ev_join) (void)hipEventDestroy(S->ev_join);
-    if (S->s2) (void)hipStreamDestroy(S->s2);
     if (S->s1) (void)hipStreamDestroy(S->s1);
     if (S->s0) (void)hipStreamDestroy(S->s0);
 }
@@ -425,50 +456,36 @@ int stage_buffers(at_serve* S, uint32_t slot, uint64_t n) {
 }
 
 // One link's chunks of a step, scanned by the tiled scan.
-struct TiledJob {
-    Link* L;
-    std::vector<const Event*> chunks;
-    uint64_t n;
-    bool opens;     // the scan opens the slice: the tile pass runs its preserve
-    bool weights;   // the slice's end is queued behind its chunks: the tile pass counts window kq
-    uint32_t kq;
-    uint32_t c0;    // block clock of the scanned slice
-    bool after_graph;  // the link's previous slice closes in this step's graph: wait for it
-};
 
 // One tiled launch of the given jobs between a pair of timing events.
-int launch_timed(at_serve* S, const atp::TileJobSpec* js, uint32_t nj, hipStream_t st, uint32_t* n_timed) {
-    while (S->tev.size() < 2 * (*n_timed + 1)) {
+int launch_timed(at_serve* S, const atp::TileJobSpec* js, uint32_t nj, hipStream_t st, int tset, uint32_t* n_timed) {
+    std::vector<hipEvent_t>& tev = S->tev[tset];
+    while (tev.size() < 2 * (*n_timed + 1)) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return AT_E_DEVICE;
-        S->tev.push_back(e);
+        tev.push_back(e);
     }
-    if (hipEventRecord(S->tev[2 * *n_timed], st) != hipSuccess) return AT_E_DEVICE;
+    if (hipEventRecord(tev[2 * *n_timed], st) != hipSuccess) return AT_E_DEVICE;
     if (atp::launch_ingest_tiled_batch(js, nj, st) != hipSuccess) return AT_E_DEVICE;
-    if (hipEventRecord(S->tev[2 * *n_timed + 1], st) != hipSuccess) return AT_E_DEVICE;
+    if (hipEventRecord(tev[2 * *n_timed + 1], st) != hipSuccess) return AT_E_DEVICE;
     ++*n_timed;
     return AT_OK;
 }
 
-// Launch the tiled jobs (events around each launch for the timing): first
-// those of links the graph leaves alone, on s2, then, once the graph is done
-// with their pools, those of links whose previous slice it closes.  When
-// every job waits for the graph they go on the graph's own stream behind it
-// (no cross-stream wait).  Jobs of one group share launches, up to
-// kTileJobsMax per launch, each with its own scratch slot; a job of more than
-// kTileBatch pairs takes launches of its own, one per kTileBatch pairs.
-int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed, uint32_t* n_jobs) {
+// Launch the step's tiled jobs on st, ahead of the step graph whose closes
+// read these pools (events around each launch for the timing).  Jobs share
+// launches, up to kTileJobsMax per launch, each with its own scratch slot; a
+// job of more than kTileBatch pairs takes launches of its own, one per
+// kTileBatch pairs.
+int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, hipStream_t st, int tset, uint32_t* n_timed,
+              uint32_t* n_jobs) {
     *n_timed = 0;
     *n_jobs = 0;
-    std::stable_partition(jobs.begin(), jobs.end(), [](const TiledJob& J) { return !J.after_graph; });
-    const bool behind_graph = std::all_of(jobs.begin(), jobs.end(), [](const TiledJob& J) { return J.after_graph; });
-    hipStream_t st = behind_graph ? S->s0 : S->s2;
-    bool waited = behind_graph;
     atp::TileJobSpec batch[atp::kTileJobsMax];
     uint32_t nb = 0;
     auto flush = [&]() -> int {
         if (nb == 0) return AT_OK;
-        const int rc = launch_timed(S, batch, nb, st, n_timed);
+        const int rc = launch_timed(S, batch, nb, st, tset, n_timed);
         *n_jobs += nb;
         nb = 0;
         return rc;
@@ -476,11 +493,6 @@ int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed, uint3
     for (TiledJob& J : jobs) {
         Link* L = J.L;
         int rc;
-        if (J.after_graph && !waited) {
-            if ((rc = flush())) return rc;
-            if (hipStreamWaitEvent(st, S->ev_graph, 0) != hipSuccess) return AT_E_DEVICE;
-            waited = true;
-        }
         const bool single = J.n <= kTileBatch;
         if (!single || nb == atp::kTileJobsMax)
             if ((rc = flush())) return rc;
@@ -488,17 +500,17 @@ int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed, uint3
         rc = tiled_buffers(S, slot, J.n);
         if (!rc && J.chunks.size() > 1) rc = stage_buffers(S, slot, J.n);
         if (rc) return rc;
-        const uint32_t* a = J.chunks[0]->aip;
-        const uint32_t* b = J.chunks[0]->bip;
+        const uint32_t* a = J.chunks[0].aip;
+        const uint32_t* b = J.chunks[0].bip;
         if (J.chunks.size() > 1) {
             atp::GatherList G{};
             uint64_t off = 0;
             for (size_t c = 0; c < J.chunks.size(); c++) {
-                G.aip[G.n] = J.chunks[c]->aip;
-                G.bip[G.n] = J.chunks[c]->bip;
-                G.cnt[G.n] = J.chunks[c]->n;
+                G.aip[G.n] = J.chunks[c].aip;
+                G.bip[G.n] = J.chunks[c].bip;
+                G.cnt[G.n] = J.chunks[c].n;
                 G.off[G.n] = off;
-                off += J.chunks[c]->n;
+                off += J.chunks[c].n;
                 if (++G.n == atp::kGatherMax || c + 1 == J.chunks.size()) {
                     if (atp::launch_gather_pairs(G, S->stage_a[slot], S->stage_b[slot], st) != hipSuccess)
                         return AT_E_DEVICE;
@@ -516,8 +528,6 @@ int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, uint32_t* n_timed, uint3
                                            w ? L->w : nullptr, J.kq, S->tb[slot]};
             if (!single && (rc = flush())) return rc;
         }
-        L->wready = J.weights && single;
-        L->wready_kq = J.kq;
     }
     return flush();
 }
@@ -565,10 +575,9 @@ int at_serve_create(const at_serve_config* cfg, at_serve** out) {
     int rc = AT_OK;
     hipError_t e = hipStreamCreateWithFlags(&S->s0, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s1, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_graph, hipEventDisableTiming);
     if (e != hipSuccess) rc = AT_E_DEVICE;
     if (!rc && ((rc = dalloc(&S->d_desc, 1)) || (rc = dalloc(&S->d_slots, atp::kServeMaxLinks)) ||
                 (rc = dalloc(&S->d_state, 1)) || (rc = dalloc(&S->d_hosts, S->max_hosts)) ||
@@ -614,7 +623,6 @@ int at_serve_destroy(at_serve* S) {
     { std::lock_guard<std::mutex> sg(S->step_mu); }
     (void)hipStreamSynchronize(S->s0);
     (void)hipStreamSynchronize(S->s1);
-    (void)hipStreamSynchronize(S->s2);
     free_server(S);
     delete S;
     return AT_OK;
@@ -810,9 +818,138 @@ uint32_t publish_pending(at_serve* S) {
     return produced;
 }
 
-// One step.  The previous step's results are published once this step's
-// work is on the GPU (so reading them overlaps it); with `flush` this step's
-// own results are published before returning.
+
+// Every active link with queued work can go into a step of tiled scans and
+// their closes only (no direct-path chunk, no close of a slice scanned
+// earlier, no empty slice to open): such a step can be planned and its scans
+// launched before the previous step's graph has finished.  Caller holds mu.
+bool tiled_only(const at_serve* S) {
+    bool any = false;
+    for (const Link* L : S->links) {
+        if (!L || L->state != L_ACTIVE || L->q.empty()) continue;
+        if (L->q.front().end) return false;
+        uint64_t n = 0;
+        for (const Event& ev : L->q) {
+            if (ev.end) break;
+            if (ev.aip) n += ev.n;
+        }
+        if (!take_tiled(S, n)) return false;
+        any = true;
+    }
+    return any;
+}
+
+// Plan one step from the queues (caller holds mu): the tiled jobs, the
+// closes (descriptors and records) and, when D is given, the direct-path
+// opens and chunks.  The step's effects on the queues and the link clocks
+// are applied at once -- handed chunks and closed ends leave the queues, a
+// closed link's clock advances -- since they do not depend on the GPU.
+void plan_step(at_serve* S, StepDesc* D, std::vector<TiledJob>& tiled, std::vector<CloseDesc>& cds,
+               std::vector<CloseRec>& closes, uint64_t& pairs) {
+    for (Link* L : S->links) {
+        if (!L || L->state != L_ACTIVE || L->q.empty()) continue;
+        const Event& first = L->q.front();
+        if (first.end && L->open) {
+            // every chunk of this slice was scanned in an earlier step: close it now
+            CloseDesc c{};
+            c.slot = (uint32_t)L->slot;
+            c.c0 = L->c0;
+            c.kq = first.kprime;
+            c.ready = 0;  // its pairs went in over earlier steps: the close counts the window
+            cds.push_back(c);
+            closes.push_back(CloseRec{L, first.kprime, first.t_arrival, L->t});
+            continue;  // the next slice waits for the next step
+        }
+        // the step's pairs of this link's current slice, and whether its end follows them
+        uint64_t n = 0;
+        const Event* end = nullptr;
+        for (const Event& ev : L->q) {
+            if (ev.end) {
+                end = &ev;
+                break;
+            }
+            if (ev.aip) n += ev.n;
+        }
+        if (take_tiled(S, n)) {
+            // scanned ahead of the graph; with its end queued the slice also
+            // closes in this step's graph, and a scan that opens it and takes
+            // all its pairs (at most one launch) counts the window for it
+            TiledJob J{L, {}, n, !L->open, false, end ? end->kprime : 0u, 0};
+            if (!L->open) {
+                L->open = true;
+                L->c0 = (uint32_t)(L->t % L->G.twok);
+            }
+            J.c0 = L->c0;
+            J.weights = J.opens && end && n <= kTileBatch;
+            for (Event& ev : L->q) {
+                if (ev.end) break;
+                if (!ev.aip) continue;
+                J.chunks.push_back(TiledChunk{ev.aip, ev.bip, ev.n});
+                ev.aip = nullptr;  // handed to this step
+            }
+            pairs += n;
+            if (end) {
+                CloseDesc c{};
+                c.slot = (uint32_t)L->slot;
+                c.c0 = L->c0;
+                c.kq = end->kprime;
+                c.ready = J.weights ? 1u : 0u;
+                cds.push_back(c);
+                closes.push_back(CloseRec{L, end->kprime, end->t_arrival, L->t});
+            }
+            tiled.push_back(std::move(J));
+            continue;
+        }
+        if (!D) continue;  // a tiled-only step never gets here (tiled_only)
+        // open the slice if needed, then queue its chunks (stopping at its end)
+        if (!L->open) {
+            OpenDesc& o = D->open[D->n_open];
+            o.slot = (uint32_t)L->slot;
+            o.c0 = (uint32_t)(L->t % L->G.twok);
+            o.S = atp::preserve_spans(L->G, o.c0);
+            D->open_prefix[D->n_open + 1] = D->open_prefix[D->n_open] + S->n_atv * (o.S.nw0 + o.S.nw1);
+            D->n_open++;
+            L->open = true;
+            L->c0 = o.c0;
+        }
+        for (auto it = L->q.begin(); it != L->q.end() && !it->end; ++it) {
+            if (D->n_chunks == atp::kServeMaxChunks) break;
+            if (it->aip == nullptr) continue;  // already handed to a step
+            ChunkDesc& cd = D->chunk[D->n_chunks++];
+            cd.aip = it->aip;
+            cd.bip = it->bip;
+            cd.n = it->n;
+            cd.unit0 = D->n_units;
+            cd.slot = (uint32_t)L->slot;
+            cd.c0 = L->c0;
+            cd.vec = ((reinterpret_cast<uintptr_t>(it->aip) | reinterpret_cast<uintptr_t>(it->bip)) & 15u) == 0;
+            D->n_units += (it->n + atp::kServeUnit - 1) / atp::kServeUnit;
+            pairs += it->n;
+            it->aip = nullptr;  // handed to this step
+        }
+    }
+    // retire handed chunks, then the ends this step closes
+    for (Link* L : S->links) {
+        if (!L || L->state != L_ACTIVE) continue;
+        while (!L->q.empty() && !L->q.front().end && L->q.front().aip == nullptr) {
+            L->q.pop_front();
+            L->consumed++;
+        }
+    }
+    for (const CloseRec& cr : closes) {
+        Link* L = cr.L;
+        L->q.pop_front();  // the end event
+        L->consumed++;
+        L->t += 1;
+        L->open = false;
+    }
+}
+
+// One step.  Its scans and graph go on s0; without `flush`, when the next
+// step can be tiled-only its scans are planned and queued at once behind this
+// step's graph (the GPU goes on with them while the host collects this step),
+// and the previous step's results are published while this one runs; with
+// `flush` this step's own results are published before returning.
 int serve_step(at_serve* S, uint32_t* n_results, bool flush) {
     if (n_results) *n_results = 0;
     std::lock_guard<std::mutex> sg(S->step_mu);
@@ -827,149 +964,74 @@ int serve_step(at_serve* S, uint32_t* n_results, bool flush) {
     D.open_prefix[0] = 0;
     const int set = S->cur_set;  // this step's results go to mapped set `set`
     D.xp = S->rs[set].xp;
-    struct CloseRec {
-        Link* L;
-        uint32_t kq;
-        double t_arrival;
-        uint64_t slice;
-    };
-    std::vector<CloseRec> closes;
     std::vector<TiledJob> tiled;
+    std::vector<CloseDesc> cds;
+    std::vector<CloseRec> closes;
     uint64_t pairs = 0;
-    for (Link* L : S->links) {
-        if (!L || L->state != L_ACTIVE || L->q.empty()) continue;
-        const Event& first = L->q.front();
-        if (first.end && L->open) {
-            // every chunk of this slice was scanned in an earlier step: close it now
-            CloseDesc& c = D.close[D.n_close++];
-            c.slot = (uint32_t)L->slot;
-            c.c0 = L->c0;
-            c.kq = first.kprime;
-            c.ready = L->wready && L->wready_kq == first.kprime ? 1u : 0u;
-            L->wready = false;
-            closes.push_back(CloseRec{L, first.kprime, first.t_arrival, L->t});
-            // the next slice's pairs queued behind this end, if the tiled scan takes
-            // them, are scanned after the graph has finished with the pool
-            uint64_t n = 0;
-            bool end_follows = false;
-            uint32_t kq = 0;
-            for (auto it = std::next(L->q.begin()); it != L->q.end(); ++it) {
-                if (it->end) {
-                    end_follows = true;
-                    kq = it->kprime;
-                    break;
-                }
-                if (it->aip) n += it->n;
-            }
-            if (take_tiled(S, n)) {
-                L->next_open = true;
-                L->next_c0 = (uint32_t)((L->t + 1) % L->G.twok);
-                TiledJob J{L, {}, n, true, end_follows, kq, L->next_c0, true};
-                for (auto it = std::next(L->q.begin()); it != L->q.end() && !it->end; ++it)
-                    if (it->aip) J.chunks.push_back(&*it);
-                pairs += n;
-                tiled.push_back(std::move(J));
-            }
-            continue;
+    at_serve::Ahead& A = S->ahead;
+    const bool from_ahead = A.valid;
+    int tset = S->tset;
+    uint32_t n_timed = 0, n_jobs = 0;
+    if (from_ahead) {
+        // planned by the previous step, its scans already queued behind that step's graph
+        tiled = std::move(A.tiled);
+        pairs = A.pairs;
+        tset = A.tset;
+        n_timed = A.n_timed;
+        n_jobs = A.n_jobs;
+        for (size_t q = 0; q < A.cds.size(); q++) {
+            const Link* L = A.closes[q].L;
+            if (L->state != L_ACTIVE || L->slot != (int)A.cds[q].slot) continue;  // closed meanwhile
+            cds.push_back(A.cds[q]);
+            closes.push_back(A.closes[q]);
         }
-        {
-            // the step's pairs of this link's current slice, and whether its end follows them
-            uint64_t n = 0;
-            bool end_follows = false;
-            uint32_t kq = 0;
-            for (const Event& ev : L->q) {
-                if (ev.end) {
-                    end_follows = true;
-                    kq = ev.kprime;
-                    break;
-                }
-                if (ev.aip) n += ev.n;
-            }
-            if (take_tiled(S, n)) {
-                TiledJob J{L, {}, n, !L->open, false, kq, 0, false};
-                if (!L->open) {
-                    L->open = true;
-                    L->c0 = (uint32_t)(L->t % L->G.twok);
-                }
-                J.c0 = L->c0;
-                J.weights = J.opens && end_follows;
-                for (Event& ev : L->q) {
-                    if (ev.end) break;
-                    if (!ev.aip) continue;
-                    J.chunks.push_back(&ev);
-                }
-                pairs += n;
-                tiled.push_back(std::move(J));
-                continue;
-            }
-        }
-        // open the slice if needed, then queue its chunks (stopping at its end)
-        if (!L->open) {
-            OpenDesc& o = D.open[D.n_open];
-            o.slot = (uint32_t)L->slot;
-            o.c0 = (uint32_t)(L->t % L->G.twok);
-            o.S = atp::preserve_spans(L->G, o.c0);
-            D.open_prefix[D.n_open + 1] = D.open_prefix[D.n_open] + S->n_atv * (o.S.nw0 + o.S.nw1);
-            D.n_open++;
-            L->open = true;
-            L->c0 = o.c0;
-        }
-        for (auto it = L->q.begin(); it != L->q.end() && !it->end; ++it) {
-            if (D.n_chunks == atp::kServeMaxChunks) break;
-            if (it->aip == nullptr) continue;  // already scanned in this step loop
-            ChunkDesc& cd = D.chunk[D.n_chunks++];
-            cd.aip = it->aip;
-            cd.bip = it->bip;
-            cd.n = it->n;
-            cd.unit0 = D.n_units;
-            cd.slot = (uint32_t)L->slot;
-            cd.c0 = L->c0;
-            cd.vec = ((reinterpret_cast<uintptr_t>(it->aip) | reinterpret_cast<uintptr_t>(it->bip)) & 15u) == 0;
-            D.n_units += (it->n + atp::kServeUnit - 1) / atp::kServeUnit;
-            pairs += it->n;
-            it->aip = nullptr;  // mark as handed to this step
-        }
+        A = at_serve::Ahead{};
+    } else {
+        plan_step(S, &D, tiled, cds, closes, pairs);
     }
+    for (const CloseDesc& c : cds) D.close[D.n_close++] = c;
     lk.unlock();
 
     const double t0 = now_ms();
-    hipError_t e = hipGraphLaunch(S->exec, S->s0);
-    if (e == hipSuccess) e = hipEventRecord(S->ev_graph, S->s0);
-    uint32_t n_timed = 0, n_jobs = 0;
-    int trc = e == hipSuccess ? run_tiled(S, tiled, &n_timed, &n_jobs) : AT_OK;
+    // the tiled scans first: the graph's closes read what they store
+    int trc = from_ahead ? AT_OK : run_tiled(S, tiled, S->s0, tset, &n_timed, &n_jobs);
+    hipError_t e = trc ? hipSuccess : hipGraphLaunch(S->exec, S->s0);
+    if (e == hipSuccess && !trc) e = hipEventRecord(S->ev_done, S->s0);
+    if (e == hipSuccess && !trc && !flush) {
+        // the next step, if it is tiled scans and their closes only
+        lk.lock();
+        if (tiled_only(S)) {
+            A.valid = true;
+            A.tset = tset ^ 1;
+            plan_step(S, nullptr, A.tiled, A.cds, A.closes, A.pairs);
+        }
+        lk.unlock();
+        if (A.valid) trc = run_tiled(S, A.tiled, S->s0, A.tset, &A.n_timed, &A.n_jobs);
+    }
     uint32_t produced = 0;
     {  // the previous step's results (the other mapped set) while this one runs
         std::lock_guard<std::mutex> g(S->mu);
         produced += publish_pending(S);
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(S->s0);
-    hipError_t e2 = hipStreamSynchronize(S->s2);
+    if (e == hipSuccess) e = hipEventSynchronize(S->ev_done);
     const double t1 = now_ms();
-    if (e != hipSuccess || e2 != hipSuccess) return AT_E_DEVICE;
+    if (e != hipSuccess) return AT_E_DEVICE;
     if (trc) return trc;
+    float tms = 0.f;
     for (uint32_t q = 0; q < n_timed; q++) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, S->tev[2 * q], S->tev[2 * q + 1]) == hipSuccess) S->tiled_ms += ms;
+        if (hipEventElapsedTime(&ms, S->tev[tset][2 * q], S->tev[tset][2 * q + 1]) == hipSuccess) tms += ms;
     }
-    S->tiled_calls += n_timed;
-    S->tiled_jobs += n_jobs;
+    S->tset = tset ^ 1;
 
     lk.lock();
+    S->tiled_ms += tms;
+    S->tiled_calls += n_timed;
+    S->tiled_jobs += n_jobs;
     S->steps++;
     S->last_step_ms = t1 - t0;
     S->pairs_ingested += pairs;
-    for (const TiledJob& J : tiled) {
-        S->tiled_pairs += J.n;
-        for (const Event* ev : J.chunks) const_cast<Event*>(ev)->aip = nullptr;  // handed to this step
-    }
-    // retire scanned chunks (those ahead of a closed slice's end, below)
-    for (Link* L : S->links) {
-        if (!L || L->state != L_ACTIVE) continue;
-        while (!L->q.empty() && !L->q.front().end && L->q.front().aip == nullptr) {
-            L->q.pop_front();
-            L->consumed++;
-        }
-    }
+    for (const TiledJob& J : tiled) S->tiled_pairs += J.n;
     // this step's closes: their results are in set `set`, published by the next
     // step (or below with flush)
     S->pending.clear();
@@ -979,20 +1041,6 @@ int serve_step(at_serve* S, uint32_t* n_results, bool flush) {
     S->pend_mlp = S->mlp_key != nullptr;
     S->pend_step_ms = t1 - t0;
     S->cur_set = set ^ 1;
-    for (uint32_t ci = 0; ci < closes.size(); ci++) {
-        const CloseRec& cr = closes[ci];
-        Link* L = cr.L;
-        L->q.pop_front();  // the end event
-        L->consumed++;
-        L->t += 1;
-        L->open = L->next_open;  // the next slice may have been opened by a scan of this step
-        L->c0 = L->next_open ? L->next_c0 : L->c0;
-        L->next_open = false;
-        while (!L->q.empty() && !L->q.front().end && L->q.front().aip == nullptr) {
-            L->q.pop_front();  // the next slice's chunks that scan took
-            L->consumed++;
-        }
-    }
     if (flush) produced += publish_pending(S);
     if (n_results) *n_results = produced;
     return AT_OK;
@@ -1012,6 +1060,7 @@ int at_serve_step(at_serve* S, uint32_t* n_results) {
 namespace {
 
 bool has_work(const at_serve* S) {  // caller holds mu
+    if (S->ahead.valid) return true;  // a step planned ahead still needs its graph
     for (const Link* L : S->links)
         if (L && L->state == L_ACTIVE && !L->q.empty()) return true;
     return false;
