@@ -112,6 +112,11 @@ struct TileJobSpec {
     TileBufs B;
 };
 hipError_t launch_ingest_tiled_batch(const TileJobSpec* jobs, uint32_t n_jobs, hipStream_t st);
+// The batch in its two halves: passes 1-2 with the column passes (they read
+// the pairs and write only the scratch; the pools are untouched), then the
+// tile pass (reads the scratch, reads and writes the pools).
+hipError_t launch_ingest_tiled_records(const TileJobSpec* jobs, uint32_t n_jobs, hipStream_t st);
+hipError_t launch_ingest_tiled_apply(const TileJobSpec* jobs, uint32_t n_jobs, hipStream_t st);
 // Windows summarised by one close: weights for window j land in
 // w[j * n_atv ...], AAT in aat[j * groups ...], super lists likewise.
 constexpr uint32_t kMaxWindows = 8;

@@ -2411,10 +2411,19 @@ size_t tiled_lds_bytes(uint32_t n_tiles) {
     return kTileRecs * sizeof(uint32_t) + (((size_t)n_tiles + 3) & ~(size_t)3) * sizeof(uint32_t);
 }
 
-hipError_t launch_ingest_tiled_batch(const TileJobSpec* js, uint32_t nj, hipStream_t st) {
+namespace {
+
+// The batch's kernel arguments and grid extents (host side).
+struct BatchPlan {
+    TileBatch Bt;
+    uint32_t max_nb, max_tiles, max_chunk;
+};
+
+hipError_t plan_batch(const TileJobSpec* js, uint32_t nj, BatchPlan* P) {
     if (nj == 0 || nj > kTileJobsMax) return hipErrorInvalidValue;
-    TileBatch Bt{};
-    uint32_t max_nb = 0, max_tiles = 0, max_chunk = 0;
+    TileBatch& Bt = P->Bt;
+    Bt = TileBatch{};
+    P->max_nb = P->max_tiles = P->max_chunk = 0;
     for (uint32_t q = 0; q < nj; q++) {
         const TileJobSpec& J = js[q];
         // one instance of each pass serves the batch: rows and AT width agree
@@ -2444,34 +2453,53 @@ hipError_t launch_ingest_tiled_batch(const TileJobSpec* js, uint32_t nj, hipStre
         T.n_tiles = z.n_tiles;
         T.nb = z.nb;
         T.nchunk = z.nchunk;
-        max_nb = std::max(max_nb, z.nb);
-        max_tiles = std::max(max_tiles, z.n_tiles);
-        max_chunk = std::max(max_chunk, z.nchunk);
+        P->max_nb = std::max(P->max_nb, z.nb);
+        P->max_tiles = std::max(P->max_tiles, z.n_tiles);
+        P->max_chunk = std::max(P->max_chunk, z.nchunk);
     }
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_ingest_tiled_records(const TileJobSpec* js, uint32_t nj, hipStream_t st) {
+    BatchPlan P;
+    hipError_t e = plan_batch(js, nj, &P);
+    if (e != hipSuccess) return e;
     // Passes 1 and 2 map blocks to XCDs by blockIdx.x alone: with several jobs
     // the row of blocks of each is a whole number of XCD rounds.
-    const uint32_t gx = nj == 1 ? max_nb : (max_nb + 7u) & ~7u;
-    const dim3 cols((max_tiles + kColTiles - 1) / kColTiles, max_chunk, nj);
+    const uint32_t gx = nj == 1 ? P.max_nb : (P.max_nb + 7u) & ~7u;
+    const dim3 cols((P.max_tiles + kColTiles - 1) / kColTiles, P.max_chunk, nj);
     const Geometry& G0 = js[0].G;
-    hipError_t e = with_rows<uint8_t>(G0.r, [&](auto rc, auto) {
+    e = with_rows<uint8_t>(G0.r, [&](auto rc, auto) {
         constexpr int RR = decltype(rc)::value;
-        hipLaunchKernelGGL((k_tile_count<RR>), dim3(gx, nj), dim3(kCountBlock), 0, st, Bt);
+        hipLaunchKernelGGL((k_tile_count<RR>), dim3(gx, nj), dim3(kCountBlock), 0, st, P.Bt);
     });
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tile_chunksum, cols, dim3(kBlock), 0, st, Bt);
-    hipLaunchKernelGGL(k_tile_rowpre, cols, dim3(kBlock), 0, st, Bt);
-    e = with_rows<uint8_t>(G0.r, [&](auto rc, auto) {
+    hipLaunchKernelGGL(k_tile_chunksum, cols, dim3(kBlock), 0, st, P.Bt);
+    hipLaunchKernelGGL(k_tile_rowpre, cols, dim3(kBlock), 0, st, P.Bt);
+    return with_rows<uint8_t>(G0.r, [&](auto rc, auto) {
         constexpr int RR = decltype(rc)::value;
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile_scatter<RR>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)tiled_lds_bytes(kMaxTiles));
-        hipLaunchKernelGGL((k_tile_scatter<RR>), dim3(gx, nj), dim3(kScatterBlock), tiled_lds_bytes(max_tiles), st,
-                           Bt);
+        hipLaunchKernelGGL((k_tile_scatter<RR>), dim3(gx, nj), dim3(kScatterBlock), tiled_lds_bytes(P.max_tiles),
+                           st, P.Bt);
     });
+}
+
+hipError_t launch_ingest_tiled_apply(const TileJobSpec* js, uint32_t nj, hipStream_t st) {
+    BatchPlan P;
+    hipError_t e = plan_batch(js, nj, &P);
     if (e != hipSuccess) return e;
-    return with_at(G0, [&](auto t) {
+    return with_at(js[0].G, [&](auto t) {
         using T = decltype(t);
-        hipLaunchKernelGGL(k_tile_apply<T>, dim3(max_tiles, nj), dim3(kApplyBlock), kTileBytes, st, Bt);
+        hipLaunchKernelGGL(k_tile_apply<T>, dim3(P.max_tiles, nj), dim3(kApplyBlock), kTileBytes, st, P.Bt);
     });
+}
+
+hipError_t launch_ingest_tiled_batch(const TileJobSpec* js, uint32_t nj, hipStream_t st) {
+    hipError_t e = launch_ingest_tiled_records(js, nj, st);
+    return e == hipSuccess ? launch_ingest_tiled_apply(js, nj, st) : e;
 }
 
 hipError_t launch_ingest_tiled(uint8_t* pool, const uint32_t* aip, const uint32_t* bip, uint64_t n,

@@ -143,6 +143,7 @@ struct CloseRec {
 struct at_serve {
     at_serve_config cfg{};
     hipStream_t s0 = nullptr, s1 = nullptr;  // s0: scan branch and graph launch; s1: close branch
+    hipStream_t s2 = nullptr;                // record passes of the tiled scans
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::mutex step_mu;  // held while device state may be in use (steps, admissions, watch lists)
     std::mutex mu;       // guards the host-side queues; never held while the GPU works
@@ -211,6 +212,7 @@ struct at_serve {
     } ahead;
     int tset = 0;                  // timing-event set of the next step's tiled launches
     hipEvent_t ev_done = nullptr;  // recorded after a step's graph: its results are complete
+    hipEvent_t ev_apply = nullptr; // recorded after each tile pass: the scratch slots are free
     int pend_set = 0;
     bool pend_mlp = false;
     double pend_step_ms = 0.0;
@@ -393,7 +395,9 @@ void free_server(at_serve* S) {
         for (hipEvent_t e : v) (void)hipEventDestroy(e);
     if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
     if (S->ev_done) (void)hipEventDestroy(S->ev_done);
+    if (S->ev_apply) (void)hipEventDestroy(S->ev_apply);
     if (S->ev_join) (void)hipEventDestroy(S->ev_join);
+    if (S->s2) (void)hipStreamDestroy(S->s2);
     if (S->s1) (void)hipStreamDestroy(S->s1);
     if (S->s0) (void)hipStreamDestroy(S->s0);
 }
@@ -458,34 +462,46 @@ int stage_buffers(at_serve* S, uint32_t slot, uint64_t n) {
 // One link's chunks of a step, scanned by the tiled scan.
 
 // One tiled launch of the given jobs between a pair of timing events.
-int launch_timed(at_serve* S, const atp::TileJobSpec* js, uint32_t nj, hipStream_t st, int tset, uint32_t* n_timed) {
+// One batch of tiled jobs.  Its record passes go on s2 once the last tile
+// pass on s0 is done with the scratch slots; its tile pass goes on s0 behind
+// them and behind whatever s0 holds before (the previous step's graph, whose
+// closes read the pools).  The record passes touch no pool, so on s2 they run
+// beside that graph.  Events around each half time it.
+int launch_timed(at_serve* S, const atp::TileJobSpec* js, uint32_t nj, int tset, uint32_t* n_timed) {
     std::vector<hipEvent_t>& tev = S->tev[tset];
-    while (tev.size() < 2 * (*n_timed + 1)) {
+    while (tev.size() < 4 * (*n_timed + 1)) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return AT_E_DEVICE;
         tev.push_back(e);
     }
-    if (hipEventRecord(tev[2 * *n_timed], st) != hipSuccess) return AT_E_DEVICE;
-    if (atp::launch_ingest_tiled_batch(js, nj, st) != hipSuccess) return AT_E_DEVICE;
-    if (hipEventRecord(tev[2 * *n_timed + 1], st) != hipSuccess) return AT_E_DEVICE;
+    hipEvent_t* ev = &tev[4 * *n_timed];
+    hipError_t r = hipStreamWaitEvent(S->s2, S->ev_apply, 0);
+    if (r == hipSuccess) r = hipEventRecord(ev[0], S->s2);
+    if (r == hipSuccess) r = atp::launch_ingest_tiled_records(js, nj, S->s2);
+    if (r == hipSuccess) r = hipEventRecord(ev[1], S->s2);
+    if (r == hipSuccess) r = hipStreamWaitEvent(S->s0, ev[1], 0);
+    if (r == hipSuccess) r = hipEventRecord(ev[2], S->s0);
+    if (r == hipSuccess) r = atp::launch_ingest_tiled_apply(js, nj, S->s0);
+    if (r == hipSuccess) r = hipEventRecord(ev[3], S->s0);
+    if (r == hipSuccess) r = hipEventRecord(S->ev_apply, S->s0);
+    if (r != hipSuccess) return AT_E_DEVICE;
     ++*n_timed;
     return AT_OK;
 }
 
-// Launch the step's tiled jobs on st, ahead of the step graph whose closes
-// read these pools (events around each launch for the timing).  Jobs share
-// launches, up to kTileJobsMax per launch, each with its own scratch slot; a
-// job of more than kTileBatch pairs takes launches of its own, one per
-// kTileBatch pairs.
-int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, hipStream_t st, int tset, uint32_t* n_timed,
-              uint32_t* n_jobs) {
+// Launch a step's tiled jobs, their tile passes on s0 ahead of the step
+// graph whose closes read these pools.  Jobs share launches, up to
+// kTileJobsMax per launch, each with its own scratch slot; a job of more than
+// kTileBatch pairs takes launches of its own, one per kTileBatch pairs.
+// Gathered chunks are staged on s2, where the record passes read them.
+int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, int tset, uint32_t* n_timed, uint32_t* n_jobs) {
     *n_timed = 0;
     *n_jobs = 0;
     atp::TileJobSpec batch[atp::kTileJobsMax];
     uint32_t nb = 0;
     auto flush = [&]() -> int {
         if (nb == 0) return AT_OK;
-        const int rc = launch_timed(S, batch, nb, st, tset, n_timed);
+        const int rc = launch_timed(S, batch, nb, tset, n_timed);
         *n_jobs += nb;
         nb = 0;
         return rc;
@@ -512,7 +528,7 @@ int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, hipStream_t st, int tset
                 G.off[G.n] = off;
                 off += J.chunks[c].n;
                 if (++G.n == atp::kGatherMax || c + 1 == J.chunks.size()) {
-                    if (atp::launch_gather_pairs(G, S->stage_a[slot], S->stage_b[slot], st) != hipSuccess)
+                    if (atp::launch_gather_pairs(G, S->stage_a[slot], S->stage_b[slot], S->s2) != hipSuccess)
                         return AT_E_DEVICE;
                     G.n = 0;
                 }
@@ -575,8 +591,10 @@ int at_serve_create(const at_serve_config* cfg, at_serve** out) {
     int rc = AT_OK;
     hipError_t e = hipStreamCreateWithFlags(&S->s0, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s1, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_apply, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) rc = AT_E_DEVICE;
     if (!rc && ((rc = dalloc(&S->d_desc, 1)) || (rc = dalloc(&S->d_slots, atp::kServeMaxLinks)) ||
@@ -623,6 +641,7 @@ int at_serve_destroy(at_serve* S) {
     { std::lock_guard<std::mutex> sg(S->step_mu); }
     (void)hipStreamSynchronize(S->s0);
     (void)hipStreamSynchronize(S->s1);
+    (void)hipStreamSynchronize(S->s2);
     free_server(S);
     delete S;
     return AT_OK;
@@ -994,7 +1013,7 @@ int serve_step(at_serve* S, uint32_t* n_results, bool flush) {
 
     const double t0 = now_ms();
     // the tiled scans first: the graph's closes read what they store
-    int trc = from_ahead ? AT_OK : run_tiled(S, tiled, S->s0, tset, &n_timed, &n_jobs);
+    int trc = from_ahead ? AT_OK : run_tiled(S, tiled, tset, &n_timed, &n_jobs);
     hipError_t e = trc ? hipSuccess : hipGraphLaunch(S->exec, S->s0);
     if (e == hipSuccess && !trc) e = hipEventRecord(S->ev_done, S->s0);
     if (e == hipSuccess && !trc && !flush) {
@@ -1006,7 +1025,7 @@ int serve_step(at_serve* S, uint32_t* n_results, bool flush) {
             plan_step(S, nullptr, A.tiled, A.cds, A.closes, A.pairs);
         }
         lk.unlock();
-        if (A.valid) trc = run_tiled(S, A.tiled, S->s0, A.tset, &A.n_timed, &A.n_jobs);
+        if (A.valid) trc = run_tiled(S, A.tiled, A.tset, &A.n_timed, &A.n_jobs);
     }
     uint32_t produced = 0;
     {  // the previous step's results (the other mapped set) while this one runs
@@ -1018,9 +1037,11 @@ int serve_step(at_serve* S, uint32_t* n_results, bool flush) {
     if (e != hipSuccess) return AT_E_DEVICE;
     if (trc) return trc;
     float tms = 0.f;
-    for (uint32_t q = 0; q < n_timed; q++) {
+    for (uint32_t q = 0; q < n_timed; q++) {  // record passes plus tile pass of each launch
+        const hipEvent_t* ev = &S->tev[tset][4 * q];
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, S->tev[tset][2 * q], S->tev[tset][2 * q + 1]) == hipSuccess) tms += ms;
+        if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) tms += ms;
+        if (hipEventElapsedTime(&ms, ev[2], ev[3]) == hipSuccess) tms += ms;
     }
     S->tset = tset ^ 1;
 
