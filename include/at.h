@@ -315,6 +315,14 @@ int at_mlp_forward(at_mlp *m, const float *x_dev, uint64_t n, float *y_dev);
  * synchronous). */
 int at_mlp_grad(at_mlp *m, const float *x_dev, const float *t_dev, uint64_t n, float *grad_dev,
                 float *loss_host);
+/* A training batch on the network's stream: for i < n, row idx_dev[i] of the
+ * n_all x 64 features x_dev into xb_dev[i*64 ..], and the network's target
+ * tb_dev[i] = lnn_dev[idx_dev[i]] - 16 * x_dev[idx_dev[i]*64 + 61] (ln n
+ * minus the plain estimate's log feature).  Device arrays; every idx_dev
+ * entry must be a row of x_dev.  Asynchronous.  AT_E_INVAL for null pointers
+ * with n > 0. */
+int at_mlp_gather_batch(at_mlp *m, const float *x_dev, const float *lnn_dev, const int64_t *idx_dev, uint64_t n,
+                        float *xb_dev, float *tb_dev);
 /* One Adam step with the given gradient (device) and learning rate. */
 int at_mlp_apply_grad(at_mlp *m, const float *grad_dev, float lr);
 /* Gradient + Adam step on one batch; loss as in at_mlp_grad (before the step). */

@@ -77,6 +77,7 @@ SIGNATURES = {
     "at_mlp_forward": (C.c_int, [_vp, _vp, C.c_uint64, _vp]),
     "at_mlp_grad": (C.c_int, [_vp, _vp, _vp, C.c_uint64, _vp, _f32p]),
     "at_mlp_apply_grad": (C.c_int, [_vp, _vp, C.c_float]),
+    "at_mlp_gather_batch": (C.c_int, [_vp, _vp, _vp, _vp, C.c_uint64, _vp, _vp]),
     "at_mlp_train_step": (C.c_int, [_vp, _vp, _vp, C.c_uint64, C.c_float, _f32p]),
     "at_estimate_learned": (C.c_int, [_vp, _vp, _u32p, C.c_uint64, _f64p, _u8p, _f64p]),
     "at_estimate_learned_dev": (C.c_int, [_vp, _vp, _vp, C.c_uint64, _vp, _vp, _vp]),
@@ -437,6 +438,13 @@ class Mlp:
 
     def apply_grad(self, grad_dev, lr: float):
         _check(self.lib.at_mlp_apply_grad(self._handle(), C.c_void_p(_dev_ptr(grad_dev)), lr), "at_mlp_apply_grad")
+
+    def gather_batch(self, x_dev, lnn_dev, idx_dev, xb_dev, tb_dev):
+        """Rows idx of the features and their targets ln n - 16 f[61] (at_mlp_gather_batch)."""
+        _check(self.lib.at_mlp_gather_batch(self._handle(), C.c_void_p(_dev_ptr(x_dev)), C.c_void_p(_dev_ptr(lnn_dev)),
+                                            C.c_void_p(_dev_ptr(idx_dev)), idx_dev.numel(),
+                                            C.c_void_p(_dev_ptr(xb_dev)), C.c_void_p(_dev_ptr(tb_dev))),
+               "at_mlp_gather_batch")
 
     def train_step(self, x_dev, t_dev, lr: float, want_loss: bool = False):
         loss = C.c_float()

@@ -229,6 +229,9 @@ hipError_t launch_mlp_forward_learned(const float* X, uint64_t n, const MlpDev& 
 hipError_t launch_mlp_train_fwd_bwd(const float* X, const float* t, uint64_t n, uint64_t nrows, const MlpDev& P,
                                     const MlpScratch& S, hipStream_t st);
 hipError_t launch_mlp_loss(const float* y, const float* t, uint64_t n, float* out, hipStream_t st);
+// Xb[i] = X[idx[i]] (64 features), Tb[i] = lnn[idx[i]] - 16 * X[idx[i]][61]
+hipError_t launch_mlp_gather(const float* X, const float* lnn, const int64_t* idx, uint64_t n, float* Xb, float* Tb,
+                             hipStream_t st);
 hipError_t launch_mlp_adam(float* w, float* m, float* v, const float* grad, const AdamConst& C, const MlpOut& O,
                            hipStream_t st);
 hipError_t launch_mlp_refresh(const float* w, const MlpOut& O, hipStream_t st);

@@ -1121,6 +1121,13 @@ int at_mlp_train_step(at_mlp* M, const float* x_dev, const float* t_dev, uint64_
     return mlp_adam(M, M->S.grad, lr);
 }
 
+int at_mlp_gather_batch(at_mlp* M, const float* x_dev, const float* lnn_dev, const int64_t* idx_dev, uint64_t n,
+                        float* xb_dev, float* tb_dev) {
+    if (!M || (n && (!x_dev || !lnn_dev || !idx_dev || !xb_dev || !tb_dev))) return AT_E_INVAL;
+    return atp::launch_mlp_gather(x_dev, lnn_dev, idx_dev, n, xb_dev, tb_dev, M->stream) == hipSuccess ? AT_OK
+                                                                                                   : AT_E_DEVICE;
+}
+
 int at_features(at_ctx* h, const uint32_t* aip_dev, uint64_t n, float* feat_dev, double* est_dev, uint8_t* flags_dev) {
     if (!h || (n && (!aip_dev || !feat_dev))) return AT_E_INVAL;
     if (!h->queryable) return AT_E_STATE;

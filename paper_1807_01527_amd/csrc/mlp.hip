@@ -322,6 +322,23 @@ __device__ __forceinline__ void refresh_bf16(uint32_t p, float w, const MlpOut& 
     }
 }
 
+// A training batch: rows idx[i] of the features and the network's target
+// for each, ln n minus the plain estimate's log feature (16 * f[61]).  One
+// wave per row; lane l copies feature l.
+__global__ __launch_bounds__(kBlock) void k_mlp_gather(const float* __restrict__ X, const float* __restrict__ lnn,
+                                                       const int64_t* __restrict__ idx, uint64_t n,
+                                                       float* __restrict__ Xb, float* __restrict__ Tb) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / 64);
+    for (uint64_t i = wave; i < n; i += nwaves) {
+        const uint64_t r = (uint64_t)idx[i];
+        const float x = X[r * 64 + lane];
+        Xb[i * 64 + lane] = x;
+        if (lane == 61) Tb[i] = lnn[r] - 16.0f * x;
+    }
+}
+
 __global__ void k_mlp_adam(float* __restrict__ w, float* __restrict__ mo, float* __restrict__ ve,
                            const float* __restrict__ grad, AdamConst C, MlpOut O) {
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -425,6 +442,15 @@ hipError_t launch_mlp_train_fwd_bwd(const float* X, const float* t, uint64_t n, 
                        nrows, S.partial);
     hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + kBlock - 1) / kBlock), dim3(kBlock), 0, st, S.partial, nchunks,
                        S.grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_gather(const float* X, const float* lnn, const int64_t* idx, uint64_t n, float* Xb, float* Tb,
+                             hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + kBlock / 64 - 1) / (kBlock / 64);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_mlp_gather, dim3((uint32_t)blocks), dim3(kBlock), 0, st, X, lnn, idx, n, Xb, Tb);
     return hipGetLastError();
 }
 

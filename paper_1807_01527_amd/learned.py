@@ -3,7 +3,8 @@
 Everything on the path runs in the HIP library:
 - the traces are ingested by at_ingest_slice / at_close_slice;
 - the features come from at_features;
-- training runs at_mlp_train_step (bf16 matrix-core forward/backward + Adam);
+- training gathers its batches and targets with at_mlp_gather_batch and runs
+  at_mlp_train_step (bf16 matrix-core forward/backward + Adam);
 - inference runs at_estimate_learned.
 
 This module only orchestrates.  Labels are the exact distinct counts of the
@@ -215,26 +216,22 @@ def build_dataset(name: str, n_samples: int, seed: int = 1, log=print):
     return torch.cat(X)[:n_samples].contiguous(), torch.cat(T)[:n_samples].contiguous()
 
 
-def residual_target(X, T):
-    """The network predicts ln n minus the plain estimate's log feature."""
-    return (T - 16.0 * X[:, 61]).contiguous()
-
-
 def train(mlp: Mlp, X, T, epochs: int = 40, batch: int = 4096, lr: float = 2e-3, seed: int = 0, log=print):
-    """T holds ln n; the network is fit to its residual over 16*f[61]."""
+    """T holds ln n; the network is fit to its residual over 16*f[61].  The
+    batch order is a seeded permutation drawn on the host; the library
+    gathers each batch and its targets on the device."""
     import torch
     n = X.shape[0]
-    T = residual_target(X, T)
     g = torch.Generator(device="cpu").manual_seed(seed)
+    xb = torch.empty((batch, 64), dtype=torch.float32, device=X.device)
+    tb = torch.empty(batch, dtype=torch.float32, device=X.device)
     losses = []
     for ep in range(epochs):
         perm = torch.randperm(n, generator=g).to(X.device)
         lr_ep = lr * (0.5 * (1 + math.cos(math.pi * ep / epochs)) * 0.95 + 0.05)
         tot, cnt = 0.0, 0
         for s in range(0, n - batch + 1, batch):
-            idx = perm[s:s + batch]
-            xb = X.index_select(0, idx).contiguous()
-            tb = T.index_select(0, idx).contiguous()
+            mlp.gather_batch(X, T, perm[s:s + batch], xb, tb)
             want = (s // batch) % 50 == 0
             loss = mlp.train_step(xb, tb, lr_ep, want_loss=want)
             if want:

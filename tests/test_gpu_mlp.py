@@ -157,6 +157,28 @@ def test_gradients_match_reference(torch_cuda, n):
         assert num <= 1e-2 * den + 1e-7, (name, num, den)
 
 
+@pytest.mark.parametrize("n_all,n", [(5000, 4096), (300, 1), (70000, 3001)])
+def test_gather_batch_matches_reference(torch_cuda, n_all, n):
+    """A training batch: rows of the features at the given indices (repeats
+    allowed) and their targets ln n - 16 f[61], against numpy indexing."""
+    from paper_1807_01527_amd.binding import Mlp
+    torch = torch_cuda
+    rng = np.random.default_rng(n_all)
+    X = rng.standard_normal((n_all, 64)).astype(np.float32)
+    lnn = rng.uniform(0, 14, n_all).astype(np.float32)
+    idx = rng.integers(0, n_all, n).astype(np.int64)
+    net = Mlp()
+    xd, ld, idd = _dev_f32(torch, X), _dev_f32(torch, lnn), torch.from_numpy(idx).cuda()
+    xb = torch.empty((n, 64), dtype=torch.float32, device="cuda")
+    tb = torch.empty(n, dtype=torch.float32, device="cuda")
+    net.gather_batch(xd, ld, idd, xb, tb)
+    torch.cuda.synchronize()
+    assert np.array_equal(xb.cpu().numpy(), X[idx])
+    want = (lnn[idx] - np.float32(16.0) * X[idx, 61]).astype(np.float32)
+    assert np.array_equal(tb.cpu().numpy(), want)
+    net.destroy()
+
+
 def test_adam_matches_reference(torch_cuda):
     torch = torch_cuda
     from paper_1807_01527_amd.binding import Mlp
