@@ -212,7 +212,7 @@ struct at_serve {
     } ahead;
     int tset = 0;                  // timing-event set of the next step's tiled launches
     hipEvent_t ev_done = nullptr;  // recorded after a step's graph: its results are complete
-    hipEvent_t ev_apply = nullptr; // recorded after each tile pass: the scratch slots are free
+    hipEvent_t ev_apply[2] = {};   // per scratch set, recorded after each tile pass: its slots are free
     int pend_set = 0;
     bool pend_mlp = false;
     double pend_step_ms = 0.0;
@@ -222,10 +222,13 @@ struct at_serve {
     // tiled scans: stream, scratch, timing
     bool tiled_ok = false;
     uint64_t pool_bytes = 0;
-    atp::TileBufs tb[atp::kTileJobsMax] = {};     // scratch of each job of a batched launch
-    uint32_t* stage_a[atp::kTileJobsMax] = {};      // gathered chunks of a job's link
-    uint32_t* stage_b[atp::kTileJobsMax] = {};
-    uint64_t stage_cap[atp::kTileJobsMax] = {};
+    // two scratch sets, used by alternate steps, so that a step's record passes
+    // can run while the previous step's tile pass still reads its set
+    atp::TileBufs tb[2][atp::kTileJobsMax] = {};    // scratch of each job of a batched launch
+    uint32_t* stage_a[2][atp::kTileJobsMax] = {};   // gathered chunks of a job's link
+    uint32_t* stage_b[2][atp::kTileJobsMax] = {};
+    uint64_t stage_cap[2][atp::kTileJobsMax] = {};
+    int tbuf = 0;                                   // the set of the next step with tiled scans
     std::vector<hipEvent_t> tev[2];  // start/end event pairs of a step's tiled launches (two steps in flight)
     uint64_t tiled_calls = 0, tiled_jobs = 0, tiled_pairs = 0;
     double tiled_ms = 0.0;
@@ -386,16 +389,19 @@ void free_server(at_serve* S) {
     for (void* p : h)
         if (p) (void)hipHostFree(p);
     for (uint32_t q = 0; q < atp::kTileJobsMax; q++) {
-        const atp::TileBufs& B = S->tb[q];
-        void* t[] = {B.rec, B.cnt, B.pre, B.csum, B.base, B.act, S->stage_a[q], S->stage_b[q]};
-        for (void* p : t)
-            if (p) (void)hipFree(p);
+        for (int x = 0; x < 2; x++) {
+            const atp::TileBufs& B = S->tb[x][q];
+            void* t[] = {B.rec, B.cnt, B.pre, B.csum, B.base, B.act, S->stage_a[x][q], S->stage_b[x][q]};
+            for (void* p : t)
+                if (p) (void)hipFree(p);
+        }
     }
     for (const std::vector<hipEvent_t>& v : S->tev)
         for (hipEvent_t e : v) (void)hipEventDestroy(e);
     if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
     if (S->ev_done) (void)hipEventDestroy(S->ev_done);
-    if (S->ev_apply) (void)hipEventDestroy(S->ev_apply);
+    for (hipEvent_t ev : S->ev_apply)
+        if (ev) (void)hipEventDestroy(ev);
     if (S->ev_join) (void)hipEventDestroy(S->ev_join);
     if (S->s2) (void)hipStreamDestroy(S->s2);
     if (S->s1) (void)hipStreamDestroy(S->s1);
@@ -418,9 +424,9 @@ bool take_tiled(const at_serve* S, uint64_t n) {  // caller holds mu
     return n * S->shape.r * per_store >= S->pool_bytes;
 }
 
-int tiled_buffers(at_serve* S, uint32_t slot, uint64_t n) {
+int tiled_buffers(at_serve* S, int set, uint32_t slot, uint64_t n) {
     const atp::TileSizes z = atp::tiled_sizes(std::min<uint64_t>(n, kTileBatch), S->pool_bytes, S->shape);
-    atp::TileBufs& B = S->tb[slot];
+    atp::TileBufs& B = S->tb[set][slot];
     int rc;
     if (z.recs > B.rec_cap) {
         if (B.rec) (void)hipFree(B.rec);
@@ -447,27 +453,28 @@ int tiled_buffers(at_serve* S, uint32_t slot, uint64_t n) {
     return AT_OK;
 }
 
-int stage_buffers(at_serve* S, uint32_t slot, uint64_t n) {
-    if (n <= S->stage_cap[slot]) return AT_OK;
-    if (S->stage_a[slot]) (void)hipFree(S->stage_a[slot]);
-    if (S->stage_b[slot]) (void)hipFree(S->stage_b[slot]);
-    S->stage_a[slot] = S->stage_b[slot] = nullptr;
-    S->stage_cap[slot] = 0;
+int stage_buffers(at_serve* S, int set, uint32_t slot, uint64_t n) {
+    if (n <= S->stage_cap[set][slot]) return AT_OK;
+    if (S->stage_a[set][slot]) (void)hipFree(S->stage_a[set][slot]);
+    if (S->stage_b[set][slot]) (void)hipFree(S->stage_b[set][slot]);
+    S->stage_a[set][slot] = S->stage_b[set][slot] = nullptr;
+    S->stage_cap[set][slot] = 0;
     int rc;
-    if ((rc = dalloc(&S->stage_a[slot], n)) || (rc = dalloc(&S->stage_b[slot], n))) return rc;
-    S->stage_cap[slot] = n;
+    if ((rc = dalloc(&S->stage_a[set][slot], n)) || (rc = dalloc(&S->stage_b[set][slot], n))) return rc;
+    S->stage_cap[set][slot] = n;
     return AT_OK;
 }
 
 // One link's chunks of a step, scanned by the tiled scan.
 
 // One tiled launch of the given jobs between a pair of timing events.
-// One batch of tiled jobs.  Its record passes go on s2 once the last tile
-// pass on s0 is done with the scratch slots; its tile pass goes on s0 behind
-// them and behind whatever s0 holds before (the previous step's graph, whose
-// closes read the pools).  The record passes touch no pool, so on s2 they run
-// beside that graph.  Events around each half time it.
-int launch_timed(at_serve* S, const atp::TileJobSpec* js, uint32_t nj, int tset, uint32_t* n_timed) {
+// One batch of tiled jobs on scratch set `set`.  Its record passes go on s2
+// once the last tile pass that read that set is done; its tile pass goes on
+// s0 behind them and behind whatever s0 holds before (the previous step's
+// graph, whose closes read the pools).  The record passes touch no pool, so
+// on s2 they run beside that graph and the previous step's tile pass, which
+// reads the other set.  Events around each half time it.
+int launch_timed(at_serve* S, const atp::TileJobSpec* js, uint32_t nj, int set, int tset, uint32_t* n_timed) {
     std::vector<hipEvent_t>& tev = S->tev[tset];
     while (tev.size() < 4 * (*n_timed + 1)) {
         hipEvent_t e;
@@ -475,7 +482,7 @@ int launch_timed(at_serve* S, const atp::TileJobSpec* js, uint32_t nj, int tset,
         tev.push_back(e);
     }
     hipEvent_t* ev = &tev[4 * *n_timed];
-    hipError_t r = hipStreamWaitEvent(S->s2, S->ev_apply, 0);
+    hipError_t r = hipStreamWaitEvent(S->s2, S->ev_apply[set], 0);
     if (r == hipSuccess) r = hipEventRecord(ev[0], S->s2);
     if (r == hipSuccess) r = atp::launch_ingest_tiled_records(js, nj, S->s2);
     if (r == hipSuccess) r = hipEventRecord(ev[1], S->s2);
@@ -483,7 +490,7 @@ int launch_timed(at_serve* S, const atp::TileJobSpec* js, uint32_t nj, int tset,
     if (r == hipSuccess) r = hipEventRecord(ev[2], S->s0);
     if (r == hipSuccess) r = atp::launch_ingest_tiled_apply(js, nj, S->s0);
     if (r == hipSuccess) r = hipEventRecord(ev[3], S->s0);
-    if (r == hipSuccess) r = hipEventRecord(S->ev_apply, S->s0);
+    if (r == hipSuccess) r = hipEventRecord(S->ev_apply[set], S->s0);
     if (r != hipSuccess) return AT_E_DEVICE;
     ++*n_timed;
     return AT_OK;
@@ -497,11 +504,14 @@ int launch_timed(at_serve* S, const atp::TileJobSpec* js, uint32_t nj, int tset,
 int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, int tset, uint32_t* n_timed, uint32_t* n_jobs) {
     *n_timed = 0;
     *n_jobs = 0;
+    if (jobs.empty()) return AT_OK;
+    const int set = S->tbuf;  // this step's scratch set; the next step takes the other
+    S->tbuf ^= 1;
     atp::TileJobSpec batch[atp::kTileJobsMax];
     uint32_t nb = 0;
     auto flush = [&]() -> int {
         if (nb == 0) return AT_OK;
-        const int rc = launch_timed(S, batch, nb, tset, n_timed);
+        const int rc = launch_timed(S, batch, nb, set, tset, n_timed);
         *n_jobs += nb;
         nb = 0;
         return rc;
@@ -513,8 +523,8 @@ int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, int tset, uint32_t* n_ti
         if (!single || nb == atp::kTileJobsMax)
             if ((rc = flush())) return rc;
         const uint32_t slot = nb;
-        rc = tiled_buffers(S, slot, J.n);
-        if (!rc && J.chunks.size() > 1) rc = stage_buffers(S, slot, J.n);
+        rc = tiled_buffers(S, set, slot, J.n);
+        if (!rc && J.chunks.size() > 1) rc = stage_buffers(S, set, slot, J.n);
         if (rc) return rc;
         const uint32_t* a = J.chunks[0].aip;
         const uint32_t* b = J.chunks[0].bip;
@@ -528,20 +538,20 @@ int run_tiled(at_serve* S, std::vector<TiledJob>& jobs, int tset, uint32_t* n_ti
                 G.off[G.n] = off;
                 off += J.chunks[c].n;
                 if (++G.n == atp::kGatherMax || c + 1 == J.chunks.size()) {
-                    if (atp::launch_gather_pairs(G, S->stage_a[slot], S->stage_b[slot], S->s2) != hipSuccess)
+                    if (atp::launch_gather_pairs(G, S->stage_a[set][slot], S->stage_b[set][slot], S->s2) != hipSuccess)
                         return AT_E_DEVICE;
                     G.n = 0;
                 }
             }
-            a = S->stage_a[slot];
-            b = S->stage_b[slot];
+            a = S->stage_a[set][slot];
+            b = S->stage_b[set][slot];
         }
         for (uint64_t off = 0; off < J.n; off += kTileBatch) {
             const uint64_t m = std::min<uint64_t>(kTileBatch, J.n - off);
             const bool first = off == 0;
             const bool w = J.weights && single;
             batch[nb++] = atp::TileJobSpec{L->pool, S->pool_bytes, a + off, b + off, m, L->G, J.c0, J.opens && first,
-                                           w ? L->w : nullptr, J.kq, S->tb[slot]};
+                                           w ? L->w : nullptr, J.kq, S->tb[set][slot]};
             if (!single && (rc = flush())) return rc;
         }
     }
@@ -594,7 +604,8 @@ int at_serve_create(const at_serve_config* cfg, at_serve** out) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s2, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_done, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_apply, hipEventDisableTiming);
+    for (hipEvent_t& ev : S->ev_apply)
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) rc = AT_E_DEVICE;
     if (!rc && ((rc = dalloc(&S->d_desc, 1)) || (rc = dalloc(&S->d_slots, atp::kServeMaxLinks)) ||
