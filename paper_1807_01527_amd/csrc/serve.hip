@@ -11,20 +11,21 @@
 //           features + plain estimates of candidates and watch hosts, and
 //           the learned correction;
 // then writes the used rows of the results straight into mapped pinned host
-// memory.  A link whose slice ends is closed in the step after its last
-// chunk was scanned, and its next slice waits for that close, so the two
-// branches never touch the same pool.
+// memory.  A link whose chunks the graph scans is closed in the following
+// step, so the two branches never touch the same pool.
 //
 // A link whose queued pairs in a step are many next to its pool takes the
 // tiled scan instead (stores grouped per 64 KiB tile and applied in LDS, the
-// pool streamed once): its chunks are gathered into one array and scanned by
-// launches on a third stream while the graph runs, since the grids of those
-// launches depend on the step's pair count.  Its slice is opened by the tile
-// pass (the preserve runs there), and when the slice's end is already queued
-// behind its chunks the tile pass also writes the window's weights, so the
-// close that follows reads no pool.  When the link's previous slice closes
-// in the same step, those launches wait on the third stream until the graph
-// has finished with the pool, so a slice takes one step instead of two.
+// pool streamed once).  The step's tiled links share launches outside the
+// graph (their grids depend on the step's pair counts), one grid row per
+// link.  A launch's record passes touch no pool and run on a stream of their
+// own; its tile pass, which opens the slice (the preserve runs there) and,
+// when the slice's end is queued behind its chunks, writes the window's
+// weights, runs on the graph's stream ahead of the graph, so such a slice is
+// scanned and closed in one step.  When the next step will be tiled scans and
+// their closes only, it is planned and its launches queued before the host
+// waits for the current graph: its record passes then run beside that graph,
+// and the GPU goes from the graph straight to its tile pass.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
