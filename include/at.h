@@ -365,7 +365,13 @@ int at_estimate_learned_end(at_ctx *h, double *est_out, uint8_t *flags_out, doub
  * and every queued chunk of every link is scanned in one launch, while the
  * slices whose chunks were all scanned in earlier steps are closed, restored
  * and estimated in a concurrent branch.  The step is a hipGraph captured
- * once and replayed with a new descriptor table each time.
+ * once and replayed with a new descriptor table each time.  A link whose
+ * step holds as many pairs as its pool is large instead takes the tiled scan
+ * (one launch for all such links of the step, ahead of the graph), and a
+ * slice whose pairs and end it takes is scanned and closed in the same step.
+ * The native thread (at_serve_start) plans a step made only of such scans
+ * and their closes while the previous one runs, and queues its scans behind
+ * the previous graph.
  *
  * All links of a server share the geometry shape (r, c, s, u, log2g, theta);
  * k and seed are per link.  Per closed slice the server returns the restore
@@ -411,7 +417,8 @@ int at_serve_open_link(at_serve *s, uint32_t k, uint64_t seed, uint64_t tuple_bu
 /* state: 0 waiting, 1 active, 2 closed; slices closed; queued events. */
 int at_serve_link_state(at_serve *s, uint32_t link_id, int *state, uint64_t *slices_closed,
                         uint64_t *pending);
-/* Release a link's memory (after the running step) and admit waiting links. */
+/* Release a link's memory (after the running step, and after any scans of
+ * its pool already queued for the next) and admit waiting links. */
 int at_serve_close_link(at_serve *s, uint32_t link_id);
 /* Hosts estimated at every close of the link (host array, <= watch_cap). */
 int at_serve_set_watch(at_serve *s, uint32_t link_id, const uint32_t *hosts_host, uint32_t n);
