@@ -496,7 +496,8 @@ def headline(args, dev, wl, mlp) -> dict:
                       "hosts": nw, "fallbacks": fb, "true_super_points": truth_total,
                       "over": "true super points of each link's full window (exact distinct count >= 1024), "
                               "at its last close"},
-        tiled={"launches": calls, "jobs": tjobs, "pairs": tpairs, "device_ms": tms, "steps": st["steps"]},
+        tiled={"launches": calls, "jobs": tjobs, "pairs": tpairs, "device_ms": tms, "steps": st["steps"],
+               "planned_ahead": t_calls1["planned_ahead"] - t_calls0["planned_ahead"]},
         tiled_paced={k: t_calls2[k] - t_calls1[k] for k in ("calls", "jobs", "pairs", "device_ms")},
         pool_bytes=pool_bytes, n_atv=pool_bytes >> LARGE["log2g"])
 
@@ -967,7 +968,7 @@ def main():
                      "bytes_per_pair": 8 + LARGE["r"],
                      "algorithmic_bytes_per_launch": {"pairs": alg_pairs, "window_count": alg_count},
                      "avg_launch_ms": avg_ms, "pairs_per_launch": ppl, "links_per_launch": jpl,
-                     "launches_timed": tl["launches"],
+                     "launches_timed": tl["launches"], "steps_planned_ahead": tl["planned_ahead"],
                      "timing": "HIP events around each launch's two halves (record passes on their own stream, "
                                "beside the previous step's close graph; the tile pass behind that graph), summed",
                      "uncontended": {"avg_launch_ms": p_ms, "achieved": p_achieved, "frac": p_achieved / HBM_PEAK_GBS,

@@ -460,9 +460,11 @@ int at_serve_read_pool(at_serve *s, uint32_t link_id, uint8_t *host_out);
  * events around each launch on its stream).  A link's step goes to the tiled
  * scan, instead of the batched byte-store scan, when its r*n stores times 12
  * (30 once the resident pools exceed the 256 MiB last-level cache) reach its
- * pool's bytes and the pool is whole 64 KiB tiles, at most 4096.  Any
- * pointer may be NULL. */
-int at_serve_tiled_stats(at_serve *s, uint64_t *calls, uint64_t *pairs, double *device_ms, uint64_t *jobs);
+ * pool's bytes and the pool is whole 64 KiB tiles, at most 4096.
+ * planned_ahead: steps the native thread planned, and whose scans it queued,
+ * before the previous step's graph had finished.  Any pointer may be NULL. */
+int at_serve_tiled_stats(at_serve *s, uint64_t *calls, uint64_t *pairs, double *device_ms, uint64_t *jobs,
+                         uint64_t *planned_ahead);
 
 /*
  * The aging-counter comparator (Section 2.3 against Section 3).  ACE keeps a

@@ -118,7 +118,7 @@ SIGNATURES.update({
                                        _f64p, _f64p, _u8p, C.c_uint32]),
     "at_serve_stats": (C.c_int, [_vp, _u64p]),
     "at_serve_read_pool": (C.c_int, [_vp, C.c_uint32, _u8p]),
-    "at_serve_tiled_stats": (C.c_int, [_vp, _u64p, _u64p, _f64p, _u64p]),
+    "at_serve_tiled_stats": (C.c_int, [_vp, _u64p, _u64p, _f64p, _u64p, _u64p]),
 })
 
 _lib = None
@@ -560,10 +560,11 @@ class Server:
         return out
 
     def tiled_stats(self) -> dict:
-        calls, pairs, ms, jobs = C.c_uint64(), C.c_uint64(), C.c_double(), C.c_uint64()
-        _check(self.lib.at_serve_tiled_stats(self.h, C.byref(calls), C.byref(pairs), C.byref(ms), C.byref(jobs)),
-               "at_serve_tiled_stats")
-        return dict(calls=int(calls.value), jobs=int(jobs.value), pairs=int(pairs.value), device_ms=float(ms.value))
+        calls, pairs, ms, jobs, ahead = C.c_uint64(), C.c_uint64(), C.c_double(), C.c_uint64(), C.c_uint64()
+        _check(self.lib.at_serve_tiled_stats(self.h, C.byref(calls), C.byref(pairs), C.byref(ms), C.byref(jobs),
+                                             C.byref(ahead)), "at_serve_tiled_stats")
+        return dict(calls=int(calls.value), jobs=int(jobs.value), pairs=int(pairs.value), device_ms=float(ms.value),
+                    planned_ahead=int(ahead.value))
 
 
 class AtCmp:

@@ -231,7 +231,7 @@ struct at_serve {
     uint64_t stage_cap[2][atp::kTileJobsMax] = {};
     int tbuf = 0;                                   // the set of the next step with tiled scans
     std::vector<hipEvent_t> tev[2];  // start/end event pairs of a step's tiled launches (two steps in flight)
-    uint64_t tiled_calls = 0, tiled_jobs = 0, tiled_pairs = 0;
+    uint64_t tiled_calls = 0, tiled_jobs = 0, tiled_pairs = 0, planned_ahead = 0;
     double tiled_ms = 0.0;
 };
 
@@ -1033,6 +1033,7 @@ int serve_step(at_serve* S, uint32_t* n_results, bool flush) {
         lk.lock();
         if (tiled_only(S)) {
             A.valid = true;
+            S->planned_ahead++;
             A.tset = tset ^ 1;
             plan_step(S, nullptr, A.tiled, A.cds, A.closes, A.pairs);
         }
@@ -1182,9 +1183,11 @@ int at_serve_stats(at_serve* S, uint64_t* out4) {
     return AT_OK;
 }
 
-int at_serve_tiled_stats(at_serve* S, uint64_t* calls, uint64_t* pairs, double* device_ms, uint64_t* jobs) {
+int at_serve_tiled_stats(at_serve* S, uint64_t* calls, uint64_t* pairs, double* device_ms, uint64_t* jobs,
+                         uint64_t* planned_ahead) {
     if (!S) return AT_E_INVAL;
     std::lock_guard<std::mutex> g(S->mu);
+    if (planned_ahead) *planned_ahead = S->planned_ahead;
     if (calls) *calls = S->tiled_calls;
     if (jobs) *jobs = S->tiled_jobs;
     if (pairs) *pairs = S->tiled_pairs;

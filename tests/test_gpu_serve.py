@@ -311,3 +311,85 @@ def test_tiled_steps_match_oracle(torch_cuda, oracle_lib):
             fin = np.isfinite(e_l)
             assert np.all(np.abs(r["watch_learned"][fin] - e_l[fin]) <= 1e-12 * np.abs(e_l[fin])), (i, s_)
         g.destroy()
+
+
+def test_native_thread_plans_tiled_steps_ahead(torch_cuda, oracle_lib):
+    """Whole slices queued with at_serve_submit_last, several per link, to a
+    server stepped by its native thread: the steps are tiled scans and their
+    closes only, so the thread plans each next one while the current graph
+    runs (record passes beside the graph, two scratch sets).  Every close
+    equals the CPU oracle and the single-link API.  One link is closed while
+    slices of it are still queued: its results are a prefix of its own."""
+    import time
+
+    from paper_1807_01527_amd.binding import AtPool, Mlp, Server
+    net = Mlp(ref.init_params(5).astype(np.float32) * np.float32(0.5))
+    links, keep = [], []
+    for i in range(5):
+        k = [3, 5, 8, 4, 6][i]
+        tr = traffic.generate(traffic.config_tiny(seed=400 + i, n_slices=2 * k + 4, pairs_per_slice=24000,
+                                                  hosts=1 << 10, planted=3, lo=200, hi=900))
+        sl = []
+        for t in range(tr.n_slices):
+            da, db = to_dev(tr.aip[t]), to_dev(tr.bip[t])
+            keep += [da, db]
+            sl.append((da, db, tr.aip[t], tr.bip[t]))
+        watch = np.unique(np.concatenate([tr.planted_hosts, tr.aip[0][:20]]))[:WATCH_CAP]
+        links.append(dict(k=k, seed=600 + i, slices=sl, watch=watch))
+    srv = Server(hbm_budget=1 << 32, max_links=8, cand_cap=CAND_CAP, watch_cap=WATCH_CAP, **TILED_SHAPE)
+    srv.set_mlp(net)
+    ids = []
+    for ln in links:
+        lid, adm = srv.open_link(ln["k"], ln["seed"], tuple_budget=TILED_BUDGET)
+        assert adm
+        srv.set_watch(lid, ln["watch"])
+        ids.append(lid)
+    srv.start()
+    closed, cut = 2, 5   # link 2 is closed once 5 of its slices have been queued
+    got = {lid: [] for lid in ids}
+    nxt = [0] * len(links)
+    while any(n < len(ln["slices"]) for n, ln in zip(nxt, links)):
+        for i, ln in enumerate(links):
+            if nxt[i] >= len(ln["slices"]) or (i == closed and nxt[i] >= cut):
+                continue
+            # up to three slices of a link in flight, as a producer would keep them
+            if nxt[i] - len(got[ids[i]]) >= 3:
+                continue
+            da, db, _, _ = ln["slices"][nxt[i]]
+            assert srv.submit_last(ids[i], da, db, ln["k"]) == 0
+            nxt[i] += 1
+        if nxt[closed] >= cut and srv.link_state(ids[closed])[0] == 1:
+            srv.close_link(ids[closed])
+        for r in srv.results():
+            got[r["link"]].append(r)
+        if nxt[closed] >= cut:
+            nxt[closed] = len(links[closed]["slices"])
+        time.sleep(0.0005)
+    srv.stop()
+    for r in srv.results():
+        got[r["link"]].append(r)
+    pools = {lid: srv.read_pool(lid) for i, lid in enumerate(ids) if i != closed}
+    ts = srv.tiled_stats()
+    srv.destroy()
+    assert ts["jobs"] > ts["calls"] > 0   # links shared launches
+    assert ts["planned_ahead"] > 0        # and steps were planned while the previous graph ran
+    jobs = [(TILED_SHAPE, ln["k"], ln["seed"],
+             [e for (_, _, a, b) in ln["slices"] for e in (("chunk", a, b), ("end", ln["k"]))],
+             ln["watch"], CAND_CAP, TILED_BUDGET) for ln in links]
+    orc = oracle_link_runs(oracle_lib, jobs)
+    for i, (lid, ln, (want, pool)) in enumerate(zip(ids, links, orc)):
+        if i == closed:
+            assert 0 < len(got[lid]) <= cut
+            compare_serve_with_oracle(got[lid], want[:len(got[lid])], f"planned-ahead link {i} (closed)")
+            continue
+        compare_serve_with_oracle(got[lid], want, f"planned-ahead link {i} vs oracle")
+        assert np.array_equal(pools[lid], pool), f"planned-ahead link {i}: pool differs from the oracle"
+        g = AtPool(k=ln["k"], seed=ln["seed"], **TILED_SHAPE)
+        for s_, ((da, db, _, _), r) in enumerate(zip(ln["slices"], got[lid])):
+            g.ingest(da, db)
+            g.close(ln["k"])
+            e_l, f_l, _ = g.estimate_learned(net, ln["watch"])
+            assert np.array_equal(r["watch_flags"], f_l), (i, s_)
+            fin = np.isfinite(e_l)
+            assert np.all(np.abs(r["watch_learned"][fin] - e_l[fin]) <= 1e-12 * np.abs(e_l[fin])), (i, s_)
+        g.destroy()
