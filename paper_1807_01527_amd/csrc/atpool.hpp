@@ -76,7 +76,7 @@ struct TileSizes {
 };
 struct TileBufs {
     uint16_t* rec;   // rec_cap records
-    uint32_t* cnt;   // table_cap: per-block tile counts
+    uint16_t* cnt;   // table_cap: per-block tile counts
     uint32_t* pre;   // table_cap: per-(block, tile) run starts
     uint32_t* csum;  // chunk_cap * 4096: per-chunk column sums, then tile and 64-tile totals (nchunk + 2 rows)
     uint32_t* base;  // 4097 region starts

@@ -204,7 +204,7 @@ uint64_t carve_tiles(uint8_t* base, const atp::TileSizes& z, const Geometry& G, 
         return p;
     };
     tb->rec = reinterpret_cast<uint16_t*>(take(z.recs * 2));
-    tb->cnt = reinterpret_cast<uint32_t*>(take(z.table * 4));
+    tb->cnt = reinterpret_cast<uint16_t*>(take(z.table * 2));
     tb->pre = reinterpret_cast<uint32_t*>(take(z.table * 4));
     tb->csum = reinterpret_cast<uint32_t*>(take((uint64_t)(z.nchunk + 2) * 4096 * 4));
     tb->base = reinterpret_cast<uint32_t*>(take(4097 * 4));
@@ -568,7 +568,8 @@ int ingest_tiled_buffers(at_ctx* h, uint64_t n) {
     if (z.table > h->tb.table_cap) {
         if (h->tb.cnt) (void)hipFree(h->tb.cnt);
         if (h->tb.pre) (void)hipFree(h->tb.pre);
-        h->tb.cnt = h->tb.pre = nullptr;
+        h->tb.cnt = nullptr;
+        h->tb.pre = nullptr;
         h->tb.table_cap = 0;
         if ((rc = dev_alloc(&h->tb.cnt, z.table)) || (rc = dev_alloc(&h->tb.pre, z.table))) return rc;
         h->tb.table_cap = z.table;

@@ -437,6 +437,7 @@ __device__ __forceinline__ void rotate_rows(uint32_t (&a)[R], uint32_t rot) {
 
 constexpr uint32_t kTileBytes = 1u << 16;
 constexpr uint32_t kTileRecs = 16384;  // records per block in passes 1 and 2
+static_assert(kTileRecs <= 0xFFFFu, "a block's count for one tile fits the 16-bit count table");
 constexpr uint32_t kMaxTiles = 4096;
 constexpr uint32_t kTileChunk = 64;    // rows (blocks) per chunk of the column scans
 constexpr uint32_t kCountBlock = 1024;  // pass 1: four pairs per thread
@@ -452,7 +453,7 @@ struct TileJob {
     const uint32_t* aip;
     const uint32_t* bip;
     uint16_t* rec;
-    uint32_t* cnt;
+    uint16_t* cnt;
     uint32_t* pre;
     uint32_t* csum;
     uint32_t* base;
@@ -503,7 +504,9 @@ __device__ __forceinline__ uint32_t xcd_contiguous_block(uint32_t w, uint32_t nb
     return x * q + (x < rem ? x : rem) + l;
 }
 
-// Pass 1: block b's per-tile store counts -> cnt[b * n_tiles + tile].  A tile
+// Pass 1: block b's per-tile store counts -> cnt[b * n_tiles + tile], 16-bit
+// (a block has at most kTileRecs stores; half the table traffic of every
+// pass that reads it).  A tile
 // holds whole ATVs (g <= the ATs of a tile), so a store's tile is its ATV's:
 // it depends on aip alone and this pass never reads bip.
 template <int R>
@@ -513,7 +516,7 @@ __global__ __launch_bounds__(kCountBlock) void k_tile_count(TileBatch J) {
     const uint32_t* __restrict__ aip = TJ.aip;
     const uint64_t n = TJ.n;
     const uint32_t ts = tile_shift(G), n_tiles = TJ.n_tiles, c0 = TJ.c0;
-    uint32_t* __restrict__ cnt = TJ.cnt;
+    uint16_t* __restrict__ cnt = TJ.cnt;
     uint32_t* __restrict__ tot = TJ.csum + (uint64_t)TJ.nchunk * n_tiles;  // the row after the chunk sums
     void* __restrict__ act_table = TJ.w_out ? TJ.act : nullptr;
     __shared__ uint32_t hist[kMaxTiles];
@@ -568,22 +571,22 @@ __global__ __launch_bounds__(kCountBlock) void k_tile_count(TileBatch J) {
         }
     }
     __syncthreads();
-    uint32_t* row = cnt + (uint64_t)blk * n_tiles;
-    for (uint32_t t = threadIdx.x; t < n_tiles; t += kCountBlock) row[t] = hist[t];
+    uint16_t* row = cnt + (uint64_t)blk * n_tiles;
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += kCountBlock) row[t] = (uint16_t)hist[t];
 }
 
 // Column sums of cnt over each chunk of kTileChunk rows -> csum[chunk][tile],
 // and their totals over the chunks -> csum[nchunk][tile].  A block takes 64
 // tiles of one chunk; each of its kColGroups waves sums kTileChunk /
 // kColGroups rows (loads issued together) and the waves' sums meet in LDS.
-// Rows of 64 tiles are 256-byte coalesced reads.
+// Rows of 64 tiles are 128-byte coalesced reads.
 constexpr uint32_t kColGroups = kBlock / kColTiles;
 constexpr uint32_t kColRows = kTileChunk / kColGroups;
 static_assert(kColGroups * kColRows == kTileChunk, "a chunk splits evenly over the waves");
 
 __global__ __launch_bounds__(kBlock) void k_tile_chunksum(TileBatch J) {
     const TileJob& TJ = J.j[blockIdx.z];
-    const uint32_t* __restrict__ cnt = TJ.cnt;
+    const uint16_t* __restrict__ cnt = TJ.cnt;
     const uint32_t nb = TJ.nb, n_tiles = TJ.n_tiles, nchunk = TJ.nchunk;
     uint32_t* __restrict__ csum = TJ.csum;
     if (blockIdx.y >= nchunk || blockIdx.x * kColTiles >= n_tiles) return;
@@ -656,7 +659,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 // loads issued together, start after the rows of the waves before it.
 __global__ __launch_bounds__(kBlock) void k_tile_rowpre(TileBatch J) {
     const TileJob& TJ = J.j[blockIdx.z];
-    const uint32_t* __restrict__ cnt = TJ.cnt;
+    const uint16_t* __restrict__ cnt = TJ.cnt;
     const uint32_t* __restrict__ csum = TJ.csum;
     const uint32_t nb = TJ.nb, n_tiles = TJ.n_tiles, nchunk = TJ.nchunk;
     uint32_t* __restrict__ pre = TJ.pre;
@@ -727,7 +730,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(TileBatch J) {
     const uint32_t* __restrict__ bip = TJ.bip;
     const uint64_t n = TJ.n;
     const uint32_t ts = tile_shift(G), n_tiles = TJ.n_tiles;
-    const uint32_t* __restrict__ cnt = TJ.cnt;
+    const uint16_t* __restrict__ cnt = TJ.cnt;
     const uint32_t* __restrict__ pre = TJ.pre;
     uint16_t* __restrict__ rec = TJ.rec;
     // 80 KiB of LDS, so that two blocks share a CU: the staged records, then
@@ -768,7 +771,7 @@ __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(TileBatch J) {
     // count table), kMaxTiles / kScatterBlock consecutive tiles per thread
     constexpr uint32_t TPT = kMaxTiles / kScatterBlock;
     const uint32_t* prow = pre + (uint64_t)blk * n_tiles;
-    const uint32_t* crow = cnt + (uint64_t)blk * n_tiles;
+    const uint16_t* crow = cnt + (uint64_t)blk * n_tiles;
     uint32_t c[TPT], sum = 0;
 #pragma unroll
     for (uint32_t e = 0; e < TPT; e++) {

@@ -438,7 +438,8 @@ int tiled_buffers(at_serve* S, int set, uint32_t slot, uint64_t n) {
     if (z.table > B.table_cap) {
         if (B.cnt) (void)hipFree(B.cnt);
         if (B.pre) (void)hipFree(B.pre);
-        B.cnt = B.pre = nullptr;
+        B.cnt = nullptr;
+        B.pre = nullptr;
         B.table_cap = 0;
         if ((rc = dalloc(&B.cnt, z.table)) || (rc = dalloc(&B.pre, z.table))) return rc;
         B.table_cap = z.table;
