@@ -427,6 +427,43 @@ def test_tiled_single_call_slices(cuda, oracle_lib, geom):
     g.destroy()
 
 
+@pytest.mark.parametrize("geom", [
+    dict(k=5, r=2, c=11, s=9, u=12, log2g=4),   # a host's two rows in one tile; 4096 tiles
+    dict(k=5, r=4, c=10, s=9, u=2, log2g=12),   # four rows in four tiles
+])
+def test_tiled_one_host_fills_blocks(cuda, oracle_lib, geom):
+    """Every pair of a slice from one host, so that all stores of a block of
+    the tiled scan land in the tiles of that host's r ATVs.  With r = 2 and
+    both rows in one tile, that tile takes all 16384 stores of every block:
+    the largest count the 16-bit per-block count table has to hold.  Then the
+    host with half the pairs among random others, then the host and one
+    other.  Pools, summaries and estimates equal the oracle's after every
+    slice."""
+    r = geom["r"]
+    geom = dict(**geom, theta=64.0, seed=9, tuple_budget=1 << 22)
+    rng = np.random.default_rng(40 + r)
+    n = 100_003
+    heavy, other = np.uint32(0x9E3779B9), np.uint32(12345)
+    rand = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    slices = [np.full(n, heavy, np.uint32),
+              np.where(rng.random(n) < 0.5, heavy, rand).astype(np.uint32),
+              np.where(rng.random(n) < 0.5, heavy, other).astype(np.uint32)]
+    g, o = make_pair(geom, oracle_lib)
+    g.set_scan_mode(3)
+    hosts = np.array([heavy, other, *rand[:32]], np.uint32)
+    for t, a in enumerate(slices):
+        b = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        g.ingest(to_dev(a), to_dev(b))
+        o.ingest(a, b)
+        g.close(5)
+        o.close(5)
+        where = f"r={r} slice {t}"
+        compare_state(g, o, where)
+        compare_summary(g, o, where)
+        compare_estimates(g, o, hosts, where)
+    g.destroy()
+
+
 def test_calls_larger_than_one_batch(cuda, oracle_lib):
     """Calls of more than 8Mi pairs are cut into batches by every scan (the
     tiled call then leaves the window count to the close).  Two slices of
