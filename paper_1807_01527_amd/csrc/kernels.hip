@@ -504,6 +504,9 @@ __device__ __forceinline__ uint32_t xcd_contiguous_block(uint32_t w, uint32_t nb
     return x * q + (x < rem ? x : rem) + l;
 }
 
+// The record passes (count, column scans, scatter) raise their waves' issue
+// priority: a server runs them beside its close graph, and the next tile pass
+// waits for them, not for the graph.
 // Pass 1: block b's per-tile store counts -> cnt[b * n_tiles + tile], 16-bit
 // (a block has at most kTileRecs stores; half the table traffic of every
 // pass that reads it).  A tile
@@ -511,6 +514,7 @@ __device__ __forceinline__ uint32_t xcd_contiguous_block(uint32_t w, uint32_t nb
 // it depends on aip alone and this pass never reads bip.
 template <int R>
 __global__ __launch_bounds__(kCountBlock) void k_tile_count(TileBatch J) {
+    __builtin_amdgcn_s_setprio(3);
     const TileJob& TJ = J.j[blockIdx.y];
     const Geometry& G = TJ.G;
     const uint32_t* __restrict__ aip = TJ.aip;
@@ -585,6 +589,7 @@ constexpr uint32_t kColRows = kTileChunk / kColGroups;
 static_assert(kColGroups * kColRows == kTileChunk, "a chunk splits evenly over the waves");
 
 __global__ __launch_bounds__(kBlock) void k_tile_chunksum(TileBatch J) {
+    __builtin_amdgcn_s_setprio(3);
     const TileJob& TJ = J.j[blockIdx.z];
     const uint16_t* __restrict__ cnt = TJ.cnt;
     const uint32_t nb = TJ.nb, n_tiles = TJ.n_tiles, nchunk = TJ.nchunk;
@@ -658,6 +663,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s
 // Within the chunk the same split as the chunk sums: each wave's 16 rows,
 // loads issued together, start after the rows of the waves before it.
 __global__ __launch_bounds__(kBlock) void k_tile_rowpre(TileBatch J) {
+    __builtin_amdgcn_s_setprio(3);
     const TileJob& TJ = J.j[blockIdx.z];
     const uint16_t* __restrict__ cnt = TJ.cnt;
     const uint32_t* __restrict__ csum = TJ.csum;
@@ -724,6 +730,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_rowpre(TileBatch J) {
 // Pass 2: the block's records grouped by tile in LDS, then written run by run.
 template <int R>
 __global__ __launch_bounds__(kScatterBlock) void k_tile_scatter(TileBatch J) {
+    __builtin_amdgcn_s_setprio(3);
     const TileJob& TJ = J.j[blockIdx.y];
     const Geometry& G = TJ.G;
     const uint32_t* __restrict__ aip = TJ.aip;
@@ -2618,6 +2625,11 @@ hipError_t launch_features(const uint8_t* pool, const uint64_t* aat, const uint3
 }
 
 constexpr uint32_t kServeGrid = 2048;  // persistent grid of the batched kernels
+// The feature kernel takes one wave per host up to 32768 hosts a step: its
+// waves are short, so the workgroups of kernels beside it (a server's record
+// passes) get CUs as they free up, which a grid that keeps every CU for the
+// whole kernel would not give them.
+constexpr uint32_t kFeatGrid = 4 * kServeGrid;
 
 hipError_t launch_serve_ingest_branch(const ServeBufs& B, const Geometry& shape, hipStream_t st) {
     hipLaunchKernelGGL(k_serve_preserve, dim3(kServeGrid), dim3(kBlock), 0, st, B.desc, B.slots);
@@ -2654,7 +2666,7 @@ hipError_t launch_serve_close_branch(const ServeBufs& B, const Geometry& shape, 
                        B.cand_cap);
 #define AT_SERVE_FEAT(RR)                                                                                     \
     case RR:                                                                                                  \
-        hipLaunchKernelGGL((k_serve_features<RR>), dim3(kServeGrid), dim3(kBlock), 0, st, B.desc, B.slots, B.state, \
+        hipLaunchKernelGGL((k_serve_features<RR>), dim3(kFeatGrid), dim3(kBlock), 0, st, B.desc, B.slots, B.state,  \
                            B.hosts, B.act, B.feat, B.est, B.pflags);                                          \
         break;
     switch (shape.r) {
