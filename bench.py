@@ -879,7 +879,7 @@ def main():
                     help="only the 256 MiB device copy, three times (the counters' calibration run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only (every box here has one); "
+        print(json.dumps({"error": "this benchmark measures the path on one GPU; "
                                    "--gpus above 1 is not supported"}))
         sys.exit(2)
     args.warmup = max(1, args.warmup)  # the first pass fills the window: measured windows hold all 60 slices
